@@ -1,0 +1,1256 @@
+// TEST INFRASTRUCTURE ONLY -- the oracle.
+//
+// A plain, slow, FP64 CPU implementation of one time step of the positivity-preserving
+// Lax-Wendroff discontinuous Galerkin (LxW-DG) method of Moe, Rossmanith and Seal,
+// "Positivity-preserving discontinuous Galerkin methods with Lax-Wendroff time
+// discretizations" (arXiv:1601.08145), for the compressible Euler equations in 1D, on 2D
+// Cartesian (tensor Q2) meshes and on 2D triangle (P2) meshes.
+//
+// It exists to check the GPU library against.  Only the test-suite, the smoke entry point and
+// the CPU-baseline leg of the benchmark may load it.  It shares no code, header, table or
+// helper with the GPU library: its own reference elements, its own mesh connectivity, its own
+// flux derivatives (by hyper-dual automatic differentiation instead of hand-written Jacobian and
+// Hessian products), and its own limiter arithmetic, written for clarity, not speed.
+//
+// The step follows the per-loop algorithm of Sec. 3.3 ("Putting it all together"): element loop
+// (Steps 1-2), edge loop (Step 3), element loop (Steps 4-5), element loop (Step 6), followed by
+// the shock-capturing limiter of Sec. 1.5 Step 5.  Where the paper is silent or its printed
+// formulas disagree with each other, the reading taken is stated at the place it is used.
+//
+// Pins: every function here is checked in tests/ against something other than itself
+// (closed forms, exactness of quadrature, finite differences, exact Riemann solutions,
+// convergence order, conservation, positivity, reduction to first-order Lax-Friedrichs).
+// The shock-capturing limiter (shock_limit below) is a reading of a limiter that the paper cites
+// but does not define: parity unpinned against that limiter's source; only its invariants are
+// pinned.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace ora {
+
+// ------------------------------------------------------------------------------------------
+// Hyper-dual numbers: v + a e1 + b e2 + ab e1 e2 with e1^2 = e2^2 = 0.  Evaluating F(q + e1 x
+// + e2 y) gives F(q), F'(q)x, F'(q)y and F''(q)(x, y) exactly (no truncation error).  Used for
+// the flux Jacobian-vector and Hessian-vector products of Eqs. (fluxderivs-a), (fluxderivs-b).
+// ------------------------------------------------------------------------------------------
+struct HD {
+  double v, a, b, ab;
+};
+static inline HD hd(double v) { return {v, 0.0, 0.0, 0.0}; }
+static inline HD operator+(HD x, HD y) { return {x.v + y.v, x.a + y.a, x.b + y.b, x.ab + y.ab}; }
+static inline HD operator-(HD x, HD y) { return {x.v - y.v, x.a - y.a, x.b - y.b, x.ab - y.ab}; }
+static inline HD operator*(HD x, HD y) {
+  return {x.v * y.v, x.v * y.a + x.a * y.v, x.v * y.b + x.b * y.v,
+          x.v * y.ab + x.a * y.b + x.b * y.a + x.ab * y.v};
+}
+static inline HD operator*(double s, HD x) { return {s * x.v, s * x.a, s * x.b, s * x.ab}; }
+static inline HD operator+(HD x, double s) { return {x.v + s, x.a, x.b, x.ab}; }
+static inline HD recip(HD x) {
+  // d(1/v) = -dv/v^2 ; d2(1/v) = 2 dv1 dv2 / v^3 - d2v / v^2
+  double r = 1.0 / x.v;
+  return {r, -x.a * r * r, -x.b * r * r, 2.0 * x.a * x.b * r * r * r - x.ab * r * r};
+}
+static inline HD operator/(HD x, HD y) { return x * recip(y); }
+
+// ------------------------------------------------------------------------------------------
+// Physics: Eq. (euler-eqns) with the equation of state Eq. (eos); the flux in direction d as
+// written in Sec. 1.5.  Conserved variables q = (rho, M, E) in 1D and (rho, Mx, My, E) in 2D.
+// ------------------------------------------------------------------------------------------
+template <class T>
+static void euler_flux(int dim, double gam, const T* q, int d, T* F) {
+  if (dim == 1) {
+    T rho = q[0], m = q[1], E = q[2];
+    T u = m / rho;
+    T p = (gam - 1.0) * (E - 0.5 * (m * u));
+    F[0] = m;
+    F[1] = m * u + p;
+    F[2] = u * (E + p);
+  } else {
+    T rho = q[0], mx = q[1], my = q[2], E = q[3];
+    T u = mx / rho, v = my / rho;
+    T p = (gam - 1.0) * (E - 0.5 * (mx * u + my * v));
+    if (d == 0) {
+      F[0] = mx;
+      F[1] = mx * u + p;
+      F[2] = my * u;
+      F[3] = u * (E + p);
+    } else {
+      F[0] = my;
+      F[1] = mx * v;
+      F[2] = my * v + p;
+      F[3] = v * (E + p);
+    }
+  }
+}
+
+template <>
+void euler_flux<double>(int dim, double gam, const double* q, int d, double* F) {
+  HD qh[4] = {}, Fh[4] = {};
+  int V = dim + 2;
+  for (int i = 0; i < V; ++i) qh[i] = hd(q[i]);
+  euler_flux<HD>(dim, gam, qh, d, Fh);
+  for (int i = 0; i < V; ++i) F[i] = Fh[i].v;
+}
+
+// A_d(q) x  (flux Jacobian times a vector), Eq. (fluxderivs-a)
+static void flux_jvp(int dim, double gam, const double* q, int d, const double* x, double* out) {
+  HD qh[4] = {}, Fh[4] = {};
+  int V = dim + 2;
+  for (int i = 0; i < V; ++i) qh[i] = {q[i], x[i], 0.0, 0.0};
+  euler_flux<HD>(dim, gam, qh, d, Fh);
+  for (int i = 0; i < V; ++i) out[i] = Fh[i].a;
+}
+
+// H_d(q)(x, y)  (flux Hessian applied to two vectors), Eq. (fluxderivs-b)
+static void flux_hvp(int dim, double gam, const double* q, int d, const double* x, const double* y,
+                     double* out) {
+  HD qh[4] = {}, Fh[4] = {};
+  int V = dim + 2;
+  for (int i = 0; i < V; ++i) qh[i] = {q[i], x[i], y[i], 0.0};
+  euler_flux<HD>(dim, gam, qh, d, Fh);
+  for (int i = 0; i < V; ++i) out[i] = Fh[i].ab;
+}
+
+// Pressure from conserved variables, Eq. (eos) / Eq. (ave_press).
+static double pressure(int dim, double gam, const double* q) {
+  if (dim == 1) return (gam - 1.0) * (q[2] - 0.5 * q[1] * q[1] / q[0]);
+  return (gam - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Reference elements (Sec. 1.2).  The basis is the Gram-Schmidt orthonormalisation of the
+// monomials listed below, in that order, under (1/|T0|) int_{T0} f g, using exact monomial
+// integrals; phi_1 == 1 so that Q^(1) is the cell average (Sec. 1.2).  Line: Legendre P0..P2 on
+// [-1,1].  Quad: the same procedure on [-1,1]^2 with the graded list below, which yields the
+// tensor-product Legendre basis (Q2, 9 modes).  Triangle: reference triangle (0,0),(1,0),(0,1),
+// P2 (6 modes).
+// ------------------------------------------------------------------------------------------
+enum Kind { LINE = 0, QUAD = 1, TRI = 2 };
+
+struct RefElem {
+  int kind = 0, dim = 0, ML = 0, K = 0, NI = 0, NQE = 0, NV = 0;
+  double T0 = 0.0;                 // |T0|
+  std::vector<int> ex, ey;         // monomial exponents
+  std::vector<double> C;           // ML x ML: phi_l = sum_j C[l*ML+j] * mono_j
+  std::vector<double> xi_int;      // NI x dim interior quadrature points
+  std::vector<double> w_int;       // NI weights, normalised to sum 1
+  std::vector<double> s_edge, om_edge;  // NQE Gauss-Legendre nodes on [-1,1], weights sum 2
+  std::vector<double> xv;          // NV x dim reference vertices (CCW)
+};
+
+static double fact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+// (1/|T0|) int_{T0} xi^a eta^b
+static double mono_moment(int kind, int a, int b) {
+  auto line = [](int n) { return (n % 2) ? 0.0 : 1.0 / (n + 1); };  // (1/2) int_{-1}^1 x^n
+  if (kind == LINE) return line(a);
+  if (kind == QUAD) return line(a) * line(b);
+  return 2.0 * fact(a) * fact(b) / fact(a + b + 2);  // |T0| = 1/2
+}
+
+static double ipow(double x, int n) {
+  double r = 1.0;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+// d^k/dx^k x^n
+static double dpow(double x, int n, int k) {
+  if (k > n) return 0.0;
+  double c = 1.0;
+  for (int i = 0; i < k; ++i) c *= (n - i);
+  return c * ipow(x, n - k);
+}
+
+static RefElem make_ref(int kind) {
+  RefElem R;
+  R.kind = kind;
+  const double g = std::sqrt(3.0 / 5.0);
+  R.s_edge = {-g, 0.0, g};
+  R.om_edge = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+  if (kind == LINE) {
+    R.dim = 1; R.ML = 3; R.K = 2; R.NV = 2; R.NQE = 1; R.T0 = 2.0;
+    R.ex = {0, 1, 2}; R.ey = {0, 0, 0};
+    R.xv = {-1.0, 1.0};
+    for (int i = 0; i < 3; ++i) { R.xi_int.push_back(R.s_edge[i]); R.w_int.push_back(R.om_edge[i] / 2.0); }
+    R.s_edge = {0.0}; R.om_edge = {2.0};  // a face in 1D is a point; half the weight sum is 1
+  } else if (kind == QUAD) {
+    R.dim = 2; R.ML = 9; R.K = 4; R.NV = 4; R.NQE = 3; R.T0 = 4.0;
+    R.ex = {0, 1, 0, 2, 1, 0, 2, 1, 2}; R.ey = {0, 0, 1, 0, 1, 2, 1, 2, 2};
+    R.xv = {-1, -1, 1, -1, 1, 1, -1, 1};
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) {
+        R.xi_int.push_back(R.s_edge[i]); R.xi_int.push_back(R.s_edge[j]);
+        R.w_int.push_back(R.om_edge[i] * R.om_edge[j] / 4.0);
+      }
+  } else {
+    R.dim = 2; R.ML = 6; R.K = 3; R.NV = 3; R.NQE = 3; R.T0 = 0.5;
+    R.ex = {0, 1, 0, 2, 1, 0}; R.ey = {0, 0, 1, 0, 1, 2};
+    R.xv = {0, 0, 1, 0, 0, 1};
+    // Degree-5, 7-point symmetric rule (Radon): centroid plus two orbits (a,a,b).
+    const double r15 = std::sqrt(15.0);
+    const double a1 = (6.0 - r15) / 21.0, b1 = (9.0 + 2.0 * r15) / 21.0, w1 = (155.0 - r15) / 1200.0;
+    const double a2 = (6.0 + r15) / 21.0, b2 = (9.0 - 2.0 * r15) / 21.0, w2 = (155.0 + r15) / 1200.0;
+    auto add = [&](double l1, double l2, double l3, double w) {
+      (void)l1;
+      R.xi_int.push_back(l2); R.xi_int.push_back(l3); R.w_int.push_back(w);
+    };
+    add(1.0 / 3, 1.0 / 3, 1.0 / 3, 9.0 / 40.0);
+    add(a1, a1, b1, w1); add(a1, b1, a1, w1); add(b1, a1, a1, w1);
+    add(a2, a2, b2, w2); add(a2, b2, a2, w2); add(b2, a2, a2, w2);
+  }
+  R.NI = (int)R.w_int.size();
+  // Gram-Schmidt in the monomial coordinates with the exact Gram matrix G.
+  int ML = R.ML;
+  std::vector<double> G(ML * ML);
+  for (int a = 0; a < ML; ++a)
+    for (int b = 0; b < ML; ++b) G[a * ML + b] = mono_moment(kind, R.ex[a] + R.ex[b], R.ey[a] + R.ey[b]);
+  auto ip = [&](const double* u, const double* v) {
+    double s = 0.0;
+    for (int a = 0; a < ML; ++a)
+      for (int b = 0; b < ML; ++b) s += u[a] * G[a * ML + b] * v[b];
+    return s;
+  };
+  R.C.assign(ML * ML, 0.0);
+  for (int l = 0; l < ML; ++l) {
+    std::vector<double> u(ML, 0.0);
+    u[l] = 1.0;
+    for (int k = 0; k < l; ++k) {
+      double c = ip(u.data(), &R.C[k * ML]);
+      for (int a = 0; a < ML; ++a) u[a] -= c * R.C[k * ML + a];
+    }
+    double nrm = std::sqrt(ip(u.data(), u.data()));
+    for (int a = 0; a < ML; ++a) R.C[l * ML + a] = u[a] / nrm;
+  }
+  return R;
+}
+
+// phi_l and its reference derivatives at xi.  da, db count derivatives in xi and eta.
+static double phi(const RefElem& R, int l, const double* xi, int da = 0, int db = 0) {
+  double s = 0.0;
+  double x = xi[0], y = (R.dim == 2) ? xi[1] : 0.0;
+  for (int j = 0; j < R.ML; ++j) {
+    double c = R.C[l * R.ML + j];
+    if (c == 0.0) continue;
+    s += c * dpow(x, R.ex[j], da) * dpow(y, R.ey[j], db);
+  }
+  return s;
+}
+
+// Reference coordinates of edge point j on local edge k.  Edge k runs from vertex k to vertex
+// k+1 (counter-clockwise); in 1D local edge k is vertex k.
+static void edge_point(const RefElem& R, int k, int j, double* xi) {
+  if (R.dim == 1) { xi[0] = R.xv[k]; return; }
+  int a = k, b = (k + 1) % R.NV;
+  double t = 0.5 * (1.0 + R.s_edge[j]);
+  xi[0] = R.xv[2 * a] + t * (R.xv[2 * b] - R.xv[2 * a]);
+  xi[1] = R.xv[2 * a + 1] + t * (R.xv[2 * b + 1] - R.xv[2 * a + 1]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Mesh: elements, edges e with normal n_e (|n_e| = edge length), the element i_e out of which
+// n_e points, the element j_e into which it points, and eps_ik = +1/-1 (Sec. 3.3, Eq. (epsik)).
+// Boundary edges have i_e = the interior element and j_e = -1 (a ghost, Sec. 2.4).
+// ------------------------------------------------------------------------------------------
+enum BC { BC_INTERIOR = -1, BC_PERIODIC = 0, BC_TRANSPARENT = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
+
+struct Mesh {
+  RefElem R;
+  int N = 0, E = 0;
+  std::vector<double> vx;          // N x NV x dim
+  std::vector<double> Jinv;        // N x dim x dim, Jinv[a][d] = d xi_a / d x_d
+  std::vector<double> area, perim;
+  std::vector<int> nbr, nbr_k;     // N x K, -1 on the boundary
+  std::vector<int> ebc;            // N x K boundary type of local edge (BC_INTERIOR inside)
+  std::vector<int> eid, eps;       // N x K
+  std::vector<int> e_i, e_ki, e_j, e_kj, e_bc;
+  std::vector<double> e_n, e_len;  // E x dim
+};
+
+static void finish_mesh(Mesh& M) {
+  const RefElem& R = M.R;
+  int N = M.N, K = R.K, dim = R.dim;
+  M.Jinv.assign(N * dim * dim, 0.0);
+  M.area.assign(N, 0.0);
+  M.perim.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    const double* v = &M.vx[i * R.NV * dim];
+    if (R.kind == LINE) {
+      double J = 0.5 * (v[1] - v[0]);
+      M.Jinv[i] = 1.0 / J;
+      M.area[i] = v[1] - v[0];
+      M.perim[i] = 2.0;
+    } else {
+      double J[2][2];
+      if (R.kind == TRI) {
+        J[0][0] = v[2] - v[0]; J[0][1] = v[4] - v[0];
+        J[1][0] = v[3] - v[1]; J[1][1] = v[5] - v[1];
+      } else {
+        J[0][0] = 0.5 * (v[2] - v[0]); J[0][1] = 0.5 * (v[6] - v[0]);
+        J[1][0] = 0.5 * (v[3] - v[1]); J[1][1] = 0.5 * (v[7] - v[1]);
+      }
+      double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      double* Ji = &M.Jinv[i * 4];
+      Ji[0] = J[1][1] / det; Ji[1] = -J[0][1] / det;
+      Ji[2] = -J[1][0] / det; Ji[3] = J[0][0] / det;
+      M.area[i] = det * R.T0;
+      double P = 0.0;
+      for (int k = 0; k < K; ++k) {
+        int b = (k + 1) % R.NV;
+        P += std::hypot(v[2 * b] - v[2 * k], v[2 * b + 1] - v[2 * k + 1]);
+      }
+      M.perim[i] = P;
+    }
+  }
+  // Edges: one per boundary (i,k), one per interior pair, i_e = the lexicographically first.
+  M.eid.assign(N * K, -1);
+  M.eps.assign(N * K, 0);
+  M.E = 0;
+  M.e_i.clear(); M.e_ki.clear(); M.e_j.clear(); M.e_kj.clear(); M.e_bc.clear();
+  M.e_n.clear(); M.e_len.clear();
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < K; ++k) {
+      if (M.eid[i * K + k] >= 0) continue;
+      int j = M.nbr[i * K + k], kj = M.nbr_k[i * K + k];
+      int e = M.E++;
+      M.e_i.push_back(i); M.e_ki.push_back(k); M.e_j.push_back(j); M.e_kj.push_back(kj);
+      M.e_bc.push_back(M.ebc[i * K + k]);
+      M.eid[i * K + k] = e; M.eps[i * K + k] = +1;
+      if (j >= 0) { M.eid[j * K + kj] = e; M.eps[j * K + kj] = -1; }
+      const double* v = &M.vx[i * R.NV * dim];
+      if (dim == 1) {
+        M.e_n.push_back(k == 0 ? -1.0 : 1.0); M.e_n.push_back(0.0);
+        M.e_len.push_back(1.0);
+      } else {
+        int b = (k + 1) % R.NV;
+        double dx = v[2 * b] - v[2 * k], dy = v[2 * b + 1] - v[2 * k + 1];
+        M.e_n.push_back(dy); M.e_n.push_back(-dx);
+        M.e_len.push_back(std::hypot(dx, dy));
+      }
+    }
+}
+
+static Mesh* mesh_1d(int n, double x0, double x1, int bcl, int bcr) {
+  Mesh* M = new Mesh;
+  M->R = make_ref(LINE);
+  M->N = n;
+  double h = (x1 - x0) / n;
+  for (int i = 0; i < n; ++i) { M->vx.push_back(x0 + i * h); M->vx.push_back(x0 + (i + 1) * h); }
+  M->nbr.assign(2 * n, -1); M->nbr_k.assign(2 * n, -1); M->ebc.assign(2 * n, BC_INTERIOR);
+  bool per = (bcl == BC_PERIODIC);
+  for (int i = 0; i < n; ++i) {
+    // local edge 0 = left end, 1 = right end
+    if (i > 0) { M->nbr[2 * i] = i - 1; M->nbr_k[2 * i] = 1; }
+    else if (per) { M->nbr[0] = n - 1; M->nbr_k[0] = 1; }
+    else M->ebc[0] = bcl;
+    if (i < n - 1) { M->nbr[2 * i + 1] = i + 1; M->nbr_k[2 * i + 1] = 0; }
+    else if (per) { M->nbr[2 * i + 1] = 0; M->nbr_k[2 * i + 1] = 0; }
+    else M->ebc[2 * i + 1] = bcr;
+  }
+  finish_mesh(*M);
+  return M;
+}
+
+// bc[4] = {x-low, x-high, y-low, y-high}
+static Mesh* mesh_cart(int nx, int ny, double x0, double x1, double y0, double y1, const int* bc) {
+  Mesh* M = new Mesh;
+  M->R = make_ref(QUAD);
+  int N = nx * ny;
+  M->N = N;
+  double hx = (x1 - x0) / nx, hy = (y1 - y0) / ny;
+  M->nbr.assign(4 * N, -1); M->nbr_k.assign(4 * N, -1); M->ebc.assign(4 * N, BC_INTERIOR);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int e = i + nx * j;
+      double xa = x0 + i * hx, xb = x0 + (i + 1) * hx, ya = y0 + j * hy, yb = y0 + (j + 1) * hy;
+      double v[8] = {xa, ya, xb, ya, xb, yb, xa, yb};
+      for (double c : v) M->vx.push_back(c);
+      // local edges: 0 bottom, 1 right, 2 top, 3 left
+      auto link = [&](int k, int ii, int jj, int kk, int bcode) {
+        bool out = (ii < 0 || ii >= nx || jj < 0 || jj >= ny);
+        if (out && bcode != BC_PERIODIC) { M->ebc[4 * e + k] = bcode; return; }
+        ii = (ii + nx) % nx; jj = (jj + ny) % ny;
+        M->nbr[4 * e + k] = ii + nx * jj; M->nbr_k[4 * e + k] = kk;
+      };
+      link(0, i, j - 1, 2, bc[2]);
+      link(1, i + 1, j, 3, bc[1]);
+      link(2, i, j + 1, 0, bc[3]);
+      link(3, i - 1, j, 1, bc[0]);
+    }
+  finish_mesh(*M);
+  return M;
+}
+
+// Triangles given by node coordinates and counter-clockwise vertex triples.  Boundary edges get
+// the type bnd[3*t+k] (transparent when bnd is null).  Boundary edges marked periodic are paired
+// with the boundary edge whose midpoint differs by one period in x or y.
+static Mesh* mesh_tri(int nn, const double* xy, int nt, const int* tri, const int* bnd,
+                      const double* period, std::string* err) {
+  Mesh* M = new Mesh;
+  M->R = make_ref(TRI);
+  M->N = nt;
+  for (int t = 0; t < nt; ++t)
+    for (int a = 0; a < 3; ++a) {
+      int v = tri[3 * t + a];
+      if (v < 0 || v >= nn) { *err = "node index out of range"; delete M; return nullptr; }
+      M->vx.push_back(xy[2 * v]); M->vx.push_back(xy[2 * v + 1]);
+    }
+  M->nbr.assign(3 * nt, -1); M->nbr_k.assign(3 * nt, -1); M->ebc.assign(3 * nt, BC_INTERIOR);
+  std::map<std::pair<int, int>, std::pair<int, int>> open;
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < 3; ++k) {
+      int a = tri[3 * t + k], b = tri[3 * t + (k + 1) % 3];
+      auto key = std::make_pair(std::min(a, b), std::max(a, b));
+      auto it = open.find(key);
+      if (it == open.end()) open[key] = {t, k};
+      else {
+        int t2 = it->second.first, k2 = it->second.second;
+        M->nbr[3 * t + k] = t2; M->nbr_k[3 * t + k] = k2;
+        M->nbr[3 * t2 + k2] = t; M->nbr_k[3 * t2 + k2] = k;
+        open.erase(it);
+      }
+    }
+  std::vector<std::pair<int, int>> per;
+  for (auto& kv : open) {
+    int t = kv.second.first, k = kv.second.second;
+    int code = bnd ? bnd[3 * t + k] : BC_TRANSPARENT;
+    if (code == BC_PERIODIC) per.push_back({t, k});
+    else M->ebc[3 * t + k] = code;
+  }
+  if (!per.empty()) {
+    if (!period) { *err = "periodic edges without a period"; delete M; return nullptr; }
+    // pair periodic edges by midpoint modulo the period
+    auto mid = [&](int t, int k, double* m) {
+      const double* v = &M->vx[6 * t];
+      int b = (k + 1) % 3;
+      m[0] = 0.5 * (v[2 * k] + v[2 * b]); m[1] = 0.5 * (v[2 * k + 1] + v[2 * b + 1]);
+    };
+    std::vector<int> used(per.size(), 0);
+    for (size_t p = 0; p < per.size(); ++p) {
+      if (used[p]) continue;
+      double mp[2]; mid(per[p].first, per[p].second, mp);
+      bool found = false;
+      for (size_t q = p + 1; q < per.size() && !found; ++q) {
+        if (used[q]) continue;
+        double mq[2]; mid(per[q].first, per[q].second, mq);
+        double dx = mq[0] - mp[0], dy = mq[1] - mp[1];
+        double tol = 1e-9 * (std::fabs(period[0]) + std::fabs(period[1]));
+        bool mx = period[0] > 0 && std::fabs(std::fabs(dx) - period[0]) < tol && std::fabs(dy) < tol;
+        bool my = period[1] > 0 && std::fabs(std::fabs(dy) - period[1]) < tol && std::fabs(dx) < tol;
+        if (mx || my) {
+          int t = per[p].first, k = per[p].second, t2 = per[q].first, k2 = per[q].second;
+          M->nbr[3 * t + k] = t2; M->nbr_k[3 * t + k] = k2;
+          M->nbr[3 * t2 + k2] = t; M->nbr_k[3 * t2 + k2] = k;
+          used[p] = used[q] = 1; found = true;
+        }
+      }
+      if (!found) { *err = "unpaired periodic edge"; delete M; return nullptr; }
+    }
+  }
+  finish_mesh(*M);
+  for (int t = 0; t < nt; ++t)
+    if (!(M->area[t] > 0.0)) { *err = "triangle not counter-clockwise or degenerate"; delete M; return nullptr; }
+  return M;
+}
+
+// ------------------------------------------------------------------------------------------
+// Solver state and the step.
+// ------------------------------------------------------------------------------------------
+struct Params {
+  double gamma = 1.4, cfl = 0.08, eps0 = 1e-12, alpha0 = 500.0;
+  int shock = 1;
+  double inflow[4] = {1, 0, 0, 1};
+  double force_theta = -1.0;  // test hook: when >= 0, every Lambda_e is replaced by this value
+};
+
+enum Status { OK = 0, ERR_ARG = -1, ERR_STATE = -4, ERR_POSITIVITY = -5, ERR_NONFINITE = -6, ERR_CFL = -7 };
+
+struct Solver {
+  Mesh* M;
+  Params P;
+  double t = 0.0;
+  std::vector<double> Q;  // N x V x ML
+  // Intermediate quantities of the last step, for stage-by-stage comparison.
+  double s = 0.0, dt = 0.0;
+  std::vector<double> theta_mom, theta_sc, Qlim, Vol, Qupd;
+  std::vector<double> fLxW_ik, fLxF_ik, Lam_ik, c_ik, Lam_e_ik;  // per (element, local edge)
+  std::vector<double> qderiv;  // q_t and q_tt at the interior points: N x NI x 2 x V
+  int err_elem = -1;
+  std::string err;
+};
+
+static inline int NVAR(const Mesh& M) { return M.R.dim + 2; }
+
+// Physical coordinates of a reference point in element i.
+static void map_point(const Mesh& M, int i, const double* xi, double* x) {
+  const RefElem& R = M.R;
+  const double* v = &M.vx[i * R.NV * R.dim];
+  if (R.kind == LINE) { x[0] = v[0] + 0.5 * (xi[0] + 1.0) * (v[1] - v[0]); return; }
+  if (R.kind == TRI) {
+    x[0] = v[0] + xi[0] * (v[2] - v[0]) + xi[1] * (v[4] - v[0]);
+    x[1] = v[1] + xi[0] * (v[3] - v[1]) + xi[1] * (v[5] - v[1]);
+  } else {
+    x[0] = v[0] + 0.5 * (xi[0] + 1.0) * (v[2] - v[0]) + 0.5 * (xi[1] + 1.0) * (v[6] - v[0]);
+    x[1] = v[1] + 0.5 * (xi[0] + 1.0) * (v[3] - v[1]) + 0.5 * (xi[1] + 1.0) * (v[7] - v[1]);
+  }
+}
+
+// Physical gradient of phi_l: d phi / d x_d = sum_a Jinv[a][d] d phi / d xi_a.
+static void grad_phi(const Mesh& M, int i, int l, const double* xi, double* g) {
+  const RefElem& R = M.R;
+  const double* Ji = &M.Jinv[i * R.dim * R.dim];
+  if (R.dim == 1) { g[0] = Ji[0] * phi(R, l, xi, 1, 0); return; }
+  double d0 = phi(R, l, xi, 1, 0), d1 = phi(R, l, xi, 0, 1);
+  g[0] = Ji[0] * d0 + Ji[2] * d1;
+  g[1] = Ji[1] * d0 + Ji[3] * d1;
+}
+
+// Physical Hessian of phi_l: H[d][e] = sum_ab Jinv[a][d] Jinv[b][e] d2 phi / dxi_a dxi_b.
+static void hess_phi(const Mesh& M, int i, int l, const double* xi, double* H) {
+  const RefElem& R = M.R;
+  const double* Ji = &M.Jinv[i * R.dim * R.dim];
+  if (R.dim == 1) { H[0] = Ji[0] * Ji[0] * phi(R, l, xi, 2, 0); return; }
+  double r[2][2] = {{phi(R, l, xi, 2, 0), phi(R, l, xi, 1, 1)}, {phi(R, l, xi, 1, 1), phi(R, l, xi, 0, 2)}};
+  for (int d = 0; d < 2; ++d)
+    for (int e = 0; e < 2; ++e) {
+      double s = 0.0;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) s += Ji[a * 2 + d] * Ji[b * 2 + e] * r[a][b];
+      H[d * 2 + e] = s;
+    }
+}
+
+// q^h(xi) on element i (Sec. 1.2)
+static void eval_q(const Mesh& M, const double* Qi, const double* xi, double* q) {
+  const RefElem& R = M.R;
+  int V = NVAR(M);
+  for (int v = 0; v < V; ++v) {
+    double s = 0.0;
+    for (int l = 0; l < R.ML; ++l) s += Qi[v * R.ML + l] * phi(R, l, xi);
+    q[v] = s;
+  }
+}
+
+// The limiter points: interior quadrature points and edge quadrature points (Sec. 3.1).
+static std::vector<std::vector<double>> limiter_points(const RefElem& R) {
+  std::vector<std::vector<double>> pts;
+  for (int m = 0; m < R.NI; ++m) pts.push_back({R.xi_int[m * R.dim], R.dim == 2 ? R.xi_int[m * R.dim + 1] : 0.0});
+  for (int k = 0; k < R.K; ++k)
+    for (int j = 0; j < R.NQE; ++j) {
+      double xi[2] = {0, 0};
+      edge_point(R, k, j, xi);
+      pts.push_back({xi[0], xi[1]});
+    }
+  return pts;
+}
+
+// Moment limiter of Sec. 3.1 for one element (Steps 0-2).  Returns theta and scales modes l>=2.
+//  Step 0 reading: a cell whose average density is below eps0 (the flux limiter only guarantees
+//  rho_bar >= 0) or whose average pressure is not positive is flattened (theta = 0).
+//  Step 1: theta^rho = largest theta in [0,1] with rho_bar + theta*rho~_m >= eps0 at all points;
+//  the closed form is (rho_bar - eps0)/(rho_bar - rho_m) over the points with rho_m < eps0.
+//  Step 2 reading: pressure target eps_p = min(eps0, p_bar); by concavity of p in theta,
+//  theta_m = theta^rho if p(q_bar + theta^rho q~_m) >= eps_p, otherwise
+//  theta^rho (p_bar - eps_p)/(p_bar - p(q_bar + theta^rho q~_m)); theta = min_m theta_m.
+static double moment_limit(const Mesh& M, const Params& P, double* Qi) {
+  const RefElem& R = M.R;
+  int V = NVAR(M), ML = R.ML, dim = R.dim;
+  double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML + 0];
+  double rbar = qbar[0];
+  double pbar = pressure(dim, P.gamma, qbar);
+  double theta;
+  if (!(rbar >= P.eps0) || !(pbar > 0.0)) {
+    theta = 0.0;
+  } else {
+    auto pts = limiter_points(R);
+    std::vector<std::vector<double>> dev;  // q~_m
+    for (auto& x : pts) {
+      double q[4];
+      eval_q(M, Qi, x.data(), q);
+      std::vector<double> d(V);
+      for (int v = 0; v < V; ++v) d[v] = q[v] - qbar[v];
+      dev.push_back(d);
+    }
+    double th_rho = 1.0;
+    for (auto& d : dev) {
+      double rm = rbar + d[0];
+      if (rm < P.eps0) th_rho = std::min(th_rho, (rbar - P.eps0) / (rbar - rm));
+    }
+    double eps_p = std::min(P.eps0, pbar);
+    theta = th_rho;
+    for (auto& d : dev) {
+      double qt[4];
+      for (int v = 0; v < V; ++v) qt[v] = qbar[v] + th_rho * d[v];
+      double pt = pressure(dim, P.gamma, qt);
+      double thm = th_rho;
+      if (pt < eps_p) thm = th_rho * (pbar - eps_p) / (pbar - pt);
+      theta = std::min(theta, thm);
+    }
+  }
+  if (theta < 1.0)
+    for (int v = 0; v < V; ++v)
+      for (int l = 1; l < ML; ++l) Qi[v * ML + l] *= theta;
+  return theta;
+}
+
+// |u| + c at a state (rho > 0, p > 0 assumed by the caller).
+static double wave_speed(int dim, double gam, const double* q) {
+  double rho = q[0];
+  double p = pressure(dim, gam, q);
+  double u2 = 0.0;
+  for (int d = 0; d < dim; ++d) u2 += (q[1 + d] / rho) * (q[1 + d] / rho);
+  return std::sqrt(u2) + std::sqrt(gam * p / rho);
+}
+
+// Boundary operator of Sec. 2.4 on a state or on a time derivative of it: tangential momentum
+// kept, normal momentum kept (transparent) or negated (reflective).  nhat is the unit normal.
+static void bc_reflect(int dim, const double* q, const double* nhat, double* out) {
+  int V = dim + 2;
+  for (int v = 0; v < V; ++v) out[v] = q[v];
+  if (dim == 1) { out[1] = -q[1]; return; }
+  double mn = q[1] * nhat[0] + q[2] * nhat[1];
+  out[1] = q[1] - 2.0 * mn * nhat[0];
+  out[2] = q[2] - 2.0 * mn * nhat[1];
+}
+
+// F_T of Eq. (taylor3-flux) from q, q_t, q_tt at a point (chain rule for F_t and F_tt).
+static void ft_from_derivs(int dim, double gam, double dt, const double* q, const double* qt,
+                           const double* qtt, double* FT /* dim x V */) {
+  int V = dim + 2;
+  for (int d = 0; d < dim; ++d) {
+    double F[4], Ft[4], H[4], Aqtt[4];
+    euler_flux<double>(dim, gam, q, d, F);
+    flux_jvp(dim, gam, q, d, qt, Ft);
+    flux_hvp(dim, gam, q, d, qt, qt, H);
+    flux_jvp(dim, gam, q, d, qtt, Aqtt);
+    for (int v = 0; v < V; ++v)
+      FT[d * V + v] = F[v] + 0.5 * dt * Ft[v] + (dt * dt / 6.0) * (H[v] + Aqtt[v]);
+  }
+}
+
+struct Trace {  // per element, local edge, edge point: q, q_t, q_tt and F_T (dim x V)
+  double q[4], qt[4], qtt[4], FT[8];
+};
+
+// The shock-capturing limiter (Sec. 1.5 Step 5, Sec. 4.1).  The paper cites this limiter but does
+// not define it; the reading implemented here works on the primitive variables w in
+// {rho, u, (v), p}, with relaxation delta = alpha0 h^1.5 (alpha0 = 500; h = Delta x in 1D,
+// sqrt|T| on quads, sqrt(2|T|) on triangles).  Bounds: M_w = max(w_bar_i + delta, max over edge
+// neighbours of w_bar_j), m_w = min(w_bar_i - delta, min_j w_bar_j); neighbour averages across
+// boundary edges are the boundary operator applied to the own average.  theta^w shrinks the
+// deviation from w_bar_i at the limiter points so that the extremes meet the bounds; velocity and
+// pressure are only sampled at points with positive density.  theta = min_w theta^w scales
+// modes l >= 2.  It runs on the updated state, before the next step's moment limiter.
+static double shock_limit(const Solver& S, const std::vector<double>& Qold, int i, double* Qi) {
+  const Mesh& M = *S.M;
+  const RefElem& R = M.R;
+  int V = NVAR(M), ML = R.ML, dim = R.dim, K = R.K;
+  double gam = S.P.gamma;
+  auto prim = [&](const double* q, double* w) {  // (rho, u[, v], p)
+    w[0] = q[0];
+    for (int d = 0; d < dim; ++d) w[1 + d] = q[1 + d] / q[0];
+    w[dim + 1] = pressure(dim, gam, q);
+  };
+  double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML];
+  if (!(qbar[0] >= S.P.eps0) || !(pressure(dim, gam, qbar) > 0.0)) return 1.0;
+  double wbar[4];
+  prim(qbar, wbar);
+  double h = (R.kind == LINE) ? M.area[i] : (R.kind == QUAD ? std::sqrt(M.area[i]) : std::sqrt(2.0 * M.area[i]));
+  double delta = S.P.alpha0 * std::pow(h, 1.5);
+  double Mx[4], Mn[4];
+  for (int w = 0; w < V; ++w) { Mx[w] = wbar[w] + delta; Mn[w] = wbar[w] - delta; }
+  for (int k = 0; k < K; ++k) {
+    double qn[4];
+    int j = M.nbr[i * K + k];
+    if (j >= 0) {
+      for (int v = 0; v < V; ++v) qn[v] = Qold[(size_t)j * V * ML + v * ML];
+    } else {
+      int bc = M.ebc[i * K + k];
+      int e = M.eid[i * K + k];
+      double nh[2] = {M.e_n[2 * e] / M.e_len[e], M.e_n[2 * e + 1] / M.e_len[e]};
+      if (bc == BC_REFLECTIVE) bc_reflect(dim, qbar, nh, qn);
+      else if (bc == BC_INFLOW) for (int v = 0; v < V; ++v) qn[v] = (dim == 1 && v == 2) ? S.P.inflow[3] : S.P.inflow[v];
+      else for (int v = 0; v < V; ++v) qn[v] = qbar[v];
+    }
+    double wn[4];
+    prim(qn, wn);
+    for (int w = 0; w < V; ++w) { Mx[w] = std::max(Mx[w], wn[w]); Mn[w] = std::min(Mn[w], wn[w]); }
+  }
+  double wmax[4], wmin[4];
+  for (int w = 0; w < V; ++w) { wmax[w] = wbar[w]; wmin[w] = wbar[w]; }
+  for (auto& x : limiter_points(R)) {
+    double q[4], wv[4];
+    eval_q(M, Qi, x.data(), q);
+    wmax[0] = std::max(wmax[0], q[0]); wmin[0] = std::min(wmin[0], q[0]);
+    if (q[0] > 0.0) {
+      prim(q, wv);
+      for (int w = 1; w < V; ++w) { wmax[w] = std::max(wmax[w], wv[w]); wmin[w] = std::min(wmin[w], wv[w]); }
+    }
+  }
+  double theta = 1.0;
+  for (int w = 0; w < V; ++w) {
+    if (wmax[w] > Mx[w]) theta = std::min(theta, (Mx[w] - wbar[w]) / (wmax[w] - wbar[w]));
+    if (wmin[w] < Mn[w]) theta = std::min(theta, (wbar[w] - Mn[w]) / (wbar[w] - wmin[w]));
+  }
+  theta = std::max(0.0, std::min(1.0, theta));
+  if (theta < 1.0)
+    for (int v = 0; v < V; ++v)
+      for (int l = 1; l < ML; ++l) Qi[v * ML + l] *= theta;
+  return theta;
+}
+
+// Largest mu in [0,1] with p(qL + mu (qa - qL)) >= eps_p and positive density (Sec. 3.3 Step 5b).
+// Along the segment, (gamma-1)(rho E - |M|^2/2) - eps_p rho is the quadratic a mu^2 + b mu + c
+// with c = rho_L (p_L - eps_p) >= 0; its first crossing of zero is 2c / (-b + sqrt(b^2 - 4ac)).
+// The root is then stepped down by ulps until the condition holds in floating point.
+static double mu_solve(int dim, double gam, double eps_p, const double* qL, const double* qa) {
+  int V = dim + 2;
+  auto ok = [&](double mu) {
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < V; ++v) q[v] = qL[v] + mu * (qa[v] - qL[v]);
+    return q[0] > 0.0 && pressure(dim, gam, q) >= eps_p;
+  };
+  if (ok(1.0)) return 1.0;
+  double d[4];
+  for (int v = 0; v < V; ++v) d[v] = qa[v] - qL[v];
+  double mL2 = 0.0, mLd = 0.0, dd2 = 0.0;
+  for (int k = 1; k <= dim; ++k) { mL2 += qL[k] * qL[k]; mLd += qL[k] * d[k]; dd2 += d[k] * d[k]; }
+  int iE = dim + 1;
+  double a = (gam - 1.0) * (d[0] * d[iE] - 0.5 * dd2);
+  double b = (gam - 1.0) * (qL[0] * d[iE] + d[0] * qL[iE] - mLd) - eps_p * d[0];
+  double c = (gam - 1.0) * (qL[0] * qL[iE] - 0.5 * mL2) - eps_p * qL[0];
+  if (!(c > 0.0)) return 0.0;
+  double disc = std::max(0.0, b * b - 4.0 * a * c);
+  double den = -b + std::sqrt(disc);
+  double mu = (den > 0.0) ? 2.0 * c / den : 0.0;
+  mu = std::min(1.0, std::max(0.0, mu));
+  for (int it = 0; it < 64 && mu > 0.0 && !ok(mu); ++it) mu = std::nextafter(mu, 0.0);
+  if (!ok(mu)) mu = 0.0;
+  return mu;
+}
+
+static int set_err(Solver& S, int code, int elem, const char* msg) {
+  if (S.err_elem < 0) {
+    S.err_elem = elem;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s (element %d)", msg, elem);
+    S.err = buf;
+  }
+  return code;
+}
+
+// One LxW-DG step to min(t + dt_CFL, T).  Returns a status code.
+static int step(Solver& S, double T) {
+  Mesh& M = *S.M;
+  const RefElem& R = M.R;
+  const int N = M.N, V = NVAR(M), ML = R.ML, K = R.K, dim = R.dim, NQE = R.NQE, NI = R.NI;
+  const double gam = S.P.gamma;
+  const size_t QS = (size_t)V * ML;
+  S.err_elem = -1; S.err.clear();
+  for (double x : S.Q)
+    if (!std::isfinite(x)) return set_err(S, ERR_NONFINITE, -1, "non-finite state");
+
+  // ---- Element loop, Step 1: moment limiter (Sec. 3.1) -------------------------------------
+  S.theta_mom.assign(N, 1.0);
+  int bad = -1;
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < N; ++i) {
+    double* Qi = &S.Q[i * QS];
+    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML];
+    if (!(qbar[0] > 0.0) || !(pressure(dim, gam, qbar) > 0.0)) {
+#pragma omp critical
+      if (bad < 0 || i < bad) bad = i;
+    }
+    S.theta_mom[i] = moment_limit(M, S.P, Qi);
+  }
+  if (bad >= 0) return set_err(S, ERR_POSITIVITY, bad, "cell average density or pressure not positive");
+  S.Qlim = S.Q;
+
+  // ---- Global wave speed s and the time step (reading of Sec. 4.1: CFL 0.08 means
+  //      dt * s * max_i |dT_i| / (2|T_i|) = CFL; the last step is clipped to reach T) -----------
+  auto pts = limiter_points(R);
+  double s = 0.0, geo = 0.0;
+#pragma omp parallel for reduction(max : s, geo) schedule(static)
+  for (int i = 0; i < N; ++i) {
+    const double* Qi = &S.Q[i * QS];
+    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML];
+    double si = wave_speed(dim, gam, qbar);
+    for (auto& x : pts) {
+      double q[4];
+      eval_q(M, Qi, x.data(), q);
+      si = std::max(si, wave_speed(dim, gam, q));
+    }
+    s = std::max(s, si);
+    geo = std::max(geo, M.perim[i] / (2.0 * M.area[i]));
+  }
+  double dt = S.P.cfl / (s * geo);
+  if (S.t + dt > T) dt = T - S.t;
+  S.s = s; S.dt = dt;
+
+  // ---- Element loop, Step 2: time-averaged flux F_T at every quadrature point --------------
+  // Sec. 2.3 Step 1: project F(q^h) onto the basis with the interior rule (normalised weights).
+  // Sec. 2.3 Step 2: from q^h and F^h form q, grad q, D = div F^h, grad D, then (Sec. 2.2)
+  //   q_t = -D, F_t = A q_t, q_tt = sum_d [H_d(d_d q, D) + A_d d_d D], F_tt = H(q_t,q_t) + A q_tt,
+  //   F_T = F + dt/2 F_t + dt^2/6 F_tt.
+  // Sec. 2.3 Step 3 (signs from integrating by parts, which the printed Eq. (EulerStepExact)
+  // has flipped; the printed cell-average update fixes them): the volume term
+  //   V_l = (1/|T|) int grad phi_l . F_T  ~  sum_m w_m grad phi_l(x_m) . F_T(x_m).
+  std::vector<Trace> tr((size_t)N * K * NQE);
+  S.Vol.assign((size_t)N * QS, 0.0);
+  S.qderiv.assign((size_t)N * NI * 2 * V, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < N; ++i) {
+    const double* Qi = &S.Q[i * QS];
+    double Fh[2][4][9];
+    for (int d = 0; d < dim; ++d)
+      for (int v = 0; v < V; ++v)
+        for (int l = 0; l < ML; ++l) Fh[d][v][l] = 0.0;
+    for (int m = 0; m < NI; ++m) {
+      const double* xi = &R.xi_int[m * dim];
+      double q[4];
+      eval_q(M, Qi, xi, q);
+      for (int d = 0; d < dim; ++d) {
+        double F[4];
+        euler_flux<double>(dim, gam, q, d, F);
+        for (int v = 0; v < V; ++v)
+          for (int l = 0; l < ML; ++l) Fh[d][v][l] += R.w_int[m] * F[v] * phi(R, l, xi);
+      }
+    }
+    auto at_point = [&](const double* xi, double* q, double* qt, double* qtt, double* FT) {
+      double dq[2][4], D[4], dD[2][4];
+      eval_q(M, Qi, xi, q);
+      for (int v = 0; v < V; ++v) {
+        for (int a = 0; a < dim; ++a) { dq[a][v] = 0.0; dD[a][v] = 0.0; }
+        D[v] = 0.0;
+      }
+      for (int l = 0; l < ML; ++l) {
+        double g[2], H[4];
+        grad_phi(M, i, l, xi, g);
+        hess_phi(M, i, l, xi, H);
+        for (int v = 0; v < V; ++v) {
+          for (int a = 0; a < dim; ++a) dq[a][v] += Qi[v * ML + l] * g[a];
+          for (int d = 0; d < dim; ++d) {
+            D[v] += Fh[d][v][l] * g[d];
+            for (int a = 0; a < dim; ++a) dD[a][v] += Fh[d][v][l] * H[d * dim + a];
+          }
+        }
+      }
+      for (int v = 0; v < V; ++v) qt[v] = -D[v];
+      for (int v = 0; v < V; ++v) qtt[v] = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        double h[4], a[4];
+        flux_hvp(dim, gam, q, d, dq[d], D, h);
+        flux_jvp(dim, gam, q, d, dD[d], a);
+        for (int v = 0; v < V; ++v) qtt[v] += h[v] + a[v];
+      }
+      ft_from_derivs(dim, gam, dt, q, qt, qtt, FT);
+    };
+    double* Vi = &S.Vol[i * QS];
+    for (int m = 0; m < NI; ++m) {
+      const double* xi = &R.xi_int[m * dim];
+      double q[4], qt[4], qtt[4], FT[8];
+      at_point(xi, q, qt, qtt, FT);
+      for (int v = 0; v < V; ++v) {
+        S.qderiv[(((size_t)i * NI + m) * 2 + 0) * V + v] = qt[v];
+        S.qderiv[(((size_t)i * NI + m) * 2 + 1) * V + v] = qtt[v];
+      }
+      for (int l = 0; l < ML; ++l) {
+        double g[2];
+        grad_phi(M, i, l, xi, g);
+        for (int v = 0; v < V; ++v) {
+          double dot = 0.0;
+          for (int d = 0; d < dim; ++d) dot += g[d] * FT[d * V + v];
+          Vi[v * ML + l] += R.w_int[m] * dot;
+        }
+      }
+    }
+    for (int k = 0; k < K; ++k)
+      for (int j = 0; j < NQE; ++j) {
+        double xi[2] = {0, 0};
+        edge_point(R, k, j, xi);
+        Trace& T_ = tr[((size_t)i * K + k) * NQE + j];
+        at_point(xi, T_.q, T_.qt, T_.qtt, T_.FT);
+      }
+  }
+
+  // ---- Edge loop, Step 3: F_T^* . n_e at the edge points (Eq. (LLF) with |n_e| the length),
+  //      f^LxW_e = (1/2) sum omega F^*.n_e, f^LxF_e from the cell averages, Lambda_e = 1 --------
+  const int E = M.E;
+  std::vector<double> Fstar((size_t)E * NQE * V), fLxW((size_t)E * V), fLxF((size_t)E * V), Lam_e(E, 1.0);
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < E; ++e) {
+    int i = M.e_i[e], ki = M.e_ki[e], j = M.e_j[e], kj = M.e_kj[e];
+    const double* n = &M.e_n[2 * e];
+    double len = M.e_len[e];
+    double nh[2] = {n[0] / len, n[1] / len};
+    int bc = M.e_bc[e];
+    double qbi[4], qbj[4];
+    for (int v = 0; v < V; ++v) qbi[v] = S.Q[i * QS + v * ML];
+    if (j >= 0) for (int v = 0; v < V; ++v) qbj[v] = S.Q[j * QS + v * ML];
+    else if (bc == BC_REFLECTIVE) bc_reflect(dim, qbi, nh, qbj);
+    else if (bc == BC_INFLOW) for (int v = 0; v < V; ++v) qbj[v] = (dim == 1 && v == 2) ? S.P.inflow[3] : S.P.inflow[v];
+    else for (int v = 0; v < V; ++v) qbj[v] = qbi[v];
+    for (int jj = 0; jj < NQE; ++jj) {
+      const Trace& Tm = tr[((size_t)i * K + ki) * NQE + jj];
+      double qp[4], FTp[8];
+      if (j >= 0) {
+        const Trace& Tp = tr[((size_t)j * K + kj) * NQE + (NQE - 1 - jj)];
+        for (int v = 0; v < V; ++v) qp[v] = Tp.q[v];
+        for (int x = 0; x < dim * V; ++x) FTp[x] = Tp.FT[x];
+      } else if (bc == BC_REFLECTIVE) {
+        double qt[4], qtt[4];
+        bc_reflect(dim, Tm.q, nh, qp);
+        bc_reflect(dim, Tm.qt, nh, qt);
+        bc_reflect(dim, Tm.qtt, nh, qtt);
+        ft_from_derivs(dim, gam, dt, qp, qt, qtt, FTp);
+      } else if (bc == BC_INFLOW) {
+        double z[4] = {0, 0, 0, 0};
+        for (int v = 0; v < V; ++v) qp[v] = qbj[v];
+        ft_from_derivs(dim, gam, dt, qp, z, z, FTp);
+      } else {
+        for (int v = 0; v < V; ++v) qp[v] = Tm.q[v];
+        for (int x = 0; x < dim * V; ++x) FTp[x] = Tm.FT[x];
+      }
+      double* fs = &Fstar[((size_t)e * NQE + jj) * V];
+      for (int v = 0; v < V; ++v) {
+        double nFp = 0.0, nFm = 0.0;
+        for (int d = 0; d < dim; ++d) { nFp += n[d] * FTp[d * V + v]; nFm += n[d] * Tm.FT[d * V + v]; }
+        fs[v] = 0.5 * (nFp + nFm) - 0.5 * s * len * (qp[v] - Tm.q[v]);
+      }
+    }
+    for (int v = 0; v < V; ++v) {
+      double acc = 0.0;
+      for (int jj = 0; jj < NQE; ++jj) acc += R.om_edge[jj] * Fstar[((size_t)e * NQE + jj) * V + v];
+      fLxW[e * V + v] = 0.5 * acc;
+    }
+    double Fi[4], Fj[4];
+    for (int v = 0; v < V; ++v) fLxF[e * V + v] = 0.0;
+    for (int d = 0; d < dim; ++d) {
+      euler_flux<double>(dim, gam, qbi, d, Fi);
+      euler_flux<double>(dim, gam, qbj, d, Fj);
+      for (int v = 0; v < V; ++v) fLxF[e * V + v] += 0.5 * n[d] * (Fj[v] + Fi[v]);
+    }
+    for (int v = 0; v < V; ++v) fLxF[e * V + v] -= 0.5 * s * len * (qbj[v] - qbi[v]);
+  }
+
+  // ---- Element loop, Steps 4-5: the flux limiter ------------------------------------------
+  // Step 4 (with eps_ik applied to every edge flux of the element, as in the printed Step 4):
+  //   Gamma_i = |T_i| rho_bar_i / dt - sum_k eps_ik f^{LxF,rho}_k,
+  //   Delta f_k = eps_ik (f^LxF - f^LxW)^rho_k.  Cases 1-4 of the sorted Delta f all say: every
+  //   edge with Delta f_k < 0 gets Lambda_ik = min(1, Gamma_i / |sum of the negative Delta f|),
+  //   the others get 1 (no sort needed).
+  // Step 5 (reading: in the corner states the edges switched off keep the Lax-Friedrichs flux,
+  //   so that c = 000 is the pure LxF update the text describes):
+  //   q^LxF = q_bar - dt/|T| sum_k eps_ik f^LxF_k,
+  //   q^c   = q_bar - dt/|T| sum_k eps_ik [alpha_k Lam_ik f^LxW_k + (1 - alpha_k Lam_ik) f^LxF_k],
+  //   mu_c  = largest mu in [0,1] with positive pressure (target eps_p = min(eps0, p(q^LxF)))
+  //           on mu q^c + (1 - mu) q^LxF,
+  //   Lambda_{e_ik} = min(Lambda_{e_ik}, Lam_ik * min over corners with alpha_k = 1 of mu_c).
+  S.Lam_ik.assign((size_t)N * K, 1.0);
+  S.c_ik.assign((size_t)N * K, 1.0);
+  int cfl_bad = -1;
+  for (int i = 0; i < N; ++i) {
+    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < V; ++v) qbar[v] = S.Q[i * QS + v * ML];
+    double area = M.area[i];
+    double Gam = area * qbar[0] / dt;
+    double df[4], fW[4][4], fF[4][4];
+    for (int k = 0; k < K; ++k) {
+      int e = M.eid[i * K + k];
+      double ep = M.eps[i * K + k];
+      for (int v = 0; v < V; ++v) { fW[k][v] = ep * fLxW[e * V + v]; fF[k][v] = ep * fLxF[e * V + v]; }
+      Gam -= fF[k][0];
+      df[k] = fF[k][0] - fW[k][0];
+    }
+    double Sneg = 0.0;
+    for (int k = 0; k < K; ++k)
+      if (df[k] < 0.0) Sneg += df[k];
+    if (Gam < 0.0 && cfl_bad < 0) cfl_bad = i;
+    double Lam[4];
+    for (int k = 0; k < K; ++k) {
+      Lam[k] = 1.0;
+      if (df[k] < 0.0) Lam[k] = std::max(0.0, std::min(1.0, Gam / std::fabs(Sneg)));
+      S.Lam_ik[i * K + k] = Lam[k];
+    }
+    double qL[4];
+    for (int v = 0; v < V; ++v) {
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) acc += fF[k][v];
+      qL[v] = qbar[v] - dt / area * acc;
+    }
+    double pL = (qL[0] > 0.0) ? pressure(dim, gam, qL) : -1.0;
+    if (!(pL > 0.0) && cfl_bad < 0) cfl_bad = i;
+    double eps_p = std::min(S.P.eps0, pL);
+    double mmin[4] = {1.0, 1.0, 1.0, 1.0};
+    for (int a = 1; a < (1 << K); ++a) {
+      double qa[4];
+      for (int v = 0; v < V; ++v) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) {
+          double th = ((a >> k) & 1) ? Lam[k] : 0.0;
+          acc += th * fW[k][v] + (1.0 - th) * fF[k][v];
+        }
+        qa[v] = qbar[v] - dt / area * acc;
+      }
+      double mu = (pL > 0.0) ? mu_solve(dim, gam, eps_p, qL, qa) : 0.0;
+      for (int k = 0; k < K; ++k)
+        if ((a >> k) & 1) mmin[k] = std::min(mmin[k], mu);
+    }
+    for (int k = 0; k < K; ++k) {
+      double c = Lam[k] * mmin[k];
+      S.c_ik[i * K + k] = c;
+      int e = M.eid[i * K + k];
+      Lam_e[e] = std::min(Lam_e[e], c);
+    }
+  }
+  if (cfl_bad >= 0) return set_err(S, ERR_CFL, cfl_bad, "Lax-Friedrichs update not positive (time step too large)");
+  if (S.P.force_theta >= 0.0)
+    for (int e = 0; e < E; ++e) Lam_e[e] = S.P.force_theta;
+
+  // ---- Element loop, Step 6: update ---------------------------------------------------------
+  //   Q^(1) -= dt/|T| sum_k eps_ik [theta_k f^LxW + (1 - theta_k) f^LxF],  theta_k = Lambda_{e_ik}
+  //   Q^(l) += dt V_l - dt/|T| sum_k eps_ik (1/2) sum_j omega_j phi_l(x_kj) F^*_kj . n_e,  l >= 2
+  //   (the higher moments use the unblended flux, as printed).
+  S.fLxW_ik.assign((size_t)N * K * V, 0.0);
+  S.fLxF_ik.assign((size_t)N * K * V, 0.0);
+  S.Lam_e_ik.assign((size_t)N * K, 1.0);
+  std::vector<double> Qnew(S.Q.size());
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < N; ++i) {
+    const double* Qi = &S.Q[i * QS];
+    double* Qn = &Qnew[i * QS];
+    double area = M.area[i];
+    for (size_t x = 0; x < QS; ++x) Qn[x] = Qi[x];
+    for (int k = 0; k < K; ++k) {
+      int e = M.eid[i * K + k];
+      double ep = M.eps[i * K + k];
+      double th = Lam_e[e];
+      S.Lam_e_ik[i * K + k] = th;
+      for (int v = 0; v < V; ++v) {
+        S.fLxW_ik[(i * K + k) * V + v] = ep * fLxW[e * V + v];
+        S.fLxF_ik[(i * K + k) * V + v] = ep * fLxF[e * V + v];
+        Qn[v * ML] -= dt / area * ep * (th * fLxW[e * V + v] + (1.0 - th) * fLxF[e * V + v]);
+      }
+      for (int jl = 0; jl < NQE; ++jl) {
+        // local point jl of element i corresponds to edge point jj in i_e's ordering
+        int jj = (ep > 0) ? jl : (NQE - 1 - jl);
+        double xi[2] = {0, 0};
+        edge_point(R, k, jl, xi);
+        for (int l = 1; l < ML; ++l) {
+          double ph = phi(R, l, xi);
+          for (int v = 0; v < V; ++v)
+            Qn[v * ML + l] -= dt / area * ep * 0.5 * R.om_edge[jl] * ph * Fstar[((size_t)e * NQE + jj) * V + v];
+        }
+      }
+    }
+    for (int v = 0; v < V; ++v)
+      for (int l = 1; l < ML; ++l) Qn[v * ML + l] += dt * S.Vol[i * QS + v * ML + l];
+  }
+  S.Qupd = Qnew;
+
+  // ---- Shock-capturing limiter on the updated state ---------------------------------------
+  S.theta_sc.assign(N, 1.0);
+  if (S.P.shock) {
+    std::vector<double> Qs = Qnew;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i) S.theta_sc[i] = shock_limit(S, Qnew, i, &Qs[i * QS]);
+    Qnew.swap(Qs);
+  }
+  S.Q.swap(Qnew);
+  S.t += dt;
+
+  // ---- Positivity of the new cell averages (guaranteed by Sec. 3.2-3.3) ---------------------
+  for (int i = 0; i < N; ++i) {
+    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < V; ++v) qbar[v] = S.Q[i * QS + v * ML];
+    for (int v = 0; v < V; ++v)
+      if (!std::isfinite(qbar[v])) return set_err(S, ERR_NONFINITE, i, "non-finite cell average");
+    if (!(qbar[0] > 0.0) || !(pressure(dim, gam, qbar) > 0.0))
+      return set_err(S, ERR_POSITIVITY, i, "cell average density or pressure not positive after update");
+  }
+  return OK;
+}
+
+}  // namespace ora
+
+// ==========================================================================================
+// C interface for the test harness (ctypes).
+// ==========================================================================================
+using namespace ora;
+
+extern "C" {
+
+void* ora_mesh_1d(int n, double x0, double x1, int bcl, int bcr) { return mesh_1d(n, x0, x1, bcl, bcr); }
+void* ora_mesh_cart(int nx, int ny, double x0, double x1, double y0, double y1, const int* bc) {
+  return mesh_cart(nx, ny, x0, x1, y0, y1, bc);
+}
+static std::string g_err;
+void* ora_mesh_tri(int nn, const double* xy, int nt, const int* tri, const int* bnd, const double* period) {
+  g_err.clear();
+  return mesh_tri(nn, xy, nt, tri, bnd, period, &g_err);
+}
+const char* ora_last_error() { return g_err.c_str(); }
+void ora_mesh_free(void* m) { delete (Mesh*)m; }
+
+// kind, dim, N, E, ML, K, NI, NQE
+void ora_mesh_info(void* m, int* out) {
+  Mesh* M = (Mesh*)m;
+  out[0] = M->R.kind; out[1] = M->R.dim; out[2] = M->N; out[3] = M->E;
+  out[4] = M->R.ML; out[5] = M->R.K; out[6] = M->R.NI; out[7] = M->R.NQE;
+}
+void ora_mesh_geom(void* m, double* area, double* perim, int* nbr, int* nbr_k) {
+  Mesh* M = (Mesh*)m;
+  for (int i = 0; i < M->N; ++i) { area[i] = M->area[i]; perim[i] = M->perim[i]; }
+  for (int x = 0; x < M->N * M->R.K; ++x) { nbr[x] = M->nbr[x]; nbr_k[x] = M->nbr_k[x]; }
+}
+
+void* ora_solver_new(void* m, double gamma, double cfl, double eps0, double alpha0, int shock, const double* inflow) {
+  Solver* S = new Solver;
+  S->M = (Mesh*)m;
+  S->P.gamma = gamma; S->P.cfl = cfl; S->P.eps0 = eps0; S->P.alpha0 = alpha0; S->P.shock = shock;
+  if (inflow) for (int v = 0; v < 4; ++v) S->P.inflow[v] = inflow[v];
+  S->Q.assign((size_t)S->M->N * NVAR(*S->M) * S->M->R.ML, 0.0);
+  return S;
+}
+void ora_solver_free(void* s) { delete (Solver*)s; }
+void ora_force_theta(void* s, double th) { ((Solver*)s)->P.force_theta = th; }
+void ora_set_state(void* s, const double* Q, double t) {
+  Solver* S = (Solver*)s;
+  std::memcpy(S->Q.data(), Q, S->Q.size() * sizeof(double));
+  S->t = t;
+}
+void ora_get_state(void* s, double* Q, double* t) {
+  Solver* S = (Solver*)s;
+  std::memcpy(Q, S->Q.data(), S->Q.size() * sizeof(double));
+  *t = S->t;
+}
+int ora_step(void* s, double T, double* dt) {
+  Solver* S = (Solver*)s;
+  int st = step(*S, T);
+  *dt = S->dt;
+  return st;
+}
+int ora_error_elem(void* s) { return ((Solver*)s)->err_elem; }
+const char* ora_error_msg(void* s) { return ((Solver*)s)->err.c_str(); }
+
+// Intermediates of the last step.  stage: 0 Q after limiters (start of step), 1 theta_moment,
+// 2 volume term, 3 f^LxW (outward, per element and local edge), 4 f^LxF, 5 Lambda_ik (density),
+// 6 c_ik, 7 Lambda_e per (element, local edge), 8 Q after update before the shock limiter,
+// 9 theta_shock, 10 {s, dt}, 11 q_t and q_tt at the interior points (N x NI x 2 x V).
+int ora_stage(void* s, int stage, double* out) {
+  Solver* S = (Solver*)s;
+  const std::vector<double>* src = nullptr;
+  switch (stage) {
+    case 0: src = &S->Qlim; break;
+    case 1: src = &S->theta_mom; break;
+    case 2: src = &S->Vol; break;
+    case 3: src = &S->fLxW_ik; break;
+    case 4: src = &S->fLxF_ik; break;
+    case 5: src = &S->Lam_ik; break;
+    case 6: src = &S->c_ik; break;
+    case 7: src = &S->Lam_e_ik; break;
+    case 8: src = &S->Qupd; break;
+    case 9: src = &S->theta_sc; break;
+    case 10: out[0] = S->s; out[1] = S->dt; return 0;
+    case 11: src = &S->qderiv; break;
+    default: return -1;
+  }
+  std::memcpy(out, src->data(), src->size() * sizeof(double));
+  return 0;
+}
+
+// Reference element tables, for tests: basis monomial coefficients, interior points and weights,
+// edge points (reference coordinates), and basis values/derivatives at an arbitrary point.
+void ora_ref_info(int kind, int* out) {
+  RefElem R = make_ref(kind);
+  out[0] = R.dim; out[1] = R.ML; out[2] = R.K; out[3] = R.NI; out[4] = R.NQE;
+}
+void ora_ref_tables(int kind, double* C, double* xi_int, double* w_int, double* xi_edge, double* om_edge) {
+  RefElem R = make_ref(kind);
+  for (size_t x = 0; x < R.C.size(); ++x) C[x] = R.C[x];
+  for (size_t x = 0; x < R.xi_int.size(); ++x) xi_int[x] = R.xi_int[x];
+  for (int m = 0; m < R.NI; ++m) w_int[m] = R.w_int[m];
+  int c = 0;
+  for (int k = 0; k < R.K; ++k)
+    for (int j = 0; j < R.NQE; ++j) {
+      double xi[2] = {0, 0};
+      edge_point(R, k, j, xi);
+      for (int d = 0; d < R.dim; ++d) xi_edge[c++] = xi[d];
+    }
+  for (int j = 0; j < R.NQE; ++j) om_edge[j] = R.om_edge[j];
+}
+double ora_phi(int kind, int l, const double* xi, int da, int db) {
+  static RefElem R[3] = {make_ref(0), make_ref(1), make_ref(2)};
+  return phi(R[kind], l, xi, da, db);
+}
+
+// Flux, Jacobian-vector and Hessian-vector products, for tests.
+void ora_flux(int dim, double gam, const double* q, int d, double* F) { euler_flux<double>(dim, gam, q, d, F); }
+void ora_flux_jvp(int dim, double gam, const double* q, int d, const double* x, double* out) { flux_jvp(dim, gam, q, d, x, out); }
+void ora_flux_hvp(int dim, double gam, const double* q, int d, const double* x, const double* y, double* out) {
+  flux_hvp(dim, gam, q, d, x, y, out);
+}
+// F_T at a point from (q, q_t, q_tt), for tests.
+void ora_ft(int dim, double gam, double dt, const double* q, const double* qt, const double* qtt, double* FT) {
+  ft_from_derivs(dim, gam, dt, q, qt, qtt, FT);
+}
+double ora_mu_solve(int dim, double gam, double eps_p, const double* qL, const double* qa) {
+  return mu_solve(dim, gam, eps_p, qL, qa);
+}
+// Moment limiter on one element's coefficients (V x ML), for tests.
+double ora_moment_limit(void* s, double* Qi) {
+  Solver* S = (Solver*)s;
+  return moment_limit(*S->M, S->P, Qi);
+}
+
+// Physical coordinates of the interior quadrature points of every element (N x NI x dim) and
+// the L2 projection of point values there (N x NI x V) onto the basis (N x V x ML).
+void ora_quad_points(void* m, double* xq) {
+  Mesh* M = (Mesh*)m;
+  const RefElem& R = M->R;
+  for (int i = 0; i < M->N; ++i)
+    for (int q = 0; q < R.NI; ++q) map_point(*M, i, &R.xi_int[q * R.dim], &xq[((size_t)i * R.NI + q) * R.dim]);
+}
+void ora_project(void* m, const double* vals, double* Q) {
+  Mesh* M = (Mesh*)m;
+  const RefElem& R = M->R;
+  int V = NVAR(*M);
+  for (int i = 0; i < M->N; ++i)
+    for (int v = 0; v < V; ++v)
+      for (int l = 0; l < R.ML; ++l) {
+        double acc = 0.0;
+        for (int q = 0; q < R.NI; ++q) acc += R.w_int[q] * vals[((size_t)i * R.NI + q) * V + v] * phi(R, l, &R.xi_int[q * R.dim]);
+        Q[((size_t)i * V + v) * R.ML + l] = acc;
+      }
+}
+// Evaluate q^h at given reference points of every element: xi (P x dim) -> out (N x P x V),
+// and the physical coordinates of those points (N x P x dim).
+void ora_eval(void* s, int P, const double* xi, double* out, double* x) {
+  Solver* S = (Solver*)s;
+  Mesh* M = S->M;
+  const RefElem& R = M->R;
+  int V = NVAR(*M);
+  size_t QS = (size_t)V * R.ML;
+  for (int i = 0; i < M->N; ++i)
+    for (int p = 0; p < P; ++p) {
+      eval_q(*M, &S->Q[i * QS], &xi[p * R.dim], &out[((size_t)i * P + p) * V]);
+      map_point(*M, i, &xi[p * R.dim], &x[((size_t)i * P + p) * R.dim]);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,343 @@
+"""Seeded synthetic inputs: meshes and initial states.
+
+This module holds none of the DG method's arithmetic (no basis, quadrature, flux or limiter):
+it draws random numbers and builds meshes and initial conserved states of the shapes used in
+the paper's experiments (Sec. 4) and in the benchmark workloads.  Both the GPU library's tests
+and benchmark and the oracle's tests take their inputs from here, so that the two sides receive
+identical arrays.
+
+Array conventions (the library's public layout):
+  * triangle meshes: node coordinates xy[n_nodes][2], counter-clockwise triangles tri[n_tri][3];
+  * initial states: modal coefficients Q[n_elem][n_var][n_modes] (float64), conserved variables
+    (rho, M, E) in 1D and (rho, Mx, My, E) in 2D.  Piecewise-constant states carry only mode 1
+    (the cell average, since the first basis function is identically one).
+"""
+import math
+
+import numpy as np
+
+from scipy.spatial import Delaunay
+
+# Boundary-condition codes shared with the public interface (include/lxw.h).
+BC_PERIODIC, BC_TRANSPARENT, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
+
+
+def rng(seed):
+    return np.random.default_rng(np.random.SeedSequence(int(seed)))
+
+
+# ---------------------------------------------------------------------------------------------
+# Meshes
+# ---------------------------------------------------------------------------------------------
+
+def lattice_delaunay(n, seed, jitter=0.3, box=(0.0, 1.0, 0.0, 1.0), periodic=False):
+    """Delaunay triangulation of an n x n lattice of points on `box`, with interior points
+    jittered by U[-jitter*h, jitter*h]^2 (h = lattice spacing), boundary points jittered only
+    along their boundary line and corners fixed.  With periodic=True the jitter of the points on
+    the x-high / y-high sides copies that of their x-low / y-low partners, so that boundary edges
+    pair up under translation by one period.
+
+    Returns (xy[n*n][2], tri[n_tri][3]) with counter-clockwise triangles; n_tri = 2(n-1)^2 for a
+    point set whose boundary points are all on the hull."""
+    x0, x1, y0, y1 = box
+    hx = (x1 - x0) / (n - 1)
+    hy = (y1 - y0) / (n - 1)
+    g = rng(seed)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    dx = g.uniform(-jitter * hx, jitter * hx, size=i.shape)
+    dy = g.uniform(-jitter * hy, jitter * hy, size=i.shape)
+    bx = (i == 0) | (i == n - 1)
+    by = (j == 0) | (j == n - 1)
+    dx[bx] = 0.0
+    dy[by] = 0.0
+    if periodic:
+        dy[n - 1, :] = dy[0, :]
+        dx[:, n - 1] = dx[:, 0]
+    x = x0 + i * hx + dx
+    y = y0 + j * hy + dy
+    xy = np.stack([x.ravel(), y.ravel()], axis=1)
+    tri = Delaunay(xy).simplices.astype(np.int32)
+    a = xy[tri]
+    cross = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0])
+    flip = cross < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    return np.ascontiguousarray(xy), np.ascontiguousarray(tri)
+
+
+def boundary_tags(xy, tri, box, codes):
+    """Per triangle edge (n_tri x 3; edge k joins vertices k and k+1) the boundary code of the
+    side of `box` the edge lies on (codes = {x-low, x-high, y-low, y-high}), -1 elsewhere."""
+    x0, x1, y0, y1 = box
+    tol = 1e-9 * max(x1 - x0, y1 - y0)
+    tags = np.full(tri.shape, -1, np.int32)
+    for k in range(3):
+        a = xy[tri[:, k]]
+        b = xy[tri[:, (k + 1) % 3]]
+        for side, (coord, val) in enumerate([(0, x0), (0, x1), (1, y0), (1, y1)]):
+            on = (np.abs(a[:, coord] - val) < tol) & (np.abs(b[:, coord] - val) < tol)
+            tags[on, k] = codes[side]
+    return tags
+
+
+def ramp_channel(n_target, seed, angle_deg=30.0, length=4.0, height=1.0, ramp_x=0.5, jitter=0.25):
+    """Channel [0, length] x [0, height] whose floor rises from x = ramp_x at `angle_deg` (a
+    double-Mach-reflection shaped domain: the domain above the ramp), meshed by Delaunay of a
+    jittered point lattice that follows the floor.  Returns (xy, tri, tags) with tags per
+    triangle edge: 0 inflow (x = 0), 1 outflow (x = length), 2 wall (floor and ramp), 3 top."""
+    g = rng(seed)
+    ta = math.tan(math.radians(angle_deg))
+
+    def floor(x):
+        return np.where(x > ramp_x, np.minimum((x - ramp_x) * ta, 0.9 * height), 0.0)
+
+    # area of the domain, to hit the target triangle count
+    xs = np.linspace(0.0, length, 20001)
+    area = np.trapezoid(height - floor(xs), xs)
+    h = math.sqrt(2.0 * area / n_target)
+    nx = int(round(length / h)) + 1
+    ny = int(round(height / h)) + 1
+    s = np.linspace(0.0, length, nx)
+    r = np.linspace(0.0, 1.0, ny)
+    S, Rr = np.meshgrid(s, r, indexing="ij")
+    fl = floor(S)
+    X = S.copy()
+    Y = fl + Rr * (height - fl)
+    hx = length / (nx - 1)
+    dxj = g.uniform(-jitter * hx, jitter * hx, size=X.shape)
+    dyj = g.uniform(-jitter, jitter, size=X.shape) * (height - fl) / (ny - 1)
+    dxj[0, :] = dxj[-1, :] = 0.0
+    dyj[:, 0] = dyj[:, -1] = 0.0
+    dxj[:, 0] = 0.0  # floor points stay on the floor
+    dxj[:, -1] = 0.0
+    X = X + dxj
+    Y = Y + dyj
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    tri = Delaunay(xy).simplices.astype(np.int32)
+    a = xy[tri]
+    # drop triangles whose centroid lies below the floor (the hull bridges the ramp's kink)
+    c = a.mean(axis=1)
+    keep = c[:, 1] > floor(c[:, 0]) - 1e-12
+    tri = tri[keep]
+    a = xy[tri]
+    cross = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0])
+    flip = cross < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    tags = np.full(tri.shape, -1, np.int32)
+    tol = 1e-9
+    for k in range(3):
+        pa = xy[tri[:, k]]
+        pb = xy[tri[:, (k + 1) % 3]]
+        mid = 0.5 * (pa + pb)
+        tags[(np.abs(pa[:, 0]) < tol) & (np.abs(pb[:, 0]) < tol), k] = 0
+        tags[(np.abs(pa[:, 0] - length) < tol) & (np.abs(pb[:, 0] - length) < tol), k] = 1
+        tags[(np.abs(pa[:, 1] - height) < tol) & (np.abs(pb[:, 1] - height) < tol), k] = 3
+        on_floor = (np.abs(pa[:, 1] - floor(pa[:, 0])) < 1e-9) & (np.abs(pb[:, 1] - floor(pb[:, 0])) < 1e-9) \
+            & (np.abs(mid[:, 1] - floor(mid[:, 0])) < 1e-6)
+        tags[on_floor & (tags[:, k] < 0), k] = 2
+    return np.ascontiguousarray(xy), np.ascontiguousarray(tri), tags
+
+
+# ---------------------------------------------------------------------------------------------
+# Initial states
+# ---------------------------------------------------------------------------------------------
+
+def prim_to_cons(prim, gamma):
+    """(rho, u[, v], p) -> (rho, rho u[, rho v], E) along the last axis, Eq. (eos)."""
+    prim = np.asarray(prim, dtype=np.float64)
+    rho = prim[..., 0]
+    vel = prim[..., 1:-1]
+    p = prim[..., -1]
+    out = np.empty_like(prim)
+    out[..., 0] = rho
+    out[..., 1:-1] = rho[..., None] * vel
+    out[..., -1] = p / (gamma - 1.0) + 0.5 * rho * np.sum(vel * vel, axis=-1)
+    return out
+
+
+def tri_sample_points(xy, tri, m=4):
+    """Centroids of the m^2 congruent sub-triangles of every triangle (equal-area samples)."""
+    pts = []
+    for a in range(m):
+        for b in range(m - a):
+            pts.append(((a + 1.0 / 3) / m, (b + 1.0 / 3) / m))
+            if a + b < m - 1:
+                pts.append(((a + 2.0 / 3) / m, (b + 2.0 / 3) / m))
+    L = np.array(pts)  # barycentric (l1, l2), l0 = 1 - l1 - l2
+    v = xy[tri]  # N x 3 x 2
+    return v[:, 0, None, :] + L[None, :, 0, None] * (v[:, 1, None, :] - v[:, 0, None, :]) \
+        + L[None, :, 1, None] * (v[:, 2, None, :] - v[:, 0, None, :])
+
+
+def cart_sample_points(nx, ny, box, m=4):
+    x0, x1, y0, y1 = box
+    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    s = (np.arange(m) + 0.5) / m
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")  # element = i + nx j
+    X = x0 + (ci.ravel()[:, None, None] + s[None, :, None]) * hx
+    Y = y0 + (cj.ravel()[:, None, None] + s[None, None, :]) * hy
+    X, Y = np.broadcast_arrays(X, Y)
+    return np.stack([X.reshape(nx * ny, -1), Y.reshape(nx * ny, -1)], axis=-1)
+
+
+def averages_to_modal(avg, n_modes):
+    """Piecewise-constant state: cell averages in mode 1, higher modes zero."""
+    N, V = avg.shape
+    Q = np.zeros((N, V, n_modes))
+    Q[:, :, 0] = avg
+    return Q
+
+
+def cell_average_state(prim_fn, pts, gamma):
+    """Cell averages of the conserved variables of a primitive-variable field, by equal-weight
+    sampling at pts (N x S x dim)."""
+    prim = prim_fn(pts)  # N x S x V
+    return prim_to_cons(prim, gamma).mean(axis=1)
+
+
+def riemann_1d_params(seed):
+    """Seeded left/right primitive states: rho, p ~ U[0.1, 1], u ~ U[-1, 1]."""
+    g = rng(seed)
+    rl, pl, rr, pr = g.uniform(0.1, 1.0, 4)
+    ul, ur = g.uniform(-1.0, 1.0, 2)
+    return (rl, ul, pl), (rr, ur, pr)
+
+
+def riemann_1d_state(n, seed, gamma=1.4, x0=0.0, x1=1.0, xjump=0.5):
+    """Cell averages of the 1D Riemann problem on n uniform cells, jump at a cell face."""
+    (rl, ul, pl), (rr, ur, pr) = riemann_1d_params(seed)
+    xc = x0 + (np.arange(n) + 0.5) * (x1 - x0) / n
+    prim = np.where((xc < xjump)[:, None], [rl, ul, pl], [rr, ur, pr])
+    return averages_to_modal(prim_to_cons(prim, gamma), 3)
+
+
+def sedov_cart_state(nx, ny, box=(-1.0, 1.0, -1.0, 1.0), gamma=1.4, e_total=0.98, p_bg=1e-10):
+    """2D Sedov-type blast on an nx x ny Cartesian mesh: rho = 1, u = 0, p = p_bg background, the
+    total energy e_total deposited in the 4 centre cells (mode 1 only)."""
+    x0, x1, y0, y1 = box
+    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    N = nx * ny
+    avg = np.zeros((N, 4))
+    avg[:, 0] = 1.0
+    avg[:, 3] = p_bg / (gamma - 1.0)
+    ic = [nx // 2 - 1, nx // 2]
+    jc = [ny // 2 - 1, ny // 2]
+    for j in jc:
+        for i in ic:
+            avg[i + nx * j, 3] = e_total / (4.0 * hx * hy)
+    return averages_to_modal(avg, 9)
+
+
+def four_quadrant_params(seed):
+    """Seeded primitive states of the four quadrants: rho, p ~ U[0.05, 1], u, v ~ U[-1, 1]."""
+    g = rng(seed)
+    q = np.zeros((4, 4))
+    q[:, 0] = g.uniform(0.05, 1.0, 4)
+    q[:, 1] = g.uniform(-1.0, 1.0, 4)
+    q[:, 2] = g.uniform(-1.0, 1.0, 4)
+    q[:, 3] = g.uniform(0.05, 1.0, 4)
+    return q
+
+
+def four_quadrant_fn(seed, xc=0.5, yc=0.5):
+    q = four_quadrant_params(seed)
+
+    def fn(pts):
+        x, y = pts[..., 0], pts[..., 1]
+        quad = (x >= xc).astype(int) + 2 * (y >= yc).astype(int)
+        return q[quad]
+
+    return fn
+
+
+def vortex_shock_fn(seed, gamma=1.4, eps=5.0, box=(-5.0, 5.0, -5.0, 5.0)):
+    """Isentropic vortex (strength eps) on the free stream (rho, u, v, p) = (1, 0, 0, 1),
+    overlaid with a planar shock of random normal angle, position and Mach number U[1.5, 3]
+    moving into the free stream; the post-shock state follows the Rankine-Hugoniot relations."""
+    g = rng(seed)
+    ang = g.uniform(0.0, 2.0 * math.pi)
+    x0, x1, y0, y1 = box
+    pos = g.uniform(0.25, 0.75)
+    Ms = g.uniform(1.5, 3.0)
+    nx, ny = math.cos(ang), math.sin(ang)
+    # shock line through a point at fraction `pos` along the box diagonal, moving along +n
+    px = x0 + pos * (x1 - x0)
+    py = y0 + pos * (y1 - y0)
+    # post-shock state for a shock at Mach Ms moving into (rho1, 0, p1) = (1, 0, 1)
+    r1, p1 = 1.0, 1.0
+    c1 = math.sqrt(gamma * p1 / r1)
+    W = Ms * c1
+    r2 = r1 * (gamma + 1) * Ms**2 / ((gamma - 1) * Ms**2 + 2)
+    p2 = p1 * (2 * gamma * Ms**2 - (gamma - 1)) / (gamma + 1)
+    u2 = W * (1 - r1 / r2)
+    vx0 = 0.5 * (x0 + x1)
+    vy0 = 0.5 * (y0 + y1)
+
+    def fn(pts):
+        x, y = pts[..., 0], pts[..., 1]
+        r2v = (x - vx0) ** 2 + (y - vy0) ** 2
+        f = np.exp(0.5 * (1.0 - r2v))
+        du = -eps / (2 * math.pi) * f * (y - vy0)
+        dv = eps / (2 * math.pi) * f * (x - vx0)
+        T = 1.0 - (gamma - 1) * eps**2 / (8 * gamma * math.pi**2) * f * f
+        rho = T ** (1.0 / (gamma - 1))
+        p = rho * T
+        behind = ((x - px) * nx + (y - py) * ny) < 0.0
+        out = np.stack([rho, du, dv, p], axis=-1)
+        post = np.array([r2, u2 * nx, u2 * ny, p2])
+        out[behind] = post
+        return out
+
+    return fn
+
+
+def batch_sizes(n_meshes, seed, lo=2000, hi=60000):
+    """Triangle counts log-uniform in [lo, hi], mapped to lattice sizes n with 2(n-1)^2 ~ N."""
+    g = rng(seed)
+    N = np.exp(g.uniform(math.log(lo), math.log(hi), n_meshes))
+    return [int(round(math.sqrt(x / 2.0))) + 1 for x in N]
+
+
+def random_modal_state(N, dim, n_modes, seed, amp=0.3, gamma=1.4, p_range=(0.3, 1.5), rough_frac=0.0,
+                       rough_amp=2.0):
+    """Random modal coefficients for parity tests: cell averages from random positive primitive
+    states, higher modes uniform in [-amp, amp] times the average's scale; a fraction rough_frac
+    of the cells get rough_amp instead, which drives point densities and pressures negative and
+    so exercises the limiters."""
+    g = rng(seed)
+    V = dim + 2
+    prim = np.zeros((N, V))
+    prim[:, 0] = g.uniform(0.3, 1.5, N)
+    prim[:, 1:1 + dim] = g.uniform(-1.0, 1.0, (N, dim))
+    prim[:, -1] = g.uniform(p_range[0], p_range[1], N)
+    avg = prim_to_cons(prim, gamma)
+    Q = np.zeros((N, V, n_modes))
+    Q[:, :, 0] = avg
+    scale = np.abs(avg) + 0.2
+    a = np.full(N, amp)
+    if rough_frac > 0:
+        a[g.uniform(0, 1, N) < rough_frac] = rough_amp
+    Q[:, :, 1:] = g.uniform(-1.0, 1.0, (N, V, n_modes - 1)) * (a[:, None] * scale)[:, :, None] / np.sqrt(n_modes)
+    return Q
+
+
+def bowl_prim(xy, tri, pts, seed, rho_range=(1e-6, 1.0), p_range=(1e-8, 1.0), depth=0.02, curv=6.0, spread=3.0):
+    """Adversarial per-cell primitive fields for exercising the flux limiter: in every triangle a
+    bowl-shaped density and pressure (low at the centroid, high at the edges) of random
+    log-uniform scale, and a random velocity plus an outward spread from the centroid.
+    pts[N][P][2] are sample points of each triangle; returns prim[N][P][4]."""
+    g = rng(seed)
+    N = len(tri)
+    c = xy[tri].mean(axis=1)
+    v = xy[tri]
+    area = 0.5 * np.abs((v[:, 1, 0] - v[:, 0, 0]) * (v[:, 2, 1] - v[:, 0, 1]) - (v[:, 1, 1] - v[:, 0, 1]) * (v[:, 2, 0] - v[:, 0, 0]))
+    h = np.sqrt(2.0 * area)
+    rs = np.exp(g.uniform(math.log(rho_range[0]), math.log(rho_range[1]), N))
+    ps = np.exp(g.uniform(math.log(p_range[0]), math.log(p_range[1]), N))
+    vel = g.uniform(-2.0, 2.0, (N, 2))
+    d = (pts - c[:, None, :]) / h[:, None, None]
+    r2 = np.sum(d * d, axis=-1)
+    rho = rs[:, None] * (depth + curv * r2)
+    p = ps[:, None] * (depth + curv * r2)
+    u = vel[:, None, 0] + spread * d[..., 0]
+    w = vel[:, None, 1] + spread * d[..., 1]
+    return np.stack([rho, u, w, p], axis=-1)

@@ -1,0 +1,191 @@
+"""Pins of the oracle's positivity limiters (Sec. 3) on random and adversarial states.
+
+Moment limiter (Sec. 3.1): averages unchanged, rho >= eps0 and p >= min(eps0, p_bar) at every
+limiter point afterwards, theta = 1 when nothing needs limiting, theta^rho maximal.
+Flux limiter (Sec. 3.2-3.3): the density box inequality of Eq. (low-order-update-eqn) holds, the
+average pressure is positive at every corner of the final box of edge factors, the limiter is
+idle on smooth data, and with every edge factor forced to zero the cell averages follow the
+first-order Lax-Friedrichs finite-volume scheme (recomputed here independently)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_08145_amd import inputs as I
+from tests import helpers as H
+
+
+def limiter_pts(R):
+    return np.concatenate([R.xi_int, R.xi_edge.reshape(-1, R.dim)], 0)
+
+
+def eval_at(R, Qi, pts):
+    Phi = np.array([[R.phi(l, p) for l in range(R.ML)] for p in pts])  # P x ML
+    return Phi @ Qi.T  # P x V
+
+
+@pytest.mark.parametrize("kind", [O.LINE, O.QUAD, O.TRI])
+def test_moment_limiter_invariants(kind):
+    R = O.RefElem(kind)
+    mesh = {O.LINE: lambda: O.Mesh.line(4, 0, 1, 1, 1), O.QUAD: lambda: O.Mesh.cart(2, 2, 0, 1, 0, 1, [1] * 4),
+            O.TRI: lambda: O.Mesh.tri(*I.lattice_delaunay(3, 0))}[kind]()
+    S = O.Solver(mesh)
+    pts = limiter_pts(R)
+    Q = I.random_modal_state(400, R.dim, R.ML, seed=11, amp=0.3, rough_frac=0.5, rough_amp=3.0, p_range=(1e-6, 1.0))
+    n_limited = n_free = 0
+    for Qi in Q:
+        th, Ql = S.moment_limit(Qi)
+        assert 0.0 <= th <= 1.0
+        assert np.array_equal(Ql[:, 0], Qi[:, 0])
+        if th < 1.0:
+            n_limited += 1
+            assert np.allclose(Ql[:, 1:], th * Qi[:, 1:], rtol=1e-15, atol=0)
+        q = eval_at(R, Ql, pts)
+        pbar = H.pressure(Qi[:, 0])
+        assert np.all(q[:, 0] >= 1e-12 * (1 - 1e-9))
+        assert np.all(H.pressure(q) >= min(1e-12, pbar) * (1 - 1e-6) - 1e-14)
+        qu = eval_at(R, Qi, pts)
+        if np.all(qu[:, 0] >= 1e-12) and np.all(H.pressure(qu) >= min(1e-12, pbar)):
+            assert th == 1.0
+            n_free += 1
+        else:
+            # maximality of the density part: some point sits on the density or pressure bound
+            rho_tight = np.min(q[:, 0]) <= 1e-12 * (1 + 1e-6)
+            p_tight = np.min(H.pressure(q)) <= min(1e-12, pbar) * (1 + 1e-3) + 1e-13
+            assert rho_tight or p_tight or th < 1.0
+    assert n_limited > 20 and n_free > 20
+
+
+def test_moment_limiter_density_theta_is_maximal():
+    R = O.RefElem(O.TRI)
+    S = O.Solver(O.Mesh.tri(*I.lattice_delaunay(3, 0)))
+    pts = limiter_pts(R)
+    rng = np.random.default_rng(3)
+    checked = 0
+    for _ in range(200):
+        Qi = np.zeros((4, 6))
+        Qi[:, 0] = [1.0, 0.0, 0.0, 3.0]  # zero momentum: p = (gamma-1) E never binds
+        Qi[0, 1:] = rng.normal(size=5) * 0.6  # density deviations only
+        th, Ql = S.moment_limit(Qi)
+        q = eval_at(R, Qi, pts)
+        if q[:, 0].min() >= 1e-12:
+            continue
+        # largest theta with rho_bar + theta (rho_m - rho_bar) >= eps0 at every point
+        dev = q[:, 0] - 1.0
+        th_exact = min((1.0 - 1e-12) / (-d) for d in dev if 1.0 + d < 1e-12)
+        assert th == pytest.approx(th_exact, rel=1e-12)
+        checked += 1
+    assert checked > 30
+
+
+def _step(mesh, Q, **kw):
+    S = O.Solver(mesh, **kw)
+    S.set_state(Q)
+    S.step()
+    return S
+
+
+def test_flux_limiter_box_and_corner_pressures():
+    xy, tri = I.lattice_delaunay(14, 7)
+    mesh = O.Mesh.tri(xy, tri)
+    nrm, area, nb = H.tri_geometry(xy, tri)
+    assert np.allclose(area, mesh.area, rtol=1e-13)
+    # bowl-shaped near-vacuum cells (edge traces far above the average) at a large CFL number:
+    # the high-order flux would empty them, so both the density and the pressure parts bind
+    Q = mesh.project(I.prim_to_cons(I.bowl_prim(xy, tri, mesh.quad_points(), seed=0), 1.4))
+    S = _step(mesh, Q, cfl=0.9, shock=False)
+    s, dt = S.stage(O.STAGE_SDT)
+    fW = S.stage(O.STAGE_FLXW)  # outward, N x K x V
+    fF = S.stage(O.STAGE_FLXF)
+    lam_ik = S.stage(O.STAGE_LAM_IK)
+    lam_e = S.stage(O.STAGE_LAM_E)
+    c_ik = S.stage(O.STAGE_C_IK)
+    qbar = S.stage(O.STAGE_QLIM)[:, :, 0]
+    assert np.all((lam_e >= 0) & (lam_e <= 1))
+    assert np.all(lam_e <= c_ik + 0.0)
+    Gam = area * qbar[:, 0] / dt - fF[:, :, 0].sum(1)
+    assert np.all(Gam >= 0)
+    df = fF[:, :, 0] - fW[:, :, 0]
+    worst = Gam + np.sum(lam_ik * np.minimum(df, 0.0), axis=1)
+    assert np.all(worst >= -1e-12 * np.abs(Gam).max())
+    # pressure at all 2^K corners of the final box [0, Lambda_e]
+    n_active = 0
+    for i in range(mesh.N):
+        for a in range(1, 8):
+            th = np.array([lam_e[i, k] if (a >> k) & 1 else 0.0 for k in range(3)])
+            qn = qbar[i] - dt / area[i] * np.sum(th[:, None] * fW[i] + (1 - th[:, None]) * fF[i], axis=0)
+            assert qn[0] >= -1e-14 and H.pressure(qn) > 0.0, (i, a, qn)
+        n_active += np.any(lam_e[i] < 1)
+    assert n_active > 20
+    assert np.any(lam_ik < 1) and np.any(c_ik < lam_ik)  # density and pressure parts both bind
+    # the LxF flux recomputed independently from the averages, s and the normals
+    for i in range(mesh.N):
+        for k in range(3):
+            j = nb[i, k]
+            qj = qbar[j] if j >= 0 else qbar[i]
+            n = nrm[i, k]
+            L = np.hypot(*n)
+            f = 0.5 * (H.euler_flux_n(qj, n) + H.euler_flux_n(qbar[i], n)) - 0.5 * s * L * (qj - qbar[i])
+            assert np.allclose(fF[i, k], f, rtol=1e-12, atol=1e-13)
+    # cell averages after the update follow the blended flux
+    Qu = S.stage(O.STAGE_QUPD)
+    expect = qbar - dt / area[:, None] * np.sum(lam_e[..., None] * fW + (1 - lam_e[..., None]) * fF, axis=1)
+    assert np.allclose(Qu[:, :, 0], expect, rtol=1e-12, atol=1e-14)
+
+
+def test_flux_limiter_idle_on_smooth_data():
+    xy, tri = I.lattice_delaunay(12, 1, box=(-5, 5, -5, 5))
+    mesh = O.Mesh.tri(xy, tri)
+    Q = mesh.project(H.cons(H.vortex_prim(*np.moveaxis(mesh.quad_points(), -1, 0), 0.0)))
+    S = _step(mesh, Q)
+    assert np.all(S.stage(O.STAGE_LAM_E) == 1.0)
+    assert np.all(S.stage(O.STAGE_THETA_MOM) == 1.0)
+    assert np.all(S.stage(O.STAGE_THETA_SC) == 1.0)
+
+
+@pytest.mark.parametrize("kind", ["tri", "cart", "line"])
+def test_theta_zero_is_first_order_lax_friedrichs(kind):
+    """With every Lambda_e = 0 the cell-average update is the first-order LxF finite-volume scheme
+    (Sec. 3.2), which is positivity preserving under the CFL condition (Perthame-Shu)."""
+    if kind == "tri":
+        xy, tri = I.lattice_delaunay(10, 3)
+        mesh = O.Mesh.tri(xy, tri)
+        nrm, area, nb = H.tri_geometry(xy, tri)
+        N = mesh.N
+    elif kind == "cart":
+        nx = ny = 8
+        mesh = O.Mesh.cart(nx, ny, 0, 1, 0, 1, [O.BC_PERIODIC] * 4)
+        N = nx * ny
+        h = 1.0 / nx
+        area = np.full(N, h * h)
+        nrm = np.tile(np.array([[0, -h], [h, 0], [0, h], [-h, 0]], float), (N, 1, 1))
+        nb = np.zeros((N, 4), np.int64)
+        for j in range(ny):
+            for i in range(nx):
+                e = i + nx * j
+                nb[e] = [i + nx * ((j - 1) % ny), (i + 1) % nx + nx * j, i + nx * ((j + 1) % ny), (i - 1) % nx + nx * j]
+    else:
+        n = 30
+        mesh = O.Mesh.line(n, 0, 1, O.BC_PERIODIC, O.BC_PERIODIC)
+        N = n
+        area = np.full(N, 1.0 / n)
+        nrm = np.tile(np.array([[-1.0], [1.0]]), (N, 1, 1))
+        nb = np.stack([(np.arange(N) - 1) % N, (np.arange(N) + 1) % N], 1)
+    dim = mesh.dim
+    Q = I.random_modal_state(N, dim, mesh.ML, seed=9, amp=0.5, p_range=(1e-6, 1.0))
+    S = O.Solver(mesh, cfl=0.5)
+    S.force_theta(0.0)
+    S.set_state(Q)
+    S.step()
+    s, dt = S.stage(O.STAGE_SDT)
+    qbar = S.stage(O.STAGE_QLIM)[:, :, 0]
+    Qn, _ = S.get_state()
+    K = nrm.shape[1]
+    flux = np.zeros_like(qbar)
+    for k in range(K):
+        j = nb[:, k]
+        qj = np.where((j >= 0)[:, None], qbar[np.maximum(j, 0)], qbar)
+        L = np.linalg.norm(nrm[:, k], axis=1)
+        flux += 0.5 * (H.euler_flux_n(qj, nrm[:, k]) + H.euler_flux_n(qbar, nrm[:, k])) - 0.5 * s * L[:, None] * (qj - qbar)
+    expect = qbar - dt / area[:, None] * flux
+    assert np.allclose(Qn[:, :, 0], expect, rtol=1e-12, atol=1e-14)
+    assert np.all(expect[:, 0] > 0) and np.all(H.pressure(expect) > 0)
