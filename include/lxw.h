@@ -1,0 +1,220 @@
+/*
+ * lxw.h -- C interface of the MI355X (gfx950) library for the positivity-preserving
+ * Lax-Wendroff discontinuous Galerkin (LxW-DG) time step for the compressible Euler equations
+ * (S. A. Moe, J. A. Rossmanith, D. C. Seal, "Positivity-preserving discontinuous Galerkin
+ * methods with Lax-Wendroff time discretizations", arXiv:1601.08145).
+ *
+ * The calls follow the paper's statement of the problem: a mesh of elements (Sec. 1.2), the gas
+ * constant gamma (Eq. (eos)), the polynomial degree M_D (Eq. (broken_space)), the initial modal
+ * coefficients Q^(l) (Sec. 1.2), the CFL number (Sec. 4.1), boundary conditions (Sec. 2.4), and
+ * advancing to a final time T (Eq. (exact-taylor)).
+ *
+ * Conventions shared by every call:
+ *  - All functions return lxw_status: LXW_OK (0) or a negative error code.  No C++ exception
+ *    crosses this interface.  lxw_last_error() returns a thread-local message for the most recent
+ *    failure on the calling thread, naming the offending element where there is one.
+ *  - Host arrays passed in are copied; the caller keeps ownership.  Device pointers (flag
+ *    LXW_DEVICE_PTR) stay owned by the caller and are only used during the call, on the solver's
+ *    stream.
+ *  - Element order in every array is the caller's order (the library reorders elements
+ *    internally for locality and maps back).
+ *  - Modal coefficients are float64, row-major Q[n_elem][n_var][n_modes], with n_var = 3 in 1D
+ *    (rho, M, E) and 4 in 2D (rho, Mx, My, E), in the documented orthonormal basis (see
+ *    lxw_refelem_info): phi_1 == 1, so Q[i][v][0] is the cell average of variable v.
+ *  - Reference elements: 1D [-1,1]; quadrilateral [-1,1]^2 with vertices (-1,-1), (1,-1), (1,1),
+ *    (-1,1); triangle (0,0), (1,0), (0,1).  Local edge k joins vertices k and k+1 (mod count);
+ *    in 1D local edge 0 is the left end and 1 the right end.
+ *  - Basis: Gram-Schmidt orthonormalisation, under (1/|T0|) int_{T0} f g, of the monomials
+ *    1D {1, x, x^2}; quadrilateral {1, x, y, x^2, xy, y^2, x^2 y, x y^2, x^2 y^2} (tensor Legendre,
+ *    9 modes); triangle {1, x, y, x^2, xy, y^2} (6 modes).
+ */
+#ifndef LXW_H
+#define LXW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lxw_status;
+
+enum {
+  LXW_OK = 0,
+  LXW_ERR_ARG = -1,         /* invalid argument (null pointer, size, enum value) */
+  LXW_ERR_UNSUPPORTED = -2, /* valid but not implemented (e.g. degree != 2) */
+  LXW_ERR_MESH = -3,        /* non-positive area, clockwise triangle, bad connectivity */
+  LXW_ERR_STATE = -4,       /* input state violates rho_bar >= eps0, p_bar > 0 (Sec. 1.5 Step 1,
+                               Sec. 3.1 Step 0) or is not finite */
+  LXW_ERR_POSITIVITY = -5,  /* a cell average lost positivity during a step */
+  LXW_ERR_NONFINITE = -6,   /* a non-finite value appeared during a step */
+  LXW_ERR_CFL = -7,         /* the first-order Lax-Friedrichs update is not positive (Gamma < 0,
+                               Sec. 3.2): the time step is too large for the CFL condition */
+  LXW_ERR_DEVICE = -8,      /* a HIP runtime call failed */
+  LXW_ERR_OOM = -9          /* device or host allocation failed */
+};
+
+/* Boundary conditions (Sec. 2.4).  Periodic pairs opposite sides.  Transparent: ghost state
+ * equals the interior trace.  Reflective: normal momentum negated, tangential kept, and the same
+ * for q_t and q_tt.  Inflow: a fixed Dirichlet state (lxw_params.inflow) with q_t = q_tt = 0. */
+enum { LXW_BC_PERIODIC = 0, LXW_BC_TRANSPARENT = 1, LXW_BC_REFLECTIVE = 2, LXW_BC_INFLOW = 3 };
+
+/* Mesh kinds. */
+enum { LXW_LINE = 0, LXW_QUAD = 1, LXW_TRI = 2 };
+
+/* Arithmetic of the step. */
+enum {
+  LXW_FP64 = 0,      /* everything in float64 */
+  LXW_FP32_MIXED = 1 /* higher modes, point values, F_T, traces and edge point fluxes in float32;
+                        cell averages, the flux limiter (Gamma, corner states, damping-factor
+                        solve), the point pressure and theta of the moment limiter, the wave
+                        speed, dt and t in float64 */
+};
+
+/* Shock-capturing limiter modes. */
+enum { LXW_SHOCK_OFF = 0, LXW_SHOCK_PLAIN = 1 };
+
+/* State transfer flags. */
+enum { LXW_HOST_PTR = 0, LXW_DEVICE_PTR = 1 };
+
+typedef struct lxw_mesh lxw_mesh;
+typedef struct lxw_solver lxw_solver;
+
+typedef struct lxw_params {
+  double gamma;      /* ratio of specific heats, Eq. (eos); > 1 */
+  int32_t degree;    /* polynomial degree M_D; only 2 is supported (LXW_ERR_UNSUPPORTED else) */
+  double cfl;        /* CFL number nu: dt = nu / (s * max_i |dT_i| / (2 |T_i|)), s the global
+                        maximum wave speed; the paper uses 0.08 (Sec. 4.1); must be in (0, 1] */
+  double eps0;       /* density cutoff eps0 of Sec. 3.1 Step 0 (1e-12 in the paper); > 0 */
+  double alpha0;     /* shock-limiter relaxation constant: delta = alpha0 h^1.5 (500, Sec. 4.1) */
+  int32_t precision; /* LXW_FP64 or LXW_FP32_MIXED */
+  int32_t shock;     /* LXW_SHOCK_OFF or LXW_SHOCK_PLAIN */
+  double inflow[4];  /* inflow state for LXW_BC_INFLOW edges: (rho, Mx, My, E); 1D uses
+                        (rho, Mx, -, E) */
+} lxw_params;
+
+/* Fills p with the paper's defaults: gamma 1.4, degree 2, CFL 0.08, eps0 1e-12, alpha0 500,
+ * FP64, plain shock limiter, inflow (1, 0, 0, 2.5). */
+lxw_status lxw_params_default(lxw_params* p);
+
+/* Message of the last failure on this thread (never null; empty when none). */
+const char* lxw_last_error(void);
+
+/* ---- Meshes (Sec. 1.2; edges, normals n_e with |n_e| = edge length, i_e, j_e and eps_ik as
+ * defined in Sec. 3.3, Eq. (epsik)) --------------------------------------------------------- */
+
+/* Uniform 1D mesh of n cells on [x0, x1]; bc_left/bc_right are LXW_BC_* (both periodic or
+ * neither).  Errors: LXW_ERR_ARG for n < 2, x1 <= x0, or an unpaired periodic side. */
+lxw_status lxw_mesh_create_1d(int32_t n, double x0, double x1, int32_t bc_left, int32_t bc_right,
+                              lxw_mesh** out);
+
+/* Cartesian mesh of nx x ny rectangles on [x0,x1] x [y0,y1]; caller element index i + nx*j.
+ * bc = {x-low, x-high, y-low, y-high}; periodic must be set on both sides of a direction. */
+lxw_status lxw_mesh_create_cart(int32_t nx, int32_t ny, double x0, double x1, double y0, double y1,
+                                const int32_t bc[4], lxw_mesh** out);
+
+/* Unstructured triangle mesh: xy[n_nodes][2] node coordinates, tri[n_tri][3] counter-clockwise
+ * vertex indices.  bnd_tag (nullable, [n_tri][3]) gives the LXW_BC_* code of local edge k of
+ * each triangle when that edge is on the boundary (ignored inside; transparent when null).
+ * Edges tagged LXW_BC_PERIODIC are paired with the boundary edge whose midpoint differs by
+ * period[0] in x or period[1] in y (period nullable otherwise).  Errors: LXW_ERR_MESH for a
+ * clockwise or degenerate triangle, an edge shared by more than two triangles, or an unpaired
+ * periodic edge; LXW_ERR_ARG for null arrays or out-of-range indices. */
+lxw_status lxw_mesh_create_tri(int32_t n_nodes, const double* xy, int32_t n_tri, const int32_t* tri,
+                               const int32_t* bnd_tag, const double* period, lxw_mesh** out);
+
+lxw_status lxw_mesh_destroy(lxw_mesh* m);
+
+typedef struct lxw_mesh_info {
+  int32_t kind;      /* LXW_LINE, LXW_QUAD, LXW_TRI */
+  int32_t dim;       /* 1 or 2 */
+  int32_t n_elem;
+  int32_t n_edge;
+  int32_t n_var;     /* 3 or 4 */
+  int32_t n_modes;   /* 3, 9 or 6 */
+  int32_t n_faces;   /* edges per element K: 2, 4 or 3 */
+  double min_area, max_area;
+} lxw_mesh_info;
+
+lxw_status lxw_mesh_get_info(const lxw_mesh* m, lxw_mesh_info* out);
+
+/* Reference-element tables so that callers can L2-project initial data (Sec. 1.2).  For mesh
+ * kind `kind`: n_pts interior quadrature points xi[n_pts][dim] with weights w[n_pts] normalised
+ * to sum to 1, and basis values phi[n_pts][n_modes].  Pass null arrays to query n_pts only.
+ * Projection: Q_l = sum_m w_m f(x(xi_m)) phi_l(xi_m), exact for f of degree <= 3 (triangle
+ * 7-point degree-5 rule; 3-point and 3x3 Gauss-Legendre in 1D and on quadrilaterals). */
+lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w, double* phi);
+
+/* ---- Solver ------------------------------------------------------------------------------ */
+
+/* Creates a solver on device 0 for mesh m (which must outlive it).  stream: a hipStream_t (null
+ * for the default stream); every kernel of the solver runs on it.  Allocates all device memory
+ * the step needs.  Errors: LXW_ERR_ARG / LXW_ERR_UNSUPPORTED for bad parameters, LXW_ERR_OOM,
+ * LXW_ERR_DEVICE. */
+lxw_status lxw_solver_create(const lxw_mesh* m, const lxw_params* p, void* stream, lxw_solver** out);
+lxw_status lxw_solver_destroy(lxw_solver* s);
+
+/* Sets the state: Q as described above (host or device memory per flags) and the time t0.
+ * Checks rho_bar >= eps0, p_bar > 0 and finiteness of every cell average (LXW_ERR_STATE, naming
+ * the first bad element in the caller's order).  Synchronous. */
+lxw_status lxw_set_state(lxw_solver* s, const double* Q, double t0, int32_t flags);
+
+/* Copies the state after the last completed step (shock-capturing limiter applied) into Q and
+ * the time into *t (t nullable).  Synchronous; also reports a pending device error. */
+lxw_status lxw_get_state(lxw_solver* s, double* Q, double* t, int32_t flags);
+
+/* One step of Sec. 3.3 (moment limiter, F_T, edge fluxes, flux limiter, update) followed by the
+ * shock-capturing limiter, with dt = min(dt_CFL, T - t).  Synchronous; *dt_taken nullable.
+ * Errors: LXW_ERR_ARG if t >= T; LXW_ERR_POSITIVITY / LXW_ERR_NONFINITE / LXW_ERR_CFL from the
+ * device checks (the state is then left as the failing step produced it). */
+lxw_status lxw_step(lxw_solver* s, double T, double* dt_taken);
+
+typedef struct lxw_stats {
+  int64_t steps;     /* steps taken by the call */
+  double t;          /* time reached */
+  double last_dt;
+  double last_s;     /* global wave speed of the last step */
+} lxw_stats;
+
+/* Steps until t == T (the last dt is clipped) or max_steps steps.  Synchronous. */
+lxw_status lxw_advance(lxw_solver* s, double T, int64_t max_steps, lxw_stats* out);
+
+/* Enqueues n_steps steps with no final time (dt from the CFL condition each step) on the
+ * solver's stream and returns without waiting; errors are reported by lxw_sync.  For timing. */
+lxw_status lxw_run_steps(lxw_solver* s, int64_t n_steps);
+
+/* Waits for the solver's stream and reports any device error. */
+lxw_status lxw_sync(lxw_solver* s);
+
+/* ---- Diagnostics ----------------------------------------------------------------------------
+ * lxw_set_debug(s, 1) makes later steps keep copies of their intermediate results, which
+ * lxw_debug_stage then returns in float64 and in the caller's element order:
+ *   LXW_STAGE_QLIM     Q after the shock and moment limiters, at the start of the step [N][V][ML]
+ *   LXW_STAGE_THETA    moment-limiter theta [N]
+ *   LXW_STAGE_VOL      volume term V_l = (1/|T|) int grad phi_l . F_T [N][V][ML] (mode 1 is 0)
+ *   LXW_STAGE_FLXW     f^LxW of each local edge, oriented out of the element [N][K][V]
+ *   LXW_STAGE_FLXF     f^LxF likewise [N][K][V]
+ *   LXW_STAGE_C        damping factor candidate Lambda_ik * min mu of each local edge [N][K]
+ *   LXW_STAGE_LAME     Lambda_e of each local edge [N][K]
+ *   LXW_STAGE_QUPD     Q after the update, before the shock-capturing limiter [N][V][ML]
+ *   LXW_STAGE_THETA_SC shock-limiter theta applied after the update [N]
+ *   LXW_STAGE_SDT      {s, dt} [2]
+ * Per-kernel timing: lxw_set_timing(s, 1) records HIP events around every kernel of later steps;
+ * lxw_kernel_times returns, per kernel id (LXW_K_*), the summed milliseconds and launch counts. */
+enum {
+  LXW_STAGE_QLIM = 0, LXW_STAGE_THETA = 1, LXW_STAGE_VOL = 2, LXW_STAGE_FLXW = 3, LXW_STAGE_FLXF = 4,
+  LXW_STAGE_C = 6, LXW_STAGE_LAME = 7, LXW_STAGE_QUPD = 8, LXW_STAGE_THETA_SC = 9, LXW_STAGE_SDT = 10
+};
+enum { LXW_K_PRE = 0, LXW_K_DT = 1, LXW_K_ELEM = 2, LXW_K_EDGE = 3, LXW_K_FLIM = 4, LXW_K_UPDATE = 5,
+       LXW_K_FINAL = 6, LXW_K_COUNT = 7 };
+
+lxw_status lxw_set_debug(lxw_solver* s, int32_t keep_stages);
+lxw_status lxw_debug_stage(lxw_solver* s, int32_t stage, double* out);
+lxw_status lxw_set_timing(lxw_solver* s, int32_t enable);
+lxw_status lxw_kernel_times(lxw_solver* s, double* ms /*[LXW_K_COUNT]*/, int64_t* launches /*[LXW_K_COUNT]*/);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LXW_H */

@@ -1,0 +1,1129 @@
+// Host runtime of the LxW-DG library: reference tables, mesh connectivity and geometry, solver
+// state, step sequencing, diagnostics and the C interface declared in include/lxw.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lxw.h"
+#include "lxw_internal.hpp"
+
+using namespace lxw;
+
+namespace {
+
+thread_local std::string g_err;
+
+lxw_status fail(lxw_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return fail(e_ == hipErrorOutOfMemory ? LXW_ERR_OOM : LXW_ERR_DEVICE,       \
+                                      std::string("HIP error: ") + hipGetErrorString(e_) + " at " + #expr); \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Reference elements.  Quadrature: Gauss-Legendre with 3 nodes on [-1,1] for edges and 1D, its
+// 3x3 tensor product on the square, and the symmetric 7-point degree-5 rule on the triangle
+// (centroid plus two three-point orbits).  Basis: on the line and the square the orthonormal
+// Legendre polynomials sqrt(2n+1) P_n and their products; on the triangle the monomials
+// 1, x, y, x^2, xy, y^2 orthonormalised through the Cholesky factor of their Gram matrix
+// (computed with the 7-point rule, exact for these degree-4 products), which is Gram-Schmidt in
+// that order.
+// ---------------------------------------------------------------------------------------------
+struct Rule {
+  std::vector<double> x, w;  // points (n x dim), weights summing to 1
+};
+
+const double GL_S[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};  // sqrt(3/5)
+const double GL_W[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+
+Rule rule_line() {
+  Rule r;
+  for (int i = 0; i < 3; ++i) { r.x.push_back(GL_S[i]); r.w.push_back(GL_W[i] / 2.0); }
+  return r;
+}
+Rule rule_quad() {
+  Rule r;
+  for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < 3; ++i) {
+      r.x.push_back(GL_S[i]);
+      r.x.push_back(GL_S[j]);
+      r.w.push_back(GL_W[i] * GL_W[j] / 4.0);
+    }
+  return r;
+}
+Rule rule_tri() {
+  Rule r;
+  const double s15 = std::sqrt(15.0);
+  const double a1 = (6.0 - s15) / 21.0, b1 = 1.0 - 2.0 * a1, w1 = (155.0 - s15) / 1200.0;
+  const double a2 = (6.0 + s15) / 21.0, b2 = 1.0 - 2.0 * a2, w2 = (155.0 + s15) / 1200.0;
+  auto pt = [&](double x, double y, double w) { r.x.push_back(x); r.x.push_back(y); r.w.push_back(w); };
+  pt(1.0 / 3.0, 1.0 / 3.0, 9.0 / 40.0);
+  pt(a1, a1, w1); pt(b1, a1, w1); pt(a1, b1, w1);
+  pt(a2, a2, w2); pt(b2, a2, w2); pt(a2, b2, w2);
+  return r;
+}
+
+// Legendre, orthonormal on [-1,1] under (1/2) int: value and derivatives of order 0..2.
+double leg(int n, double x, int der) {
+  const double s3 = std::sqrt(3.0), s5 = std::sqrt(5.0);
+  if (n == 0) return der == 0 ? 1.0 : 0.0;
+  if (n == 1) return der == 0 ? s3 * x : (der == 1 ? s3 : 0.0);
+  if (der == 0) return 0.5 * s5 * (3.0 * x * x - 1.0);
+  if (der == 1) return 3.0 * s5 * x;
+  return 3.0 * s5;
+}
+
+const int QUAD_I[9] = {0, 1, 0, 2, 1, 0, 2, 1, 2};
+const int QUAD_J[9] = {0, 0, 1, 0, 1, 2, 1, 2, 2};
+const int TRI_EX[6] = {0, 1, 0, 2, 1, 0};
+const int TRI_EY[6] = {0, 0, 1, 0, 1, 2};
+
+double dmono(double x, int n, int k) {
+  if (k > n) return 0.0;
+  double c = 1.0;
+  for (int i = 0; i < k; ++i) c *= (n - i);
+  double r = c;
+  for (int i = 0; i < n - k; ++i) r *= x;
+  return r;
+}
+
+struct TriBasis {
+  double C[6][6];  // phi_l = sum_j C[l][j] x^ex_j y^ey_j
+  TriBasis() {
+    Rule r = rule_tri();
+    double G[6][6] = {};
+    for (size_t q = 0; q < r.w.size(); ++q) {
+      double m[6];
+      for (int a = 0; a < 6; ++a) m[a] = dmono(r.x[2 * q], TRI_EX[a], 0) * dmono(r.x[2 * q + 1], TRI_EY[a], 0);
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) G[a][b] += r.w[q] * m[a] * m[b];
+    }
+    double L[6][6] = {};
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double s = G[i][j];
+        for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+        L[i][j] = (i == j) ? std::sqrt(s) : s / L[j][j];
+      }
+    // C = L^{-1} (lower triangular)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) C[i][j] = 0.0;
+    for (int col = 0; col < 6; ++col)
+      for (int i = col; i < 6; ++i) {
+        double s = (i == col) ? 1.0 : 0.0;
+        for (int k = col; k < i; ++k) s -= L[i][k] * C[k][col];
+        C[i][col] = s / L[i][i];
+      }
+  }
+};
+
+// basis value / derivative: dx, dy derivative orders
+double basis(int kind, int l, const double* xi, int dx, int dy) {
+  if (kind == LXW_LINE) return dy ? 0.0 : leg(l, xi[0], dx);
+  if (kind == LXW_QUAD) return leg(QUAD_I[l], xi[0], dx) * leg(QUAD_J[l], xi[1], dy);
+  static const TriBasis tb;
+  double s = 0.0;
+  for (int j = 0; j < 6; ++j) s += tb.C[l][j] * dmono(xi[0], TRI_EX[j], dx) * dmono(xi[1], TRI_EY[j], dy);
+  return s;
+}
+
+int nverts(int kind) { return kind == LXW_LINE ? 2 : (kind == LXW_QUAD ? 4 : 3); }
+
+void ref_vertex(int kind, int a, double* xi) {
+  static const double line[2] = {-1, 1};
+  static const double quad[8] = {-1, -1, 1, -1, 1, 1, -1, 1};
+  static const double tri[6] = {0, 0, 1, 0, 0, 1};
+  if (kind == LXW_LINE) xi[0] = line[a];
+  else if (kind == LXW_QUAD) { xi[0] = quad[2 * a]; xi[1] = quad[2 * a + 1]; }
+  else { xi[0] = tri[2 * a]; xi[1] = tri[2 * a + 1]; }
+}
+
+// limiter / update points: interior rule, then edge k Gauss point j (counter-clockwise)
+template <class E>
+std::vector<double> all_points() {
+  Rule r = E::kind == LXW_LINE ? rule_line() : (E::kind == LXW_QUAD ? rule_quad() : rule_tri());
+  std::vector<double> pts = r.x;
+  for (int k = 0; k < E::K; ++k)
+    for (int j = 0; j < E::NQE; ++j) {
+      double a[2] = {0, 0}, b[2] = {0, 0};
+      ref_vertex(E::kind, k, a);
+      ref_vertex(E::kind, (k + 1) % nverts(E::kind), b);
+      if (E::DIM == 1) { pts.push_back(a[0]); continue; }
+      const double t = 0.5 * (1.0 + GL_S[j]);
+      pts.push_back(a[0] + t * (b[0] - a[0]));
+      pts.push_back(a[1] + t * (b[1] - a[1]));
+    }
+  return pts;
+}
+
+template <class E, class R>
+void fill_tab(RefTab<E, R>& T) {
+  std::memset(&T, 0, sizeof(T));
+  Rule r = E::kind == LXW_LINE ? rule_line() : (E::kind == LXW_QUAD ? rule_quad() : rule_tri());
+  std::vector<double> pts = all_points<E>();
+  for (int p = 0; p < E::NP; ++p) {
+    double xi[2] = {pts[p * E::DIM], E::DIM == 2 ? pts[p * E::DIM + 1] : 0.0};
+    for (int l = 0; l < E::ML; ++l) {
+      T.phi[p][l] = R(basis(E::kind, l, xi, 0, 0));
+      T.dphi[p][0][l] = R(basis(E::kind, l, xi, 1, 0));
+      T.d2phi[p][0][l] = R(basis(E::kind, l, xi, 2, 0));
+      if constexpr (E::DIM == 2) {
+        T.dphi[p][1][l] = R(basis(E::kind, l, xi, 0, 1));
+        T.d2phi[p][1][l] = R(basis(E::kind, l, xi, 1, 1));
+        T.d2phi[p][2][l] = R(basis(E::kind, l, xi, 0, 2));
+      }
+    }
+  }
+  for (int m = 0; m < E::NI; ++m)
+    for (int l = 0; l < E::ML; ++l) {
+      double xi[2] = {pts[m * E::DIM], E::DIM == 2 ? pts[m * E::DIM + 1] : 0.0};
+      T.wphi[m][l] = R(r.w[m] * basis(E::kind, l, xi, 0, 0));
+      T.wdphi[m][0][l] = R(r.w[m] * basis(E::kind, l, xi, 1, 0));
+      if constexpr (E::DIM == 2) T.wdphi[m][1][l] = R(r.w[m] * basis(E::kind, l, xi, 0, 1));
+    }
+  // in 1D a face is a point with the single weight 2, so that (1/2) sum omega = 1
+  const double om1d[1] = {2.0};
+  for (int j = 0; j < E::NQE; ++j) T.om[j] = R(E::DIM == 1 ? om1d[0] : GL_W[j]);
+  for (int k = 0; k < E::K; ++k)
+    for (int j = 0; j < E::NQE; ++j) {
+      const double om = E::DIM == 1 ? om1d[0] : GL_W[j];
+      const int p = E::NI + k * E::NQE + j;
+      double xi[2] = {pts[p * E::DIM], E::DIM == 2 ? pts[p * E::DIM + 1] : 0.0};
+      for (int l = 0; l < E::ML; ++l) T.ephi[k][j][l] = R(0.5 * om * basis(E::kind, l, xi, 0, 0));
+    }
+}
+
+std::mutex g_init_mu;
+int g_init_state = 0;  // 0 not done, 1 ok, -1 failed
+
+lxw_status ensure_init() {
+  std::lock_guard<std::mutex> lk(g_init_mu);
+  if (g_init_state == 1) return LXW_OK;
+  std::unique_ptr<HostTabs> t(new HostTabs);
+  fill_tab(t->line_d); fill_tab(t->line_f);
+  fill_tab(t->quad_d); fill_tab(t->quad_f);
+  fill_tab(t->tri_d); fill_tab(t->tri_f);
+  hipError_t e = upload_tables(*t);
+  if (e != hipSuccess) {
+    g_init_state = -1;
+    return fail(LXW_ERR_DEVICE, std::string("uploading reference tables: ") + hipGetErrorString(e));
+  }
+  g_init_state = 1;
+  return LXW_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Mesh: connectivity in the caller's order, then a Morton (Z-order) renumbering of 2D elements by
+// centroid for locality, then edges numbered in the new element order (i_e = the first element
+// to visit the edge), geometry and the per-element edge slots.
+// ---------------------------------------------------------------------------------------------
+struct lxw_mesh {
+  int kind = 0, dim = 0, N = 0, E = 0, K = 0, V = 0, ML = 0;
+  std::vector<int> perm, iperm;     // internal -> caller, caller -> internal
+  std::vector<double> vx;           // internal order: N x nv x dim
+  std::vector<double> area, perim, Jinv, nout, hsz;  // N; N; N*dim*dim; N*K*dim; N
+  std::vector<int> nbr, nbr_k, bcode;                // N*K (internal indices); bcode LXW_BC_* or -1
+  std::vector<int> eslot;                            // N*K
+  std::vector<int> e_i, e_j, e_bc;
+  std::vector<double> e_n;                           // E*dim
+  double geo = 0.0;
+};
+
+namespace {
+
+int bc_to_slot(int bc) {
+  switch (bc) {
+    case LXW_BC_TRANSPARENT: return SB_TRANSPARENT;
+    case LXW_BC_REFLECTIVE: return SB_REFLECTIVE;
+    case LXW_BC_INFLOW: return SB_INFLOW;
+    default: return SB_INTERIOR;
+  }
+}
+
+uint64_t morton2(uint32_t x, uint32_t y) {
+  auto spread = [](uint64_t v) {
+    v &= 0xffffffffull;
+    v = (v | (v << 16)) & 0x0000ffff0000ffffull;
+    v = (v | (v << 8)) & 0x00ff00ff00ff00ffull;
+    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1);
+}
+
+// Finish a mesh given, in caller order: vertex coordinates cvx (N x nv x dim), neighbours cnb /
+// cnk (N x K, -1 on the boundary) and boundary codes cbc (N x K).
+lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::vector<int>& cnb,
+                       const std::vector<int>& cnk, const std::vector<int>& cbc, double alpha_unused) {
+  (void)alpha_unused;
+  const int N = M->N, K = M->K, dim = M->dim, nv = nverts(M->kind);
+  // renumbering
+  M->perm.resize(N);
+  for (int i = 0; i < N; ++i) M->perm[i] = i;
+  if (dim == 2 && N > 1) {
+    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+    std::vector<double> cen(2 * N);
+    for (int i = 0; i < N; ++i)
+      for (int d = 0; d < 2; ++d) {
+        double c = 0.0;
+        for (int a = 0; a < nv; ++a) c += cvx[(i * nv + a) * 2 + d];
+        cen[2 * i + d] = c / nv;
+        lo[d] = std::min(lo[d], cen[2 * i + d]);
+        hi[d] = std::max(hi[d], cen[2 * i + d]);
+      }
+    std::vector<uint64_t> code(N);
+    for (int i = 0; i < N; ++i) {
+      uint32_t q[2];
+      for (int d = 0; d < 2; ++d) {
+        double f = (hi[d] > lo[d]) ? (cen[2 * i + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+        q[d] = (uint32_t)std::min(65535.0, std::max(0.0, f * 65535.0));
+      }
+      code[i] = morton2(q[0], q[1]);
+    }
+    std::stable_sort(M->perm.begin(), M->perm.end(), [&](int a, int b) { return code[a] < code[b]; });
+  }
+  M->iperm.resize(N);
+  for (int i = 0; i < N; ++i) M->iperm[M->perm[i]] = i;
+  M->vx.resize((size_t)N * nv * dim);
+  M->nbr.assign((size_t)N * K, -1);
+  M->nbr_k.assign((size_t)N * K, -1);
+  M->bcode.assign((size_t)N * K, -1);
+  for (int i = 0; i < N; ++i) {
+    const int c = M->perm[i];
+    for (int x = 0; x < nv * dim; ++x) M->vx[(size_t)i * nv * dim + x] = cvx[(size_t)c * nv * dim + x];
+    for (int k = 0; k < K; ++k) {
+      const int j = cnb[(size_t)c * K + k];
+      M->nbr[(size_t)i * K + k] = j >= 0 ? M->iperm[j] : -1;
+      M->nbr_k[(size_t)i * K + k] = cnk[(size_t)c * K + k];
+      M->bcode[(size_t)i * K + k] = j >= 0 ? -1 : cbc[(size_t)c * K + k];
+    }
+  }
+  // geometry
+  M->area.resize(N);
+  M->perim.resize(N);
+  M->Jinv.resize((size_t)N * dim * dim);
+  M->nout.resize((size_t)N * K * dim);
+  M->hsz.resize(N);
+  double geo = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double* v = &M->vx[(size_t)i * nv * dim];
+    if (M->kind == LXW_LINE) {
+      const double h = v[1] - v[0];
+      if (!(h > 0.0)) return fail(LXW_ERR_MESH, "non-positive cell length");
+      M->area[i] = h;
+      M->perim[i] = 2.0;
+      M->Jinv[i] = 2.0 / h;
+      M->nout[(size_t)i * K + 0] = -1.0;
+      M->nout[(size_t)i * K + 1] = 1.0;
+      M->hsz[i] = h;
+    } else {
+      double J[2][2];
+      if (M->kind == LXW_TRI) {
+        J[0][0] = v[2] - v[0]; J[0][1] = v[4] - v[0];
+        J[1][0] = v[3] - v[1]; J[1][1] = v[5] - v[1];
+      } else {
+        J[0][0] = 0.5 * (v[2] - v[0]); J[0][1] = 0.5 * (v[6] - v[0]);
+        J[1][0] = 0.5 * (v[3] - v[1]); J[1][1] = 0.5 * (v[7] - v[1]);
+      }
+      const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      if (!(det > 0.0)) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "element %d is clockwise or degenerate", M->perm[i]);
+        return fail(LXW_ERR_MESH, buf);
+      }
+      double* Ji = &M->Jinv[(size_t)i * 4];
+      Ji[0] = J[1][1] / det; Ji[1] = -J[0][1] / det;
+      Ji[2] = -J[1][0] / det; Ji[3] = J[0][0] / det;
+      M->area[i] = det * (M->kind == LXW_TRI ? 0.5 : 4.0);
+      double P = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const int b = (k + 1) % nv;
+        const double dx = v[2 * b] - v[2 * k], dy = v[2 * b + 1] - v[2 * k + 1];
+        M->nout[((size_t)i * K + k) * 2 + 0] = dy;
+        M->nout[((size_t)i * K + k) * 2 + 1] = -dx;
+        P += std::sqrt(dx * dx + dy * dy);
+      }
+      M->perim[i] = P;
+      M->hsz[i] = M->kind == LXW_TRI ? std::sqrt(2.0 * M->area[i]) : std::sqrt(M->area[i]);
+    }
+    geo = std::max(geo, M->perim[i] / (2.0 * M->area[i]));
+  }
+  M->geo = geo;
+  // edges in internal element order
+  M->eslot.assign((size_t)N * K, -1);
+  M->e_i.clear(); M->e_j.clear(); M->e_bc.clear(); M->e_n.clear();
+  int E = 0;
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < K; ++k) {
+      if (M->eslot[(size_t)i * K + k] >= 0) continue;
+      const int j = M->nbr[(size_t)i * K + k], kj = M->nbr_k[(size_t)i * K + k];
+      const int e = E++;
+      const int bc = j >= 0 ? SB_INTERIOR : bc_to_slot(M->bcode[(size_t)i * K + k]);
+      M->e_i.push_back(i);
+      M->e_j.push_back(j);
+      M->e_bc.push_back(bc);
+      for (int d = 0; d < dim; ++d) M->e_n.push_back(M->nout[((size_t)i * K + k) * dim + d]);
+      M->eslot[(size_t)i * K + k] = e * 8 + 0 * 4 + bc;
+      if (j >= 0) {
+        if (M->eslot[(size_t)j * K + kj] >= 0) return fail(LXW_ERR_MESH, "an edge is shared by more than two elements");
+        M->eslot[(size_t)j * K + kj] = e * 8 + 1 * 4 + SB_INTERIOR;
+      }
+    }
+  M->E = E;
+  return LXW_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Solver
+// ---------------------------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+struct lxw_solver {
+  const lxw_mesh* M = nullptr;
+  lxw_params P{};
+  hipStream_t st = nullptr;
+  bool fp32 = false;
+  std::vector<DevBuf> bufs;
+  View<double> vd{};
+  View<float> vf{};
+  Scalars* sc = nullptr;
+  DevError* err = nullptr;
+  Scalars hsc{};
+  bool debug = false;
+  // diagnostics copies
+  double *dq_lim_bar = nullptr, *dq_upd_bar = nullptr;
+  void *dq_lim_h = nullptr, *dq_upd_h = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  std::vector<int> ev_kid;
+  size_t ev_used = 0;
+  double kms[LXW_K_COUNT] = {};
+  int64_t kcount[LXW_K_COUNT] = {};
+  ~lxw_solver() {
+    for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+    for (auto& e : ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  }
+  template <class T>
+  lxw_status alloc(T** out, size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) return fail(LXW_ERR_OOM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    bufs.push_back({p, count * sizeof(T)});
+    *out = (T*)p;
+    return LXW_OK;
+  }
+};
+
+namespace {
+
+template <class T>
+lxw_status upload(lxw_solver* S, const T** dst, const std::vector<T>& host) {
+  T* p = nullptr;
+  lxw_status s = S->alloc(&p, host.size());
+  if (s) return s;
+  hipError_t e = hipMemcpy(p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(LXW_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+  *dst = p;
+  return LXW_OK;
+}
+
+// Upload geometry and allocate the work arrays for precision R.
+template <class R>
+lxw_status setup_view(lxw_solver* S, View<R>& v) {
+  const lxw_mesh& M = *S->M;
+  const int N = M.N, E = M.E, K = M.K, dim = M.dim, V = M.V, ML = M.ML;
+  const int NQE = M.kind == LXW_LINE ? 1 : 3;
+  std::memset(&v, 0, sizeof(v));
+  v.N = N;
+  v.E = E;
+  lxw_status st;
+  // SoA transposes
+  std::vector<double> Ji((size_t)dim * dim * N), no((size_t)K * dim * N), delta(N);
+  std::vector<int> es((size_t)K * N), nb((size_t)K * N);
+  for (int i = 0; i < N; ++i) {
+    for (int x = 0; x < dim * dim; ++x) Ji[(size_t)x * N + i] = M.Jinv[(size_t)i * dim * dim + x];
+    for (int k = 0; k < K; ++k) {
+      for (int d = 0; d < dim; ++d) no[((size_t)k * dim + d) * N + i] = M.nout[((size_t)i * K + k) * dim + d];
+      es[(size_t)k * N + i] = M.eslot[(size_t)i * K + k];
+      nb[(size_t)k * N + i] = M.nbr[(size_t)i * K + k];
+    }
+    delta[i] = S->P.alpha0 * std::pow(M.hsz[i], 1.5);
+  }
+  std::vector<R> JiR(Ji.begin(), Ji.end()), noR(no.begin(), no.end());
+  std::vector<double> en((size_t)dim * E);
+  for (int e = 0; e < E; ++e)
+    for (int d = 0; d < dim; ++d) en[(size_t)d * E + e] = M.e_n[(size_t)e * dim + d];
+  if ((st = upload(S, &v.area, M.area))) return st;
+  if ((st = upload(S, &v.Jinv, JiR))) return st;
+  if ((st = upload(S, &v.nout, noR))) return st;
+  if ((st = upload(S, &v.eslot, es))) return st;
+  if ((st = upload(S, &v.nbr, nb))) return st;
+  if ((st = upload(S, &v.delta, delta))) return st;
+  if ((st = upload(S, &v.e_i, M.e_i))) return st;
+  if ((st = upload(S, &v.e_j, M.e_j))) return st;
+  if ((st = upload(S, &v.e_bc, M.e_bc))) return st;
+  if ((st = upload(S, &v.e_n, en))) return st;
+  v.mesh_of = nullptr;
+  v.e_mesh = nullptr;
+  if ((st = S->alloc(&v.Qbar, (size_t)V * N))) return st;
+  if ((st = S->alloc(&v.Qh, (size_t)V * (ML - 1) * N))) return st;
+  if ((st = S->alloc(&v.tq, (size_t)2 * NQE * V * E))) return st;
+  if ((st = S->alloc(&v.tf, (size_t)2 * NQE * V * E))) return st;
+  if ((st = S->alloc(&v.fstar, (size_t)NQE * V * E))) return st;
+  if ((st = S->alloc(&v.fLxW, (size_t)V * E))) return st;
+  if ((st = S->alloc(&v.fLxF, (size_t)V * E))) return st;
+  if ((st = S->alloc(&v.cedge, (size_t)2 * E))) return st;
+  {
+    std::vector<double> ones((size_t)2 * E, 1.0);
+    HIPCHK(hipMemcpy(v.cedge, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  v.sc = S->sc;
+  v.err = S->err;
+  v.gamma = S->P.gamma;
+  v.eps0 = S->P.eps0;
+  for (int c = 0; c < 4; ++c) v.inflow[c] = S->P.inflow[c];
+  v.shock = S->P.shock;
+  return LXW_OK;
+}
+
+template <class E, class R>
+hipError_t launch_one(lxw_solver* S, const View<R>& v, KernelId k, double T, int mode) {
+  const int pub = (k == K_SHOCK) ? LXW_K_PRE : (int)k;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (S->timing) {
+    if (S->ev_used == S->ev_pool.size()) {
+      hipEvent_t x, y;
+      if (hipEventCreate(&x) != hipSuccess || hipEventCreate(&y) != hipSuccess) return hipErrorOutOfMemory;
+      S->ev_pool.push_back({x, y});
+      S->ev_kid.push_back(0);
+    }
+    a = S->ev_pool[S->ev_used].first;
+    b = S->ev_pool[S->ev_used].second;
+    S->ev_kid[S->ev_used] = pub;
+    S->ev_used++;
+    hipError_t e = hipEventRecord(a, S->st);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch<E, R>(k, v, S->st, 1, T, mode);
+  if (e != hipSuccess) return e;
+  if (S->timing) e = hipEventRecord(b, S->st);
+  return e;
+}
+
+template <class E, class R>
+lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v, double T) {
+  const lxw_mesh& M = *S->M;
+  const int V = M.V, ML = M.ML, N = M.N;
+  HIPCHK((launch_one<E, R>(S, v, K_PRE, T, 0)));
+  if (S->debug) {
+    HIPCHK(hipMemcpyAsync(S->dq_lim_bar, v.Qbar, (size_t)V * N * sizeof(double), hipMemcpyDeviceToDevice, S->st));
+    HIPCHK(hipMemcpyAsync(S->dq_lim_h, v.Qh, (size_t)V * (ML - 1) * N * sizeof(R), hipMemcpyDeviceToDevice, S->st));
+  }
+  HIPCHK((launch_one<E, R>(S, v, K_DT, T, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_ELEM, T, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_EDGE, T, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_FLIM, T, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_UPDATE, T, 0)));
+  if (S->debug) {
+    HIPCHK(hipMemcpyAsync(S->dq_upd_bar, v.Qbar, (size_t)V * N * sizeof(double), hipMemcpyDeviceToDevice, S->st));
+    HIPCHK(hipMemcpyAsync(S->dq_upd_h, v.Qh, (size_t)V * (ML - 1) * N * sizeof(R), hipMemcpyDeviceToDevice, S->st));
+  }
+  HIPCHK((launch_one<E, R>(S, v, K_FINAL, T, 0)));
+  return LXW_OK;
+}
+
+template <class E, class R>
+lxw_status enqueue_shock_t(lxw_solver* S, const View<R>& v) {
+  HIPCHK((launch_one<E, R>(S, v, K_SHOCK, 0.0, 1)));
+  HIPCHK((launch_one<E, R>(S, v, K_FINAL, 0.0, 1)));
+  return LXW_OK;
+}
+
+lxw_status enqueue_step(lxw_solver* S, double T) {
+  switch (S->M->kind) {
+    case LXW_LINE: return S->fp32 ? enqueue_step_t<ElLine, float>(S, S->vf, T) : enqueue_step_t<ElLine, double>(S, S->vd, T);
+    case LXW_QUAD: return S->fp32 ? enqueue_step_t<ElQuad, float>(S, S->vf, T) : enqueue_step_t<ElQuad, double>(S, S->vd, T);
+    default: return S->fp32 ? enqueue_step_t<ElTri, float>(S, S->vf, T) : enqueue_step_t<ElTri, double>(S, S->vd, T);
+  }
+}
+
+lxw_status enqueue_shock(lxw_solver* S) {
+  switch (S->M->kind) {
+    case LXW_LINE: return S->fp32 ? enqueue_shock_t<ElLine, float>(S, S->vf) : enqueue_shock_t<ElLine, double>(S, S->vd);
+    case LXW_QUAD: return S->fp32 ? enqueue_shock_t<ElQuad, float>(S, S->vf) : enqueue_shock_t<ElQuad, double>(S, S->vd);
+    default: return S->fp32 ? enqueue_shock_t<ElTri, float>(S, S->vf) : enqueue_shock_t<ElTri, double>(S, S->vd);
+  }
+}
+
+// Wait for the stream, read the scalars and the error record, accumulate kernel timings.
+lxw_status sync_check(lxw_solver* S) {
+  HIPCHK(hipStreamSynchronize(S->st));
+  if (S->timing) {
+    for (size_t x = 0; x < S->ev_used; ++x) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, S->ev_pool[x].first, S->ev_pool[x].second));
+      S->kms[S->ev_kid[x]] += ms;
+      S->kcount[S->ev_kid[x]] += 1;
+    }
+    S->ev_used = 0;
+  }
+  HIPCHK(hipMemcpy(&S->hsc, S->sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+  DevError de{};
+  HIPCHK(hipMemcpy(&de, S->err, sizeof(DevError), hipMemcpyDeviceToHost));
+  if (de.code != 0) {
+    const int caller = (de.elem >= 0 && de.elem < S->M->N) ? S->M->perm[de.elem] : -1;
+    const char* what = de.code == LXW_ERR_CFL ? "Lax-Friedrichs update not positive: time step too large"
+                       : de.code == LXW_ERR_NONFINITE ? "non-finite value"
+                                                      : "cell-average density or pressure not positive";
+    char buf[200];
+    snprintf(buf, sizeof buf, "%s (element %d, t = %.17g)", what, caller, S->hsc.t);
+    DevError z{};
+    HIPCHK(hipMemcpy(S->err, &z, sizeof(DevError), hipMemcpyHostToDevice));
+    return fail(de.code, buf);
+  }
+  return LXW_OK;
+}
+
+lxw_status check_solver(lxw_solver* s) {
+  if (!s) return fail(LXW_ERR_ARG, "null solver");
+  return LXW_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C interface
+// =============================================================================================
+extern "C" {
+
+lxw_status lxw_params_default(lxw_params* p) {
+  if (!p) return fail(LXW_ERR_ARG, "null params");
+  p->gamma = 1.4;
+  p->degree = 2;
+  p->cfl = 0.08;
+  p->eps0 = 1e-12;
+  p->alpha0 = 500.0;
+  p->precision = LXW_FP64;
+  p->shock = LXW_SHOCK_PLAIN;
+  p->inflow[0] = 1.0; p->inflow[1] = 0.0; p->inflow[2] = 0.0; p->inflow[3] = 2.5;
+  return LXW_OK;
+}
+
+const char* lxw_last_error(void) { return g_err.c_str(); }
+
+lxw_status lxw_mesh_create_1d(int32_t n, double x0, double x1, int32_t bcl, int32_t bcr, lxw_mesh** out) {
+  if (!out) return fail(LXW_ERR_ARG, "null output");
+  *out = nullptr;
+  if (n < 2 || !(x1 > x0)) return fail(LXW_ERR_ARG, "need n >= 2 and x1 > x0");
+  if (bcl < 0 || bcl > 3 || bcr < 0 || bcr > 3) return fail(LXW_ERR_ARG, "bad boundary code");
+  if ((bcl == LXW_BC_PERIODIC) != (bcr == LXW_BC_PERIODIC)) return fail(LXW_ERR_ARG, "periodic must be set on both ends");
+  std::unique_ptr<lxw_mesh> M(new (std::nothrow) lxw_mesh);
+  if (!M) return fail(LXW_ERR_OOM, "host allocation");
+  M->kind = LXW_LINE; M->dim = 1; M->N = n; M->K = 2; M->V = 3; M->ML = 3;
+  const double h = (x1 - x0) / n;
+  std::vector<double> cvx(2 * (size_t)n);
+  std::vector<int> nb(2 * (size_t)n, -1), nk(2 * (size_t)n, -1), bc(2 * (size_t)n, -1);
+  const bool per = bcl == LXW_BC_PERIODIC;
+  for (int i = 0; i < n; ++i) {
+    cvx[2 * i] = x0 + i * h;
+    cvx[2 * i + 1] = (i == n - 1) ? x1 : x0 + (i + 1) * h;
+    if (i > 0 || per) { nb[2 * i] = (i - 1 + n) % n; nk[2 * i] = 1; } else bc[2 * i] = bcl;
+    if (i < n - 1 || per) { nb[2 * i + 1] = (i + 1) % n; nk[2 * i + 1] = 0; } else bc[2 * i + 1] = bcr;
+  }
+  lxw_status s = finish_mesh(M.get(), cvx, nb, nk, bc, 0.0);
+  if (s) return s;
+  *out = M.release();
+  return LXW_OK;
+}
+
+lxw_status lxw_mesh_create_cart(int32_t nx, int32_t ny, double x0, double x1, double y0, double y1, const int32_t bc[4],
+                                lxw_mesh** out) {
+  if (!out || !bc) return fail(LXW_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (nx < 2 || ny < 2 || !(x1 > x0) || !(y1 > y0)) return fail(LXW_ERR_ARG, "need nx, ny >= 2 and a non-empty box");
+  for (int s = 0; s < 4; ++s)
+    if (bc[s] < 0 || bc[s] > 3) return fail(LXW_ERR_ARG, "bad boundary code");
+  if ((bc[0] == LXW_BC_PERIODIC) != (bc[1] == LXW_BC_PERIODIC) || (bc[2] == LXW_BC_PERIODIC) != (bc[3] == LXW_BC_PERIODIC))
+    return fail(LXW_ERR_ARG, "periodic must be set on both sides of a direction");
+  std::unique_ptr<lxw_mesh> M(new (std::nothrow) lxw_mesh);
+  if (!M) return fail(LXW_ERR_OOM, "host allocation");
+  const int N = nx * ny;
+  M->kind = LXW_QUAD; M->dim = 2; M->N = N; M->K = 4; M->V = 4; M->ML = 9;
+  const double hx = (x1 - x0) / nx, hy = (y1 - y0) / ny;
+  std::vector<double> cvx((size_t)N * 8);
+  std::vector<int> nb((size_t)N * 4, -1), nk((size_t)N * 4, -1), bcv((size_t)N * 4, -1);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int e = i + nx * j;
+      const double xa = x0 + i * hx, xb = (i == nx - 1) ? x1 : x0 + (i + 1) * hx;
+      const double ya = y0 + j * hy, yb = (j == ny - 1) ? y1 : y0 + (j + 1) * hy;
+      const double v[8] = {xa, ya, xb, ya, xb, yb, xa, yb};
+      for (int x = 0; x < 8; ++x) cvx[(size_t)e * 8 + x] = v[x];
+      struct L { int k, ii, jj, kk, code; } links[4] = {
+          {0, i, j - 1, 2, bc[2]}, {1, i + 1, j, 3, bc[1]}, {2, i, j + 1, 0, bc[3]}, {3, i - 1, j, 1, bc[0]}};
+      for (auto& l : links) {
+        const bool outside = l.ii < 0 || l.ii >= nx || l.jj < 0 || l.jj >= ny;
+        if (outside && l.code != LXW_BC_PERIODIC) { bcv[(size_t)e * 4 + l.k] = l.code; continue; }
+        const int ii = (l.ii + nx) % nx, jj = (l.jj + ny) % ny;
+        nb[(size_t)e * 4 + l.k] = ii + nx * jj;
+        nk[(size_t)e * 4 + l.k] = l.kk;
+      }
+    }
+  lxw_status s = finish_mesh(M.get(), cvx, nb, nk, bcv, 0.0);
+  if (s) return s;
+  *out = M.release();
+  return LXW_OK;
+}
+
+lxw_status lxw_mesh_create_tri(int32_t n_nodes, const double* xy, int32_t n_tri, const int32_t* tri,
+                               const int32_t* bnd_tag, const double* period, lxw_mesh** out) {
+  if (!out || !xy || !tri) return fail(LXW_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (n_nodes < 3 || n_tri < 1) return fail(LXW_ERR_ARG, "need at least one triangle");
+  std::unique_ptr<lxw_mesh> M(new (std::nothrow) lxw_mesh);
+  if (!M) return fail(LXW_ERR_OOM, "host allocation");
+  const int N = n_tri;
+  M->kind = LXW_TRI; M->dim = 2; M->N = N; M->K = 3; M->V = 4; M->ML = 6;
+  std::vector<double> cvx((size_t)N * 6);
+  for (int t = 0; t < N; ++t)
+    for (int a = 0; a < 3; ++a) {
+      const int v = tri[3 * t + a];
+      if (v < 0 || v >= n_nodes) return fail(LXW_ERR_ARG, "node index out of range in triangle " + std::to_string(t));
+      cvx[(size_t)t * 6 + 2 * a] = xy[2 * v];
+      cvx[(size_t)t * 6 + 2 * a + 1] = xy[2 * v + 1];
+    }
+  std::vector<int> nb((size_t)N * 3, -1), nk((size_t)N * 3, -1), bcv((size_t)N * 3, -1);
+  std::unordered_map<uint64_t, int64_t> open;  // vertex pair -> t*3+k
+  open.reserve((size_t)N * 2);
+  for (int t = 0; t < N; ++t)
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t a = tri[3 * t + k], b = tri[3 * t + (k + 1) % 3];
+      const uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
+      auto it = open.find(key);
+      if (it == open.end()) {
+        open.emplace(key, (int64_t)t * 3 + k);
+      } else {
+        if (it->second < 0) return fail(LXW_ERR_MESH, "an edge is shared by more than two triangles");
+        const int t2 = (int)(it->second / 3), k2 = (int)(it->second % 3);
+        nb[(size_t)t * 3 + k] = t2; nk[(size_t)t * 3 + k] = k2;
+        nb[(size_t)t2 * 3 + k2] = t; nk[(size_t)t2 * 3 + k2] = k;
+        it->second = -1;
+      }
+    }
+  // boundary edges and periodic pairing by midpoint modulo the period
+  std::map<std::pair<int64_t, int64_t>, int64_t> pmap;
+  for (auto& kv : open) {
+    if (kv.second < 0) continue;
+    const int t = (int)(kv.second / 3), k = (int)(kv.second % 3);
+    const int code = bnd_tag ? bnd_tag[3 * t + k] : LXW_BC_TRANSPARENT;
+    if (code < 0 || code > 3) return fail(LXW_ERR_ARG, "bad boundary code on triangle " + std::to_string(t));
+    if (code != LXW_BC_PERIODIC) { bcv[(size_t)t * 3 + k] = code; continue; }
+    if (!period) return fail(LXW_ERR_ARG, "periodic edges need a period");
+    const double* v = &cvx[(size_t)t * 6];
+    const int b = (k + 1) % 3;
+    double m[2] = {0.5 * (v[2 * k] + v[2 * b]), 0.5 * (v[2 * k + 1] + v[2 * b + 1])};
+    int64_t q[2];
+    for (int d = 0; d < 2; ++d) {
+      const double L = period[d];
+      const int64_t Q = 1ll << 24;
+      if (L > 0) {
+        int64_t x = (int64_t)std::llround(m[d] / L * (double)Q);
+        q[d] = ((x % Q) + Q) % Q;
+      } else {
+        q[d] = (int64_t)std::llround(m[d] * 1e9);
+      }
+    }
+    auto key = std::make_pair(q[0], q[1]);
+    auto it = pmap.find(key);
+    if (it == pmap.end()) {
+      pmap.emplace(key, (int64_t)t * 3 + k);
+    } else {
+      const int t2 = (int)(it->second / 3), k2 = (int)(it->second % 3);
+      nb[(size_t)t * 3 + k] = t2; nk[(size_t)t * 3 + k] = k2;
+      nb[(size_t)t2 * 3 + k2] = t; nk[(size_t)t2 * 3 + k2] = k;
+      pmap.erase(it);
+    }
+  }
+  if (!pmap.empty()) return fail(LXW_ERR_MESH, "unpaired periodic edge");
+  lxw_status s = finish_mesh(M.get(), cvx, nb, nk, bcv, 0.0);
+  if (s) return s;
+  *out = M.release();
+  return LXW_OK;
+}
+
+lxw_status lxw_mesh_destroy(lxw_mesh* m) {
+  delete m;
+  return LXW_OK;
+}
+
+lxw_status lxw_mesh_get_info(const lxw_mesh* m, lxw_mesh_info* out) {
+  if (!m || !out) return fail(LXW_ERR_ARG, "null argument");
+  out->kind = m->kind; out->dim = m->dim; out->n_elem = m->N; out->n_edge = m->E;
+  out->n_var = m->V; out->n_modes = m->ML; out->n_faces = m->K;
+  out->min_area = m->N ? *std::min_element(m->area.begin(), m->area.end()) : 0.0;
+  out->max_area = m->N ? *std::max_element(m->area.begin(), m->area.end()) : 0.0;
+  return LXW_OK;
+}
+
+lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w, double* phi) {
+  if (kind < 0 || kind > 2 || !n_pts) return fail(LXW_ERR_ARG, "bad kind or null n_pts");
+  Rule r = kind == LXW_LINE ? rule_line() : (kind == LXW_QUAD ? rule_quad() : rule_tri());
+  const int dim = kind == LXW_LINE ? 1 : 2, ML = kind == LXW_LINE ? 3 : (kind == LXW_QUAD ? 9 : 6);
+  const int n = (int)r.w.size();
+  *n_pts = n;
+  if (xi) for (int x = 0; x < n * dim; ++x) xi[x] = r.x[x];
+  if (w) for (int m = 0; m < n; ++m) w[m] = r.w[m];
+  if (phi)
+    for (int m = 0; m < n; ++m) {
+      double p[2] = {r.x[m * dim], dim == 2 ? r.x[m * dim + 1] : 0.0};
+      for (int l = 0; l < ML; ++l) phi[m * ML + l] = basis(kind, l, p, 0, 0);
+    }
+  return LXW_OK;
+}
+
+lxw_status lxw_solver_create(const lxw_mesh* m, const lxw_params* p, void* stream, lxw_solver** out) {
+  if (!m || !p || !out) return fail(LXW_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (p->degree != 2) return fail(LXW_ERR_UNSUPPORTED, "only polynomial degree 2 is implemented");
+  if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl <= 1.0) || !(p->eps0 > 0.0) || !(p->alpha0 >= 0.0))
+    return fail(LXW_ERR_ARG, "need gamma > 1, 0 < cfl <= 1, eps0 > 0, alpha0 >= 0");
+  if (p->precision != LXW_FP64 && p->precision != LXW_FP32_MIXED) return fail(LXW_ERR_ARG, "bad precision");
+  if (p->shock != LXW_SHOCK_OFF && p->shock != LXW_SHOCK_PLAIN) return fail(LXW_ERR_UNSUPPORTED, "bad shock-limiter mode");
+  lxw_status s = ensure_init();
+  if (s) return s;
+  std::unique_ptr<lxw_solver> S(new (std::nothrow) lxw_solver);
+  if (!S) return fail(LXW_ERR_OOM, "host allocation");
+  S->M = m;
+  S->P = *p;
+  S->st = (hipStream_t)stream;
+  S->fp32 = p->precision == LXW_FP32_MIXED;
+  if ((s = S->alloc(&S->sc, 1))) return s;
+  if ((s = S->alloc(&S->err, 1))) return s;
+  Scalars z{};
+  z.geo = m->geo;
+  z.cfl = p->cfl;
+  HIPCHK(hipMemcpy(S->sc, &z, sizeof z, hipMemcpyHostToDevice));
+  DevError ze{};
+  HIPCHK(hipMemcpy(S->err, &ze, sizeof ze, hipMemcpyHostToDevice));
+  S->hsc = z;
+  if (S->fp32) s = setup_view<float>(S.get(), S->vf);
+  else s = setup_view<double>(S.get(), S->vd);
+  if (s) return s;
+  *out = S.release();
+  return LXW_OK;
+}
+
+lxw_status lxw_solver_destroy(lxw_solver* s) {
+  if (s) (void)hipStreamSynchronize(s->st);
+  delete s;
+  return LXW_OK;
+}
+
+lxw_status lxw_set_state(lxw_solver* S, const double* Q, double t0, int32_t flags) {
+  if (check_solver(S) || !Q) return fail(LXW_ERR_ARG, "null argument");
+  const lxw_mesh& M = *S->M;
+  const int N = M.N, V = M.V, ML = M.ML, dim = M.dim;
+  const size_t n = (size_t)N * V * ML;
+  std::vector<double> h(n);
+  if (flags & LXW_DEVICE_PTR) {
+    HIPCHK(hipMemcpyAsync(h.data(), Q, n * sizeof(double), hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+  } else {
+    std::memcpy(h.data(), Q, n * sizeof(double));
+  }
+  for (int c = 0; c < N; ++c) {
+    const double* q = &h[(size_t)c * V * ML];
+    double qb[4];
+    bool fin = true;
+    for (int v = 0; v < V; ++v) { qb[v] = q[v * ML]; for (int l = 0; l < ML; ++l) fin = fin && std::isfinite(q[v * ML + l]); }
+    double k = 0.0;
+    for (int d = 0; d < dim; ++d) k += qb[1 + d] * qb[1 + d];
+    const double pb = (S->P.gamma - 1.0) * (qb[V - 1] - 0.5 * k / qb[0]);
+    if (!fin || !(qb[0] >= S->P.eps0) || !(pb > 0.0)) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "initial state violates rho_bar >= eps0, p_bar > 0 or is not finite (element %d)", c);
+      return fail(LXW_ERR_STATE, buf);
+    }
+  }
+  std::vector<double> qbar((size_t)V * N);
+  std::vector<double> qh((size_t)V * (ML - 1) * N);
+  for (int i = 0; i < N; ++i) {
+    const double* q = &h[(size_t)M.perm[i] * V * ML];
+    for (int v = 0; v < V; ++v) {
+      qbar[(size_t)v * N + i] = q[v * ML];
+      for (int l = 1; l < ML; ++l) qh[((size_t)v * (ML - 1) + l - 1) * N + i] = q[v * ML + l];
+    }
+  }
+  HIPCHK(hipStreamSynchronize(S->st));
+  if (S->fp32) {
+    std::vector<float> f(qh.begin(), qh.end());
+    HIPCHK(hipMemcpy(S->vf.Qbar, qbar.data(), qbar.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->vf.Qh, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    HIPCHK(hipMemcpy(S->vd.Qbar, qbar.data(), qbar.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->vd.Qh, qh.data(), qh.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  Scalars z{};
+  z.geo = M.geo;
+  z.cfl = S->P.cfl;
+  z.t = t0;
+  HIPCHK(hipMemcpy(S->sc, &z, sizeof z, hipMemcpyHostToDevice));
+  DevError ze{};
+  HIPCHK(hipMemcpy(S->err, &ze, sizeof ze, hipMemcpyHostToDevice));
+  S->hsc = z;
+  return LXW_OK;
+}
+
+// device state -> caller layout (float64, caller order)
+static lxw_status read_state(lxw_solver* S, std::vector<double>& out, bool upd_copy) {
+  const lxw_mesh& M = *S->M;
+  const int N = M.N, V = M.V, ML = M.ML;
+  std::vector<double> qbar((size_t)V * N), qh((size_t)V * (ML - 1) * N);
+  const void* src_bar = upd_copy ? (const void*)S->dq_upd_bar : (S->fp32 ? (const void*)S->vf.Qbar : (const void*)S->vd.Qbar);
+  const void* src_h = upd_copy ? S->dq_upd_h : (S->fp32 ? (const void*)S->vf.Qh : (const void*)S->vd.Qh);
+  HIPCHK(hipMemcpy(qbar.data(), src_bar, qbar.size() * sizeof(double), hipMemcpyDeviceToHost));
+  if (S->fp32) {
+    std::vector<float> f(qh.size());
+    HIPCHK(hipMemcpy(f.data(), src_h, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t x = 0; x < f.size(); ++x) qh[x] = f[x];
+  } else {
+    HIPCHK(hipMemcpy(qh.data(), src_h, qh.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  out.assign((size_t)N * V * ML, 0.0);
+  for (int i = 0; i < N; ++i) {
+    double* q = &out[(size_t)M.perm[i] * V * ML];
+    for (int v = 0; v < V; ++v) {
+      q[v * ML] = qbar[(size_t)v * N + i];
+      for (int l = 1; l < ML; ++l) q[v * ML + l] = qh[((size_t)v * (ML - 1) + l - 1) * N + i];
+    }
+  }
+  return LXW_OK;
+}
+
+lxw_status lxw_get_state(lxw_solver* S, double* Q, double* t, int32_t flags) {
+  if (check_solver(S) || !Q) return fail(LXW_ERR_ARG, "null argument");
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  if (S->hsc.shock_pending && S->P.shock) {
+    if ((s = enqueue_shock(S))) return s;
+    if ((s = sync_check(S))) return s;
+  }
+  std::vector<double> h;
+  if ((s = read_state(S, h, false))) return s;
+  if (flags & LXW_DEVICE_PTR) {
+    HIPCHK(hipMemcpyAsync(Q, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+  } else {
+    std::memcpy(Q, h.data(), h.size() * sizeof(double));
+  }
+  if (t) *t = S->hsc.t;
+  return LXW_OK;
+}
+
+lxw_status lxw_step(lxw_solver* S, double T, double* dt_taken) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  if (!(S->hsc.t < T)) return fail(LXW_ERR_ARG, "t >= T");
+  lxw_status s = enqueue_step(S, T);
+  if (s) return s;
+  s = sync_check(S);
+  if (dt_taken) *dt_taken = S->hsc.dt;
+  return s;
+}
+
+lxw_status lxw_advance(lxw_solver* S, double T, int64_t max_steps, lxw_stats* out) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  int64_t n = 0;
+  lxw_status s = LXW_OK;
+  while (S->hsc.t < T && n < max_steps) {
+    s = enqueue_step(S, T);
+    if (!s) s = sync_check(S);
+    if (s) break;
+    ++n;
+  }
+  if (out) { out->steps = n; out->t = S->hsc.t; out->last_dt = S->hsc.dt; out->last_s = S->hsc.s; }
+  return s;
+}
+
+lxw_status lxw_run_steps(lxw_solver* S, int64_t n_steps) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  if (n_steps < 0) return fail(LXW_ERR_ARG, "negative step count");
+  const double inf = std::numeric_limits<double>::infinity();
+  for (int64_t k = 0; k < n_steps; ++k) {
+    lxw_status s = enqueue_step(S, inf);
+    if (s) return s;
+  }
+  return LXW_OK;
+}
+
+lxw_status lxw_sync(lxw_solver* S) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  return sync_check(S);
+}
+
+lxw_status lxw_set_debug(lxw_solver* S, int32_t keep) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  S->debug = keep != 0;
+  if (!S->debug) return LXW_OK;
+  const lxw_mesh& M = *S->M;
+  const int N = M.N, V = M.V, ML = M.ML, K = M.K;
+  if (!S->dq_lim_bar) {
+    lxw_status s;
+    const size_t rs = S->fp32 ? sizeof(float) : sizeof(double);
+    if ((s = S->alloc(&S->dq_lim_bar, (size_t)V * N))) return s;
+    if ((s = S->alloc(&S->dq_upd_bar, (size_t)V * N))) return s;
+    char* p1 = nullptr;
+    char* p2 = nullptr;
+    if ((s = S->alloc(&p1, (size_t)V * (ML - 1) * N * rs))) return s;
+    if ((s = S->alloc(&p2, (size_t)V * (ML - 1) * N * rs))) return s;
+    S->dq_lim_h = p1;
+    S->dq_upd_h = p2;
+    double *a, *b, *c, *d;
+    if ((s = S->alloc(&a, N))) return s;
+    if ((s = S->alloc(&b, N))) return s;
+    if ((s = S->alloc(&c, (size_t)V * ML * N))) return s;
+    if ((s = S->alloc(&d, (size_t)K * N))) return s;
+    std::vector<double> ones(N, 1.0);
+    HIPCHK(hipMemcpy(b, ones.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    auto set = [&](auto& v) { v.dbg_theta = a; v.dbg_theta_sc = b; v.dbg_vol = c; v.dbg_lame = d; };
+    set(S->vd);
+    set(S->vf);
+  }
+  return LXW_OK;
+}
+
+lxw_status lxw_debug_stage(lxw_solver* S, int32_t stage, double* out) {
+  if (check_solver(S) || !out) return fail(LXW_ERR_ARG, "null argument");
+  if (!S->debug || !S->dq_lim_bar) return fail(LXW_ERR_ARG, "stages are kept only after lxw_set_debug(s, 1)");
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  const lxw_mesh& M = *S->M;
+  const int N = M.N, V = M.V, ML = M.ML, K = M.K, E = M.E;
+  auto dget = [&](const double* src, size_t n, std::vector<double>& h) -> lxw_status {
+    h.resize(n);
+    HIPCHK(hipMemcpy(h.data(), src, n * sizeof(double), hipMemcpyDeviceToHost));
+    return LXW_OK;
+  };
+  std::vector<double> h;
+  const double* vol = S->fp32 ? S->vf.dbg_vol : S->vd.dbg_vol;
+  switch (stage) {
+    case LXW_STAGE_QLIM:
+    case LXW_STAGE_QUPD: {
+      const bool upd = stage == LXW_STAGE_QUPD;
+      std::vector<double> qbar((size_t)V * N), qh((size_t)V * (ML - 1) * N);
+      HIPCHK(hipMemcpy(qbar.data(), upd ? S->dq_upd_bar : S->dq_lim_bar, qbar.size() * sizeof(double), hipMemcpyDeviceToHost));
+      const void* src = upd ? S->dq_upd_h : S->dq_lim_h;
+      if (S->fp32) {
+        std::vector<float> f(qh.size());
+        HIPCHK(hipMemcpy(f.data(), src, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t x = 0; x < f.size(); ++x) qh[x] = f[x];
+      } else {
+        HIPCHK(hipMemcpy(qh.data(), src, qh.size() * sizeof(double), hipMemcpyDeviceToHost));
+      }
+      for (int i = 0; i < N; ++i) {
+        double* q = &out[(size_t)M.perm[i] * V * ML];
+        for (int v = 0; v < V; ++v) {
+          q[v * ML] = qbar[(size_t)v * N + i];
+          for (int l = 1; l < ML; ++l) q[v * ML + l] = qh[((size_t)v * (ML - 1) + l - 1) * N + i];
+        }
+      }
+      return LXW_OK;
+    }
+    case LXW_STAGE_THETA:
+    case LXW_STAGE_THETA_SC: {
+      if ((s = dget(stage == LXW_STAGE_THETA ? S->vd.dbg_theta ? S->vd.dbg_theta : S->vf.dbg_theta
+                                             : (S->vd.dbg_theta_sc ? S->vd.dbg_theta_sc : S->vf.dbg_theta_sc),
+                    N, h))) return s;
+      for (int i = 0; i < N; ++i) out[M.perm[i]] = h[i];
+      return LXW_OK;
+    }
+    case LXW_STAGE_VOL: {
+      if ((s = dget(vol, (size_t)V * ML * N, h))) return s;
+      for (int i = 0; i < N; ++i)
+        for (int v = 0; v < V; ++v)
+          for (int l = 0; l < ML; ++l) out[((size_t)M.perm[i] * V + v) * ML + l] = h[((size_t)v * ML + l) * N + i];
+      return LXW_OK;
+    }
+    case LXW_STAGE_FLXW:
+    case LXW_STAGE_FLXF: {
+      const double* src = stage == LXW_STAGE_FLXW ? (S->fp32 ? S->vf.fLxW : S->vd.fLxW) : (S->fp32 ? S->vf.fLxF : S->vd.fLxF);
+      if ((s = dget(src, (size_t)V * E, h))) return s;
+      for (int i = 0; i < N; ++i)
+        for (int k = 0; k < K; ++k) {
+          const int slot = M.eslot[(size_t)i * K + k];
+          const int e = slot >> 3;
+          const double ep = ((slot >> 2) & 1) ? -1.0 : 1.0;
+          for (int v = 0; v < V; ++v) out[((size_t)M.perm[i] * K + k) * V + v] = ep * h[(size_t)v * E + e];
+        }
+      return LXW_OK;
+    }
+    case LXW_STAGE_C: {
+      if ((s = dget(S->fp32 ? S->vf.cedge : S->vd.cedge, (size_t)2 * E, h))) return s;
+      for (int i = 0; i < N; ++i)
+        for (int k = 0; k < K; ++k) {
+          const int slot = M.eslot[(size_t)i * K + k];
+          out[(size_t)M.perm[i] * K + k] = h[(size_t)((slot >> 2) & 1) * E + (slot >> 3)];
+        }
+      return LXW_OK;
+    }
+    case LXW_STAGE_LAME: {
+      if ((s = dget(S->fp32 ? S->vf.dbg_lame : S->vd.dbg_lame, (size_t)K * N, h))) return s;
+      for (int i = 0; i < N; ++i)
+        for (int k = 0; k < K; ++k) out[(size_t)M.perm[i] * K + k] = h[(size_t)k * N + i];
+      return LXW_OK;
+    }
+    case LXW_STAGE_SDT:
+      out[0] = S->hsc.s;
+      out[1] = S->hsc.dt;
+      return LXW_OK;
+    default:
+      return fail(LXW_ERR_ARG, "unknown stage");
+  }
+}
+
+lxw_status lxw_set_timing(lxw_solver* S, int32_t enable) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  S->timing = enable != 0;
+  for (int k = 0; k < LXW_K_COUNT; ++k) { S->kms[k] = 0.0; S->kcount[k] = 0; }
+  return LXW_OK;
+}
+
+lxw_status lxw_kernel_times(lxw_solver* S, double* ms, int64_t* launches) {
+  if (check_solver(S) || !ms || !launches) return fail(LXW_ERR_ARG, "null argument");
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  for (int k = 0; k < LXW_K_COUNT; ++k) { ms[k] = S->kms[k]; launches[k] = S->kcount[k]; }
+  return LXW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations shared by the host runtime (lxw_host.cpp) and the kernels
+// (lxw_kernels.hip) of the LxW-DG library.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lxw {
+
+// ---- Element configurations (Sec. 1.2): P2 on the line, tensor Q2 on quads, P2 on triangles.
+// NI interior quadrature points, K faces with NQE Gauss points each; NP = NI + K*NQE limiter
+// points (Sec. 3.1 uses exactly the points of the update); NC = 2^K - 1 pressure corners
+// (Sec. 3.3 Step 5a).
+struct ElLine {
+  static constexpr int kind = 0, DIM = 1, V = 3, ML = 3, K = 2, NI = 3, NQE = 1;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 1;
+};
+struct ElQuad {
+  static constexpr int kind = 1, DIM = 2, V = 4, ML = 9, K = 4, NI = 9, NQE = 3;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3;
+};
+struct ElTri {
+  static constexpr int kind = 2, DIM = 2, V = 4, ML = 6, K = 3, NI = 7, NQE = 3;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3;
+};
+
+// Reference tables of one element kind in one precision, kept in __constant__ memory so that
+// every lane of a wave (one element per lane) reads the same entry through the scalar cache.
+// Points are ordered interior first, then edge k, Gauss point j (counter-clockwise along k).
+template <class E, class R>
+struct RefTab {
+  R phi[E::NP][E::ML];             // basis values
+  R dphi[E::NP][E::DIM][E::ML];    // reference gradient
+  R d2phi[E::NP][E::ND2][E::ML];   // reference second derivatives (xx[, xy, yy])
+  R wphi[E::NI][E::ML];            // w_m phi_l(x_m): projection onto the basis
+  R wdphi[E::NI][E::DIM][E::ML];   // w_m grad phi_l(x_m): volume term
+  R ephi[E::K][E::NQE][E::ML];     // (1/2) omega_j phi_l(x_kj): edge term of the update
+  R om[E::NQE];                    // Gauss-Legendre weights on [-1, 1]
+};
+
+// Per-mesh device scalars (one record per mesh; the batched form holds many).
+struct Scalars {
+  unsigned long long s_bits;  // global wave speed as the bit pattern of a non-negative double
+  double s, dt, t, T;
+  double geo;                 // max_i |dT_i| / (2|T_i|)
+  double cfl;
+  int shock_pending;          // the shock-capturing limiter of the previous step is still due
+  int pad;
+  long long steps;
+};
+
+// Device error record: first error wins (atomicCAS on code).
+struct DevError {
+  int code;
+  int elem;
+};
+
+// Boundary codes stored in an element's edge slot (slot = edge*8 + side*4 + bc).
+enum { SB_INTERIOR = 0, SB_TRANSPARENT = 1, SB_REFLECTIVE = 2, SB_INFLOW = 3 };
+
+// Everything a kernel needs, passed by value.  R is the arithmetic of the bulk (double for
+// LXW_FP64, float for LXW_FP32_MIXED); cell averages and the flux limiter are always double.
+template <class R>
+struct View {
+  int N, E;
+  // elements (internal order)
+  const double* area;     // [N]
+  const R* Jinv;          // [DIM*DIM][N], Jinv[a][d] = d xi_a / d x_d
+  const R* nout;          // [K][DIM][N] outward normal of local edge k, length = edge length
+  const int* eslot;       // [K][N] edge*8 + side*4 + boundary code
+  const int* nbr;         // [K][N] neighbour element or -1
+  const double* delta;    // [N] shock-limiter relaxation alpha0 h^1.5
+  const int* mesh_of;     // [N] mesh index (batched form) or null
+  // edges
+  const int* e_i;         // [E] element i_e (n_e points out of it)
+  const int* e_j;         // [E] element j_e or -1
+  const int* e_bc;        // [E] boundary code (SB_*)
+  const double* e_n;      // [DIM][E] n_e, |n_e| = edge length
+  const int* e_mesh;      // [E] mesh index or null
+  // state
+  double* Qbar;           // [V][N] cell averages
+  R* Qh;                  // [V][ML-1][N] modes 2..ML
+  // work
+  R* tq;                  // [2][NQE][V][E] traces q (side 0 = i_e, side 1 = j_e or ghost)
+  R* tf;                  // [2][NQE][V][E] traces n_out . F_T of that side
+  R* fstar;               // [NQE][V][E] F*_T . n_e at the edge points
+  double* fLxW;           // [V][E]
+  double* fLxF;           // [V][E]
+  double* cedge;          // [2][E] damping candidate of each side (1 on a ghost side)
+  Scalars* sc;
+  DevError* err;
+  // parameters
+  double gamma, eps0;
+  double inflow[4];
+  int shock;
+  // diagnostics (null unless requested)
+  double* dbg_theta;      // [N]
+  double* dbg_theta_sc;   // [N]
+  double* dbg_vol;        // [V][ML][N]
+  double* dbg_lame;       // [K][N]
+};
+
+// All reference tables in both precisions (built on the host by lxw_host.cpp).
+struct HostTabs {
+  RefTab<ElLine, double> line_d;
+  RefTab<ElLine, float> line_f;
+  RefTab<ElQuad, double> quad_d;
+  RefTab<ElQuad, float> quad_f;
+  RefTab<ElTri, double> tri_d;
+  RefTab<ElTri, float> tri_f;
+};
+
+// ---- host-side launchers implemented in lxw_kernels.hip -----------------------------------
+hipError_t upload_tables(const HostTabs& t);
+
+enum KernelId { K_PRE = 0, K_DT = 1, K_ELEM = 2, K_EDGE = 3, K_FLIM = 4, K_UPDATE = 5, K_FINAL = 6, K_SHOCK = 7 };
+
+template <class E, class R>
+hipError_t launch(KernelId k, const View<R>& v, hipStream_t st, int n_mesh, double T, int mode);
+
+}  // namespace lxw

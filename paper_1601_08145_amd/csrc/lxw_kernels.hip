@@ -1,0 +1,943 @@
+// HIP kernels (gfx950) of the positivity-preserving Lax-Wendroff DG step
+// (Moe, Rossmanith, Seal, arXiv:1601.08145).
+//
+// One step is six launches on one stream (grid-wide dependencies separate them):
+//   k_pre    per element: pending shock-capturing limiter of the previous step (Sec. 1.5 Step 5),
+//            moment limiter (Sec. 3.1), cell-average checks, and the global wave speed s
+//            (wavefront max, one atomic max per wavefront);
+//   k_dt     per mesh: dt = CFL / (s max_i |dT_i|/(2|T_i|)), clipped to reach T;
+//   k_elem   per element: Galerkin projection of F (Sec. 2.3 Step 1), the time-averaged flux F_T
+//            of Eq. (taylor3-flux) at every interior and edge point (Sec. 2.2, 2.3 Step 2), the
+//            volume term (Sec. 2.3 Step 3) added to the higher modes, and the edge traces;
+//   k_edge   per edge: Lax-Friedrichs flux of F_T at the edge points (Eq. (LLF)), the
+//            edge-averaged high-order flux f^LxW and the low-order flux f^LxF (Sec. 3.3 Step 3);
+//   k_flim   per element, float64: the flux limiter of Sec. 3.3 Steps 4-5 (Gamma, Lambda_ik, the
+//            corner states and the damping-factor solve mu_c), one candidate per (element, edge);
+//   k_update per element: Lambda_e = min over the two sides, the blended cell-average update and
+//            the higher-moment update of Sec. 3.3 Step 6, and the positivity check;
+//   k_final  per mesh: t += dt.
+// Thread-per-element (or per-edge) mapping; reference tables sit in __constant__ memory and are
+// read through the scalar cache (every lane of a wave reads the same entry).  State is stored as
+// structure-of-arrays: cell averages Qbar[V][N] (float64) and higher modes Qh[V][ML-1][N].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "lxw_internal.hpp"
+
+namespace lxw {
+
+__constant__ RefTab<ElLine, double> c_line_d;
+__constant__ RefTab<ElLine, float> c_line_f;
+__constant__ RefTab<ElQuad, double> c_quad_d;
+__constant__ RefTab<ElQuad, float> c_quad_f;
+__constant__ RefTab<ElTri, double> c_tri_d;
+__constant__ RefTab<ElTri, float> c_tri_f;
+
+template <class E, class R>
+struct TabSel;
+template <> struct TabSel<ElLine, double> { static __device__ __forceinline__ const RefTab<ElLine, double>& get() { return c_line_d; } };
+template <> struct TabSel<ElLine, float> { static __device__ __forceinline__ const RefTab<ElLine, float>& get() { return c_line_f; } };
+template <> struct TabSel<ElQuad, double> { static __device__ __forceinline__ const RefTab<ElQuad, double>& get() { return c_quad_d; } };
+template <> struct TabSel<ElQuad, float> { static __device__ __forceinline__ const RefTab<ElQuad, float>& get() { return c_quad_f; } };
+template <> struct TabSel<ElTri, double> { static __device__ __forceinline__ const RefTab<ElTri, double>& get() { return c_tri_d; } };
+template <> struct TabSel<ElTri, float> { static __device__ __forceinline__ const RefTab<ElTri, float>& get() { return c_tri_f; } };
+
+hipError_t upload_tables(const HostTabs& t) {
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_line_d), &t.line_d, sizeof(t.line_d));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_line_f), &t.line_f, sizeof(t.line_f));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_quad_d), &t.quad_d, sizeof(t.quad_d));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_quad_f), &t.quad_f, sizeof(t.quad_f));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri_d), &t.tri_d, sizeof(t.tri_d));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri_f), &t.tri_f, sizeof(t.tri_f));
+  return e;
+}
+
+// Error codes (public values, see lxw.h).
+enum { E_POSITIVITY = -5, E_NONFINITE = -6, E_CFL = -7 };
+
+__device__ __forceinline__ void report(DevError* err, int code, int elem) {
+  if (atomicCAS(&err->code, 0, code) == 0) err->elem = elem;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Physics.  q = (rho, M_1..M_DIM, E); F_d(q) = (M_d, M u_d + p e_d, u_d (E + p)) (Sec. 1.5) with
+// p from Eq. (eos).  Jacobian and Hessian products (Eqs. (fluxderivs-a), (fluxderivs-b)) are
+// written as first and second directional variations through the variations of u and p:
+//   du_k = (a_Mk - u_k a_rho)/rho,  dp = (gamma-1)(a_E - u.a_M + |u|^2 a_rho / 2),
+//   d2u_k = -(du_k[a] b_rho + du_k[b] a_rho)/rho,  d2p = -(gamma-1) rho du[a].du[b].
+// ---------------------------------------------------------------------------------------------
+template <int DIM, class R>
+struct St {
+  R rho, r, u[DIM], m[DIM], E, p, Ep, u2;
+};
+
+template <int DIM, class R>
+__device__ __forceinline__ St<DIM, R> base_state(const R* q, R gm1) {
+  St<DIM, R> s;
+  s.rho = q[0];
+  s.r = R(1) / q[0];
+  R mu = R(0), u2 = R(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    s.m[d] = q[1 + d];
+    s.u[d] = s.m[d] * s.r;
+    mu += s.m[d] * s.u[d];
+    u2 += s.u[d] * s.u[d];
+  }
+  s.u2 = u2;
+  s.E = q[DIM + 1];
+  s.p = gm1 * (s.E - R(0.5) * mu);
+  s.Ep = s.E + s.p;
+  return s;
+}
+
+template <int DIM, class R>
+struct Var {
+  R du[DIM];
+  R dp;
+};
+
+template <int DIM, class R>
+__device__ __forceinline__ Var<DIM, R> var1(const St<DIM, R>& s, const R* a, R gm1) {
+  Var<DIM, R> v;
+  R t = a[DIM + 1] + R(0.5) * s.u2 * a[0];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    v.du[d] = (a[1 + d] - s.u[d] * a[0]) * s.r;
+    t -= s.u[d] * a[1 + d];
+  }
+  v.dp = gm1 * t;
+  return v;
+}
+
+template <int DIM, class R>
+__device__ __forceinline__ void flux(const St<DIM, R>& s, int d, R* F) {
+  F[0] = s.m[d];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) F[1 + k] = s.m[k] * s.u[d] + (k == d ? s.p : R(0));
+  F[DIM + 1] = s.u[d] * s.Ep;
+}
+
+// A_d a
+template <int DIM, class R>
+__device__ __forceinline__ void dflux(const St<DIM, R>& s, int d, const R* a, const Var<DIM, R>& va, R* F) {
+  F[0] = a[1 + d];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) F[1 + k] = a[1 + k] * s.u[d] + s.m[k] * va.du[d] + (k == d ? va.dp : R(0));
+  F[DIM + 1] = va.du[d] * s.Ep + s.u[d] * (a[DIM + 1] + va.dp);
+}
+
+// H_d(a, b); d2p = -(gamma-1) rho du[a].du[b] is shared by all d and passed in.
+template <int DIM, class R>
+__device__ __forceinline__ void d2flux(const St<DIM, R>& s, int d, const R* a, const Var<DIM, R>& va, const R* b,
+                                       const Var<DIM, R>& vb, R d2p, R* F) {
+  R d2u = -(va.du[d] * b[0] + vb.du[d] * a[0]) * s.r;
+  F[0] = R(0);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) F[1 + k] = a[1 + k] * vb.du[d] + b[1 + k] * va.du[d] + s.m[k] * d2u + (k == d ? d2p : R(0));
+  F[DIM + 1] = d2u * s.Ep + va.du[d] * (b[DIM + 1] + vb.dp) + vb.du[d] * (a[DIM + 1] + va.dp) + s.u[d] * d2p;
+}
+
+template <int DIM, class R>
+__device__ __forceinline__ R d2p_of(const St<DIM, R>& s, const Var<DIM, R>& va, const Var<DIM, R>& vb, R gm1) {
+  R t = R(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) t += va.du[d] * vb.du[d];
+  return -gm1 * s.rho * t;
+}
+
+// F_T = F + dt/2 A q_t + dt^2/6 (H(q_t, q_t) + A q_tt) for every direction d (Eq. (taylor3-flux)
+// with the chain rule of Sec. 2.2; also the ghost-state flux of Sec. 2.4).
+template <int DIM, class R>
+__device__ __forceinline__ void ft_from(const R* q, const R* qt, const R* qtt, R gm1, R dt, R FT[DIM][DIM + 2]) {
+  constexpr int V = DIM + 2;
+  St<DIM, R> s = base_state<DIM, R>(q, gm1);
+  Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
+  Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
+  R d2p = d2p_of<DIM, R>(s, vt, vt, gm1);
+  R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    R F[V], A1[V], H[V], A2[V];
+    flux<DIM, R>(s, d, F);
+    dflux<DIM, R>(s, d, qt, vt, A1);
+    d2flux<DIM, R>(s, d, qt, vt, qt, vt, d2p, H);
+    dflux<DIM, R>(s, d, qtt, vtt, A2);
+#pragma unroll
+    for (int c = 0; c < V; ++c) FT[d][c] = F[c] + c1 * A1[c] + c2 * (H[c] + A2[c]);
+  }
+}
+
+// Pressure and wave speed (double, for the limiters and s).
+template <int DIM>
+__device__ __forceinline__ double pressure(const double* q, double gam) {
+  double k = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) k += q[1 + d] * q[1 + d];
+  return (gam - 1.0) * (q[DIM + 1] - 0.5 * k / q[0]);
+}
+
+template <int DIM>
+__device__ __forceinline__ double wave_speed(const double* q, double gam) {
+  double u2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) u2 += (q[1 + d] / q[0]) * (q[1 + d] / q[0]);
+  return sqrt(u2) + sqrt(gam * pressure<DIM>(q, gam) / q[0]);
+}
+
+// Boundary operator of Sec. 2.4: keep the tangential momentum, negate the normal one.
+template <int DIM, class T>
+__device__ __forceinline__ void reflect(const T* q, const T* nh, T* out) {
+  constexpr int V = DIM + 2;
+#pragma unroll
+  for (int c = 0; c < V; ++c) out[c] = q[c];
+  if constexpr (DIM == 1) {
+    out[1] = -q[1];
+  } else {
+    T mn = q[1] * nh[0] + q[DIM] * nh[DIM - 1];
+    out[1] = q[1] - T(2) * mn * nh[0];
+    out[DIM] = q[DIM] - T(2) * mn * nh[DIM - 1];
+  }
+}
+
+template <int DIM, class T>
+__device__ __forceinline__ void inflow_state(const double* inflow, T* out) {
+  if constexpr (DIM == 1) { out[0] = T(inflow[0]); out[1] = T(inflow[1]); out[2] = T(inflow[3]); }
+  else { out[0] = T(inflow[0]); out[1] = T(inflow[1]); out[DIM] = T(inflow[2]); out[DIM + 1] = T(inflow[3]); }
+}
+
+template <class R>
+__device__ __forceinline__ int mesh_id(const int* mesh_of, int i) { return mesh_of ? mesh_of[i] : 0; }
+
+// Per-mesh maximum of a non-negative double: wavefront reduction when the wavefront lies in one
+// mesh, else one atomic per lane.
+__device__ __forceinline__ void atomic_max_per_mesh(Scalars* sc, int mid, double val, bool valid) {
+  int lane = threadIdx.x & 63;
+  int m0 = __shfl(mid, 0);
+  bool uniform = __all(!valid || mid == m0);
+  if (uniform) {
+    double x = valid ? val : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    if (lane == 0 && __any(valid)) atomicMax(&sc[m0].s_bits, (unsigned long long)__double_as_longlong(x));
+  } else if (valid) {
+    atomicMax(&sc[mid].s_bits, (unsigned long long)__double_as_longlong(val));
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_pre: pending shock-capturing limiter, moment limiter, checks, wave speed.
+//   mode 0: full pre-step work; mode 1: apply only the pending shock limiter (state read-out).
+// ---------------------------------------------------------------------------------------------
+template <class E, class R>
+__global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
+  constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
+  const RefTab<E, R>& T = TabSel<E, R>::get();
+  const int N = v.N;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < N;
+  const double gam = v.gamma, eps0 = v.eps0;
+  double smax = 0.0;
+  int mid = 0;
+  if (valid) {
+    mid = mesh_id<R>(v.mesh_of, i);
+    double qb[V];
+    R Qh[V][ML - 1];
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      qb[c] = v.Qbar[c * N + i];
+#pragma unroll
+      for (int l = 0; l < ML - 1; ++l) Qh[c][l] = v.Qh[(c * (ML - 1) + l) * N + i];
+    }
+    const double pb = pressure<DIM>(qb, gam);
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < V; ++c) finite = finite && isfinite(qb[c]);
+    if (!finite) report(v.err, E_NONFINITE, i);
+    else if (!(qb[0] > 0.0) || !(pb > 0.0)) report(v.err, E_POSITIVITY, i);
+    const bool ok = finite && qb[0] >= eps0 && pb > 0.0;
+
+    // deviation from the cell average at limiter point p (Sec. 3.1, Eq. (q-theta))
+    auto dev = [&](int p, double* d) {
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R acc = R(0);
+#pragma unroll
+        for (int l = 1; l < ML; ++l) acc += Qh[c][l - 1] * T.phi[p][l];
+        d[c] = double(acc);
+      }
+    };
+
+    // ---- shock-capturing limiter on the primitive variables (reading documented in the
+    // library's design notes; bounds from the edge neighbours' averages, relaxation alpha0 h^1.5)
+    double th_sc = 1.0;
+    if (v.shock && v.sc[mid].shock_pending && ok) {
+      auto prim = [&](const double* q, double* w) {
+        w[0] = q[0];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) w[1 + d] = q[1 + d] / q[0];
+        w[DIM + 1] = pressure<DIM>(q, gam);
+      };
+      double wb[V], Mx[V], Mn[V];
+      prim(qb, wb);
+      const double dl = v.delta[i];
+#pragma unroll
+      for (int c = 0; c < V; ++c) { Mx[c] = wb[c] + dl; Mn[c] = wb[c] - dl; }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double qn[V], wn[V];
+        const int j = v.nbr[k * N + i];
+        if (j >= 0) {
+#pragma unroll
+          for (int c = 0; c < V; ++c) qn[c] = v.Qbar[c * N + j];
+        } else {
+          const int bc = v.eslot[k * N + i] & 3;
+          if (bc == SB_REFLECTIVE) {
+            double nh[DIM], len2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) { nh[d] = double(v.nout[(k * DIM + d) * N + i]); len2 += nh[d] * nh[d]; }
+            const double il = 1.0 / sqrt(len2);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) nh[d] *= il;
+            reflect<DIM, double>(qb, nh, qn);
+          } else if (bc == SB_INFLOW) {
+            inflow_state<DIM, double>(v.inflow, qn);
+          } else {
+#pragma unroll
+            for (int c = 0; c < V; ++c) qn[c] = qb[c];
+          }
+        }
+        prim(qn, wn);
+#pragma unroll
+        for (int c = 0; c < V; ++c) { Mx[c] = fmax(Mx[c], wn[c]); Mn[c] = fmin(Mn[c], wn[c]); }
+      }
+      double wmax[V], wmin[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) { wmax[c] = wb[c]; wmin[c] = wb[c]; }
+      for (int p = 0; p < NP; ++p) {
+        double d[V], q[V], w[V];
+        dev(p, d);
+#pragma unroll
+        for (int c = 0; c < V; ++c) q[c] = qb[c] + d[c];
+        wmax[0] = fmax(wmax[0], q[0]);
+        wmin[0] = fmin(wmin[0], q[0]);
+        if (q[0] > 0.0) {
+          prim(q, w);
+#pragma unroll
+          for (int c = 1; c < V; ++c) { wmax[c] = fmax(wmax[c], w[c]); wmin[c] = fmin(wmin[c], w[c]); }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        if (wmax[c] > Mx[c]) th_sc = fmin(th_sc, (Mx[c] - wb[c]) / (wmax[c] - wb[c]));
+        if (wmin[c] < Mn[c]) th_sc = fmin(th_sc, (wb[c] - Mn[c]) / (wb[c] - wmin[c]));
+      }
+      th_sc = fmax(0.0, fmin(1.0, th_sc));
+    }
+
+    // ---- moment limiter (Sec. 3.1): Step 0 flattens cells below eps0 or with p_bar <= 0;
+    // Step 1 density, closed form of the largest theta; Step 2 pressure by concavity with the
+    // target eps_p = min(eps0, p_bar).
+    double th = 1.0;
+    if (mode == 0) {
+      if (!ok) {
+        th = 0.0;
+      } else {
+        double thr = 1.0;
+        for (int p = 0; p < NP; ++p) {
+          double d[V];
+          dev(p, d);
+          const double rm = qb[0] + th_sc * d[0];
+          if (rm < eps0) thr = fmin(thr, (qb[0] - eps0) / (qb[0] - rm));
+        }
+        const double epsp = fmin(eps0, pb);
+        th = thr;
+        for (int p = 0; p < NP; ++p) {
+          double d[V], q[V];
+          dev(p, d);
+#pragma unroll
+          for (int c = 0; c < V; ++c) q[c] = qb[c] + thr * (th_sc * d[c]);
+          const double pt = pressure<DIM>(q, gam);
+          if (pt < epsp) th = fmin(th, thr * (pb - epsp) / (pb - pt));
+        }
+      }
+    }
+    const double tt = th_sc * th;
+    if (tt < 1.0) {
+#pragma unroll
+      for (int c = 0; c < V; ++c)
+#pragma unroll
+        for (int l = 0; l < ML - 1; ++l) {
+          Qh[c][l] = R(tt) * Qh[c][l];
+          v.Qh[(c * (ML - 1) + l) * N + i] = Qh[c][l];
+        }
+    }
+    if (mode == 0) {
+      if (finite && qb[0] > 0.0 && pb > 0.0) {
+        smax = wave_speed<DIM>(qb, gam);
+        if (tt > 0.0) {
+          for (int p = 0; p < NP; ++p) {
+            double d[V], q[V];
+            dev(p, d);  // Qh already scaled
+#pragma unroll
+            for (int c = 0; c < V; ++c) q[c] = qb[c] + d[c];
+            smax = fmax(smax, wave_speed<DIM>(q, gam));
+          }
+        }
+      }
+      if (v.dbg_theta) v.dbg_theta[i] = th;
+    }
+    if (v.dbg_theta_sc && v.shock && v.sc[mid].shock_pending) v.dbg_theta_sc[i] = th_sc;
+  }
+  if (mode == 0) atomic_max_per_mesh(v.sc, mid, smax, valid);
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_dt: per mesh, dt from the CFL condition (reading of Sec. 4.1, "CFL 0.08"), clipped to T.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_dt(Scalars* sc, DevError* err, int n_mesh, double T) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_mesh) return;
+  Scalars& S = sc[m];
+  const double s = __longlong_as_double((long long)S.s_bits);
+  S.s = s;
+  if (!(s > 0.0) || !isfinite(s)) {
+    report(err, E_NONFINITE, -1);
+    S.dt = 0.0;
+    return;
+  }
+  double dt = S.cfl / (s * S.geo);
+  if (S.t + dt > T) dt = T - S.t;
+  S.dt = dt;
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_elem: projection of F onto the basis, F_T at all points, volume term, edge traces.
+// F^h is projected in contravariant form Fc_a = sum_d Jinv[a][d] F_d, so that div F^h =
+// sum_a d/dxi_a Fc_a^h and grad D follows from reference second derivatives (affine elements).
+// ---------------------------------------------------------------------------------------------
+template <class E, class R>
+__global__ __launch_bounds__(128) void k_elem(View<R> v) {
+  constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NI = E::NI, K = E::K, NQE = E::NQE;
+  const RefTab<E, R>& T = TabSel<E, R>::get();
+  const int N = v.N, NE = v.E;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int mid = mesh_id<R>(v.mesh_of, i);
+  const R dt = R(v.sc[mid].dt);
+  const R gm1 = R(v.gamma - 1.0);
+
+  R Q[V][ML];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    Q[c][0] = R(v.Qbar[c * N + i]);
+#pragma unroll
+    for (int l = 1; l < ML; ++l) Q[c][l] = v.Qh[(c * (ML - 1) + l - 1) * N + i];
+  }
+  R Ji[DIM][DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Ji[a][d] = v.Jinv[(a * DIM + d) * N + i];
+
+  // Sec. 2.3 Step 1: Fc^h_a = sum_m w_m Fc_a(q(x_m)) phi_l(x_m)
+  R Fh[DIM][V][ML];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int c = 0; c < V; ++c)
+#pragma unroll
+      for (int l = 0; l < ML; ++l) Fh[a][c][l] = R(0);
+  for (int m = 0; m < NI; ++m) {
+    R q[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      R acc = R(0);
+#pragma unroll
+      for (int l = 0; l < ML; ++l) acc += Q[c][l] * T.phi[m][l];
+      q[c] = acc;
+    }
+    St<DIM, R> s = base_state<DIM, R>(q, gm1);
+    R F[DIM][V];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) flux<DIM, R>(s, d, F[d]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R fc = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) fc += Ji[a][d] * F[d][c];
+#pragma unroll
+        for (int l = 0; l < ML; ++l) Fh[a][c][l] += T.wphi[m][l] * fc;
+      }
+  }
+
+  R vol[V][ML - 1];
+#pragma unroll
+  for (int c = 0; c < V; ++c)
+#pragma unroll
+    for (int l = 0; l < ML - 1; ++l) vol[c][l] = R(0);
+
+  // Sec. 2.3 Step 2 at point p: q, grad q, D = div F^h, grad D, then q_t, q_tt and F_T.
+  auto point = [&](int p, R* q, R* qt, R* qtt, R FT[DIM][V]) {
+    R gq[DIM][V], D[V], gD[DIM][V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      R acc = R(0);
+      R g[DIM];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) g[a] = R(0);
+      R dd = R(0);
+      R h[DIM];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) h[a] = R(0);
+#pragma unroll
+      for (int l = 0; l < ML; ++l) {
+        acc += Q[c][l] * T.phi[p][l];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          g[a] += Q[c][l] * T.dphi[p][a][l];
+          dd += Fh[a][c][l] * T.dphi[p][a][l];
+        }
+        if constexpr (DIM == 1) {
+          h[0] += Fh[0][c][l] * T.d2phi[p][0][l];
+        } else {
+          // d/dxi_b sum_a d/dxi_a Fc_a: b = 0 uses (xx, xy), b = 1 uses (xy, yy)
+          h[0] += Fh[0][c][l] * T.d2phi[p][0][l] + Fh[DIM - 1][c][l] * T.d2phi[p][1][l];
+          h[DIM - 1] += Fh[0][c][l] * T.d2phi[p][1][l] + Fh[DIM - 1][c][l] * T.d2phi[p][DIM][l];
+        }
+      }
+      q[c] = acc;
+      D[c] = dd;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        R sg = R(0), sh = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) { sg += Ji[a][d] * g[a]; sh += Ji[a][d] * h[a]; }
+        gq[d][c] = sg;
+        gD[d][c] = sh;
+      }
+    }
+    St<DIM, R> s = base_state<DIM, R>(q, gm1);
+    Var<DIM, R> vD = var1<DIM, R>(s, D, gm1);
+#pragma unroll
+    for (int c = 0; c < V; ++c) { qt[c] = -D[c]; qtt[c] = R(0); }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      Var<DIM, R> vq = var1<DIM, R>(s, gq[d], gm1);
+      Var<DIM, R> vg = var1<DIM, R>(s, gD[d], gm1);
+      R d2p = d2p_of<DIM, R>(s, vq, vD, gm1);
+      R H[V], A[V];
+      d2flux<DIM, R>(s, d, gq[d], vq, D, vD, d2p, H);
+      dflux<DIM, R>(s, d, gD[d], vg, A);
+#pragma unroll
+      for (int c = 0; c < V; ++c) qtt[c] += H[c] + A[c];
+    }
+    ft_from<DIM, R>(q, qt, qtt, gm1, dt, FT);
+  };
+
+  // interior points: volume term V_l = sum_m w_m grad phi_l . F_T
+  for (int m = 0; m < NI; ++m) {
+    R q[V], qt[V], qtt[V], FT[DIM][V];
+    point(m, q, qt, qtt, FT);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R fc = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) fc += Ji[a][d] * FT[d][c];
+#pragma unroll
+        for (int l = 1; l < ML; ++l) vol[c][l - 1] += T.wdphi[m][a][l] * fc;
+      }
+  }
+
+  // edge points: traces q and n_out . F_T (and the ghost side on boundary edges)
+  for (int k = 0; k < K; ++k) {
+    const int slot = v.eslot[k * N + i];
+    const int e = slot >> 3, side = (slot >> 2) & 1, bc = slot & 3;
+    R n[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) n[d] = v.nout[(k * DIM + d) * N + i];
+    for (int jl = 0; jl < NQE; ++jl) {
+      const int p = NI + k * NQE + jl;
+      const int jj = side ? (NQE - 1 - jl) : jl;
+      R q[V], qt[V], qtt[V], FT[DIM][V];
+      point(p, q, qt, qtt, FT);
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R fn = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) fn += n[d] * FT[d][c];
+        v.tq[((side * NQE + jj) * V + c) * NE + e] = q[c];
+        v.tf[((side * NQE + jj) * V + c) * NE + e] = fn;
+      }
+      if (bc != SB_INTERIOR) {
+        R qg[V], FTg[DIM][V];
+        if (bc == SB_TRANSPARENT) {
+#pragma unroll
+          for (int c = 0; c < V; ++c) qg[c] = q[c];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d)
+#pragma unroll
+            for (int c = 0; c < V; ++c) FTg[d][c] = FT[d][c];
+        } else if (bc == SB_REFLECTIVE) {
+          R nh[DIM], len2 = R(0);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) len2 += n[d] * n[d];
+          const R il = R(1) / sqrt(len2);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) nh[d] = n[d] * il;
+          R qtg[V], qttg[V];
+          reflect<DIM, R>(q, nh, qg);
+          reflect<DIM, R>(qt, nh, qtg);
+          reflect<DIM, R>(qtt, nh, qttg);
+          ft_from<DIM, R>(qg, qtg, qttg, gm1, dt, FTg);
+        } else {
+          R z[V];
+#pragma unroll
+          for (int c = 0; c < V; ++c) z[c] = R(0);
+          inflow_state<DIM, R>(v.inflow, qg);
+          ft_from<DIM, R>(qg, z, z, gm1, dt, FTg);
+        }
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          R fn = R(0);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) fn += n[d] * FTg[d][c];
+          v.tq[((NQE + jj) * V + c) * NE + e] = qg[c];
+          v.tf[((NQE + jj) * V + c) * NE + e] = -fn;
+        }
+      }
+    }
+  }
+
+  // Sec. 2.3 Step 3 / Sec. 3.3 Step 6, volume part: Q^(l) += dt V_l for l >= 2
+#pragma unroll
+  for (int c = 0; c < V; ++c)
+#pragma unroll
+    for (int l = 1; l < ML; ++l) v.Qh[(c * (ML - 1) + l - 1) * N + i] = Q[c][l] + dt * vol[c][l - 1];
+  if (v.dbg_vol) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      v.dbg_vol[(c * ML) * N + i] = 0.0;
+#pragma unroll
+      for (int l = 1; l < ML; ++l) v.dbg_vol[(c * ML + l) * N + i] = double(vol[c][l - 1]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_edge: F*_T . n_e = (1/2)(n_e.F_T(q+) + n_e.F_T(q-)) - (s |n_e| / 2)(q+ - q-) at each edge point
+// (Eq. (LLF) with the scaled normal), f^LxW_e = (1/2) sum_j omega_j F*_j (float64 sum), and
+// f^LxF_e = (1/2) n_e.(F(q_bar_j) + F(q_bar_i)) - (s |n_e| / 2)(q_bar_j - q_bar_i) in float64.
+// ---------------------------------------------------------------------------------------------
+template <class E, class R>
+__global__ __launch_bounds__(256) void k_edge(View<R> v) {
+  constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE;
+  const RefTab<E, R>& T = TabSel<E, R>::get();
+  const int NE = v.E, N = v.N;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NE) return;
+  const int mid = v.e_mesh ? v.e_mesh[e] : 0;
+  const double s = v.sc[mid].s;
+  const double gam = v.gamma;
+  double n[DIM], len2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) { n[d] = v.e_n[d * NE + e]; len2 += n[d] * n[d]; }
+  const double len = sqrt(len2);
+  const R hs = R(0.5 * s * len);
+  double W[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) W[c] = 0.0;
+#pragma unroll
+  for (int jj = 0; jj < NQE; ++jj) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      const R qm = v.tq[((0 * NQE + jj) * V + c) * NE + e];
+      const R fm = v.tf[((0 * NQE + jj) * V + c) * NE + e];
+      const R qp = v.tq[((1 * NQE + jj) * V + c) * NE + e];
+      const R fp = -v.tf[((1 * NQE + jj) * V + c) * NE + e];
+      const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
+      v.fstar[(jj * V + c) * NE + e] = fs;
+      W[c] += 0.5 * double(T.om[jj]) * double(fs);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < V; ++c) v.fLxW[c * NE + e] = W[c];
+
+  const int i = v.e_i[e], j = v.e_j[e];
+  double qi[V], qj[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) qi[c] = v.Qbar[c * N + i];
+  if (j >= 0) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) qj[c] = v.Qbar[c * N + j];
+  } else {
+    const int bc = v.e_bc[e];
+    if (bc == SB_REFLECTIVE) {
+      double nh[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) nh[d] = n[d] / len;
+      reflect<DIM, double>(qi, nh, qj);
+    } else if (bc == SB_INFLOW) {
+      inflow_state<DIM, double>(v.inflow, qj);
+    } else {
+#pragma unroll
+      for (int c = 0; c < V; ++c) qj[c] = qi[c];
+    }
+  }
+  St<DIM, double> si = base_state<DIM, double>(qi, gam - 1.0);
+  St<DIM, double> sj = base_state<DIM, double>(qj, gam - 1.0);
+  double Lf[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) Lf[c] = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    double Fi[V], Fj[V];
+    flux<DIM, double>(si, d, Fi);
+    flux<DIM, double>(sj, d, Fj);
+#pragma unroll
+    for (int c = 0; c < V; ++c) Lf[c] += 0.5 * n[d] * (Fj[c] + Fi[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < V; ++c) v.fLxF[c * NE + e] = Lf[c] - 0.5 * s * len * (qj[c] - qi[c]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Damping factor mu (Sec. 3.3 Step 5b): the largest mu in [0,1] with positive density and
+// pressure >= eps_p on qL + mu (qa - qL).  Along the segment (gamma-1)(rho E - |M|^2/2) - eps_p rho
+// is a quadratic a mu^2 + b mu + c with c >= 0; its first zero is 2c/(-b + sqrt(b^2 - 4ac)),
+// which is then lowered by ulps until the condition holds in float64.
+// ---------------------------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ bool mu_ok(const double* qL, const double* qa, double mu, double gam, double epsp) {
+  constexpr int V = DIM + 2;
+  double q[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) q[c] = qL[c] + mu * (qa[c] - qL[c]);
+  return q[0] > 0.0 && pressure<DIM>(q, gam) >= epsp;
+}
+
+template <int DIM>
+__device__ double mu_solve(const double* qL, const double* qa, double gam, double epsp) {
+  constexpr int V = DIM + 2;
+  if (mu_ok<DIM>(qL, qa, 1.0, gam, epsp)) return 1.0;
+  double dq[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) dq[c] = qa[c] - qL[c];
+  double mL2 = 0.0, mLd = 0.0, dd2 = 0.0;
+#pragma unroll
+  for (int k = 1; k <= DIM; ++k) { mL2 += qL[k] * qL[k]; mLd += qL[k] * dq[k]; dd2 += dq[k] * dq[k]; }
+  const double g1 = gam - 1.0;
+  const double a = g1 * (dq[0] * dq[V - 1] - 0.5 * dd2);
+  const double b = g1 * (qL[0] * dq[V - 1] + dq[0] * qL[V - 1] - mLd) - epsp * dq[0];
+  const double c = g1 * (qL[0] * qL[V - 1] - 0.5 * mL2) - epsp * qL[0];
+  if (!(c > 0.0)) return 0.0;
+  const double den = -b + sqrt(fmax(0.0, b * b - 4.0 * a * c));
+  double mu = den > 0.0 ? 2.0 * c / den : 0.0;
+  mu = fmin(1.0, fmax(0.0, mu));
+  for (int it = 0; it < 64 && mu > 0.0 && !mu_ok<DIM>(qL, qa, mu, gam, epsp); ++it) mu = nextafter(mu, 0.0);
+  if (!mu_ok<DIM>(qL, qa, mu, gam, epsp)) mu = 0.0;
+  return mu;
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_flim: the flux limiter of Sec. 3.3 Steps 4-5, float64, per element.  Readings: every edge flux
+// of the element carries eps_ik (as in the printed Step 4); Cases 1-4 of the sorted Delta f are
+// evaluated as "each edge with Delta f_k < 0 gets min(1, Gamma / |sum of the negative Delta f|)"
+// (no sort); the corner states keep the Lax-Friedrichs flux on the edges switched off, so that
+// corner 000 is the pure LxF update; the pressure target is eps_p = min(eps0, p(q^LxF)).
+// ---------------------------------------------------------------------------------------------
+template <class E, class R>
+__global__ __launch_bounds__(256) void k_flim(View<R> v) {
+  constexpr int V = E::V, DIM = E::DIM, K = E::K;
+  const int N = v.N, NE = v.E;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int mid = mesh_id<R>(v.mesh_of, i);
+  const double dt = v.sc[mid].dt;
+  const double gam = v.gamma;
+  const double area = v.area[i];
+  const double r = dt / area;
+  double qb[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) qb[c] = v.Qbar[c * N + i];
+  double fW[K][V], fF[K][V], df[K];
+  int eidx[K], sd[K];
+  double Gam = area * qb[0] / dt;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int slot = v.eslot[k * N + i];
+    eidx[k] = slot >> 3;
+    sd[k] = (slot >> 2) & 1;
+    const double ep = sd[k] ? -1.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      fW[k][c] = ep * v.fLxW[c * NE + eidx[k]];
+      fF[k][c] = ep * v.fLxF[c * NE + eidx[k]];
+    }
+    Gam -= fF[k][0];
+    df[k] = fF[k][0] - fW[k][0];
+  }
+  double Sneg = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (df[k] < 0.0) Sneg += df[k];
+  bool bad = Gam < 0.0;
+  double Lam[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) Lam[k] = df[k] < 0.0 ? fmax(0.0, fmin(1.0, Gam / fabs(Sneg))) : 1.0;
+  double qL[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc += fF[k][c];
+    qL[c] = qb[c] - r * acc;
+  }
+  const double pL = qL[0] > 0.0 ? pressure<DIM>(qL, gam) : -1.0;
+  bad = bad || !(pL > 0.0);
+  const double epsp = fmin(v.eps0, pL);
+  double mm[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) mm[k] = 1.0;
+  for (int a = 1; a < (1 << K); ++a) {
+    double qa[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double th = ((a >> k) & 1) ? Lam[k] : 0.0;
+        acc += th * fW[k][c] + (1.0 - th) * fF[k][c];
+      }
+      qa[c] = qb[c] - r * acc;
+    }
+    const double mu = pL > 0.0 ? mu_solve<DIM>(qL, qa, gam, epsp) : 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if ((a >> k) & 1) mm[k] = fmin(mm[k], mu);
+  }
+  if (bad) report(v.err, E_CFL, i);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v.cedge[sd[k] * NE + eidx[k]] = Lam[k] * mm[k];
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_update: Sec. 3.3 Step 6 with theta_k = Lambda_{e_ik} = min(1, both sides' candidates):
+//   Q^(1) -= dt/|T| sum_k eps_ik [theta_k f^LxW + (1 - theta_k) f^LxF]            (float64)
+//   Q^(l) -= dt/|T| sum_k eps_ik (1/2) sum_j omega_j phi_l(x_kj) F*_kj . n_e,  l >= 2
+// (the volume part of the higher moments was added by k_elem), then the positivity check of the
+// new cell average.
+// ---------------------------------------------------------------------------------------------
+template <class E, class R>
+__global__ __launch_bounds__(256) void k_update(View<R> v) {
+  constexpr int V = E::V, ML = E::ML, DIM = E::DIM, K = E::K, NQE = E::NQE;
+  const RefTab<E, R>& T = TabSel<E, R>::get();
+  const int N = v.N, NE = v.E;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int mid = mesh_id<R>(v.mesh_of, i);
+  const double dt = v.sc[mid].dt;
+  const double r = dt / v.area[i];
+  double qb[V];
+  R Qh[V][ML - 1];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    qb[c] = v.Qbar[c * N + i];
+#pragma unroll
+    for (int l = 0; l < ML - 1; ++l) Qh[c][l] = v.Qh[(c * (ML - 1) + l) * N + i];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int slot = v.eslot[k * N + i];
+    const int e = slot >> 3, side = (slot >> 2) & 1;
+    const double ep = side ? -1.0 : 1.0;
+    const double th = fmin(1.0, fmin(v.cedge[e], v.cedge[NE + e]));
+    if (v.dbg_lame) v.dbg_lame[k * N + i] = th;
+#pragma unroll
+    for (int c = 0; c < V; ++c) qb[c] -= r * ep * (th * v.fLxW[c * NE + e] + (1.0 - th) * v.fLxF[c * NE + e]);
+    const R re = R(r * ep);
+#pragma unroll
+    for (int jl = 0; jl < NQE; ++jl) {
+      const int jj = side ? (NQE - 1 - jl) : jl;
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        const R fs = re * v.fstar[(jj * V + c) * NE + e];
+#pragma unroll
+        for (int l = 1; l < ML; ++l) Qh[c][l - 1] -= T.ephi[k][jl][l] * fs;
+      }
+    }
+  }
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    v.Qbar[c * N + i] = qb[c];
+    finite = finite && isfinite(qb[c]);
+#pragma unroll
+    for (int l = 0; l < ML - 1; ++l) v.Qh[(c * (ML - 1) + l) * N + i] = Qh[c][l];
+  }
+  if (!finite) report(v.err, E_NONFINITE, i);
+  else if (!(qb[0] > 0.0) || !(pressure<DIM>(qb, v.gamma) > 0.0)) report(v.err, E_POSITIVITY, i);
+}
+
+// k_final: mode 0 ends a step (t += dt, reset s, shock limiter now due); mode 1 marks the pending
+// shock limiter as applied (after a state read-out applied it).
+__global__ void k_final(Scalars* sc, int n_mesh, int shock, int mode) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_mesh) return;
+  Scalars& S = sc[m];
+  if (mode == 0) {
+    S.t += S.dt;
+    S.steps += 1;
+    S.s_bits = 0ull;
+    S.shock_pending = shock ? 1 : 0;
+  } else {
+    S.shock_pending = 0;
+  }
+}
+
+template <class E, class R>
+hipError_t launch(KernelId k, const View<R>& v, hipStream_t st, int n_mesh, double T, int mode) {
+  auto grid = [](int n, int b) { return dim3((unsigned)((n + b - 1) / b)); };
+  switch (k) {
+    case K_PRE:
+      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), grid(v.N, 256), dim3(256), 0, st, v, 0);
+      break;
+    case K_SHOCK:
+      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), grid(v.N, 256), dim3(256), 0, st, v, 1);
+      break;
+    case K_DT:
+      hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh, T);
+      break;
+    case K_ELEM:
+      if (v.N > 0) hipLaunchKernelGGL((k_elem<E, R>), grid(v.N, 128), dim3(128), 0, st, v);
+      break;
+    case K_EDGE:
+      if (v.E > 0) hipLaunchKernelGGL((k_edge<E, R>), grid(v.E, 256), dim3(256), 0, st, v);
+      break;
+    case K_FLIM:
+      if (v.N > 0) hipLaunchKernelGGL((k_flim<E, R>), grid(v.N, 256), dim3(256), 0, st, v);
+      break;
+    case K_UPDATE:
+      if (v.N > 0) hipLaunchKernelGGL((k_update<E, R>), grid(v.N, 256), dim3(256), 0, st, v);
+      break;
+    case K_FINAL:
+      hipLaunchKernelGGL(k_final, grid(n_mesh, 64), dim3(64), 0, st, v.sc, n_mesh, v.shock, mode);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch<ElLine, double>(KernelId, const View<double>&, hipStream_t, int, double, int);
+template hipError_t launch<ElLine, float>(KernelId, const View<float>&, hipStream_t, int, double, int);
+template hipError_t launch<ElQuad, double>(KernelId, const View<double>&, hipStream_t, int, double, int);
+template hipError_t launch<ElQuad, float>(KernelId, const View<float>&, hipStream_t, int, double, int);
+template hipError_t launch<ElTri, double>(KernelId, const View<double>&, hipStream_t, int, double, int);
+template hipError_t launch<ElTri, float>(KernelId, const View<float>&, hipStream_t, int, double, int);
+
+}  // namespace lxw

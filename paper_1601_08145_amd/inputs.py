@@ -79,62 +79,62 @@ def boundary_tags(xy, tri, box, codes):
     return tags
 
 
-def ramp_channel(n_target, seed, angle_deg=30.0, length=4.0, height=1.0, ramp_x=0.5, jitter=0.25):
-    """Channel [0, length] x [0, height] whose floor rises from x = ramp_x at `angle_deg` (a
-    double-Mach-reflection shaped domain: the domain above the ramp), meshed by Delaunay of a
-    jittered point lattice that follows the floor.  Returns (xy, tri, tags) with tags per
-    triangle edge: 0 inflow (x = 0), 1 outflow (x = length), 2 wall (floor and ramp), 3 top."""
+def ramp_channel(n_target, seed, angle_deg=30.0, length=4.0, height=1.5, ramp_x=0.5, ramp_len=1.0, jitter=0.25):
+    """Channel [0, length] x [floor, height] whose floor rises at `angle_deg` from x = ramp_x over a
+    horizontal run ramp_len and is flat after it (a double-Mach-reflection shaped domain), meshed
+    by Delaunay triangulation of a jittered point lattice that follows the floor.  Returns
+    (xy, tri, tags) with tags per triangle edge (edge k joins vertices k and k+1): 0 on the inflow
+    side x = 0, 1 on the outflow side x = length, 3 on the top, 2 (wall) on the floor and the ramp,
+    -1 for interior edges."""
     g = rng(seed)
     ta = math.tan(math.radians(angle_deg))
 
     def floor(x):
-        return np.where(x > ramp_x, np.minimum((x - ramp_x) * ta, 0.9 * height), 0.0)
+        return np.clip(x - ramp_x, 0.0, ramp_len) * ta
 
-    # area of the domain, to hit the target triangle count
     xs = np.linspace(0.0, length, 20001)
     area = np.trapezoid(height - floor(xs), xs)
-    h = math.sqrt(2.0 * area / n_target)
-    nx = int(round(length / h)) + 1
-    ny = int(round(height / h)) + 1
+    n_pts = n_target / 2.0
+    ny = max(3, int(round(math.sqrt(n_pts * height / length))) + 1)
+    nx = max(3, int(round(n_pts / ny)) + 1)
     s = np.linspace(0.0, length, nx)
     r = np.linspace(0.0, 1.0, ny)
     S, Rr = np.meshgrid(s, r, indexing="ij")
     fl = floor(S)
-    X = S.copy()
-    Y = fl + Rr * (height - fl)
     hx = length / (nx - 1)
-    dxj = g.uniform(-jitter * hx, jitter * hx, size=X.shape)
-    dyj = g.uniform(-jitter, jitter, size=X.shape) * (height - fl) / (ny - 1)
+    dxj = g.uniform(-jitter * hx, jitter * hx, size=S.shape)
+    dyj = g.uniform(-jitter, jitter, size=S.shape) / (ny - 1)
     dxj[0, :] = dxj[-1, :] = 0.0
+    dxj[:, 0] = dxj[:, -1] = 0.0   # floor and top points keep their x (the floor has a kink)
     dyj[:, 0] = dyj[:, -1] = 0.0
-    dxj[:, 0] = 0.0  # floor points stay on the floor
-    dxj[:, -1] = 0.0
-    X = X + dxj
-    Y = Y + dyj
+    X = S + dxj
+    Y = floor(X) + np.clip(Rr + dyj, 0.0, 1.0) * (height - floor(X))
     xy = np.stack([X.ravel(), Y.ravel()], axis=1)
     tri = Delaunay(xy).simplices.astype(np.int32)
     a = xy[tri]
-    # drop triangles whose centroid lies below the floor (the hull bridges the ramp's kink)
     c = a.mean(axis=1)
-    keep = c[:, 1] > floor(c[:, 0]) - 1e-12
-    tri = tri[keep]
+    tri = tri[c[:, 1] > floor(c[:, 0]) + 1e-12]  # the hull bridges the concave ramp foot
     a = xy[tri]
     cross = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0])
     flip = cross < 0
     tri[flip] = tri[flip][:, [0, 2, 1]]
+    tri = np.ascontiguousarray(tri)
+    # boundary edges: those used by one triangle only
+    e = np.concatenate([np.sort(np.stack([tri[:, k], tri[:, (k + 1) % 3]], 1), 1) for k in range(3)], 0)
+    key = e[:, 0].astype(np.int64) * len(xy) + e[:, 1]
+    uniq, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    on_bnd = (cnt[inv] == 1).reshape(3, -1).T  # n_tri x 3
     tags = np.full(tri.shape, -1, np.int32)
     tol = 1e-9
     for k in range(3):
         pa = xy[tri[:, k]]
         pb = xy[tri[:, (k + 1) % 3]]
-        mid = 0.5 * (pa + pb)
-        tags[(np.abs(pa[:, 0]) < tol) & (np.abs(pb[:, 0]) < tol), k] = 0
-        tags[(np.abs(pa[:, 0] - length) < tol) & (np.abs(pb[:, 0] - length) < tol), k] = 1
-        tags[(np.abs(pa[:, 1] - height) < tol) & (np.abs(pb[:, 1] - height) < tol), k] = 3
-        on_floor = (np.abs(pa[:, 1] - floor(pa[:, 0])) < 1e-9) & (np.abs(pb[:, 1] - floor(pb[:, 0])) < 1e-9) \
-            & (np.abs(mid[:, 1] - floor(mid[:, 0])) < 1e-6)
-        tags[on_floor & (tags[:, k] < 0), k] = 2
-    return np.ascontiguousarray(xy), np.ascontiguousarray(tri), tags
+        t = np.full(len(tri), 2, np.int32)
+        t[(np.abs(pa[:, 0]) < tol) & (np.abs(pb[:, 0]) < tol)] = 0
+        t[(np.abs(pa[:, 0] - length) < tol) & (np.abs(pb[:, 0] - length) < tol)] = 1
+        t[(np.abs(pa[:, 1] - height) < tol) & (np.abs(pb[:, 1] - height) < tol)] = 3
+        tags[on_bnd[:, k], k] = t[on_bnd[:, k]]
+    return np.ascontiguousarray(xy), tri, tags
 
 
 # ---------------------------------------------------------------------------------------------

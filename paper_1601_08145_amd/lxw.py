@@ -1,0 +1,281 @@
+"""Python binding of the LxW-DG library (include/lxw.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module converts arrays, passes
+pointers and sizes, and turns status codes into exceptions.  PyTorch is used for device memory and
+streams (a solver runs on a torch stream; states may be torch tensors on the GPU).  torch is
+imported before the library is loaded so that both use the same HIP runtime.
+
+There is no fallback: if liblxw.so is missing, importing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading liblxw.so: one HIP runtime per process)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblxw.so")
+
+LXW_OK = 0
+ERRORS = {-1: "LXW_ERR_ARG", -2: "LXW_ERR_UNSUPPORTED", -3: "LXW_ERR_MESH", -4: "LXW_ERR_STATE",
+          -5: "LXW_ERR_POSITIVITY", -6: "LXW_ERR_NONFINITE", -7: "LXW_ERR_CFL", -8: "LXW_ERR_DEVICE",
+          -9: "LXW_ERR_OOM"}
+BC_PERIODIC, BC_TRANSPARENT, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
+LINE, QUAD, TRI = 0, 1, 2
+FP64, FP32_MIXED = 0, 1
+SHOCK_OFF, SHOCK_PLAIN = 0, 1
+HOST_PTR, DEVICE_PTR = 0, 1
+STAGE_QLIM, STAGE_THETA, STAGE_VOL, STAGE_FLXW, STAGE_FLXF = 0, 1, 2, 3, 4
+STAGE_C, STAGE_LAME, STAGE_QUPD, STAGE_THETA_SC, STAGE_SDT = 6, 7, 8, 9, 10
+K_PRE, K_DT, K_ELEM, K_EDGE, K_FLIM, K_UPDATE, K_FINAL, K_COUNT = 0, 1, 2, 3, 4, 5, 6, 7
+KERNEL_NAMES = ["k_pre", "k_dt", "k_elem", "k_edge", "k_flim", "k_update", "k_final"]
+
+
+class LxwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+        self.msg = msg
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("degree", ctypes.c_int32), ("cfl", ctypes.c_double),
+                ("eps0", ctypes.c_double), ("alpha0", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("shock", ctypes.c_int32), ("inflow", ctypes.c_double * 4)]
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_elem", ctypes.c_int32),
+                ("n_edge", ctypes.c_int32), ("n_var", ctypes.c_int32), ("n_modes", ctypes.c_int32),
+                ("n_faces", ctypes.c_int32), ("min_area", ctypes.c_double), ("max_area", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("t", ctypes.c_double), ("last_dt", ctypes.c_double),
+                ("last_s", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "lxw_params_default": [ctypes.POINTER(Params)],
+        "lxw_mesh_create_1d": [I32, D, D, I32, I32, ctypes.POINTER(P)],
+        "lxw_mesh_create_cart": [I32, I32, D, D, D, D, ip, ctypes.POINTER(P)],
+        "lxw_mesh_create_tri": [I32, dp, I32, ip, ip, dp, ctypes.POINTER(P)],
+        "lxw_mesh_destroy": [P],
+        "lxw_mesh_get_info": [P, ctypes.POINTER(MeshInfo)],
+        "lxw_refelem_info": [I32, ip, dp, dp, dp],
+        "lxw_solver_create": [P, ctypes.POINTER(Params), P, ctypes.POINTER(P)],
+        "lxw_solver_destroy": [P],
+        "lxw_set_state": [P, P, D, I32],
+        "lxw_get_state": [P, P, dp, I32],
+        "lxw_step": [P, D, dp],
+        "lxw_advance": [P, D, I64, ctypes.POINTER(Stats)],
+        "lxw_run_steps": [P, I64],
+        "lxw_sync": [P],
+        "lxw_set_debug": [P, I32],
+        "lxw_debug_stage": [P, I32, dp],
+        "lxw_set_timing": [P, I32],
+        "lxw_kernel_times": [P, dp, ctypes.POINTER(ctypes.c_int64)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.lxw_last_error.argtypes = []
+    L.lxw_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_L = _load()
+
+
+def lib():
+    return _L
+
+
+def _check(code):
+    if code != LXW_OK:
+        raise LxwError(code, _L.lxw_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def default_params(**kw):
+    p = Params()
+    _check(_L.lxw_params_default(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k == "inflow":
+            for c in range(4):
+                p.inflow[c] = float(v[c])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def refelem_info(kind):
+    """Interior quadrature points xi[n][dim], weights w[n] (sum 1) and basis values phi[n][n_modes]."""
+    n = ctypes.c_int32(0)
+    _check(_L.lxw_refelem_info(kind, ctypes.byref(n), None, None, None))
+    dim = 1 if kind == LINE else 2
+    ml = {LINE: 3, QUAD: 9, TRI: 6}[kind]
+    xi = np.zeros((n.value, dim))
+    w = np.zeros(n.value)
+    phi = np.zeros((n.value, ml))
+    _check(_L.lxw_refelem_info(kind, ctypes.byref(n), _dp(xi), _dp(w), _dp(phi)))
+    return xi, w, phi
+
+
+class Mesh:
+    def __init__(self, handle, kind, verts):
+        self.h = handle
+        self.kind = kind
+        info = MeshInfo()
+        _check(_L.lxw_mesh_get_info(self.h, ctypes.byref(info)))
+        self.info = info
+        self.N, self.E = info.n_elem, info.n_edge
+        self.V, self.ML, self.K, self.dim = info.n_var, info.n_modes, info.n_faces, info.dim
+        self.verts = verts  # caller-order element vertex coordinates (N x nv x dim), for projection
+
+    def __del__(self, _destroy=_L.lxw_mesh_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    @staticmethod
+    def line(n, x0, x1, bc_left, bc_right):
+        h = ctypes.c_void_p()
+        _check(_L.lxw_mesh_create_1d(n, x0, x1, bc_left, bc_right, ctypes.byref(h)))
+        xs = np.linspace(x0, x1, n + 1)
+        return Mesh(h, LINE, np.stack([xs[:-1], xs[1:]], 1)[:, :, None])
+
+    @staticmethod
+    def cart(nx, ny, x0, x1, y0, y1, bc):
+        b = np.ascontiguousarray(bc, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(_L.lxw_mesh_create_cart(nx, ny, x0, x1, y0, y1, _ip(b), ctypes.byref(h)))
+        xs = np.linspace(x0, x1, nx + 1)
+        ys = np.linspace(y0, y1, ny + 1)
+        i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+        i, j = i.ravel(), j.ravel()
+        v = np.stack([np.stack([xs[i], ys[j]], 1), np.stack([xs[i + 1], ys[j]], 1),
+                      np.stack([xs[i + 1], ys[j + 1]], 1), np.stack([xs[i], ys[j + 1]], 1)], 1)
+        return Mesh(h, QUAD, v)
+
+    @staticmethod
+    def tri(xy, tri, bnd=None, period=None):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        b = np.ascontiguousarray(bnd, dtype=np.int32) if bnd is not None else None
+        p = np.ascontiguousarray(period, dtype=np.float64) if period is not None else None
+        h = ctypes.c_void_p()
+        _check(_L.lxw_mesh_create_tri(len(xy), _dp(xy), len(tri), _ip(tri), _ip(b) if b is not None else None,
+                                      _dp(p) if p is not None else None, ctypes.byref(h)))
+        return Mesh(h, TRI, xy[tri])
+
+    def quad_points(self):
+        """Physical coordinates of the interior quadrature points of every element (N x n x dim)."""
+        xi, w, phi = refelem_info(self.kind)
+        v = self.verts
+        if self.kind == LINE:
+            return v[:, 0, None, :] + 0.5 * (xi[None, :, :] + 1.0) * (v[:, 1, None, :] - v[:, 0, None, :])
+        if self.kind == TRI:
+            return v[:, 0, None, :] + xi[None, :, 0, None] * (v[:, 1, None, :] - v[:, 0, None, :]) \
+                + xi[None, :, 1, None] * (v[:, 2, None, :] - v[:, 0, None, :])
+        return v[:, 0, None, :] + 0.5 * (xi[None, :, 0, None] + 1) * (v[:, 1, None, :] - v[:, 0, None, :]) \
+            + 0.5 * (xi[None, :, 1, None] + 1) * (v[:, 3, None, :] - v[:, 0, None, :])
+
+    def project(self, vals):
+        """L2 projection of point values at quad_points() (N x n x V) onto the documented basis,
+        with the library's quadrature tables: Q_l = sum_m w_m f(x_m) phi_l(x_m)."""
+        xi, w, phi = refelem_info(self.kind)
+        return np.einsum("m,nmv,ml->nvl", w, np.asarray(vals, dtype=np.float64), phi)
+
+
+class Solver:
+    def __init__(self, mesh, stream=None, **params):
+        self.mesh = mesh
+        self.params = default_params(**params)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(_L.lxw_solver_create(mesh.h, ctypes.byref(self.params), ctypes.c_void_p(stream.cuda_stream),
+                                    ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self, _destroy=_L.lxw_solver_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    @property
+    def shape(self):
+        return (self.mesh.N, self.mesh.V, self.mesh.ML)
+
+    def set_state(self, Q, t0=0.0):
+        if isinstance(Q, torch.Tensor) and Q.is_cuda:
+            assert Q.dtype == torch.float64 and Q.is_contiguous() and tuple(Q.shape) == self.shape
+            _check(_L.lxw_set_state(self.h, ctypes.c_void_p(Q.data_ptr()), t0, DEVICE_PTR))
+        else:
+            Q = np.ascontiguousarray(Q, dtype=np.float64)
+            assert Q.shape == self.shape, (Q.shape, self.shape)
+            _check(_L.lxw_set_state(self.h, Q.ctypes.data_as(ctypes.c_void_p), t0, HOST_PTR))
+
+    def get_state(self, out=None):
+        t = ctypes.c_double(0.0)
+        if isinstance(out, torch.Tensor) and out.is_cuda:
+            _check(_L.lxw_get_state(self.h, ctypes.c_void_p(out.data_ptr()), ctypes.byref(t), DEVICE_PTR))
+            return out, t.value
+        Q = np.zeros(self.shape)
+        _check(_L.lxw_get_state(self.h, Q.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t), HOST_PTR))
+        return Q, t.value
+
+    def step(self, T=float("inf")):
+        dt = ctypes.c_double(0.0)
+        _check(_L.lxw_step(self.h, T, ctypes.byref(dt)))
+        return dt.value
+
+    def advance(self, T, max_steps=2**62):
+        st = Stats()
+        _check(_L.lxw_advance(self.h, T, max_steps, ctypes.byref(st)))
+        return st
+
+    def run_steps(self, n):
+        _check(_L.lxw_run_steps(self.h, n))
+
+    def sync(self):
+        _check(_L.lxw_sync(self.h))
+
+    def set_debug(self, on=True):
+        _check(_L.lxw_set_debug(self.h, int(on)))
+
+    def stage(self, stage):
+        m = self.mesh
+        shapes = {STAGE_QLIM: self.shape, STAGE_QUPD: self.shape, STAGE_VOL: self.shape, STAGE_THETA: (m.N,),
+                  STAGE_THETA_SC: (m.N,), STAGE_FLXW: (m.N, m.K, m.V), STAGE_FLXF: (m.N, m.K, m.V),
+                  STAGE_C: (m.N, m.K), STAGE_LAME: (m.N, m.K), STAGE_SDT: (2,)}
+        out = np.zeros(shapes[stage])
+        _check(_L.lxw_debug_stage(self.h, stage, _dp(out)))
+        return out
+
+    def set_timing(self, on=True):
+        _check(_L.lxw_set_timing(self.h, int(on)))
+
+    def kernel_times(self):
+        ms = np.zeros(K_COUNT)
+        n = np.zeros(K_COUNT, dtype=np.int64)
+        _check(_L.lxw_kernel_times(self.h, _dp(ms), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return {KERNEL_NAMES[k]: (float(ms[k]), int(n[k])) for k in range(K_COUNT)}

@@ -1,0 +1,85 @@
+"""CPU-side checks of the GPU library: it loads, exports every symbol declared in include/lxw.h,
+and its host logic (parameters, reference tables, mesh connectivity) is right.  No compute call
+is made here (no GPU in this environment)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_08145_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1601_08145_amd import lxw
+    return lxw
+
+
+def test_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "lxw.h")).read()
+    names = sorted(set(re.findall(r"\b(lxw_[a-z0-9_]+)\s*\(", hdr)))
+    assert len(names) >= 20
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_params(L):
+    p = L.default_params()
+    assert (p.gamma, p.degree, p.cfl, p.eps0, p.alpha0) == (1.4, 2, 0.08, 1e-12, 500.0)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_refelem_tables_match_the_oracle(L, kind):
+    """The library builds its basis independently (closed-form Legendre; Cholesky of the
+    triangle Gram matrix); at every quadrature point it must equal the oracle's Gram-Schmidt
+    basis, and the rules must integrate exactly what the oracle's do."""
+    xi, w, phi = L.refelem_info(kind)
+    R = O.RefElem(kind)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    for m in range(len(w)):
+        for l in range(R.ML):
+            assert phi[m, l] == pytest.approx(R.phi(l, xi[m]), abs=1e-13)
+    # same rule as a set of (point, weight) pairs
+    a = sorted(zip(map(tuple, np.round(xi, 12)), np.round(w, 14)))
+    b = sorted(zip(map(tuple, np.round(R.xi_int, 12)), np.round(R.w_int, 14)))
+    assert a == b
+
+
+def test_mesh_connectivity_counts(L):
+    xy, tri = I.lattice_delaunay(15, 2)
+    m = L.Mesh.tri(xy, tri)
+    mo = O.Mesh.tri(xy, tri)
+    assert (m.N, m.E) == (mo.N, mo.E)
+    xy, tri = I.lattice_delaunay(9, 1, periodic=True)
+    tags = I.boundary_tags(xy, tri, (0, 1, 0, 1), [0, 0, 0, 0])
+    m = L.Mesh.tri(xy, tri, tags, (1.0, 1.0))
+    assert m.E == 3 * m.N // 2  # closed (periodic) triangulation: every edge is shared
+    c = L.Mesh.cart(6, 5, 0, 1, 0, 1, [0, 0, 1, 1])
+    assert (c.N, c.E) == (30, 6 * 5 + 6 * 6)
+    l1 = L.Mesh.line(7, 0, 1, 1, 1)
+    assert (l1.N, l1.E) == (7, 8)
+
+
+def test_mesh_errors(L):
+    xy, tri = I.lattice_delaunay(5, 0)
+    bad = tri.copy()
+    bad[3] = bad[3][[0, 2, 1]]
+    with pytest.raises(L.LxwError) as e:
+        L.Mesh.tri(xy, bad)
+    assert e.value.name == "LXW_ERR_MESH"
+    with pytest.raises(L.LxwError) as e:
+        L.Mesh.line(1, 0, 1, 1, 1)
+    assert e.value.name == "LXW_ERR_ARG"
+    with pytest.raises(L.LxwError) as e:
+        L.Mesh.cart(4, 4, 0, 1, 0, 1, [0, 1, 1, 1])
+    assert e.value.name == "LXW_ERR_ARG"
+    tags = I.boundary_tags(xy, tri, (0, 1, 0, 1), [0, 1, 1, 1])
+    with pytest.raises(L.LxwError) as e:
+        L.Mesh.tri(xy, tri, tags, (1.0, 1.0))
+    assert e.value.name == "LXW_ERR_MESH"
