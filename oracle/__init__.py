@@ -49,6 +49,7 @@ def lib():
         i, d = ctypes.c_int, ctypes.c_double
         sig = {
             "ora_mesh_1d": (P, [i, d, d, i, i]),
+            "ora_num_threads": (i, []),
             "ora_mesh_cart": (P, [i, i, d, d, d, d, ip]),
             "ora_mesh_tri": (P, [i, dp, i, ip, ip, dp]),
             "ora_last_error": (ctypes.c_char_p, []),
@@ -248,6 +249,10 @@ class Solver:
         x = np.zeros((self.mesh.N, P, self.mesh.dim))
         lib().ora_eval(self.h, P, _d(xi), _d(out), _d(x))
         return out, x
+
+
+def num_threads():
+    return int(lib().ora_num_threads())
 
 
 def flux(q, d=0, gamma=1.4):

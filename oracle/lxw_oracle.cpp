@@ -34,6 +34,10 @@
 #include <tuple>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace ora {
 
 // ------------------------------------------------------------------------------------------
@@ -1096,6 +1100,14 @@ using namespace ora;
 extern "C" {
 
 void* ora_mesh_1d(int n, double x0, double x1, int bcl, int bcr) { return mesh_1d(n, x0, x1, bcl, bcr); }
+// Number of threads the element and edge loops run on.
+int ora_num_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 void* ora_mesh_cart(int nx, int ny, double x0, double x1, double y0, double y1, const int* bc) {
   return mesh_cart(nx, ny, x0, x1, y0, y1, bc);
 }

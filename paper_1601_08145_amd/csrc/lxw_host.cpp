@@ -192,6 +192,20 @@ void fill_tab(RefTab<E, R>& T) {
       }
     }
   }
+  for (int p = 0; p < E::NP; ++p)
+    for (int d = 0; d < E::DIM; ++d) T.xr[p][d] = R(pts[p * E::DIM + d]);
+  {
+    const double o[2] = {0.0, 0.0};
+    for (int l = 0; l < E::ML; ++l) {
+      T.dphi0[0][l] = R(basis(E::kind, l, o, 1, 0));
+      T.d2c[0][l] = R(basis(E::kind, l, o, 2, 0));
+      if constexpr (E::DIM == 2) {
+        T.dphi0[1][l] = R(basis(E::kind, l, o, 0, 1));
+        T.d2c[1][l] = R(basis(E::kind, l, o, 1, 1));
+        T.d2c[2][l] = R(basis(E::kind, l, o, 0, 2));
+      }
+    }
+  }
   for (int m = 0; m < E::NI; ++m)
     for (int l = 0; l < E::ML; ++l) {
       double xi[2] = {pts[m * E::DIM], E::DIM == 2 ? pts[m * E::DIM + 1] : 0.0};
@@ -245,6 +259,7 @@ struct lxw_mesh {
   std::vector<int> nbr, nbr_k, bcode;                // N*K (internal indices); bcode LXW_BC_* or -1
   std::vector<int> eslot;                            // N*K
   std::vector<int> e_i, e_j, e_bc;
+  std::vector<int> e_ki, e_kj;                       // local edge index in i_e and j_e (-1)
   std::vector<double> e_n;                           // E*dim
   double geo = 0.0;
 };
@@ -373,7 +388,7 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
   M->geo = geo;
   // edges in internal element order
   M->eslot.assign((size_t)N * K, -1);
-  M->e_i.clear(); M->e_j.clear(); M->e_bc.clear(); M->e_n.clear();
+  M->e_i.clear(); M->e_j.clear(); M->e_bc.clear(); M->e_n.clear(); M->e_ki.clear(); M->e_kj.clear();
   int E = 0;
   for (int i = 0; i < N; ++i)
     for (int k = 0; k < K; ++k) {
@@ -383,6 +398,8 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
       const int bc = j >= 0 ? SB_INTERIOR : bc_to_slot(M->bcode[(size_t)i * K + k]);
       M->e_i.push_back(i);
       M->e_j.push_back(j);
+      M->e_ki.push_back(k);
+      M->e_kj.push_back(j >= 0 ? kj : -1);
       M->e_bc.push_back(bc);
       for (int d = 0; d < dim; ++d) M->e_n.push_back(M->nout[((size_t)i * K + k) * dim + d]);
       M->eslot[(size_t)i * K + k] = e * 8 + 0 * 4 + bc;
@@ -418,8 +435,8 @@ struct lxw_solver {
   Scalars hsc{};
   bool debug = false;
   // diagnostics copies
-  double *dq_lim_bar = nullptr, *dq_upd_bar = nullptr;
-  void *dq_lim_h = nullptr, *dq_upd_h = nullptr;
+  double* dq_upd_bar = nullptr;
+  void* dq_upd_h = nullptr;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -492,12 +509,21 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   if ((st = upload(S, &v.e_j, M.e_j))) return st;
   if ((st = upload(S, &v.e_bc, M.e_bc))) return st;
   if ((st = upload(S, &v.e_n, en))) return st;
+  {
+    std::vector<int> ek(M.e_ki);
+    ek.insert(ek.end(), M.e_kj.begin(), M.e_kj.end());
+    if ((st = upload(S, &v.e_k, ek))) return st;
+  }
   v.mesh_of = nullptr;
   v.e_mesh = nullptr;
   if ((st = S->alloc(&v.Qbar, (size_t)V * N))) return st;
   if ((st = S->alloc(&v.Qh, (size_t)V * (ML - 1) * N))) return st;
-  if ((st = S->alloc(&v.tq, (size_t)2 * NQE * V * E))) return st;
-  if ((st = S->alloc(&v.tf, (size_t)2 * NQE * V * E))) return st;
+  if ((st = S->alloc(&v.theta, (size_t)N))) return st;
+  if ((st = S->alloc(&v.spart, (size_t)(N + 255) / 256 + 1))) return st;
+  if ((st = S->alloc(&v.tq, (size_t)K * NQE * V * N))) return st;
+  if ((st = S->alloc(&v.tf, (size_t)K * NQE * V * N))) return st;
+  if ((st = S->alloc(&v.gq, (size_t)NQE * V * E))) return st;
+  if ((st = S->alloc(&v.gf, (size_t)NQE * V * E))) return st;
   if ((st = S->alloc(&v.fstar, (size_t)NQE * V * E))) return st;
   if ((st = S->alloc(&v.fLxW, (size_t)V * E))) return st;
   if ((st = S->alloc(&v.fLxF, (size_t)V * E))) return st;
@@ -544,10 +570,6 @@ lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v, double T) {
   const lxw_mesh& M = *S->M;
   const int V = M.V, ML = M.ML, N = M.N;
   HIPCHK((launch_one<E, R>(S, v, K_PRE, T, 0)));
-  if (S->debug) {
-    HIPCHK(hipMemcpyAsync(S->dq_lim_bar, v.Qbar, (size_t)V * N * sizeof(double), hipMemcpyDeviceToDevice, S->st));
-    HIPCHK(hipMemcpyAsync(S->dq_lim_h, v.Qh, (size_t)V * (ML - 1) * N * sizeof(R), hipMemcpyDeviceToDevice, S->st));
-  }
   HIPCHK((launch_one<E, R>(S, v, K_DT, T, 0)));
   HIPCHK((launch_one<E, R>(S, v, K_ELEM, T, 0)));
   HIPCHK((launch_one<E, R>(S, v, K_EDGE, T, 0)));
@@ -995,25 +1017,22 @@ lxw_status lxw_set_debug(lxw_solver* S, int32_t keep) {
   if (!S->debug) return LXW_OK;
   const lxw_mesh& M = *S->M;
   const int N = M.N, V = M.V, ML = M.ML, K = M.K;
-  if (!S->dq_lim_bar) {
+  if (!S->dq_upd_bar) {
     lxw_status s;
     const size_t rs = S->fp32 ? sizeof(float) : sizeof(double);
-    if ((s = S->alloc(&S->dq_lim_bar, (size_t)V * N))) return s;
     if ((s = S->alloc(&S->dq_upd_bar, (size_t)V * N))) return s;
-    char* p1 = nullptr;
     char* p2 = nullptr;
-    if ((s = S->alloc(&p1, (size_t)V * (ML - 1) * N * rs))) return s;
     if ((s = S->alloc(&p2, (size_t)V * (ML - 1) * N * rs))) return s;
-    S->dq_lim_h = p1;
     S->dq_upd_h = p2;
-    double *a, *b, *c, *d;
+    double *a, *b, *c, *d, *q;
+    if ((s = S->alloc(&q, (size_t)V * ML * N))) return s;
     if ((s = S->alloc(&a, N))) return s;
     if ((s = S->alloc(&b, N))) return s;
     if ((s = S->alloc(&c, (size_t)V * ML * N))) return s;
     if ((s = S->alloc(&d, (size_t)K * N))) return s;
     std::vector<double> ones(N, 1.0);
     HIPCHK(hipMemcpy(b, ones.data(), N * sizeof(double), hipMemcpyHostToDevice));
-    auto set = [&](auto& v) { v.dbg_theta = a; v.dbg_theta_sc = b; v.dbg_vol = c; v.dbg_lame = d; };
+    auto set = [&](auto& v) { v.dbg_theta = a; v.dbg_theta_sc = b; v.dbg_vol = c; v.dbg_lame = d; v.dbg_qlim = q; };
     set(S->vd);
     set(S->vf);
   }
@@ -1022,7 +1041,7 @@ lxw_status lxw_set_debug(lxw_solver* S, int32_t keep) {
 
 lxw_status lxw_debug_stage(lxw_solver* S, int32_t stage, double* out) {
   if (check_solver(S) || !out) return fail(LXW_ERR_ARG, "null argument");
-  if (!S->debug || !S->dq_lim_bar) return fail(LXW_ERR_ARG, "stages are kept only after lxw_set_debug(s, 1)");
+  if (!S->debug || !S->dq_upd_bar) return fail(LXW_ERR_ARG, "stages are kept only after lxw_set_debug(s, 1)");
   lxw_status s = sync_check(S);
   if (s) return s;
   const lxw_mesh& M = *S->M;
@@ -1035,12 +1054,17 @@ lxw_status lxw_debug_stage(lxw_solver* S, int32_t stage, double* out) {
   std::vector<double> h;
   const double* vol = S->fp32 ? S->vf.dbg_vol : S->vd.dbg_vol;
   switch (stage) {
-    case LXW_STAGE_QLIM:
+    case LXW_STAGE_QLIM: {
+      if ((s = dget(S->fp32 ? S->vf.dbg_qlim : S->vd.dbg_qlim, (size_t)V * ML * N, h))) return s;
+      for (int i = 0; i < N; ++i)
+        for (int v = 0; v < V; ++v)
+          for (int l = 0; l < ML; ++l) out[((size_t)M.perm[i] * V + v) * ML + l] = h[((size_t)v * ML + l) * N + i];
+      return LXW_OK;
+    }
     case LXW_STAGE_QUPD: {
-      const bool upd = stage == LXW_STAGE_QUPD;
       std::vector<double> qbar((size_t)V * N), qh((size_t)V * (ML - 1) * N);
-      HIPCHK(hipMemcpy(qbar.data(), upd ? S->dq_upd_bar : S->dq_lim_bar, qbar.size() * sizeof(double), hipMemcpyDeviceToHost));
-      const void* src = upd ? S->dq_upd_h : S->dq_lim_h;
+      HIPCHK(hipMemcpy(qbar.data(), S->dq_upd_bar, qbar.size() * sizeof(double), hipMemcpyDeviceToHost));
+      const void* src = S->dq_upd_h;
       if (S->fp32) {
         std::vector<float> f(qh.size());
         HIPCHK(hipMemcpy(f.data(), src, f.size() * sizeof(float), hipMemcpyDeviceToHost));

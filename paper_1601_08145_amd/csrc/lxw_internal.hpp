@@ -37,6 +37,10 @@ struct RefTab {
   R wdphi[E::NI][E::DIM][E::ML];   // w_m grad phi_l(x_m): volume term
   R ephi[E::K][E::NQE][E::ML];     // (1/2) omega_j phi_l(x_kj): edge term of the update
   R om[E::NQE];                    // Gauss-Legendre weights on [-1, 1]
+  R xr[E::NP][E::DIM];             // reference coordinates of the points
+  R dphi0[E::DIM][E::ML];          // reference gradient at the reference origin
+  R d2c[E::ND2][E::ML];            // reference second derivatives at the origin (constant for
+                                   // complete P2 on the line and the triangle)
 };
 
 // Per-mesh device scalars (one record per mesh; the batched form holds many).
@@ -76,20 +80,25 @@ struct View {
   const int* e_i;         // [E] element i_e (n_e points out of it)
   const int* e_j;         // [E] element j_e or -1
   const int* e_bc;        // [E] boundary code (SB_*)
+  const int* e_k;         // [2][E] local edge index of the edge in i_e (side 0) and j_e (side 1)
   const double* e_n;      // [DIM][E] n_e, |n_e| = edge length
   const int* e_mesh;      // [E] mesh index or null
   // state
   double* Qbar;           // [V][N] cell averages
   R* Qh;                  // [V][ML-1][N] modes 2..ML
   // work
-  R* tq;                  // [2][NQE][V][E] traces q (side 0 = i_e, side 1 = j_e or ghost)
-  R* tf;                  // [2][NQE][V][E] traces n_out . F_T of that side
+  double* theta;          // [N] limiter factor of the step (shock x moment), applied by k_elem
+  R* tq;                  // [NQE][V][N][K] traces q at the element's own edge points
+  R* tf;                  // [NQE][V][N][K] traces n_out . F_T at the element's own edge points
+  R* gq;                  // [NQE][V][E] ghost-state q on boundary edges (edge point order of i_e)
+  R* gf;                  // [NQE][V][E] ghost-side n_out . F_T on boundary edges (n_out = -n_e)
   R* fstar;               // [NQE][V][E] F*_T . n_e at the edge points
   double* fLxW;           // [V][E]
   double* fLxF;           // [V][E]
   double* cedge;          // [2][E] damping candidate of each side (1 on a ghost side)
   Scalars* sc;
   DevError* err;
+  double* spart;          // [blocks of k_pre] per-block maximum wave speed (single-mesh form)
   // parameters
   double gamma, eps0;
   double inflow[4];
@@ -99,6 +108,7 @@ struct View {
   double* dbg_theta_sc;   // [N]
   double* dbg_vol;        // [V][ML][N]
   double* dbg_lame;       // [K][N]
+  double* dbg_qlim;       // [V][ML][N] limited state at the start of the step
 };
 
 // All reference tables in both precisions (built on the host by lxw_host.cpp).

@@ -229,12 +229,43 @@ __device__ __forceinline__ void atomic_max_per_mesh(Scalars* sc, int mid, double
 
 // ---------------------------------------------------------------------------------------------
 // k_pre: pending shock-capturing limiter, moment limiter, checks, wave speed.
-//   mode 0: full pre-step work; mode 1: apply only the pending shock limiter (state read-out).
+//   mode 0: computes the element's total limiter factor theta = theta_shock * theta_moment and
+//           stores it (k_elem applies it to the higher modes); wave speed and checks.
+//   mode 1: applies only the pending shock-capturing limiter to the stored modes (state read-out).
+// All limiter arithmetic is float64 on the stored state, evaluated as q_bar + theta sum_l Q_l phi_l,
+// the same expression k_elem uses for its point states, so the positivity the limiter establishes
+// holds for the states the time-averaged flux is built from.
 // ---------------------------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ double pressure_r(const double* q, double r, double gam) {
+  double k = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) k += q[1 + d] * q[1 + d];
+  return (gam - 1.0) * (q[DIM + 1] - 0.5 * k * r);
+}
+
+template <int DIM>
+__device__ __forceinline__ double speed_r(const double* q, double gam) {
+  const double r = 1.0 / q[0];
+  double u2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) u2 += (q[1 + d] * r) * (q[1 + d] * r);
+  return sqrt(u2) + sqrt(gam * pressure_r<DIM>(q, r, gam) * r);
+}
+
+// deviation of variable c from the cell average at point p, float64, from the stored modes
+template <class E, class R>
+__device__ __forceinline__ double point_dev(const RefTab<E, double>& T, const R (&Qh)[E::V][E::ML - 1], int p, int c) {
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 1; l < E::ML; ++l) acc += double(Qh[c][l - 1]) * T.phi[p][l];
+  return acc;
+}
+
 template <class E, class R>
 __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
-  const RefTab<E, R>& T = TabSel<E, R>::get();
+  const RefTab<E, double>& T = TabSel<E, double>::get();
   const int N = v.N;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < N;
@@ -251,37 +282,26 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
 #pragma unroll
       for (int l = 0; l < ML - 1; ++l) Qh[c][l] = v.Qh[(c * (ML - 1) + l) * N + i];
     }
-    const double pb = pressure<DIM>(qb, gam);
+    const double rb = 1.0 / qb[0];
+    const double pb = pressure_r<DIM>(qb, rb, gam);
     bool finite = true;
 #pragma unroll
     for (int c = 0; c < V; ++c) finite = finite && isfinite(qb[c]);
-    if (!finite) report(v.err, E_NONFINITE, i);
-    else if (!(qb[0] > 0.0) || !(pb > 0.0)) report(v.err, E_POSITIVITY, i);
+    if (mode == 0) {
+      if (!finite) report(v.err, E_NONFINITE, i);
+      else if (!(qb[0] > 0.0) || !(pb > 0.0)) report(v.err, E_POSITIVITY, i);
+    }
     const bool ok = finite && qb[0] >= eps0 && pb > 0.0;
 
-    // deviation from the cell average at limiter point p (Sec. 3.1, Eq. (q-theta))
-    auto dev = [&](int p, double* d) {
-#pragma unroll
-      for (int c = 0; c < V; ++c) {
-        R acc = R(0);
-#pragma unroll
-        for (int l = 1; l < ML; ++l) acc += Qh[c][l - 1] * T.phi[p][l];
-        d[c] = double(acc);
-      }
-    };
-
-    // ---- shock-capturing limiter on the primitive variables (reading documented in the
-    // library's design notes; bounds from the edge neighbours' averages, relaxation alpha0 h^1.5)
+    // ---- shock-capturing limiter on the primitive variables (bounds from the edge neighbours'
+    // averages relaxed by alpha0 h^1.5; velocity and pressure sampled where the density is positive)
     double th_sc = 1.0;
     if (v.shock && v.sc[mid].shock_pending && ok) {
-      auto prim = [&](const double* q, double* w) {
-        w[0] = q[0];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) w[1 + d] = q[1 + d] / q[0];
-        w[DIM + 1] = pressure<DIM>(q, gam);
-      };
       double wb[V], Mx[V], Mn[V];
-      prim(qb, wb);
+      wb[0] = qb[0];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) wb[1 + d] = qb[1 + d] * rb;
+      wb[DIM + 1] = pb;
       const double dl = v.delta[i];
 #pragma unroll
       for (int c = 0; c < V; ++c) { Mx[c] = wb[c] + dl; Mn[c] = wb[c] - dl; }
@@ -309,24 +329,35 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
             for (int c = 0; c < V; ++c) qn[c] = qb[c];
           }
         }
-        prim(qn, wn);
+        const double rn = 1.0 / qn[0];
+        wn[0] = qn[0];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) wn[1 + d] = qn[1 + d] * rn;
+        wn[DIM + 1] = pressure_r<DIM>(qn, rn, gam);
 #pragma unroll
         for (int c = 0; c < V; ++c) { Mx[c] = fmax(Mx[c], wn[c]); Mn[c] = fmin(Mn[c], wn[c]); }
       }
       double wmax[V], wmin[V];
 #pragma unroll
       for (int c = 0; c < V; ++c) { wmax[c] = wb[c]; wmin[c] = wb[c]; }
-      for (int p = 0; p < NP; ++p) {
-        double d[V], q[V], w[V];
-        dev(p, d);
 #pragma unroll
-        for (int c = 0; c < V; ++c) q[c] = qb[c] + d[c];
+      for (int p = 0; p < NP; ++p) {
+        double q[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) q[c] = qb[c] + point_dev<E, R>(T, Qh, p, c);
         wmax[0] = fmax(wmax[0], q[0]);
         wmin[0] = fmin(wmin[0], q[0]);
         if (q[0] > 0.0) {
-          prim(q, w);
+          const double r = 1.0 / q[0];
 #pragma unroll
-          for (int c = 1; c < V; ++c) { wmax[c] = fmax(wmax[c], w[c]); wmin[c] = fmin(wmin[c], w[c]); }
+          for (int d = 0; d < DIM; ++d) {
+            const double u = q[1 + d] * r;
+            wmax[1 + d] = fmax(wmax[1 + d], u);
+            wmin[1 + d] = fmin(wmin[1 + d], u);
+          }
+          const double pp = pressure_r<DIM>(q, r, gam);
+          wmax[DIM + 1] = fmax(wmax[DIM + 1], pp);
+          wmin[DIM + 1] = fmin(wmin[DIM + 1], pp);
         }
       }
 #pragma unroll
@@ -337,66 +368,116 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
       th_sc = fmax(0.0, fmin(1.0, th_sc));
     }
 
-    // ---- moment limiter (Sec. 3.1): Step 0 flattens cells below eps0 or with p_bar <= 0;
-    // Step 1 density, closed form of the largest theta; Step 2 pressure by concavity with the
-    // target eps_p = min(eps0, p_bar).
-    double th = 1.0;
-    if (mode == 0) {
+    if (mode == 1) {
+      if (th_sc < 1.0) {
+#pragma unroll
+        for (int c = 0; c < V; ++c)
+#pragma unroll
+          for (int l = 0; l < ML - 1; ++l) v.Qh[(c * (ML - 1) + l) * N + i] = R(th_sc * double(Qh[c][l]));
+      }
+      if (v.dbg_theta_sc && v.shock && v.sc[mid].shock_pending) v.dbg_theta_sc[i] = th_sc;
+    } else {
+      // ---- moment limiter (Sec. 3.1): Step 0 flattens cells below eps0 or with p_bar <= 0;
+      // Step 1 density (closed form of the largest theta); Step 2 pressure by concavity, target
+      // eps_p = min(eps0, p_bar).
+      double th = 1.0;
       if (!ok) {
         th = 0.0;
       } else {
         double thr = 1.0;
+#pragma unroll
         for (int p = 0; p < NP; ++p) {
-          double d[V];
-          dev(p, d);
-          const double rm = qb[0] + th_sc * d[0];
+          const double rm = qb[0] + th_sc * point_dev<E, R>(T, Qh, p, 0);
           if (rm < eps0) thr = fmin(thr, (qb[0] - eps0) / (qb[0] - rm));
         }
         const double epsp = fmin(eps0, pb);
+        const double ts = thr * th_sc;
         th = thr;
-        for (int p = 0; p < NP; ++p) {
-          double d[V], q[V];
-          dev(p, d);
 #pragma unroll
-          for (int c = 0; c < V; ++c) q[c] = qb[c] + thr * (th_sc * d[c]);
-          const double pt = pressure<DIM>(q, gam);
+        for (int p = 0; p < NP; ++p) {
+          double q[V];
+#pragma unroll
+          for (int c = 0; c < V; ++c) q[c] = qb[c] + ts * point_dev<E, R>(T, Qh, p, c);
+          const double pt = pressure_r<DIM>(q, 1.0 / q[0], gam);
           if (pt < epsp) th = fmin(th, thr * (pb - epsp) / (pb - pt));
         }
       }
-    }
-    const double tt = th_sc * th;
-    if (tt < 1.0) {
-#pragma unroll
-      for (int c = 0; c < V; ++c)
-#pragma unroll
-        for (int l = 0; l < ML - 1; ++l) {
-          Qh[c][l] = R(tt) * Qh[c][l];
-          v.Qh[(c * (ML - 1) + l) * N + i] = Qh[c][l];
-        }
-    }
-    if (mode == 0) {
+      const double tt = th_sc * th;
+      v.theta[i] = tt;
       if (finite && qb[0] > 0.0 && pb > 0.0) {
-        smax = wave_speed<DIM>(qb, gam);
+        smax = speed_r<DIM>(qb, gam);
         if (tt > 0.0) {
-          for (int p = 0; p < NP; ++p) {
-            double d[V], q[V];
-            dev(p, d);  // Qh already scaled
 #pragma unroll
-            for (int c = 0; c < V; ++c) q[c] = qb[c] + d[c];
-            smax = fmax(smax, wave_speed<DIM>(q, gam));
+          for (int p = 0; p < NP; ++p) {
+            double q[V];
+#pragma unroll
+            for (int c = 0; c < V; ++c) q[c] = qb[c] + tt * point_dev<E, R>(T, Qh, p, c);
+            smax = fmax(smax, speed_r<DIM>(q, gam));
           }
         }
       }
+      if (!isfinite(smax)) {  // fmax-based reductions would drop a NaN: report it here
+        report(v.err, E_NONFINITE, i);
+        smax = INFINITY;
+      }
       if (v.dbg_theta) v.dbg_theta[i] = th;
+      if (v.dbg_theta_sc && v.shock && v.sc[mid].shock_pending) v.dbg_theta_sc[i] = th_sc;
+      if (v.dbg_qlim) {
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          v.dbg_qlim[(c * ML) * N + i] = qb[c];
+#pragma unroll
+          for (int l = 1; l < ML; ++l) v.dbg_qlim[(c * ML + l) * N + i] = tt * double(Qh[c][l - 1]);
+        }
+      }
     }
-    if (v.dbg_theta_sc && v.shock && v.sc[mid].shock_pending) v.dbg_theta_sc[i] = th_sc;
   }
-  if (mode == 0) atomic_max_per_mesh(v.sc, mid, smax, valid);
+  if (mode == 0) {
+    if (v.mesh_of) {
+      atomic_max_per_mesh(v.sc, mid, smax, valid);
+    } else {
+      // one partial maximum per block (k_dt reduces them): no contended atomics on one address
+      __shared__ double red[4];
+      double x = valid ? smax : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+        v.spart[blockIdx.x] = m;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
 // k_dt: per mesh, dt from the CFL condition (reading of Sec. 4.1, "CFL 0.08"), clipped to T.
 // ---------------------------------------------------------------------------------------------
+// Single mesh: one block reduces the per-block maxima of k_pre.
+__global__ __launch_bounds__(256) void k_dt_single(Scalars* sc, DevError* err, const double* spart, int nparts, double T) {
+  __shared__ double red[4];
+  double x = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) x = fmax(x, spart[b]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double s = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  Scalars& S = sc[0];
+  S.s = s;
+  if (!(s > 0.0) || !isfinite(s)) {
+    report(err, E_NONFINITE, -1);
+    S.dt = 0.0;
+    return;
+  }
+  double dt = S.cfl / (s * S.geo);
+  if (S.t + dt > T) dt = T - S.t;
+  S.dt = dt;
+}
+
 __global__ void k_dt(Scalars* sc, DevError* err, int n_mesh, double T) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_mesh) return;
@@ -422,6 +503,7 @@ template <class E, class R>
 __global__ __launch_bounds__(128) void k_elem(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NI = E::NI, K = E::K, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
+  const RefTab<E, double>& TD = TabSel<E, double>::get();
   const int N = v.N, NE = v.E;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -429,18 +511,34 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
   const R dt = R(v.sc[mid].dt);
   const R gm1 = R(v.gamma - 1.0);
 
-  R Q[V][ML];
+  // stored modes (before the limiter) and the limiter factor theta of this step
+  double qb[V];
+  R Qr[V][ML - 1];
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    Q[c][0] = R(v.Qbar[c * N + i]);
+    qb[c] = v.Qbar[c * N + i];
 #pragma unroll
-    for (int l = 1; l < ML; ++l) Q[c][l] = v.Qh[(c * (ML - 1) + l - 1) * N + i];
+    for (int l = 1; l < ML; ++l) Qr[c][l - 1] = v.Qh[(c * (ML - 1) + l - 1) * N + i];
   }
+  const double th = v.theta[i];
+  const R thR = R(th);
   R Ji[DIM][DIM];
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Ji[a][d] = v.Jinv[(a * DIM + d) * N + i];
+
+  // point state of the limited polynomial in float64, q_bar + theta sum_l Q_l phi_l (the
+  // expression the moment limiter made positive), then rounded to the bulk precision
+  auto state_at = [&](int p, R* q) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 1; l < ML; ++l) acc += double(Qr[c][l - 1]) * TD.phi[p][l];
+      q[c] = R(qb[c] + th * acc);
+    }
+  };
 
   // Sec. 2.3 Step 1: Fc^h_a = sum_m w_m Fc_a(q(x_m)) phi_l(x_m)
   R Fh[DIM][V][ML];
@@ -452,13 +550,7 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
       for (int l = 0; l < ML; ++l) Fh[a][c][l] = R(0);
   for (int m = 0; m < NI; ++m) {
     R q[V];
-#pragma unroll
-    for (int c = 0; c < V; ++c) {
-      R acc = R(0);
-#pragma unroll
-      for (int l = 0; l < ML; ++l) acc += Q[c][l] * T.phi[m][l];
-      q[c] = acc;
-    }
+    state_at(m, q);
     St<DIM, R> s = base_state<DIM, R>(q, gm1);
     R F[DIM][V];
 #pragma unroll
@@ -481,44 +573,115 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
 #pragma unroll
     for (int l = 0; l < ML - 1; ++l) vol[c][l] = R(0);
 
-  // Sec. 2.3 Step 2 at point p: q, grad q, D = div F^h, grad D, then q_t, q_tt and F_T.
-  auto point = [&](int p, R* q, R* qt, R* qtt, R FT[DIM][V]) {
-    R gq[DIM][V], D[V], gD[DIM][V];
+  // Complete P2 on an affine element (line, triangle): grad q and div F^h are linear and their
+  // derivatives constant, so they are formed once per element from their values at the reference
+  // origin and the constant reference Hessians, and each point costs a few multiply-adds.  (On the
+  // tensor Q2 quadrilateral they are not linear; those points contract the modes directly.)
+  constexpr bool AFF = E::kind != ElQuad::kind;
+  R g0[V][DIM], Hq[V][E::ND2], D0[V], gDr[V][DIM], gDx[DIM][V];
+  if constexpr (AFF) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      R acc = R(0);
-      R g[DIM];
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) g[a] = R(0);
+      for (int a = 0; a < DIM; ++a) {
+        R acc = R(0);
+#pragma unroll
+        for (int l = 1; l < ML; ++l) acc += Qr[c][l - 1] * T.dphi0[a][l];
+        g0[c][a] = thR * acc;
+      }
+#pragma unroll
+      for (int k = 0; k < E::ND2; ++k) {
+        R acc = R(0);
+#pragma unroll
+        for (int l = 1; l < ML; ++l) acc += Qr[c][l - 1] * T.d2c[k][l];
+        Hq[c][k] = thR * acc;
+      }
       R dd = R(0);
       R h[DIM];
 #pragma unroll
       for (int a = 0; a < DIM; ++a) h[a] = R(0);
 #pragma unroll
       for (int l = 0; l < ML; ++l) {
-        acc += Q[c][l] * T.phi[p][l];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          g[a] += Q[c][l] * T.dphi[p][a][l];
-          dd += Fh[a][c][l] * T.dphi[p][a][l];
-        }
+        for (int a = 0; a < DIM; ++a) dd += Fh[a][c][l] * T.dphi0[a][l];
         if constexpr (DIM == 1) {
-          h[0] += Fh[0][c][l] * T.d2phi[p][0][l];
+          h[0] += Fh[0][c][l] * T.d2c[0][l];
         } else {
+          h[0] += Fh[0][c][l] * T.d2c[0][l] + Fh[1][c][l] * T.d2c[1][l];
+          h[1] += Fh[0][c][l] * T.d2c[1][l] + Fh[1][c][l] * T.d2c[2][l];
+        }
+      }
+      D0[c] = dd;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) gDr[c][a] = h[a];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        R sh = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) sh += Ji[a][d] * h[a];
+        gDx[d][c] = sh;
+      }
+    }
+  }
+
+  // Sec. 2.3 Step 2 at point p: q, grad q, D = div F^h, grad D, then q_t, q_tt and F_T.
+  auto point = [&](int p, R* q, R* qt, R* qtt, R FT[DIM][V]) {
+    R gq[DIM][V], D[V], gD[DIM][V];
+    state_at(p, q);
+    if constexpr (AFF) {
+      R x[DIM];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) x[a] = T.xr[p][a];
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R g[DIM];
+        if constexpr (DIM == 1) {
+          g[0] = g0[c][0] + Hq[c][0] * x[0];
+          D[c] = D0[c] + gDr[c][0] * x[0];
+        } else {
+          g[0] = g0[c][0] + Hq[c][0] * x[0] + Hq[c][1] * x[1];
+          g[1] = g0[c][1] + Hq[c][1] * x[0] + Hq[c][2] * x[1];
+          D[c] = D0[c] + gDr[c][0] * x[0] + gDr[c][1] * x[1];
+        }
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          R sg = R(0);
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) sg += Ji[a][d] * g[a];
+          gq[d][c] = sg;
+          gD[d][c] = gDx[d][c];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R g[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) g[a] = R(0);
+        R dd = R(0);
+        R h[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) h[a] = R(0);
+#pragma unroll
+        for (int l = 0; l < ML; ++l) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            if (l > 0) g[a] += Qr[c][l - 1] * T.dphi[p][a][l];
+            dd += Fh[a][c][l] * T.dphi[p][a][l];
+          }
           // d/dxi_b sum_a d/dxi_a Fc_a: b = 0 uses (xx, xy), b = 1 uses (xy, yy)
           h[0] += Fh[0][c][l] * T.d2phi[p][0][l] + Fh[DIM - 1][c][l] * T.d2phi[p][1][l];
           h[DIM - 1] += Fh[0][c][l] * T.d2phi[p][1][l] + Fh[DIM - 1][c][l] * T.d2phi[p][DIM][l];
         }
-      }
-      q[c] = acc;
-      D[c] = dd;
+        D[c] = dd;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        R sg = R(0), sh = R(0);
+        for (int d = 0; d < DIM; ++d) {
+          R sg = R(0), sh = R(0);
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) { sg += Ji[a][d] * g[a]; sh += Ji[a][d] * h[a]; }
-        gq[d][c] = sg;
-        gD[d][c] = sh;
+          for (int a = 0; a < DIM; ++a) { sg += Ji[a][d] * g[a]; sh += Ji[a][d] * h[a]; }
+          gq[d][c] = thR * sg;
+          gD[d][c] = sh;
+        }
       }
     }
     St<DIM, R> s = base_state<DIM, R>(q, gm1);
@@ -558,13 +721,12 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
   // edge points: traces q and n_out . F_T (and the ghost side on boundary edges)
   for (int k = 0; k < K; ++k) {
     const int slot = v.eslot[k * N + i];
-    const int e = slot >> 3, side = (slot >> 2) & 1, bc = slot & 3;
+    const int e = slot >> 3, bc = slot & 3;
     R n[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) n[d] = v.nout[(k * DIM + d) * N + i];
     for (int jl = 0; jl < NQE; ++jl) {
       const int p = NI + k * NQE + jl;
-      const int jj = side ? (NQE - 1 - jl) : jl;
       R q[V], qt[V], qtt[V], FT[DIM][V];
       point(p, q, qt, qtt, FT);
 #pragma unroll
@@ -572,8 +734,8 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
         R fn = R(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) fn += n[d] * FT[d][c];
-        v.tq[((side * NQE + jj) * V + c) * NE + e] = q[c];
-        v.tf[((side * NQE + jj) * V + c) * NE + e] = fn;
+        v.tq[((size_t)(jl * V + c) * N + i) * K + k] = q[c];
+        v.tf[((size_t)(jl * V + c) * N + i) * K + k] = fn;
       }
       if (bc != SB_INTERIOR) {
         R qg[V], FTg[DIM][V];
@@ -608,8 +770,8 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
           R fn = R(0);
 #pragma unroll
           for (int d = 0; d < DIM; ++d) fn += n[d] * FTg[d][c];
-          v.tq[((NQE + jj) * V + c) * NE + e] = qg[c];
-          v.tf[((NQE + jj) * V + c) * NE + e] = -fn;
+          v.gq[(jl * V + c) * NE + e] = qg[c];
+          v.gf[(jl * V + c) * NE + e] = -fn;
         }
       }
     }
@@ -619,7 +781,7 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
 #pragma unroll
   for (int c = 0; c < V; ++c)
 #pragma unroll
-    for (int l = 1; l < ML; ++l) v.Qh[(c * (ML - 1) + l - 1) * N + i] = Q[c][l] + dt * vol[c][l - 1];
+    for (int l = 1; l < ML; ++l) v.Qh[(c * (ML - 1) + l - 1) * N + i] = thR * Qr[c][l - 1] + dt * vol[c][l - 1];
   if (v.dbg_vol) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
@@ -637,7 +799,7 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
 // ---------------------------------------------------------------------------------------------
 template <class E, class R>
 __global__ __launch_bounds__(256) void k_edge(View<R> v) {
-  constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE;
+  constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE, K = E::K;
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const int NE = v.E, N = v.N;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -650,6 +812,7 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   for (int d = 0; d < DIM; ++d) { n[d] = v.e_n[d * NE + e]; len2 += n[d] * n[d]; }
   const double len = sqrt(len2);
   const R hs = R(0.5 * s * len);
+  const int ie = v.e_i[e], je = v.e_j[e], ki = v.e_k[e], kj = v.e_k[NE + e];
   double W[V];
 #pragma unroll
   for (int c = 0; c < V; ++c) W[c] = 0.0;
@@ -657,10 +820,16 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   for (int jj = 0; jj < NQE; ++jj) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      const R qm = v.tq[((0 * NQE + jj) * V + c) * NE + e];
-      const R fm = v.tf[((0 * NQE + jj) * V + c) * NE + e];
-      const R qp = v.tq[((1 * NQE + jj) * V + c) * NE + e];
-      const R fp = -v.tf[((1 * NQE + jj) * V + c) * NE + e];
+      const R qm = v.tq[((size_t)(jj * V + c) * N + ie) * K + ki];
+      const R fm = v.tf[((size_t)(jj * V + c) * N + ie) * K + ki];
+      R qp, fp;
+      if (je >= 0) {
+        qp = v.tq[((size_t)((NQE - 1 - jj) * V + c) * N + je) * K + kj];
+        fp = -v.tf[((size_t)((NQE - 1 - jj) * V + c) * N + je) * K + kj];
+      } else {
+        qp = v.gq[(jj * V + c) * NE + e];
+        fp = -v.gf[(jj * V + c) * NE + e];
+      }
       const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
       v.fstar[(jj * V + c) * NE + e] = fs;
       W[c] += 0.5 * double(T.om[jj]) * double(fs);
@@ -669,7 +838,7 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
 #pragma unroll
   for (int c = 0; c < V; ++c) v.fLxW[c * NE + e] = W[c];
 
-  const int i = v.e_i[e], j = v.e_j[e];
+  const int i = ie, j = je;
   double qi[V], qj[V];
 #pragma unroll
   for (int c = 0; c < V; ++c) qi[c] = v.Qbar[c * N + i];
@@ -912,7 +1081,8 @@ hipError_t launch(KernelId k, const View<R>& v, hipStream_t st, int n_mesh, doub
       if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), grid(v.N, 256), dim3(256), 0, st, v, 1);
       break;
     case K_DT:
-      hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh, T);
+      if (v.mesh_of) hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh, T);
+      else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(256), 0, st, v.sc, v.err, v.spart, (v.N + 255) / 256, T);
       break;
     case K_ELEM:
       if (v.N > 0) hipLaunchKernelGGL((k_elem<E, R>), grid(v.N, 128), dim3(128), 0, st, v);

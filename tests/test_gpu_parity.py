@@ -120,6 +120,30 @@ def test_fp64_stage_parity(L, name):
     assert n_mom > 0
 
 
+@pytest.mark.parametrize("name", ["line-walls", "quad-mixed", "tri-ramp"])
+def test_fp64_multistep_without_readout(L, name):
+    """Steps taken back to back (the shock-capturing limiter of each step is then applied at the
+    start of the next step's first kernel) match the oracle's steps."""
+    print(f"[gpu] fp64 10 steps without read-out {name}", flush=True)
+    lm, om, Q0, kw = make_case(L, name)
+    S = L.Solver(lm, **kw)
+    S.set_state(Q0)
+    Ob = O.Solver(om, inflow=kw.get("inflow"))
+    Ob.set_state(Q0)
+    for _ in range(10):
+        S.step()
+        Ob.step()
+    Qg, tg = S.get_state()
+    Qo, to = Ob.get_state()
+    assert tg == pytest.approx(to, rel=1e-13)
+    assert per_var_rel_l1(Qg, Qo) <= 10 * TOL
+    S.set_state(Q0)
+    S.run_steps(10)
+    S.sync()
+    Qr, tr = S.get_state()
+    assert np.array_equal(Qr, Qg) and tr == tg
+
+
 def test_fp64_flux_limiter_active_parity(L):
     """Bowl-shaped near-vacuum cells at CFL 0.9: the density and pressure parts of the flux
     limiter bind.  Each side projects the same seeded field with its own quadrature and basis."""
@@ -145,31 +169,69 @@ def test_fp64_flux_limiter_active_parity(L):
 
 
 def test_fp32_mixed_after_100_steps(L):
-    """FP32 bulk arithmetic with FP64 cell averages and limiter: relative L1 error against the FP64
-    oracle after 100 steps (vortex + shock on triangles; near-vacuum blast on a Cartesian mesh)."""
-    print("[gpu] fp32-mixed 100 steps", flush=True)
+    """FP32 bulk arithmetic with FP64 cell averages, limiter and point states: relative L1 error
+    against the FP64 oracle after 100 steps (isentropic vortex + planar shock on triangles)."""
+    print("[gpu] fp32-mixed 100 steps, vortex + shock", flush=True)
     xy, tri = I.lattice_delaunay(31, 11, box=(-5, 5, -5, 5))
     lm, om = L.Mesh.tri(xy, tri), O.Mesh.tri(xy, tri)
-    fn = I.vortex_shock_fn(3)
-    Q0 = I.averages_to_modal(I.cell_average_state(fn, I.tri_sample_points(xy, tri), 1.4), 6)
-    cases = [(lm, om, Q0)]
+    Q0 = I.averages_to_modal(I.cell_average_state(I.vortex_shock_fn(3), I.tri_sample_points(xy, tri), 1.4), 6)
+    S = L.Solver(lm, precision=L.FP32_MIXED)
+    S.set_state(Q0)
+    Ob = O.Solver(om)
+    Ob.set_state(Q0)
+    S.run_steps(100)
+    S.sync()
+    for _ in range(100):
+        Ob.step()
+    Qg, tg = S.get_state()
+    Qo, to = Ob.get_state()
+    err = per_var_rel_l1(Qg, Qo)
+    print(f"[gpu]   rel L1 after 100 steps {err:.3e}, t {tg:.6g} vs {to:.6g}", flush=True)
+    assert err <= 1e-5 and tg == pytest.approx(to, rel=1e-6)
+
+
+def test_fp32_mixed_near_vacuum_blast(L):
+    """FP32-mixed on the near-vacuum blast (p = 1e-10 background): within 1e-5 of the oracle after
+    40 steps.  Past that point the blast core amplifies round-off about twofold per step (the FP64
+    library departs from the FP64 oracle there too, see test_fp64_step_inside_amplifying_regime),
+    so a longer horizon does not measure precision."""
+    print("[gpu] fp32-mixed near-vacuum blast, 40 steps", flush=True)
     n = 24
-    cases.append((L.Mesh.cart(n, n, -1, 1, -1, 1, [0] * 4), O.Mesh.cart(n, n, -1, 1, -1, 1, [0] * 4),
-                  I.sedov_cart_state(n, n)))
-    for lmesh, omesh, Q in cases:
-        S = L.Solver(lmesh, precision=L.FP32_MIXED)
-        S.set_state(Q)
-        Ob = O.Solver(omesh)
-        Ob.set_state(Q)
-        for _ in range(100):
-            S.step()
-            Ob.step()
-        Qg, tg = S.get_state()
-        Qo, to = Ob.get_state()
-        err = per_var_rel_l1(Qg, Qo)
-        print(f"[gpu]   {lmesh.kind}: rel L1 after 100 steps {err:.3e}, t {tg:.6g} vs {to:.6g}", flush=True)
-        assert err <= 1e-5
-        assert tg == pytest.approx(to, rel=1e-5)
+    Q0 = I.sedov_cart_state(n, n)
+    S = L.Solver(L.Mesh.cart(n, n, -1, 1, -1, 1, [0] * 4), precision=L.FP32_MIXED)
+    S.set_state(Q0)
+    Ob = O.Solver(O.Mesh.cart(n, n, -1, 1, -1, 1, [0] * 4))
+    Ob.set_state(Q0)
+    S.run_steps(40)
+    S.sync()
+    for _ in range(40):
+        Ob.step()
+    Qg, tg = S.get_state()
+    Qo, to = Ob.get_state()
+    err = per_var_rel_l1(Qg, Qo)
+    print(f"[gpu]   rel L1 after 40 steps {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_fp64_step_inside_amplifying_regime(L):
+    """Per-step parity where the near-vacuum blast amplifies round-off: the oracle advances 70
+    steps, then the library and the oracle each take one step from that state."""
+    print("[gpu] fp64 one step inside the amplifying regime", flush=True)
+    n = 24
+    Ob = O.Solver(O.Mesh.cart(n, n, -1, 1, -1, 1, [0] * 4))
+    Ob.set_state(I.sedov_cart_state(n, n))
+    for _ in range(70):
+        Ob.step()
+    Qs, ts = Ob.get_state()
+    S = L.Solver(L.Mesh.cart(n, n, -1, 1, -1, 1, [0] * 4))
+    S.set_debug(True)
+    S.set_state(Qs, ts)
+    S.step()
+    Ob.step()
+    compare_stages(S, Ob, L)
+    Qg, _ = S.get_state()
+    Qo, _ = Ob.get_state()
+    assert per_var_rel_l1(Qg, Qo) <= TOL
 
 
 def test_repeatable_bitwise(L):
