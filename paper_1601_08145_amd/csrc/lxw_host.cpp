@@ -509,21 +509,14 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   if ((st = upload(S, &v.e_j, M.e_j))) return st;
   if ((st = upload(S, &v.e_bc, M.e_bc))) return st;
   if ((st = upload(S, &v.e_n, en))) return st;
-  {
-    std::vector<int> ek(M.e_ki);
-    ek.insert(ek.end(), M.e_kj.begin(), M.e_kj.end());
-    if ((st = upload(S, &v.e_k, ek))) return st;
-  }
   v.mesh_of = nullptr;
   v.e_mesh = nullptr;
   if ((st = S->alloc(&v.Qbar, (size_t)V * N))) return st;
   if ((st = S->alloc(&v.Qh, (size_t)V * (ML - 1) * N))) return st;
   if ((st = S->alloc(&v.theta, (size_t)N))) return st;
-  if ((st = S->alloc(&v.spart, (size_t)(N + 255) / 256 + 1))) return st;
-  if ((st = S->alloc(&v.tq, (size_t)K * NQE * V * N))) return st;
-  if ((st = S->alloc(&v.tf, (size_t)K * NQE * V * N))) return st;
-  if ((st = S->alloc(&v.gq, (size_t)NQE * V * E))) return st;
-  if ((st = S->alloc(&v.gf, (size_t)NQE * V * E))) return st;
+  if ((st = S->alloc(&v.spart, (size_t)((N + 255) / 256 + 7) / 8 * 8))) return st;
+  if ((st = S->alloc(&v.tq, (size_t)2 * NQE * V * E))) return st;
+  if ((st = S->alloc(&v.tf, (size_t)2 * NQE * V * E))) return st;
   if ((st = S->alloc(&v.fstar, (size_t)NQE * V * E))) return st;
   if ((st = S->alloc(&v.fLxW, (size_t)V * E))) return st;
   if ((st = S->alloc(&v.fLxF, (size_t)V * E))) return st;

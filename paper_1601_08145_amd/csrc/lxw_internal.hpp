@@ -80,7 +80,6 @@ struct View {
   const int* e_i;         // [E] element i_e (n_e points out of it)
   const int* e_j;         // [E] element j_e or -1
   const int* e_bc;        // [E] boundary code (SB_*)
-  const int* e_k;         // [2][E] local edge index of the edge in i_e (side 0) and j_e (side 1)
   const double* e_n;      // [DIM][E] n_e, |n_e| = edge length
   const int* e_mesh;      // [E] mesh index or null
   // state
@@ -88,10 +87,9 @@ struct View {
   R* Qh;                  // [V][ML-1][N] modes 2..ML
   // work
   double* theta;          // [N] limiter factor of the step (shock x moment), applied by k_elem
-  R* tq;                  // [NQE][V][N][K] traces q at the element's own edge points
-  R* tf;                  // [NQE][V][N][K] traces n_out . F_T at the element's own edge points
-  R* gq;                  // [NQE][V][E] ghost-state q on boundary edges (edge point order of i_e)
-  R* gf;                  // [NQE][V][E] ghost-side n_out . F_T on boundary edges (n_out = -n_e)
+  R* tq;                  // [2][NQE][V][E] traces q (side 0 = i_e, side 1 = j_e or the ghost state),
+                          //   points in i_e's order along the edge
+  R* tf;                  // [2][NQE][V][E] traces n_out . F_T of that side
   R* fstar;               // [NQE][V][E] F*_T . n_e at the edge points
   double* fLxW;           // [V][E]
   double* fLxF;           // [V][E]

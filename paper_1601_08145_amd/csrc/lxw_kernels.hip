@@ -211,6 +211,16 @@ __device__ __forceinline__ void inflow_state(const double* inflow, T* out) {
 template <class R>
 __device__ __forceinline__ int mesh_id(const int* mesh_of, int i) { return mesh_of ? mesh_of[i] : 0; }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Elements (and
+// edges, numbered in element order) are in space-filling-curve order, so neighbouring work items
+// share data; give every XCD one contiguous range of blocks (the grid is padded to a multiple of 8
+// blocks) so that shared lines are reused within one L2.
+__device__ __forceinline__ int xcd_item() {
+  const int nb = (int)gridDim.x;  // multiple of 8
+  const int b = (int)blockIdx.x;
+  return ((b & 7) * (nb >> 3) + (b >> 3)) * (int)blockDim.x + (int)threadIdx.x;
+}
+
 // Per-mesh maximum of a non-negative double: wavefront reduction when the wavefront lies in one
 // mesh, else one atomic per lane.
 __device__ __forceinline__ void atomic_max_per_mesh(Scalars* sc, int mid, double val, bool valid) {
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
   const RefTab<E, double>& T = TabSel<E, double>::get();
   const int N = v.N;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_item();
   const bool valid = i < N;
   const double gam = v.gamma, eps0 = v.eps0;
   double smax = 0.0;
@@ -505,7 +515,7 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const RefTab<E, double>& TD = TabSel<E, double>::get();
   const int N = v.N, NE = v.E;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   const R dt = R(v.sc[mid].dt);
@@ -721,12 +731,13 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
   // edge points: traces q and n_out . F_T (and the ghost side on boundary edges)
   for (int k = 0; k < K; ++k) {
     const int slot = v.eslot[k * N + i];
-    const int e = slot >> 3, bc = slot & 3;
+    const int e = slot >> 3, side = (slot >> 2) & 1, bc = slot & 3;
     R n[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) n[d] = v.nout[(k * DIM + d) * N + i];
     for (int jl = 0; jl < NQE; ++jl) {
       const int p = NI + k * NQE + jl;
+      const int jj = side ? (NQE - 1 - jl) : jl;  // point order of i_e along the edge
       R q[V], qt[V], qtt[V], FT[DIM][V];
       point(p, q, qt, qtt, FT);
 #pragma unroll
@@ -734,8 +745,8 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
         R fn = R(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) fn += n[d] * FT[d][c];
-        v.tq[((size_t)(jl * V + c) * N + i) * K + k] = q[c];
-        v.tf[((size_t)(jl * V + c) * N + i) * K + k] = fn;
+        v.tq[((size_t)(side * NQE + jj) * V + c) * NE + e] = q[c];
+        v.tf[((size_t)(side * NQE + jj) * V + c) * NE + e] = fn;
       }
       if (bc != SB_INTERIOR) {
         R qg[V], FTg[DIM][V];
@@ -770,8 +781,8 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
           R fn = R(0);
 #pragma unroll
           for (int d = 0; d < DIM; ++d) fn += n[d] * FTg[d][c];
-          v.gq[(jl * V + c) * NE + e] = qg[c];
-          v.gf[(jl * V + c) * NE + e] = -fn;
+          v.tq[((size_t)(NQE + jj) * V + c) * NE + e] = qg[c];
+          v.tf[((size_t)(NQE + jj) * V + c) * NE + e] = -fn;
         }
       }
     }
@@ -799,10 +810,10 @@ __global__ __launch_bounds__(128) void k_elem(View<R> v) {
 // ---------------------------------------------------------------------------------------------
 template <class E, class R>
 __global__ __launch_bounds__(256) void k_edge(View<R> v) {
-  constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE, K = E::K;
+  constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const int NE = v.E, N = v.N;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = xcd_item();
   if (e >= NE) return;
   const int mid = v.e_mesh ? v.e_mesh[e] : 0;
   const double s = v.sc[mid].s;
@@ -812,7 +823,7 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   for (int d = 0; d < DIM; ++d) { n[d] = v.e_n[d * NE + e]; len2 += n[d] * n[d]; }
   const double len = sqrt(len2);
   const R hs = R(0.5 * s * len);
-  const int ie = v.e_i[e], je = v.e_j[e], ki = v.e_k[e], kj = v.e_k[NE + e];
+  const int ie = v.e_i[e], je = v.e_j[e];
   double W[V];
 #pragma unroll
   for (int c = 0; c < V; ++c) W[c] = 0.0;
@@ -820,16 +831,10 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   for (int jj = 0; jj < NQE; ++jj) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      const R qm = v.tq[((size_t)(jj * V + c) * N + ie) * K + ki];
-      const R fm = v.tf[((size_t)(jj * V + c) * N + ie) * K + ki];
-      R qp, fp;
-      if (je >= 0) {
-        qp = v.tq[((size_t)((NQE - 1 - jj) * V + c) * N + je) * K + kj];
-        fp = -v.tf[((size_t)((NQE - 1 - jj) * V + c) * N + je) * K + kj];
-      } else {
-        qp = v.gq[(jj * V + c) * NE + e];
-        fp = -v.gf[(jj * V + c) * NE + e];
-      }
+      const R qm = v.tq[((size_t)(0 * NQE + jj) * V + c) * NE + e];
+      const R fm = v.tf[((size_t)(0 * NQE + jj) * V + c) * NE + e];
+      const R qp = v.tq[((size_t)(1 * NQE + jj) * V + c) * NE + e];
+      const R fp = -v.tf[((size_t)(1 * NQE + jj) * V + c) * NE + e];
       const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
       v.fstar[(jj * V + c) * NE + e] = fs;
       W[c] += 0.5 * double(T.om[jj]) * double(fs);
@@ -925,7 +930,7 @@ template <class E, class R>
 __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   constexpr int V = E::V, DIM = E::DIM, K = E::K;
   const int N = v.N, NE = v.E;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   const double dt = v.sc[mid].dt;
@@ -1008,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, K = E::K, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const int N = v.N, NE = v.E;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   const double dt = v.sc[mid].dt;
@@ -1073,28 +1078,30 @@ __global__ void k_final(Scalars* sc, int n_mesh, int shock, int mode) {
 template <class E, class R>
 hipError_t launch(KernelId k, const View<R>& v, hipStream_t st, int n_mesh, double T, int mode) {
   auto grid = [](int n, int b) { return dim3((unsigned)((n + b - 1) / b)); };
+  // element and edge kernels: grid padded to a multiple of 8 blocks (XCD-contiguous block order)
+  auto egrid = [](int n, int b) { return dim3((unsigned)(((n + b - 1) / b + 7) / 8 * 8)); };
   switch (k) {
     case K_PRE:
-      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), grid(v.N, 256), dim3(256), 0, st, v, 0);
+      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, 256), dim3(256), 0, st, v, 0);
       break;
     case K_SHOCK:
-      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), grid(v.N, 256), dim3(256), 0, st, v, 1);
+      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, 256), dim3(256), 0, st, v, 1);
       break;
     case K_DT:
       if (v.mesh_of) hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh, T);
-      else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(256), 0, st, v.sc, v.err, v.spart, (v.N + 255) / 256, T);
+      else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(256), 0, st, v.sc, v.err, v.spart, ((v.N + 255) / 256 + 7) / 8 * 8, T);
       break;
     case K_ELEM:
-      if (v.N > 0) hipLaunchKernelGGL((k_elem<E, R>), grid(v.N, 128), dim3(128), 0, st, v);
+      if (v.N > 0) hipLaunchKernelGGL((k_elem<E, R>), egrid(v.N, 128), dim3(128), 0, st, v);
       break;
     case K_EDGE:
-      if (v.E > 0) hipLaunchKernelGGL((k_edge<E, R>), grid(v.E, 256), dim3(256), 0, st, v);
+      if (v.E > 0) hipLaunchKernelGGL((k_edge<E, R>), egrid(v.E, 256), dim3(256), 0, st, v);
       break;
     case K_FLIM:
-      if (v.N > 0) hipLaunchKernelGGL((k_flim<E, R>), grid(v.N, 256), dim3(256), 0, st, v);
+      if (v.N > 0) hipLaunchKernelGGL((k_flim<E, R>), egrid(v.N, 256), dim3(256), 0, st, v);
       break;
     case K_UPDATE:
-      if (v.N > 0) hipLaunchKernelGGL((k_update<E, R>), grid(v.N, 256), dim3(256), 0, st, v);
+      if (v.N > 0) hipLaunchKernelGGL((k_update<E, R>), egrid(v.N, 256), dim3(256), 0, st, v);
       break;
     case K_FINAL:
       hipLaunchKernelGGL(k_final, grid(n_mesh, 64), dim3(64), 0, st, v.sc, n_mesh, v.shock, mode);
