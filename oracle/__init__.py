@@ -59,6 +59,7 @@ def lib():
             "ora_solver_new": (P, [P, d, d, d, d, i, dp]),
             "ora_solver_free": (None, [P]),
             "ora_force_theta": (None, [P, d]),
+            "ora_set_shock_mask": (None, [P, P]),
             "ora_set_state": (None, [P, dp, d]),
             "ora_get_state": (None, [P, dp, dp]),
             "ora_step": (i, [P, d, dp]),
@@ -193,6 +194,16 @@ class Solver:
         if getattr(self, "h", None) and _lib is not None:
             _lib.ora_solver_free(self.h)
             self.h = None
+
+    def set_shock_mask(self, mask):
+        """Cells on which the shock-capturing limiter may act (None: all), for the learned form."""
+        if mask is None:
+            lib().ora_set_shock_mask(self.h, None)
+            return
+        m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+        assert m.shape == (self.mesh.N,)
+        self._mask = m
+        lib().ora_set_shock_mask(self.h, m.ctypes.data_as(ctypes.c_void_p))
 
     def force_theta(self, th):
         """Test hook: replace every edge blending factor Lambda_e by th (th < 0 switches it off)."""

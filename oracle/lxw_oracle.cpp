@@ -490,6 +490,9 @@ struct Solver {
   std::vector<double> theta_mom, theta_sc, Qlim, Vol, Qupd;
   std::vector<double> fLxW_ik, fLxF_ik, Lam_ik, c_ik, Lam_e_ik;  // per (element, local edge)
   std::vector<double> qderiv;  // q_t and q_tt at the interior points: N x NI x 2 x V
+  // Cells the shock-capturing limiter may act on (empty: all).  A learned troubled-cell
+  // indicator replaces only the detection of that limiter; this mask carries its decisions.
+  std::vector<unsigned char> shock_mask;
   int err_elem = -1;
   std::string err;
 };
@@ -1072,7 +1075,8 @@ static int step(Solver& S, double T) {
   if (S.P.shock) {
     std::vector<double> Qs = Qnew;
 #pragma omp parallel for schedule(static)
-    for (int i = 0; i < N; ++i) S.theta_sc[i] = shock_limit(S, Qnew, i, &Qs[i * QS]);
+    for (int i = 0; i < N; ++i)
+      if (S.shock_mask.empty() || S.shock_mask[i]) S.theta_sc[i] = shock_limit(S, Qnew, i, &Qs[i * QS]);
     Qnew.swap(Qs);
   }
   S.Q.swap(Qnew);
@@ -1141,6 +1145,11 @@ void* ora_solver_new(void* m, double gamma, double cfl, double eps0, double alph
 }
 void ora_solver_free(void* s) { delete (Solver*)s; }
 void ora_force_theta(void* s, double th) { ((Solver*)s)->P.force_theta = th; }
+void ora_set_shock_mask(void* s, const unsigned char* mask) {
+  Solver* S = (Solver*)s;
+  if (mask) S->shock_mask.assign(mask, mask + S->M->N);
+  else S->shock_mask.clear();
+}
 void ora_set_state(void* s, const double* Q, double t) {
   Solver* S = (Solver*)s;
   std::memcpy(S->Q.data(), Q, S->Q.size() * sizeof(double));
