@@ -79,6 +79,7 @@ enum { LXW_HOST_PTR = 0, LXW_DEVICE_PTR = 1 };
 
 typedef struct lxw_mesh lxw_mesh;
 typedef struct lxw_solver lxw_solver;
+typedef struct lxw_batch lxw_batch;
 
 typedef struct lxw_params {
   double gamma;      /* ratio of specific heats, Eq. (eos); > 1 */
@@ -180,8 +181,15 @@ typedef struct lxw_stats {
 lxw_status lxw_advance(lxw_solver* s, double T, int64_t max_steps, lxw_stats* out);
 
 /* Enqueues n_steps steps with no final time (dt from the CFL condition each step) on the
- * solver's stream and returns without waiting; errors are reported by lxw_sync.  For timing. */
+ * solver's stream and returns without waiting; errors are reported by lxw_sync.  Unless per-kernel
+ * timing or stage read-out is on, the steps are replays of one step captured in a HIP graph (on a
+ * stream the library creates; the replays go to the solver's stream).  Results are identical
+ * either way. */
 lxw_status lxw_run_steps(lxw_solver* s, int64_t n_steps);
+
+/* lxw_set_graph(s, 0) makes lxw_run_steps launch every kernel itself instead of replaying the
+ * captured graph; 1 (the default) restores graph replay. */
+lxw_status lxw_set_graph(lxw_solver* s, int32_t enable);
 
 /* Waits for the solver's stream and reports any device error. */
 lxw_status lxw_sync(lxw_solver* s);
@@ -206,12 +214,58 @@ enum {
   LXW_STAGE_C = 6, LXW_STAGE_LAME = 7, LXW_STAGE_QUPD = 8, LXW_STAGE_THETA_SC = 9, LXW_STAGE_SDT = 10
 };
 enum { LXW_K_PRE = 0, LXW_K_DT = 1, LXW_K_ELEM = 2, LXW_K_EDGE = 3, LXW_K_FLIM = 4, LXW_K_UPDATE = 5,
-       LXW_K_FINAL = 6, LXW_K_COUNT = 7 };
+       LXW_K_FINAL = 6, LXW_K_IND = 7, LXW_K_COUNT = 8 };
 
 lxw_status lxw_set_debug(lxw_solver* s, int32_t keep_stages);
 lxw_status lxw_debug_stage(lxw_solver* s, int32_t stage, double* out);
 lxw_status lxw_set_timing(lxw_solver* s, int32_t enable);
 lxw_status lxw_kernel_times(lxw_solver* s, double* ms /*[LXW_K_COUNT]*/, int64_t* launches /*[LXW_K_COUNT]*/);
+
+/* ---- Launch shapes and the autotuner --------------------------------------------------------
+ * Every element kernel runs one lane per element and the edge kernel one lane per edge, so the
+ * workgroup size block[k] of kernel k (indexed by LXW_K_*) is also its number of elements (edges)
+ * per workgroup.  LXW_K_PRE, LXW_K_ELEM, LXW_K_EDGE, LXW_K_FLIM and LXW_K_UPDATE accept 64, 128 or
+ * 256 (defaults 256, 128, 256, 256, 256); the entries of LXW_K_DT, LXW_K_FINAL and LXW_K_IND are
+ * ignored.
+ * Launch shapes change no result bit. */
+typedef struct lxw_tune {
+  int32_t block[LXW_K_COUNT];
+} lxw_tune;
+
+lxw_status lxw_get_tune(const lxw_solver* s, lxw_tune* out);
+/* LXW_ERR_ARG for a size other than 64, 128, 256 in a tunable entry. */
+lxw_status lxw_set_tune(lxw_solver* s, const lxw_tune* t);
+/* Times each allowed size of each tunable kernel on the solver's own mesh and current state (one
+ * warm-up step, then trial_steps timed steps per candidate, kernels tuned one after another),
+ * keeps the fastest per kernel, and restores the state, time and counters it found, so tuning does
+ * not change the trajectory.  Synchronous; the chosen shapes also go to *out (nullable).  A device
+ * error during the trials is returned after the state has been restored. */
+lxw_status lxw_autotune(lxw_solver* s, int32_t trial_steps, lxw_tune* out);
+
+/* ---- Batched form -------------------------------------------------------------------------
+ * n independent meshes of one kind advanced together: each kernel of a step is one launch over
+ * every element (edge) of every mesh, and a step is replayed from a HIP graph.  Each mesh keeps its
+ * own wave speed s, time step dt (the CFL condition of Sec. 4.1 per mesh) and time t; the scheme
+ * per mesh is exactly that of a single-mesh solver, bit for bit (same kernels, same arithmetic).
+ * Parameters are shared.  meshes[i] must outlive the batch.  Errors: LXW_ERR_ARG for n < 1, a null
+ * mesh, meshes of different kinds or more than 2^28 elements or edges in total; as
+ * lxw_solver_create otherwise. */
+lxw_status lxw_batch_create(int32_t n, const lxw_mesh* const* meshes, const lxw_params* p, void* stream,
+                            lxw_batch** out);
+lxw_status lxw_batch_destroy(lxw_batch* b);
+/* State of mesh i, layout and checks as lxw_set_state / lxw_get_state; time t0 for that mesh.
+ * Synchronous. */
+lxw_status lxw_batch_set_state(lxw_batch* b, int32_t i, const double* Q, double t0, int32_t flags);
+lxw_status lxw_batch_get_state(lxw_batch* b, int32_t i, double* Q, double* t, int32_t flags);
+/* Enqueues n_steps steps of every mesh (no final time) and returns without waiting. */
+lxw_status lxw_batch_advance_steps(lxw_batch* b, int64_t n_steps);
+/* Waits, then reports mesh i: steps since its state was set, t, last dt and last s. */
+lxw_status lxw_batch_stats(lxw_batch* b, int32_t i, lxw_stats* out);
+/* The solver that runs the batch, for lxw_sync, lxw_set_tune / lxw_get_tune / lxw_autotune,
+ * lxw_set_graph, lxw_set_timing and lxw_kernel_times (the per-mesh calls above handle state;
+ * lxw_step, lxw_advance, lxw_set_state, lxw_get_state and lxw_set_debug return
+ * LXW_ERR_UNSUPPORTED on it).  Owned by the batch. */
+lxw_solver* lxw_batch_solver(lxw_batch* b);
 
 #ifdef __cplusplus
 }

@@ -444,7 +444,22 @@ struct lxw_solver {
   size_t ev_used = 0;
   double kms[LXW_K_COUNT] = {};
   int64_t kcount[LXW_K_COUNT] = {};
+  // launch shapes
+  LaunchCfg cfg{};
+  // batched form: n_mesh meshes concatenated into M (elements of mesh b at [eoff[b], eoff[b+1]))
+  int n_mesh = 1;
+  bool batch = false;
+  std::vector<int> eoff{0, 0};
+  std::vector<int> mesh_of, e_mesh;  // host copies uploaded by setup_view (batched form only)
+  std::vector<double> geo_m;         // per mesh max |dT|/(2|T|)
+  std::vector<Scalars> hscv;         // per-mesh scalars after the last sync
+  // one step captured in a HIP graph (replayed by lxw_run_steps)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;
   ~lxw_solver() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap) (void)hipStreamDestroy(cap);
     for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
     for (auto& e : ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   }
@@ -458,6 +473,15 @@ struct lxw_solver {
     *out = (T*)p;
     return LXW_OK;
   }
+};
+
+// A batch: independent meshes of one kind concatenated into one internal mesh, advanced by one
+// solver whose kernels cover all of them (each mesh keeps its own s, dt and t).
+struct lxw_batch {
+  std::vector<const lxw_mesh*> ms;  // caller's meshes (outlive the batch)
+  lxw_mesh merged;
+  lxw_solver* S = nullptr;
+  ~lxw_batch() { delete S; }
 };
 
 namespace {
@@ -511,10 +535,14 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   if ((st = upload(S, &v.e_n, en))) return st;
   v.mesh_of = nullptr;
   v.e_mesh = nullptr;
+  if (S->batch) {
+    if ((st = upload(S, &v.mesh_of, S->mesh_of))) return st;
+    if ((st = upload(S, &v.e_mesh, S->e_mesh))) return st;
+  }
   if ((st = S->alloc(&v.Qbar, (size_t)V * N))) return st;
   if ((st = S->alloc(&v.Qh, (size_t)V * (ML - 1) * N))) return st;
   if ((st = S->alloc(&v.theta, (size_t)N))) return st;
-  if ((st = S->alloc(&v.spart, (size_t)((N + 255) / 256 + 7) / 8 * 8))) return st;
+  if ((st = S->alloc(&v.spart, (size_t)egrid_blocks(N, 64)))) return st;  // smallest tunable workgroup
   if ((st = S->alloc(&v.tq, (size_t)2 * NQE * V * E))) return st;
   if ((st = S->alloc(&v.tf, (size_t)2 * NQE * V * E))) return st;
   if ((st = S->alloc(&v.fstar, (size_t)NQE * V * E))) return st;
@@ -552,7 +580,7 @@ hipError_t launch_one(lxw_solver* S, const View<R>& v, KernelId k, double T, int
     hipError_t e = hipEventRecord(a, S->st);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = launch<E, R>(k, v, S->st, 1, T, mode);
+  hipError_t e = launch<E, R>(k, v, S->cfg, S->st, S->n_mesh, T, mode);
   if (e != hipSuccess) return e;
   if (S->timing) e = hipEventRecord(b, S->st);
   return e;
@@ -611,7 +639,9 @@ lxw_status sync_check(lxw_solver* S) {
     }
     S->ev_used = 0;
   }
-  HIPCHK(hipMemcpy(&S->hsc, S->sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+  S->hscv.resize(S->n_mesh);
+  HIPCHK(hipMemcpy(S->hscv.data(), S->sc, S->n_mesh * sizeof(Scalars), hipMemcpyDeviceToHost));
+  S->hsc = S->hscv[0];
   DevError de{};
   HIPCHK(hipMemcpy(&de, S->err, sizeof(DevError), hipMemcpyDeviceToHost));
   if (de.code != 0) {
@@ -619,12 +649,264 @@ lxw_status sync_check(lxw_solver* S) {
     const char* what = de.code == LXW_ERR_CFL ? "Lax-Friedrichs update not positive: time step too large"
                        : de.code == LXW_ERR_NONFINITE ? "non-finite value"
                                                       : "cell-average density or pressure not positive";
-    char buf[200];
-    snprintf(buf, sizeof buf, "%s (element %d, t = %.17g)", what, caller, S->hsc.t);
+    char buf[240];
+    if (S->batch && caller >= 0) {
+      const int b = (int)(std::upper_bound(S->eoff.begin(), S->eoff.end(), caller) - S->eoff.begin()) - 1;
+      snprintf(buf, sizeof buf, "%s (mesh %d, element %d, t = %.17g)", what, b, caller - S->eoff[b], S->hscv[b].t);
+    } else {
+      snprintf(buf, sizeof buf, "%s (element %d, t = %.17g)", what, caller, S->hsc.t);
+    }
     DevError z{};
     HIPCHK(hipMemcpy(S->err, &z, sizeof(DevError), hipMemcpyHostToDevice));
     return fail(de.code, buf);
   }
+  return LXW_OK;
+}
+
+// Checks a caller state of mesh Mloc (rho_bar >= eps0, p_bar > 0, finite) and uploads it, in the
+// internal order, into elements [off, off + Mloc.N) of the solver's state.
+lxw_status load_state(lxw_solver* S, const lxw_mesh& Mloc, int off, const double* Q, int32_t flags) {
+  const int N = Mloc.N, V = Mloc.V, ML = Mloc.ML, dim = Mloc.dim, Nt = S->M->N;
+  const size_t n = (size_t)N * V * ML;
+  std::vector<double> h(n);
+  HIPCHK(hipStreamSynchronize(S->st));
+  if (flags & LXW_DEVICE_PTR) {
+    HIPCHK(hipMemcpy(h.data(), Q, n * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(h.data(), Q, n * sizeof(double));
+  }
+  for (int c = 0; c < N; ++c) {
+    const double* q = &h[(size_t)c * V * ML];
+    double qb[4];
+    bool fin = true;
+    for (int v = 0; v < V; ++v) { qb[v] = q[v * ML]; for (int l = 0; l < ML; ++l) fin = fin && std::isfinite(q[v * ML + l]); }
+    double k = 0.0;
+    for (int d = 0; d < dim; ++d) k += qb[1 + d] * qb[1 + d];
+    const double pb = (S->P.gamma - 1.0) * (qb[V - 1] - 0.5 * k / qb[0]);
+    if (!fin || !(qb[0] >= S->P.eps0) || !(pb > 0.0)) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "initial state violates rho_bar >= eps0, p_bar > 0 or is not finite (element %d)", c);
+      return fail(LXW_ERR_STATE, buf);
+    }
+  }
+  std::vector<double> qbar((size_t)V * N);
+  std::vector<double> qh((size_t)V * (ML - 1) * N);
+  for (int i = 0; i < N; ++i) {
+    const double* q = &h[(size_t)Mloc.perm[i] * V * ML];
+    for (int v = 0; v < V; ++v) {
+      qbar[(size_t)v * N + i] = q[v * ML];
+      for (int l = 1; l < ML; ++l) qh[((size_t)v * (ML - 1) + l - 1) * N + i] = q[v * ML + l];
+    }
+  }
+  double* dbar = S->fp32 ? S->vf.Qbar : S->vd.Qbar;
+  for (int v = 0; v < V; ++v)
+    HIPCHK(hipMemcpy(dbar + (size_t)v * Nt + off, &qbar[(size_t)v * N], N * sizeof(double), hipMemcpyHostToDevice));
+  const int rows = V * (ML - 1);
+  if (S->fp32) {
+    std::vector<float> f(qh.begin(), qh.end());
+    for (int r = 0; r < rows; ++r)
+      HIPCHK(hipMemcpy(S->vf.Qh + (size_t)r * Nt + off, &f[(size_t)r * N], N * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    for (int r = 0; r < rows; ++r)
+      HIPCHK(hipMemcpy(S->vd.Qh + (size_t)r * Nt + off, &qh[(size_t)r * N], N * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return LXW_OK;
+}
+
+// Time t0, no step taken, no limiter pending, for mesh b.
+lxw_status reset_scalars(lxw_solver* S, int b, double t0) {
+  Scalars z{};
+  z.geo = S->geo_m[b];
+  z.cfl = S->P.cfl;
+  z.t = t0;
+  HIPCHK(hipMemcpy(S->sc + b, &z, sizeof z, hipMemcpyHostToDevice));
+  if ((int)S->hscv.size() != S->n_mesh) S->hscv.assign(S->n_mesh, Scalars{});
+  S->hscv[b] = z;
+  S->hsc = S->hscv[0];
+  return LXW_OK;
+}
+
+// Device state of elements [off, off + Mloc.N) -> caller layout of mesh Mloc (float64).
+lxw_status store_state(lxw_solver* S, const lxw_mesh& Mloc, int off, bool upd_copy, std::vector<double>& out) {
+  const int N = Mloc.N, V = Mloc.V, ML = Mloc.ML, Nt = S->M->N;
+  std::vector<double> qbar((size_t)V * N), qh((size_t)V * (ML - 1) * N);
+  const double* src_bar = upd_copy ? S->dq_upd_bar : (S->fp32 ? S->vf.Qbar : S->vd.Qbar);
+  const char* src_h = (const char*)(upd_copy ? S->dq_upd_h : (S->fp32 ? (const void*)S->vf.Qh : (const void*)S->vd.Qh));
+  for (int v = 0; v < V; ++v)
+    HIPCHK(hipMemcpy(&qbar[(size_t)v * N], src_bar + (size_t)v * Nt + off, N * sizeof(double), hipMemcpyDeviceToHost));
+  const int rows = V * (ML - 1);
+  if (S->fp32) {
+    std::vector<float> f(qh.size());
+    for (int r = 0; r < rows; ++r)
+      HIPCHK(hipMemcpy(&f[(size_t)r * N], src_h + ((size_t)r * Nt + off) * sizeof(float), N * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t x = 0; x < f.size(); ++x) qh[x] = f[x];
+  } else {
+    for (int r = 0; r < rows; ++r)
+      HIPCHK(hipMemcpy(&qh[(size_t)r * N], src_h + ((size_t)r * Nt + off) * sizeof(double), N * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  out.assign((size_t)N * V * ML, 0.0);
+  for (int i = 0; i < N; ++i) {
+    double* q = &out[(size_t)Mloc.perm[i] * V * ML];
+    for (int v = 0; v < V; ++v) {
+      q[v * ML] = qbar[(size_t)v * N + i];
+      for (int l = 1; l < ML; ++l) q[v * ML + l] = qh[((size_t)v * (ML - 1) + l - 1) * N + i];
+    }
+  }
+  return LXW_OK;
+}
+
+// Capture one step (no final time) on the library's own stream into a graph.
+lxw_status capture_step(lxw_solver* S) {
+  if (!S->cap) HIPCHK(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
+  hipStream_t user = S->st;
+  S->st = S->cap;
+  lxw_status s = enqueue_step(S, std::numeric_limits<double>::infinity());
+  S->st = user;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(S->cap, &g);
+  if (s) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(LXW_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    S->gexec = nullptr;
+    return fail(LXW_ERR_DEVICE, std::string("graph instantiation: ") + hipGetErrorString(e));
+  }
+  return LXW_OK;
+}
+
+void drop_graph(lxw_solver* S) {
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  S->gexec = nullptr;
+}
+
+lxw_status check_params(const lxw_params* p) {
+  if (p->degree != 2) return fail(LXW_ERR_UNSUPPORTED, "only polynomial degree 2 is implemented");
+  if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl <= 1.0) || !(p->eps0 > 0.0) || !(p->alpha0 >= 0.0))
+    return fail(LXW_ERR_ARG, "need gamma > 1, 0 < cfl <= 1, eps0 > 0, alpha0 >= 0");
+  if (p->precision != LXW_FP64 && p->precision != LXW_FP32_MIXED) return fail(LXW_ERR_ARG, "bad precision");
+  if (p->shock != LXW_SHOCK_OFF && p->shock != LXW_SHOCK_PLAIN) return fail(LXW_ERR_UNSUPPORTED, "bad shock-limiter mode");
+  return LXW_OK;
+}
+
+// Solver over mesh m.  With `batch` (the merged mesh of a batch, m == batch->mesh), the per-mesh
+// offsets, element and edge mesh indices and geometry factors come from it.
+struct BatchLayout {
+  std::vector<int> eoff, mesh_of, e_mesh;
+  std::vector<double> geo;
+};
+
+// Concatenate meshes (each already in its internal order) into one: elements of mesh b occupy
+// [eoff[b], eoff[b+1]), its edges a contiguous range in the same order; caller order of the merged
+// mesh is the concatenation of the meshes' caller orders.
+lxw_status merge_meshes(const std::vector<const lxw_mesh*>& ms, lxw_mesh& M, BatchLayout& bl) {
+  const lxw_mesh& m0 = *ms[0];
+  M.kind = m0.kind; M.dim = m0.dim; M.K = m0.K; M.V = m0.V; M.ML = m0.ML;
+  int64_t Nt = 0, Et = 0;
+  for (const lxw_mesh* m : ms) { Nt += m->N; Et += m->E; }
+  if (Nt > (int64_t)INT32_MAX / 8 || Et > (int64_t)INT32_MAX / 8) return fail(LXW_ERR_ARG, "batch too large for 32-bit indices");
+  M.N = (int)Nt;
+  M.E = (int)Et;
+  const int K = M.K, nvd = nverts(M.kind) * M.dim;
+  bl.eoff.assign(1, 0);
+  bl.geo.clear();
+  bl.mesh_of.resize(Nt);
+  bl.e_mesh.resize(Et);
+  M.geo = 0.0;
+  int eo = 0, go = 0;
+  for (size_t b = 0; b < ms.size(); ++b) {
+    const lxw_mesh& m = *ms[b];
+    for (int i = 0; i < m.N; ++i) {
+      M.perm.push_back(eo + m.perm[i]);
+      bl.mesh_of[eo + i] = (int)b;
+    }
+    for (int i = 0; i < m.N; ++i) M.iperm.push_back(eo + m.iperm[i]);
+    M.vx.insert(M.vx.end(), m.vx.begin(), m.vx.begin() + (size_t)m.N * nvd);
+    M.area.insert(M.area.end(), m.area.begin(), m.area.end());
+    M.perim.insert(M.perim.end(), m.perim.begin(), m.perim.end());
+    M.Jinv.insert(M.Jinv.end(), m.Jinv.begin(), m.Jinv.end());
+    M.nout.insert(M.nout.end(), m.nout.begin(), m.nout.end());
+    M.hsz.insert(M.hsz.end(), m.hsz.begin(), m.hsz.end());
+    for (size_t x = 0; x < (size_t)m.N * K; ++x) {
+      M.nbr.push_back(m.nbr[x] >= 0 ? m.nbr[x] + eo : -1);
+      M.nbr_k.push_back(m.nbr_k[x]);
+      M.bcode.push_back(m.bcode[x]);
+      M.eslot.push_back(((m.eslot[x] >> 3) + go) * 8 + (m.eslot[x] & 7));
+    }
+    for (int e = 0; e < m.E; ++e) {
+      M.e_i.push_back(m.e_i[e] + eo);
+      M.e_j.push_back(m.e_j[e] >= 0 ? m.e_j[e] + eo : -1);
+      M.e_bc.push_back(m.e_bc[e]);
+      M.e_ki.push_back(m.e_ki[e]);
+      M.e_kj.push_back(m.e_kj[e]);
+      bl.e_mesh[go + e] = (int)b;
+    }
+    M.e_n.insert(M.e_n.end(), m.e_n.begin(), m.e_n.end());
+    bl.geo.push_back(m.geo);
+    M.geo = std::max(M.geo, m.geo);
+    eo += m.N;
+    go += m.E;
+    bl.eoff.push_back(eo);
+  }
+  return LXW_OK;
+}
+
+lxw_status create_solver(const lxw_mesh* m, const lxw_params* p, void* stream, BatchLayout* bl, lxw_solver** out) {
+  if (!p || !out) return fail(LXW_ERR_ARG, "null argument");
+  *out = nullptr;
+  lxw_status s = check_params(p);
+  if (s) return s;
+  if ((s = ensure_init())) return s;
+  std::unique_ptr<lxw_solver> S(new (std::nothrow) lxw_solver);
+  if (!S) return fail(LXW_ERR_OOM, "host allocation");
+  S->M = m;
+  S->P = *p;
+  S->st = (hipStream_t)stream;
+  S->fp32 = p->precision == LXW_FP32_MIXED;
+  if (bl) {
+    S->batch = true;
+    S->n_mesh = (int)bl->geo.size();
+    S->eoff = std::move(bl->eoff);
+    S->mesh_of = std::move(bl->mesh_of);
+    S->e_mesh = std::move(bl->e_mesh);
+    S->geo_m = std::move(bl->geo);
+  } else {
+    S->eoff = {0, m->N};
+    S->geo_m = {m->geo};
+  }
+  if ((s = S->alloc(&S->sc, S->n_mesh))) return s;
+  if ((s = S->alloc(&S->err, 1))) return s;
+  for (int b = 0; b < S->n_mesh; ++b)
+    if ((s = reset_scalars(S.get(), b, 0.0))) return s;
+  DevError ze{};
+  HIPCHK(hipMemcpy(S->err, &ze, sizeof ze, hipMemcpyHostToDevice));
+  if (S->fp32) s = setup_view<float>(S.get(), S->vf);
+  else s = setup_view<double>(S.get(), S->vd);
+  if (s) return s;
+  *out = S.release();
+  return LXW_OK;
+}
+
+lxw_status run_steps_impl(lxw_solver* S, int64_t n_steps) {
+  if (n_steps < 0) return fail(LXW_ERR_ARG, "negative step count");
+  if (n_steps == 0) return LXW_OK;
+  if (S->timing || S->debug || !S->use_graph) {
+    const double inf = std::numeric_limits<double>::infinity();
+    for (int64_t k = 0; k < n_steps; ++k) {
+      lxw_status s = enqueue_step(S, inf);
+      if (s) return s;
+    }
+    return LXW_OK;
+  }
+  if (!S->gexec) {
+    lxw_status s = capture_step(S);
+    if (s) return s;
+  }
+  for (int64_t k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(S->gexec, S->st));
   return LXW_OK;
 }
 
@@ -826,35 +1108,8 @@ lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w,
 }
 
 lxw_status lxw_solver_create(const lxw_mesh* m, const lxw_params* p, void* stream, lxw_solver** out) {
-  if (!m || !p || !out) return fail(LXW_ERR_ARG, "null argument");
-  *out = nullptr;
-  if (p->degree != 2) return fail(LXW_ERR_UNSUPPORTED, "only polynomial degree 2 is implemented");
-  if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl <= 1.0) || !(p->eps0 > 0.0) || !(p->alpha0 >= 0.0))
-    return fail(LXW_ERR_ARG, "need gamma > 1, 0 < cfl <= 1, eps0 > 0, alpha0 >= 0");
-  if (p->precision != LXW_FP64 && p->precision != LXW_FP32_MIXED) return fail(LXW_ERR_ARG, "bad precision");
-  if (p->shock != LXW_SHOCK_OFF && p->shock != LXW_SHOCK_PLAIN) return fail(LXW_ERR_UNSUPPORTED, "bad shock-limiter mode");
-  lxw_status s = ensure_init();
-  if (s) return s;
-  std::unique_ptr<lxw_solver> S(new (std::nothrow) lxw_solver);
-  if (!S) return fail(LXW_ERR_OOM, "host allocation");
-  S->M = m;
-  S->P = *p;
-  S->st = (hipStream_t)stream;
-  S->fp32 = p->precision == LXW_FP32_MIXED;
-  if ((s = S->alloc(&S->sc, 1))) return s;
-  if ((s = S->alloc(&S->err, 1))) return s;
-  Scalars z{};
-  z.geo = m->geo;
-  z.cfl = p->cfl;
-  HIPCHK(hipMemcpy(S->sc, &z, sizeof z, hipMemcpyHostToDevice));
-  DevError ze{};
-  HIPCHK(hipMemcpy(S->err, &ze, sizeof ze, hipMemcpyHostToDevice));
-  S->hsc = z;
-  if (S->fp32) s = setup_view<float>(S.get(), S->vf);
-  else s = setup_view<double>(S.get(), S->vd);
-  if (s) return s;
-  *out = S.release();
-  return LXW_OK;
+  if (!m) return fail(LXW_ERR_ARG, "null argument");
+  return create_solver(m, p, stream, nullptr, out);
 }
 
 lxw_status lxw_solver_destroy(lxw_solver* s) {
@@ -865,87 +1120,18 @@ lxw_status lxw_solver_destroy(lxw_solver* s) {
 
 lxw_status lxw_set_state(lxw_solver* S, const double* Q, double t0, int32_t flags) {
   if (check_solver(S) || !Q) return fail(LXW_ERR_ARG, "null argument");
-  const lxw_mesh& M = *S->M;
-  const int N = M.N, V = M.V, ML = M.ML, dim = M.dim;
-  const size_t n = (size_t)N * V * ML;
-  std::vector<double> h(n);
-  if (flags & LXW_DEVICE_PTR) {
-    HIPCHK(hipMemcpyAsync(h.data(), Q, n * sizeof(double), hipMemcpyDeviceToHost, S->st));
-    HIPCHK(hipStreamSynchronize(S->st));
-  } else {
-    std::memcpy(h.data(), Q, n * sizeof(double));
-  }
-  for (int c = 0; c < N; ++c) {
-    const double* q = &h[(size_t)c * V * ML];
-    double qb[4];
-    bool fin = true;
-    for (int v = 0; v < V; ++v) { qb[v] = q[v * ML]; for (int l = 0; l < ML; ++l) fin = fin && std::isfinite(q[v * ML + l]); }
-    double k = 0.0;
-    for (int d = 0; d < dim; ++d) k += qb[1 + d] * qb[1 + d];
-    const double pb = (S->P.gamma - 1.0) * (qb[V - 1] - 0.5 * k / qb[0]);
-    if (!fin || !(qb[0] >= S->P.eps0) || !(pb > 0.0)) {
-      char buf[160];
-      snprintf(buf, sizeof buf, "initial state violates rho_bar >= eps0, p_bar > 0 or is not finite (element %d)", c);
-      return fail(LXW_ERR_STATE, buf);
-    }
-  }
-  std::vector<double> qbar((size_t)V * N);
-  std::vector<double> qh((size_t)V * (ML - 1) * N);
-  for (int i = 0; i < N; ++i) {
-    const double* q = &h[(size_t)M.perm[i] * V * ML];
-    for (int v = 0; v < V; ++v) {
-      qbar[(size_t)v * N + i] = q[v * ML];
-      for (int l = 1; l < ML; ++l) qh[((size_t)v * (ML - 1) + l - 1) * N + i] = q[v * ML + l];
-    }
-  }
-  HIPCHK(hipStreamSynchronize(S->st));
-  if (S->fp32) {
-    std::vector<float> f(qh.begin(), qh.end());
-    HIPCHK(hipMemcpy(S->vf.Qbar, qbar.data(), qbar.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(S->vf.Qh, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-  } else {
-    HIPCHK(hipMemcpy(S->vd.Qbar, qbar.data(), qbar.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(S->vd.Qh, qh.data(), qh.size() * sizeof(double), hipMemcpyHostToDevice));
-  }
-  Scalars z{};
-  z.geo = M.geo;
-  z.cfl = S->P.cfl;
-  z.t = t0;
-  HIPCHK(hipMemcpy(S->sc, &z, sizeof z, hipMemcpyHostToDevice));
+  if (S->batch) return fail(LXW_ERR_UNSUPPORTED, "a batch's state is set per mesh (lxw_batch_set_state)");
+  lxw_status s = load_state(S, *S->M, 0, Q, flags);
+  if (s) return s;
+  if ((s = reset_scalars(S, 0, t0))) return s;
   DevError ze{};
   HIPCHK(hipMemcpy(S->err, &ze, sizeof ze, hipMemcpyHostToDevice));
-  S->hsc = z;
-  return LXW_OK;
-}
-
-// device state -> caller layout (float64, caller order)
-static lxw_status read_state(lxw_solver* S, std::vector<double>& out, bool upd_copy) {
-  const lxw_mesh& M = *S->M;
-  const int N = M.N, V = M.V, ML = M.ML;
-  std::vector<double> qbar((size_t)V * N), qh((size_t)V * (ML - 1) * N);
-  const void* src_bar = upd_copy ? (const void*)S->dq_upd_bar : (S->fp32 ? (const void*)S->vf.Qbar : (const void*)S->vd.Qbar);
-  const void* src_h = upd_copy ? S->dq_upd_h : (S->fp32 ? (const void*)S->vf.Qh : (const void*)S->vd.Qh);
-  HIPCHK(hipMemcpy(qbar.data(), src_bar, qbar.size() * sizeof(double), hipMemcpyDeviceToHost));
-  if (S->fp32) {
-    std::vector<float> f(qh.size());
-    HIPCHK(hipMemcpy(f.data(), src_h, f.size() * sizeof(float), hipMemcpyDeviceToHost));
-    for (size_t x = 0; x < f.size(); ++x) qh[x] = f[x];
-  } else {
-    HIPCHK(hipMemcpy(qh.data(), src_h, qh.size() * sizeof(double), hipMemcpyDeviceToHost));
-  }
-  out.assign((size_t)N * V * ML, 0.0);
-  for (int i = 0; i < N; ++i) {
-    double* q = &out[(size_t)M.perm[i] * V * ML];
-    for (int v = 0; v < V; ++v) {
-      q[v * ML] = qbar[(size_t)v * N + i];
-      for (int l = 1; l < ML; ++l) q[v * ML + l] = qh[((size_t)v * (ML - 1) + l - 1) * N + i];
-    }
-  }
   return LXW_OK;
 }
 
 lxw_status lxw_get_state(lxw_solver* S, double* Q, double* t, int32_t flags) {
   if (check_solver(S) || !Q) return fail(LXW_ERR_ARG, "null argument");
+  if (S->batch) return fail(LXW_ERR_UNSUPPORTED, "a batch's state is read per mesh (lxw_batch_get_state)");
   lxw_status s = sync_check(S);
   if (s) return s;
   if (S->hsc.shock_pending && S->P.shock) {
@@ -953,7 +1139,7 @@ lxw_status lxw_get_state(lxw_solver* S, double* Q, double* t, int32_t flags) {
     if ((s = sync_check(S))) return s;
   }
   std::vector<double> h;
-  if ((s = read_state(S, h, false))) return s;
+  if ((s = store_state(S, *S->M, 0, false, h))) return s;
   if (flags & LXW_DEVICE_PTR) {
     HIPCHK(hipMemcpyAsync(Q, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, S->st));
     HIPCHK(hipStreamSynchronize(S->st));
@@ -966,6 +1152,7 @@ lxw_status lxw_get_state(lxw_solver* S, double* Q, double* t, int32_t flags) {
 
 lxw_status lxw_step(lxw_solver* S, double T, double* dt_taken) {
   if (check_solver(S)) return LXW_ERR_ARG;
+  if (S->batch) return fail(LXW_ERR_UNSUPPORTED, "a batch advances by step counts (lxw_batch_advance_steps)");
   if (!(S->hsc.t < T)) return fail(LXW_ERR_ARG, "t >= T");
   lxw_status s = enqueue_step(S, T);
   if (s) return s;
@@ -976,6 +1163,7 @@ lxw_status lxw_step(lxw_solver* S, double T, double* dt_taken) {
 
 lxw_status lxw_advance(lxw_solver* S, double T, int64_t max_steps, lxw_stats* out) {
   if (check_solver(S)) return LXW_ERR_ARG;
+  if (S->batch) return fail(LXW_ERR_UNSUPPORTED, "a batch advances by step counts (lxw_batch_advance_steps)");
   int64_t n = 0;
   lxw_status s = LXW_OK;
   while (S->hsc.t < T && n < max_steps) {
@@ -990,12 +1178,12 @@ lxw_status lxw_advance(lxw_solver* S, double T, int64_t max_steps, lxw_stats* ou
 
 lxw_status lxw_run_steps(lxw_solver* S, int64_t n_steps) {
   if (check_solver(S)) return LXW_ERR_ARG;
-  if (n_steps < 0) return fail(LXW_ERR_ARG, "negative step count");
-  const double inf = std::numeric_limits<double>::infinity();
-  for (int64_t k = 0; k < n_steps; ++k) {
-    lxw_status s = enqueue_step(S, inf);
-    if (s) return s;
-  }
+  return run_steps_impl(S, n_steps);
+}
+
+lxw_status lxw_set_graph(lxw_solver* S, int32_t enable) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  S->use_graph = enable != 0;
   return LXW_OK;
 }
 
@@ -1006,6 +1194,7 @@ lxw_status lxw_sync(lxw_solver* S) {
 
 lxw_status lxw_set_debug(lxw_solver* S, int32_t keep) {
   if (check_solver(S)) return LXW_ERR_ARG;
+  if (S->batch) return fail(LXW_ERR_UNSUPPORTED, "stage read-out is for single meshes");
   S->debug = keep != 0;
   if (!S->debug) return LXW_OK;
   const lxw_mesh& M = *S->M;
@@ -1140,6 +1329,181 @@ lxw_status lxw_kernel_times(lxw_solver* S, double* ms, int64_t* launches) {
   lxw_status s = sync_check(S);
   if (s) return s;
   for (int k = 0; k < LXW_K_COUNT; ++k) { ms[k] = S->kms[k]; launches[k] = S->kcount[k]; }
+  return LXW_OK;
+}
+
+// ---- launch shapes and the autotuner --------------------------------------------------------
+
+lxw_status lxw_get_tune(const lxw_solver* S, lxw_tune* out) {
+  if (!S || !out) return fail(LXW_ERR_ARG, "null argument");
+  for (int k = 0; k < LXW_K_COUNT; ++k) out->block[k] = S->cfg.bs[k];
+  return LXW_OK;
+}
+
+lxw_status lxw_set_tune(lxw_solver* S, const lxw_tune* t) {
+  if (check_solver(S) || !t) return fail(LXW_ERR_ARG, "null argument");
+  LaunchCfg c = S->cfg;
+  for (int k = 0; k < LXW_K_COUNT; ++k) {
+    if (!tunable(k)) continue;
+    const int b = t->block[k];
+    if (b != 64 && b != 128 && b != 256) return fail(LXW_ERR_ARG, "workgroup sizes must be 64, 128 or 256");
+    c.bs[k] = b;
+  }
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  S->cfg = c;
+  drop_graph(S);
+  return LXW_OK;
+}
+
+lxw_status lxw_autotune(lxw_solver* S, int32_t trial_steps, lxw_tune* out) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  if (trial_steps < 1) return fail(LXW_ERR_ARG, "trial_steps must be >= 1");
+  if (S->debug) return fail(LXW_ERR_ARG, "switch stage read-out off before tuning");
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  const lxw_mesh& M = *S->M;
+  const size_t nbar = (size_t)M.V * M.N * sizeof(double);
+  const size_t nh = (size_t)M.V * (M.ML - 1) * M.N * (S->fp32 ? sizeof(float) : sizeof(double));
+  void* dbar = S->fp32 ? (void*)S->vf.Qbar : (void*)S->vd.Qbar;
+  void* dh = S->fp32 ? (void*)S->vf.Qh : (void*)S->vd.Qh;
+  // snapshot of the state and the scalars, restored afterwards
+  void *sbar = nullptr, *sh = nullptr;
+  HIPCHK(hipMalloc(&sbar, nbar ? nbar : 1));
+  if (hipMalloc(&sh, nh ? nh : 1) != hipSuccess) { (void)hipFree(sbar); return fail(LXW_ERR_OOM, "tuning snapshot"); }
+  std::vector<Scalars> ssc(S->n_mesh);
+  auto cleanup = [&]() { (void)hipFree(sbar); (void)hipFree(sh); };
+  if (hipMemcpy(sbar, dbar, nbar, hipMemcpyDeviceToDevice) != hipSuccess ||
+      hipMemcpy(sh, dh, nh, hipMemcpyDeviceToDevice) != hipSuccess ||
+      hipMemcpy(ssc.data(), S->sc, S->n_mesh * sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess) {
+    cleanup();
+    return fail(LXW_ERR_DEVICE, "tuning snapshot copy failed");
+  }
+  const bool timing0 = S->timing;
+  double kms0[LXW_K_COUNT];
+  int64_t kc0[LXW_K_COUNT];
+  std::memcpy(kms0, S->kms, sizeof kms0);
+  std::memcpy(kc0, S->kcount, sizeof kc0);
+  S->timing = true;
+  LaunchCfg best = S->cfg;
+  const int sizes[3] = {64, 128, 256};
+  const int order[5] = {K_ELEM, K_PRE, K_EDGE, K_UPDATE, K_FLIM};
+  const double inf = std::numeric_limits<double>::infinity();
+  for (int k : order) {
+    double best_ms = inf;
+    int best_bs = best.bs[k];
+    for (int bs : sizes) {
+      S->cfg = best;
+      S->cfg.bs[k] = bs;
+      s = enqueue_step(S, inf);  // warm-up with this shape
+      if (!s) s = sync_check(S);
+      S->kms[k] = 0.0;
+      S->kcount[k] = 0;
+      for (int t = 0; t < trial_steps && !s; ++t) s = enqueue_step(S, inf);
+      if (!s) s = sync_check(S);
+      if (s) break;
+      const double ms = S->kms[k] / (double)std::max<int64_t>(S->kcount[k], 1);
+      if (ms < best_ms) { best_ms = ms; best_bs = bs; }
+    }
+    if (s) break;
+    best.bs[k] = best_bs;
+  }
+  S->cfg = best;
+  S->timing = timing0;
+  std::memcpy(S->kms, kms0, sizeof kms0);
+  std::memcpy(S->kcount, kc0, sizeof kc0);
+  drop_graph(S);
+  (void)hipStreamSynchronize(S->st);
+  hipError_t e1 = hipMemcpy(dbar, sbar, nbar, hipMemcpyDeviceToDevice);
+  hipError_t e2 = hipMemcpy(dh, sh, nh, hipMemcpyDeviceToDevice);
+  hipError_t e3 = hipMemcpy(S->sc, ssc.data(), S->n_mesh * sizeof(Scalars), hipMemcpyHostToDevice);
+  cleanup();
+  if (s) return s;
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(LXW_ERR_DEVICE, "tuning restore failed");
+  S->hscv = ssc;
+  S->hsc = ssc[0];
+  if (out) for (int k = 0; k < LXW_K_COUNT; ++k) out->block[k] = S->cfg.bs[k];
+  return LXW_OK;
+}
+
+// ---- batched form -------------------------------------------------------------------------
+
+lxw_status lxw_batch_create(int32_t n, const lxw_mesh* const* meshes, const lxw_params* p, void* stream, lxw_batch** out) {
+  if (!meshes || !p || !out) return fail(LXW_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (n < 1) return fail(LXW_ERR_ARG, "a batch needs at least one mesh");
+  for (int b = 0; b < n; ++b) {
+    if (!meshes[b]) return fail(LXW_ERR_ARG, "null mesh " + std::to_string(b));
+    if (meshes[b]->kind != meshes[0]->kind) return fail(LXW_ERR_ARG, "all meshes of a batch must be of one kind");
+  }
+  lxw_status s = check_params(p);
+  if (s) return s;
+  std::unique_ptr<lxw_batch> B(new (std::nothrow) lxw_batch);
+  if (!B) return fail(LXW_ERR_OOM, "host allocation");
+  B->ms.assign(meshes, meshes + n);
+  BatchLayout bl;
+  if ((s = merge_meshes(B->ms, B->merged, bl))) return s;
+  if ((s = create_solver(&B->merged, p, stream, &bl, &B->S))) return s;
+  *out = B.release();
+  return LXW_OK;
+}
+
+lxw_status lxw_batch_destroy(lxw_batch* b) {
+  if (b && b->S) (void)hipStreamSynchronize(b->S->st);
+  delete b;
+  return LXW_OK;
+}
+
+lxw_solver* lxw_batch_solver(lxw_batch* b) { return b ? b->S : nullptr; }
+
+lxw_status lxw_batch_set_state(lxw_batch* B, int32_t i, const double* Q, double t0, int32_t flags) {
+  if (!B || !Q) return fail(LXW_ERR_ARG, "null argument");
+  if (i < 0 || i >= (int)B->ms.size()) return fail(LXW_ERR_ARG, "mesh index out of range");
+  lxw_solver* S = B->S;
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  if ((s = load_state(S, *B->ms[i], S->eoff[i], Q, flags))) return s;
+  return reset_scalars(S, i, t0);
+}
+
+lxw_status lxw_batch_get_state(lxw_batch* B, int32_t i, double* Q, double* t, int32_t flags) {
+  if (!B || !Q) return fail(LXW_ERR_ARG, "null argument");
+  if (i < 0 || i >= (int)B->ms.size()) return fail(LXW_ERR_ARG, "mesh index out of range");
+  lxw_solver* S = B->S;
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  bool pending = false;
+  for (const Scalars& x : S->hscv) pending = pending || x.shock_pending;
+  if (pending && S->P.shock) {
+    if ((s = enqueue_shock(S))) return s;
+    if ((s = sync_check(S))) return s;
+  }
+  std::vector<double> h;
+  if ((s = store_state(S, *B->ms[i], S->eoff[i], false, h))) return s;
+  if (flags & LXW_DEVICE_PTR) {
+    HIPCHK(hipMemcpy(Q, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(Q, h.data(), h.size() * sizeof(double));
+  }
+  if (t) *t = S->hscv[i].t;
+  return LXW_OK;
+}
+
+lxw_status lxw_batch_advance_steps(lxw_batch* B, int64_t n_steps) {
+  if (!B) return fail(LXW_ERR_ARG, "null batch");
+  return run_steps_impl(B->S, n_steps);
+}
+
+lxw_status lxw_batch_stats(lxw_batch* B, int32_t i, lxw_stats* out) {
+  if (!B || !out) return fail(LXW_ERR_ARG, "null argument");
+  if (i < 0 || i >= (int)B->ms.size()) return fail(LXW_ERR_ARG, "mesh index out of range");
+  lxw_status s = sync_check(B->S);
+  if (s) return s;
+  const Scalars& x = B->S->hscv[i];
+  out->steps = x.steps;
+  out->t = x.t;
+  out->last_dt = x.dt;
+  out->last_s = x.s;
   return LXW_OK;
 }
 

@@ -94,6 +94,8 @@ struct View {
   double* fLxW;           // [V][E]
   double* fLxF;           // [V][E]
   double* cedge;          // [2][E] damping candidate of each side (1 on a ghost side)
+  const unsigned char* ind_flag;  // [N] learned indicator decision (0: the shock-capturing limiter
+                                 //   is skipped) or null (plain detection everywhere)
   Scalars* sc;
   DevError* err;
   double* spart;          // [blocks of k_pre] per-block maximum wave speed (single-mesh form)
@@ -122,9 +124,67 @@ struct HostTabs {
 // ---- host-side launchers implemented in lxw_kernels.hip -----------------------------------
 hipError_t upload_tables(const HostTabs& t);
 
-enum KernelId { K_PRE = 0, K_DT = 1, K_ELEM = 2, K_EDGE = 3, K_FLIM = 4, K_UPDATE = 5, K_FINAL = 6, K_SHOCK = 7 };
+enum KernelId { K_PRE = 0, K_DT = 1, K_ELEM = 2, K_EDGE = 3, K_FLIM = 4, K_UPDATE = 5, K_FINAL = 6, K_IND = 7,
+                K_SHOCK = 8 };
+
+// Workgroup size (one lane per element or edge, so also elements or edges per workgroup) of each
+// kernel, indexed by KernelId; the scalar kernels (K_DT, K_FINAL) and the indicator (K_IND, one
+// wavefront per 64 elements) have fixed shapes.  Every
+// tunable kernel accepts 64, 128 or 256.
+struct LaunchCfg {
+  int bs[8] = {256, 0, 128, 256, 256, 256, 0, 0};
+};
+inline bool tunable(int k) { return k == K_PRE || k == K_ELEM || k == K_EDGE || k == K_FLIM || k == K_UPDATE; }
+// Number of workgroups of an element or edge kernel: padded to a multiple of 8 (one contiguous
+// range of workgroups per XCD).
+inline int egrid_blocks(int n, int bs) { return ((n + bs - 1) / bs + 7) / 8 * 8; }
 
 template <class E, class R>
-hipError_t launch(KernelId k, const View<R>& v, hipStream_t st, int n_mesh, double T, int mode);
+hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_t st, int n_mesh, double T, int mode);
+
+// ---- learned troubled-cell indicator (lxw_indicator.hip) ------------------------------------
+// Network 48 -> 64 (ReLU) -> 64 (ReLU) -> 1 (sigmoid); flat FP32 parameters W1[48][64], b1[64],
+// W2[64][64], b2[64], w3[64], b3.
+constexpr int IND_NIN = 48, IND_NH = 64;
+constexpr int IND_NPARAM = IND_NIN * IND_NH + IND_NH + IND_NH * IND_NH + IND_NH + IND_NH + 1;  // 7361
+constexpr int IND_OFF_W1 = 0, IND_OFF_B1 = 3072, IND_OFF_W2 = 3136, IND_OFF_B2 = 7232, IND_OFF_W3 = 7296,
+              IND_OFF_B3 = 7360;
+constexpr int IND_PART = 7368;  // stride of one block's partial gradient (7361 gradients, loss, pad)
+
+// Inference weights in the lane layout of the 32x32x16 bf16 matrix instruction (packed on the
+// host from the FP32 parameters).  uint16_t holds bfloat16 bit patterns.
+struct IndW {
+  const uint16_t* A1;  // [2 row tiles][3 k-steps][64 lanes][8]
+  const uint16_t* A2;  // [2 row tiles][4 k-steps][64 lanes][8]
+  const float* b1;     // [2 row tiles][2 lane halves][16 accumulator registers]
+  const float* b2;     // same layout
+  const float* w3;     // same layout
+  float b3;
+  float tau_lo, tau_hi;
+};
+
+template <class R>
+hipError_t launch_indicator(const View<R>& v, const IndW& W, unsigned char* flag, unsigned long long* counts,
+                            hipStream_t st);
+template <class R>
+hipError_t launch_features(const View<R>& v, float* X, hipStream_t st);
+hipError_t launch_predict(const IndW& W, const float* X, int n, float* p, hipStream_t st);
+// Training: per-block partial gradients of the class-weighted cross-entropy over samples
+// order[base + s] (s < n; order null: base + s), then the in-order reduction and, with adam != 0,
+// the Adam update of theta / m / v (bc1 = 1 - beta1^t, bc2 = 1 - beta2^t).
+struct TrainArgs {
+  const float* X;
+  const float* y;
+  const int* order;
+  int base, n;
+  float w_pos, w_neg, inv_n;
+  const float* theta;
+  float* part;
+};
+hipError_t launch_mlp_grad(const TrainArgs& a, hipStream_t st);
+hipError_t launch_mlp_reduce(int nblk, const float* part, float* theta, float* m, float* v, float* grad_out,
+                             float* loss_out, int adam, float lr, float b1, float b2, float eps, float bc1,
+                             float bc2, hipStream_t st);
+inline int mlp_blocks(int n) { return (n + 63) / 64; }
 
 }  // namespace lxw

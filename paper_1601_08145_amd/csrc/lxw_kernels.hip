@@ -242,6 +242,10 @@ __device__ __forceinline__ void atomic_max_per_mesh(Scalars* sc, int mid, double
 //   mode 0: computes the element's total limiter factor theta = theta_shock * theta_moment and
 //           stores it (k_elem applies it to the higher modes); wave speed and checks.
 //   mode 1: applies only the pending shock-capturing limiter to the stored modes (state read-out).
+//   mode 2: stores the pending shock-capturing limiter's factor in theta, changing nothing else
+//           (training data for the learned indicator).
+// With a learned indicator, elements it clears (ind_flag 0) skip the shock-capturing limiter in
+// modes 0 and 1; the positivity limiter is never skipped.
 // All limiter arithmetic is float64 on the stored state, evaluated as q_bar + theta sum_l Q_l phi_l,
 // the same expression k_elem uses for its point states, so the positivity the limiter establishes
 // holds for the states the time-averaged flux is built from.
@@ -306,7 +310,8 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
     // ---- shock-capturing limiter on the primitive variables (bounds from the edge neighbours'
     // averages relaxed by alpha0 h^1.5; velocity and pressure sampled where the density is positive)
     double th_sc = 1.0;
-    if (v.shock && v.sc[mid].shock_pending && ok) {
+    const bool detect = mode == 2 || !v.ind_flag || v.ind_flag[i] != 0;
+    if (v.shock && v.sc[mid].shock_pending && ok && detect) {
       double wb[V], Mx[V], Mn[V];
       wb[0] = qb[0];
 #pragma unroll
@@ -378,7 +383,9 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
       th_sc = fmax(0.0, fmin(1.0, th_sc));
     }
 
-    if (mode == 1) {
+    if (mode == 2) {
+      v.theta[i] = th_sc;  // the factor the limiter would apply; the state is left as it is
+    } else if (mode == 1) {
       if (th_sc < 1.0) {
 #pragma unroll
         for (int c = 0; c < V; ++c)
@@ -509,8 +516,13 @@ __global__ void k_dt(Scalars* sc, DevError* err, int n_mesh, double T) {
 // F^h is projected in contravariant form Fc_a = sum_d Jinv[a][d] F_d, so that div F^h =
 // sum_a d/dxi_a Fc_a^h and grad D follows from reference second derivatives (affine elements).
 // ---------------------------------------------------------------------------------------------
+// Waves per SIMD the register allocation of k_elem targets: two for float32 triangles (measured
+// faster: latency of the trace stores is hidden), one elsewhere (float64 would spill at two).
 template <class E, class R>
-__global__ __launch_bounds__(128) void k_elem(View<R> v) {
+struct ElemOcc { static constexpr int waves = (E::kind == ElTri::kind && sizeof(R) == 4) ? 2 : 1; };
+
+template <class E, class R>
+__global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NI = E::NI, K = E::K, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const RefTab<E, double>& TD = TabSel<E, double>::get();
@@ -1076,32 +1088,37 @@ __global__ void k_final(Scalars* sc, int n_mesh, int shock, int mode) {
 }
 
 template <class E, class R>
-hipError_t launch(KernelId k, const View<R>& v, hipStream_t st, int n_mesh, double T, int mode) {
+hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_t st, int n_mesh, double T, int mode) {
   auto grid = [](int n, int b) { return dim3((unsigned)((n + b - 1) / b)); };
   // element and edge kernels: grid padded to a multiple of 8 blocks (XCD-contiguous block order)
-  auto egrid = [](int n, int b) { return dim3((unsigned)(((n + b - 1) / b + 7) / 8 * 8)); };
+  auto egrid = [](int n, int b) { return dim3((unsigned)egrid_blocks(n, b)); };
+  const int bs = (k == K_SHOCK) ? cfg.bs[K_PRE] : (tunable(k) ? cfg.bs[k] : 0);
+  if (tunable(k == K_SHOCK ? K_PRE : k) && bs != 64 && bs != 128 && bs != 256) return hipErrorInvalidConfiguration;
   switch (k) {
     case K_PRE:
-      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, 256), dim3(256), 0, st, v, 0);
+      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v, 0);
       break;
     case K_SHOCK:
-      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, 256), dim3(256), 0, st, v, 1);
+      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v, mode);
       break;
+    case K_IND:
+      return hipErrorInvalidValue;  // launched through launch_indicator
     case K_DT:
       if (v.mesh_of) hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh, T);
-      else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(256), 0, st, v.sc, v.err, v.spart, ((v.N + 255) / 256 + 7) / 8 * 8, T);
+      else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(256), 0, st, v.sc, v.err, v.spart,
+                              v.N > 0 ? egrid_blocks(v.N, cfg.bs[K_PRE]) : 0, T);
       break;
     case K_ELEM:
-      if (v.N > 0) hipLaunchKernelGGL((k_elem<E, R>), egrid(v.N, 128), dim3(128), 0, st, v);
+      if (v.N > 0) hipLaunchKernelGGL((k_elem<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v);
       break;
     case K_EDGE:
-      if (v.E > 0) hipLaunchKernelGGL((k_edge<E, R>), egrid(v.E, 256), dim3(256), 0, st, v);
+      if (v.E > 0) hipLaunchKernelGGL((k_edge<E, R>), egrid(v.E, bs), dim3(bs), 0, st, v);
       break;
     case K_FLIM:
-      if (v.N > 0) hipLaunchKernelGGL((k_flim<E, R>), egrid(v.N, 256), dim3(256), 0, st, v);
+      if (v.N > 0) hipLaunchKernelGGL((k_flim<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v);
       break;
     case K_UPDATE:
-      if (v.N > 0) hipLaunchKernelGGL((k_update<E, R>), egrid(v.N, 256), dim3(256), 0, st, v);
+      if (v.N > 0) hipLaunchKernelGGL((k_update<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v);
       break;
     case K_FINAL:
       hipLaunchKernelGGL(k_final, grid(n_mesh, 64), dim3(64), 0, st, v.sc, n_mesh, v.shock, mode);
@@ -1110,11 +1127,11 @@ hipError_t launch(KernelId k, const View<R>& v, hipStream_t st, int n_mesh, doub
   return hipGetLastError();
 }
 
-template hipError_t launch<ElLine, double>(KernelId, const View<double>&, hipStream_t, int, double, int);
-template hipError_t launch<ElLine, float>(KernelId, const View<float>&, hipStream_t, int, double, int);
-template hipError_t launch<ElQuad, double>(KernelId, const View<double>&, hipStream_t, int, double, int);
-template hipError_t launch<ElQuad, float>(KernelId, const View<float>&, hipStream_t, int, double, int);
-template hipError_t launch<ElTri, double>(KernelId, const View<double>&, hipStream_t, int, double, int);
-template hipError_t launch<ElTri, float>(KernelId, const View<float>&, hipStream_t, int, double, int);
+template hipError_t launch<ElLine, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, double, int);
+template hipError_t launch<ElLine, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, double, int);
+template hipError_t launch<ElQuad, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, double, int);
+template hipError_t launch<ElQuad, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, double, int);
+template hipError_t launch<ElTri, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, double, int);
+template hipError_t launch<ElTri, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, double, int);
 
 }  // namespace lxw

@@ -297,6 +297,41 @@ def batch_sizes(n_meshes, seed, lo=2000, hi=60000):
     return [int(round(math.sqrt(x / 2.0))) + 1 for x in N]
 
 
+def batch_case(n, seed, m=2, gamma=1.4, box=(-5.0, 5.0, -5.0, 5.0)):
+    """One mesh of the batched workload: an n x n jittered-lattice Delaunay mesh on `box` (seed
+    `seed`) with the vortex + shock field of the same seed as cell averages (m^2 samples per
+    triangle), higher modes zero.  Returns (xy, tri, Q)."""
+    xy, tri = lattice_delaunay(n, seed, box=box)
+    Q = averages_to_modal(cell_average_state(vortex_shock_fn(seed, gamma, box=box), tri_sample_points(xy, tri, m),
+                                             gamma), 6)
+    return xy, tri, Q
+
+
+def batch_workload(n_meshes, seed, lo=2000, hi=60000, m=2):
+    """The batched workload as a generator of (xy, tri, Q): mesh b has batch_sizes(...)[b] lattice
+    points per side and seed seed * 100000 + b."""
+    for b, n in enumerate(batch_sizes(n_meshes, seed, lo, hi)):
+        yield batch_case(n, seed * 100000 + b, m)
+
+
+def _batch_case_avg(args):
+    n, seed, m = args
+    xy, tri, Q = batch_case(n, seed, m)
+    return xy, tri, Q[:, :, 0].copy()
+
+
+def batch_workload_parallel(n_meshes, seed, lo=2000, hi=60000, m=2, workers=8):
+    """batch_workload as a list, built by `workers` freshly spawned processes (no state of the
+    caller's process, GPU runtime included, is shared with them)."""
+    import concurrent.futures
+    import multiprocessing
+    jobs = [(n, seed * 100000 + b, m) for b, n in enumerate(batch_sizes(n_meshes, seed, lo, hi))]
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        out = list(ex.map(_batch_case_avg, jobs, chunksize=4))
+    return [(xy, tri, averages_to_modal(avg, 6)) for xy, tri, avg in out]
+
+
 def random_modal_state(N, dim, n_modes, seed, amp=0.3, gamma=1.4, p_range=(0.3, 1.5), rough_frac=0.0,
                        rough_amp=2.0):
     """Random modal coefficients for parity tests: cell averages from random positive primitive

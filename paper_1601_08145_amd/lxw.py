@@ -27,8 +27,8 @@ SHOCK_OFF, SHOCK_PLAIN = 0, 1
 HOST_PTR, DEVICE_PTR = 0, 1
 STAGE_QLIM, STAGE_THETA, STAGE_VOL, STAGE_FLXW, STAGE_FLXF = 0, 1, 2, 3, 4
 STAGE_C, STAGE_LAME, STAGE_QUPD, STAGE_THETA_SC, STAGE_SDT = 6, 7, 8, 9, 10
-K_PRE, K_DT, K_ELEM, K_EDGE, K_FLIM, K_UPDATE, K_FINAL, K_COUNT = 0, 1, 2, 3, 4, 5, 6, 7
-KERNEL_NAMES = ["k_pre", "k_dt", "k_elem", "k_edge", "k_flim", "k_update", "k_final"]
+K_PRE, K_DT, K_ELEM, K_EDGE, K_FLIM, K_UPDATE, K_FINAL, K_IND, K_COUNT = 0, 1, 2, 3, 4, 5, 6, 7, 8
+KERNEL_NAMES = ["k_pre", "k_dt", "k_elem", "k_edge", "k_flim", "k_update", "k_final", "k_ind"]
 
 
 class LxwError(RuntimeError):
@@ -49,6 +49,10 @@ class MeshInfo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_elem", ctypes.c_int32),
                 ("n_edge", ctypes.c_int32), ("n_var", ctypes.c_int32), ("n_modes", ctypes.c_int32),
                 ("n_faces", ctypes.c_int32), ("min_area", ctypes.c_double), ("max_area", ctypes.c_double)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32 * 8)]
 
 
 class Stats(ctypes.Structure):
@@ -83,6 +87,16 @@ def _load():
         "lxw_debug_stage": [P, I32, dp],
         "lxw_set_timing": [P, I32],
         "lxw_kernel_times": [P, dp, ctypes.POINTER(ctypes.c_int64)],
+        "lxw_set_graph": [P, I32],
+        "lxw_get_tune": [P, ctypes.POINTER(Tune)],
+        "lxw_set_tune": [P, ctypes.POINTER(Tune)],
+        "lxw_autotune": [P, I32, ctypes.POINTER(Tune)],
+        "lxw_batch_create": [I32, ctypes.POINTER(P), ctypes.POINTER(Params), P, ctypes.POINTER(P)],
+        "lxw_batch_destroy": [P],
+        "lxw_batch_set_state": [P, I32, P, D, I32],
+        "lxw_batch_get_state": [P, I32, P, dp, I32],
+        "lxw_batch_advance_steps": [P, I64],
+        "lxw_batch_stats": [P, I32, ctypes.POINTER(Stats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -90,6 +104,8 @@ def _load():
         f.restype = ctypes.c_int32
     L.lxw_last_error.argtypes = []
     L.lxw_last_error.restype = ctypes.c_char_p
+    L.lxw_batch_solver.argtypes = [P]
+    L.lxw_batch_solver.restype = P
     return L
 
 
@@ -204,7 +220,47 @@ class Mesh:
         return np.einsum("m,nmv,ml->nvl", w, np.asarray(vals, dtype=np.float64), phi)
 
 
-class Solver:
+class _Ops:
+    """Calls shared by a solver and the solver that runs a batch."""
+
+    def run_steps(self, n):
+        _check(_L.lxw_run_steps(self._sh(), n))
+
+    def sync(self):
+        _check(_L.lxw_sync(self._sh()))
+
+    def set_timing(self, on=True):
+        _check(_L.lxw_set_timing(self._sh(), int(on)))
+
+    def kernel_times(self):
+        ms = np.zeros(K_COUNT)
+        n = np.zeros(K_COUNT, dtype=np.int64)
+        _check(_L.lxw_kernel_times(self._sh(), _dp(ms), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return {KERNEL_NAMES[k]: (float(ms[k]), int(n[k])) for k in range(K_COUNT)}
+
+    def set_graph(self, on=True):
+        _check(_L.lxw_set_graph(self._sh(), int(on)))
+
+    def get_tune(self):
+        t = Tune()
+        _check(_L.lxw_get_tune(self._sh(), ctypes.byref(t)))
+        return {KERNEL_NAMES[k]: int(t.block[k]) for k in range(K_COUNT)}
+
+    def set_tune(self, blocks):
+        """blocks: {kernel name: workgroup size} for any of the tunable kernels."""
+        t = Tune()
+        _check(_L.lxw_get_tune(self._sh(), ctypes.byref(t)))
+        for name, b in blocks.items():
+            t.block[KERNEL_NAMES.index(name)] = int(b)
+        _check(_L.lxw_set_tune(self._sh(), ctypes.byref(t)))
+
+    def autotune(self, trial_steps=3):
+        t = Tune()
+        _check(_L.lxw_autotune(self._sh(), trial_steps, ctypes.byref(t)))
+        return {KERNEL_NAMES[k]: int(t.block[k]) for k in range(K_COUNT)}
+
+
+class Solver(_Ops):
     def __init__(self, mesh, stream=None, **params):
         self.mesh = mesh
         self.params = default_params(**params)
@@ -220,6 +276,9 @@ class Solver:
         if getattr(self, "h", None):
             _destroy(self.h)
             self.h = None
+
+    def _sh(self):
+        return self.h
 
     @property
     def shape(self):
@@ -253,12 +312,6 @@ class Solver:
         _check(_L.lxw_advance(self.h, T, max_steps, ctypes.byref(st)))
         return st
 
-    def run_steps(self, n):
-        _check(_L.lxw_run_steps(self.h, n))
-
-    def sync(self):
-        _check(_L.lxw_sync(self.h))
-
     def set_debug(self, on=True):
         _check(_L.lxw_set_debug(self.h, int(on)))
 
@@ -271,11 +324,50 @@ class Solver:
         _check(_L.lxw_debug_stage(self.h, stage, _dp(out)))
         return out
 
-    def set_timing(self, on=True):
-        _check(_L.lxw_set_timing(self.h, int(on)))
 
-    def kernel_times(self):
-        ms = np.zeros(K_COUNT)
-        n = np.zeros(K_COUNT, dtype=np.int64)
-        _check(_L.lxw_kernel_times(self.h, _dp(ms), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
-        return {KERNEL_NAMES[k]: (float(ms[k]), int(n[k])) for k in range(K_COUNT)}
+class Batch(_Ops):
+    """Independent meshes of one kind advanced together (lxw_batch_*): per-mesh s, dt and t."""
+
+    def __init__(self, meshes, stream=None, **params):
+        self.meshes = list(meshes)
+        self.params = default_params(**params)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m.h.value if isinstance(m.h, ctypes.c_void_p) else m.h
+                                                      for m in self.meshes])
+        h = ctypes.c_void_p()
+        _check(_L.lxw_batch_create(len(self.meshes), arr, ctypes.byref(self.params),
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self, _destroy=_L.lxw_batch_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def _sh(self):
+        return _L.lxw_batch_solver(self.h)
+
+    def shape(self, i):
+        m = self.meshes[i]
+        return (m.N, m.V, m.ML)
+
+    def set_state(self, i, Q, t0=0.0):
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        assert Q.shape == self.shape(i), (Q.shape, self.shape(i))
+        _check(_L.lxw_batch_set_state(self.h, i, Q.ctypes.data_as(ctypes.c_void_p), t0, HOST_PTR))
+
+    def get_state(self, i):
+        t = ctypes.c_double(0.0)
+        Q = np.zeros(self.shape(i))
+        _check(_L.lxw_batch_get_state(self.h, i, Q.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t), HOST_PTR))
+        return Q, t.value
+
+    def advance_steps(self, n):
+        _check(_L.lxw_batch_advance_steps(self.h, n))
+
+    def stats(self, i):
+        st = Stats()
+        _check(_L.lxw_batch_stats(self.h, i, ctypes.byref(st)))
+        return st

@@ -1,0 +1,206 @@
+"""GPU tests of the batched form, graph replay and launch-shape tuning (through the C interface).
+
+A batch concatenates independent meshes; each mesh keeps its own wave speed, time step and time,
+and must evolve exactly as a single-mesh solver of that mesh does (same kernels, same arithmetic,
+so bit for bit).  Graph replays are checked against eager launches with the program's own eager
+work and synchronisations between replays; tuning must leave the state untouched and change no
+result bit.  One step of batched meshes is also compared with the FP64 oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_08145_amd import inputs as I
+from tests.helpers import rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1601_08145_amd import lxw
+    return lxw
+
+
+def per_var_rel_l1(a, b):
+    return max(rel_l1(a[:, v], b[:, v]) for v in range(a.shape[1]))
+
+
+def small_batch(L, sizes=(9, 14, 6, 21, 11), seed=3):
+    """Uneven vortex + shock meshes (lattice sides `sizes`), shared kernel launches."""
+    cases = [I.batch_case(n, seed * 1000 + b) for b, n in enumerate(sizes)]
+    meshes = [L.Mesh.tri(xy, tri) for xy, tri, _ in cases]
+    return cases, meshes
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_matches_single_solvers_bitwise(L, prec):
+    print(f"[gpu] batch vs single solvers, precision {prec}", flush=True)
+    cases, meshes = small_batch(L)
+    B = L.Batch(meshes, precision=prec)
+    for b, (_, _, Q) in enumerate(cases):
+        B.set_state(b, Q)
+    singles = []
+    for b, (_, _, Q) in enumerate(cases):
+        S = L.Solver(meshes[b], precision=prec)
+        S.set_state(Q)
+        singles.append(S)
+    # three chunks of graph replays with eager read-outs and synchronisations in between
+    for chunk in range(3):
+        B.advance_steps(4)
+        for S in singles:
+            for _ in range(4):
+                S.step()
+        for b, S in enumerate(singles):
+            Qb, tb = B.get_state(b)
+            Qs, ts = S.get_state()
+            st = B.stats(b)
+            assert st.steps == 4 * (chunk + 1)
+            assert tb == ts, (chunk, b)
+            assert np.array_equal(Qb, Qs), (chunk, b, np.abs(Qb - Qs).max())
+    # meshes with different wave speeds took different time steps
+    ts = [B.stats(b).t for b in range(len(meshes))]
+    assert len(set(ts)) > 1
+
+
+def test_batch_one_step_vs_oracle(L):
+    print("[gpu] batch one step vs oracle", flush=True)
+    cases, meshes = small_batch(L, sizes=(12, 7, 17), seed=5)
+    B = L.Batch(meshes)
+    for b, (_, _, Q) in enumerate(cases):
+        B.set_state(b, Q)
+    B.advance_steps(1)
+    for b, (xy, tri, Q) in enumerate(cases):
+        Ob = O.Solver(O.Mesh.tri(xy, tri))
+        Ob.set_state(Q)
+        Ob.step()
+        Qo, to = Ob.get_state()
+        Qg, tg = B.get_state(b)
+        assert tg == pytest.approx(to, rel=1e-11)
+        assert per_var_rel_l1(Qg, Qo) <= 1e-12
+
+
+def test_batch_state_is_per_mesh(L):
+    """Setting one mesh's state restarts only that mesh's time and step count."""
+    cases, meshes = small_batch(L, sizes=(8, 10))
+    B = L.Batch(meshes)
+    for b, (_, _, Q) in enumerate(cases):
+        B.set_state(b, Q)
+    B.advance_steps(3)
+    B.set_state(1, cases[1][2], t0=0.5)
+    s0, s1 = B.stats(0), B.stats(1)
+    assert s0.steps == 3 and s0.t > 0
+    assert s1.steps == 0 and s1.t == 0.5
+    Q1, t1 = B.get_state(1)
+    assert t1 == 0.5 and np.array_equal(Q1, cases[1][2])
+
+
+def test_batch_errors(L):
+    cases, meshes = small_batch(L, sizes=(8, 10))
+    with pytest.raises(L.LxwError) as e:
+        L.Batch([meshes[0], L.Mesh.line(20, 0, 1, 1, 1)])
+    assert e.value.name == "LXW_ERR_ARG"
+    with pytest.raises(L.LxwError):
+        L.Batch([])
+    B = L.Batch(meshes)
+    import ctypes
+    Q0 = np.ascontiguousarray(cases[0][2])
+    assert L.lib().lxw_batch_set_state(B.h, 2, Q0.ctypes.data_as(ctypes.c_void_p), 0.0, 0) == -1
+    assert L.lib().lxw_batch_set_state(B.h, -1, Q0.ctypes.data_as(ctypes.c_void_p), 0.0, 0) == -1
+    bad = cases[1][2].copy()
+    bad[3, 0, 0] = -1.0
+    with pytest.raises(L.LxwError) as e:
+        B.set_state(1, bad)
+    assert e.value.name == "LXW_ERR_STATE" and "element 3" in e.value.msg
+    # single-mesh calls refuse the batch's solver
+    lib = L.lib()
+    assert lib.lxw_set_debug(B._sh(), 1) == -2
+    assert lib.lxw_step(B._sh(), 1.0, None) == -2
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replay_matches_eager(L, prec):
+    xy, tri, Q = I.batch_case(25, 77)
+    m = L.Mesh.tri(xy, tri)
+    res = []
+    for graph in (True, False):
+        S = L.Solver(m, precision=prec)
+        S.set_graph(graph)
+        S.set_state(Q)
+        for _ in range(3):
+            S.run_steps(5)
+            S.sync()
+            res.append(S.get_state())
+    for k in range(3):
+        assert np.array_equal(res[k][0], res[3 + k][0]) and res[k][1] == res[3 + k][1]
+
+
+def test_launch_shapes_change_no_bit(L):
+    xy, tri, Q = I.batch_case(30, 78)
+    m = L.Mesh.tri(xy, tri)
+    out = []
+    for shape in (64, 128, 256):
+        S = L.Solver(m, precision=1)
+        S.set_tune({k: shape for k in ("k_pre", "k_elem", "k_edge", "k_flim", "k_update")})
+        S.set_state(Q)
+        S.run_steps(6)
+        out.append(S.get_state())
+    for k in (1, 2):
+        assert np.array_equal(out[0][0], out[k][0]) and out[0][1] == out[k][1]
+    S = L.Solver(m)
+    with pytest.raises(L.LxwError) as e:
+        S.set_tune({"k_elem": 96})
+    assert e.value.name == "LXW_ERR_ARG"
+
+
+def test_autotune_leaves_state_and_trajectory(L):
+    print("[gpu] autotune", flush=True)
+    cases, meshes = small_batch(L, sizes=(30, 12, 45), seed=9)
+    ref = L.Batch(meshes, precision=1)
+    B = L.Batch(meshes, precision=1)
+    for b, (_, _, Q) in enumerate(cases):
+        ref.set_state(b, Q)
+        B.set_state(b, Q)
+    ref.advance_steps(2)
+    B.advance_steps(2)
+    before = [B.get_state(b) for b in range(3)]
+    tune = B.autotune(2)
+    assert all(tune[k] in (64, 128, 256) for k in ("k_pre", "k_elem", "k_edge", "k_flim", "k_update"))
+    assert B.get_tune() == tune
+    for b in range(3):
+        Qb, tb = B.get_state(b)
+        assert np.array_equal(Qb, before[b][0]) and tb == before[b][1]
+        assert B.stats(b).steps == 2
+    ref.advance_steps(5)
+    B.advance_steps(5)
+    for b in range(3):
+        assert np.array_equal(B.get_state(b)[0], ref.get_state(b)[0])
+
+
+@pytest.mark.skipif(os.environ.get("LXW_SKIP_FULL") == "1", reason="full-size case skipped on request")
+def test_full_size_batch_sampled(L):
+    """The batched workload at full size (512 meshes, 2k-60k triangles each, FP32-mixed, graph
+    replay, the launch shapes the benchmark tunes): after one step, the smallest, the largest and
+    a middle mesh against one FP64 oracle step each."""
+    print("[gpu] full-size batch: building 512 meshes", flush=True)
+    sizes = I.batch_sizes(512, 0)
+    work = I.batch_workload_parallel(512, 0)
+    meshes = [L.Mesh.tri(xy, tri) for xy, tri, _ in work]
+    B = L.Batch(meshes, precision=1)
+    for b in range(len(meshes)):
+        B.set_state(b, work[b][2])
+    B.autotune(1)
+    B.advance_steps(1)
+    order = np.argsort(sizes)
+    for b in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        xy, tri, Q = work[b]
+        Ob = O.Solver(O.Mesh.tri(xy, tri))
+        Ob.set_state(Q)
+        Ob.step()
+        Qo, to = Ob.get_state()
+        Qg, tg = B.get_state(b)
+        err = per_var_rel_l1(Qg, Qo)
+        print(f"[gpu]   mesh {b} ({meshes[b].N} triangles): rel L1 {err:.3e}", flush=True)
+        assert tg == pytest.approx(to, rel=1e-6)
+        assert err <= 1e-6
