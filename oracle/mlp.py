@@ -10,7 +10,9 @@ layer by layer, for the GPU kernels to be checked against.  Only the tests use i
 Features (48 per triangle): cells c = (i, n_0, n_1, n_2), n_k the neighbour across local edge k
 (i itself where edge k is on the boundary); variables rho and E; for each variable the 24 values
 Q[c][var][l] (l = 0..5, cell-major), with the centre cell's average subtracted from the four
-mode-1 entries, divided by (max |value| + 1e-30).  Feature index = var * 24 + c * 6 + l.
+mode-1 entries, divided by (max |value| + 1e-6 |centre average| + 1e-30).  The floor keeps a
+uniform region at features near zero instead of normalising its round-off to unit size.
+Feature index = var * 24 + c * 6 + l.
 
 Network: 48 -> 64 (ReLU) -> 64 (ReLU) -> 1 (sigmoid).  Parameters in one flat vector:
 W1[48][64], b1[64], W2[64][64], b2[64], w3[64], b3 (7,361 values).
@@ -61,7 +63,7 @@ def features(Q, nb):
         vals = Q[cells, var, :].copy()            # N x 4 x 6
         vals[:, :, 0] -= Q[:, var, 0][:, None]    # averages relative to the centre cell
         vals = vals.reshape(N, 24)
-        scale = np.abs(vals).max(axis=1) + 1e-30
+        scale = np.abs(vals).max(axis=1) + 1e-6 * np.abs(Q[:, var, 0]) + 1e-30
         F[:, vi * 24:(vi + 1) * 24] = vals / scale[:, None]
     return F
 
