@@ -10,8 +10,11 @@ layer by layer, for the GPU kernels to be checked against.  Only the tests use i
 Features (48 per triangle): cells c = (i, n_0, n_1, n_2), n_k the neighbour across local edge k
 (i itself where edge k is on the boundary); variables rho and E; for each variable the 24 values
 Q[c][var][l] (l = 0..5, cell-major), with the centre cell's average subtracted from the four
-mode-1 entries, divided by (max |value| + 1e-6 |centre average| + 1e-30).  The floor keeps a
-uniform region at features near zero instead of normalising its round-off to unit size.
+mode-1 entries, divided by (max |value| + delta_i + 1e-6 |centre average| + 1e-30), where
+delta_i = alpha0 h_i^1.5 is the shock-capturing limiter's own relaxation of its bounds (h_i =
+sqrt(2 |T_i|)).  The floor carries the magnitude the limiter's decision depends on: variations far
+below delta_i (which the limiter never acts on) give features near zero, variations far above it
+give their normalised shape; and a uniform region's round-off is never normalised to unit size.
 Feature index = var * 24 + c * 6 + l.
 
 Network: 48 -> 64 (ReLU) -> 64 (ReLU) -> 1 (sigmoid).  Parameters in one flat vector:
@@ -54,8 +57,17 @@ def tri_neighbours(tri):
     return nb
 
 
-def features(Q, nb):
-    """48 features per triangle from modal coefficients Q[N][4][6] and neighbours nb[N][3]."""
+def tri_delta(xy, tri, alpha0=500.0):
+    """delta_i = alpha0 h_i^1.5 with h_i = sqrt(2 |T_i|)."""
+    a = np.asarray(xy, dtype=np.float64)[np.asarray(tri)]
+    area = 0.5 * np.abs((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1])
+                        - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0]))
+    return alpha0 * np.sqrt(2.0 * area) ** 1.5
+
+
+def features(Q, nb, delta):
+    """48 features per triangle from modal coefficients Q[N][4][6], neighbours nb[N][3] and the
+    limiter relaxation delta[N]."""
     N = Q.shape[0]
     cells = np.concatenate([np.arange(N)[:, None], np.where(nb >= 0, nb, np.arange(N)[:, None])], axis=1)
     F = np.zeros((N, N_IN))
@@ -63,7 +75,7 @@ def features(Q, nb):
         vals = Q[cells, var, :].copy()            # N x 4 x 6
         vals[:, :, 0] -= Q[:, var, 0][:, None]    # averages relative to the centre cell
         vals = vals.reshape(N, 24)
-        scale = np.abs(vals).max(axis=1) + 1e-6 * np.abs(Q[:, var, 0]) + 1e-30
+        scale = np.abs(vals).max(axis=1) + delta + 1e-6 * np.abs(Q[:, var, 0]) + 1e-30
         F[:, vi * 24:(vi + 1) * 24] = vals / scale[:, None]
     return F
 

@@ -93,10 +93,10 @@ def test_neighbours_and_hand_computed_features():
     Q[1, 0, :] = [3.0, 0.0, 0.0, 0.0, 0.0, 0.0]
     Q[0, 3, 0] = 2.0
     Q[1, 3, 0] = 2.0
-    F = M.features(Q, nb)
-    # t0, rho: cells (0, 0, 1, 0): averages 0, 0, 2, 0 relative to 1.0; scale 2 + 1e-6 * 1
+    F = M.features(Q, nb, np.array([0.25, 0.5]))
+    # t0, rho: cells (0, 0, 1, 0): averages 0, 0, 2, 0 relative to 1.0; scale 2 + 0.25 + 1e-6 * 1
     rho = F[0, :24].reshape(4, 6)
-    sc = 2.0 + 1e-6
+    sc = 2.0 + 0.25 + 1e-6
     assert np.allclose(rho[0], np.array([0.0, 0.2, 0, 0, 0, 0.1]) / sc, rtol=1e-14)
     assert np.allclose(rho[2], np.array([2.0, 0, 0, 0, 0, 0]) / sc, rtol=1e-14)
     assert np.allclose(rho[1], rho[0]) and np.allclose(rho[3], rho[0])
@@ -104,19 +104,29 @@ def test_neighbours_and_hand_computed_features():
     assert np.all(F[:, 24:] == 0.0)
 
 
-def test_features_scale_invariant_and_bounded():
+def test_features_bounded_and_magnitude_aware():
     g = np.random.default_rng(7)
     from paper_1601_08145_amd import inputs as I
     xy, tri = I.lattice_delaunay(12, 3)
     nb = M.tri_neighbours(tri)
+    delta = M.tri_delta(xy, tri, alpha0=0.5)
     Q = I.random_modal_state(len(tri), 2, 6, seed=4, amp=0.5)
-    F = M.features(Q, nb)
-    assert np.allclose(M.features(3.7 * Q, nb), F, rtol=1e-13, atol=1e-15)
+    F = M.features(Q, nb, delta)
+    assert np.all(np.abs(F) < 1.0)
+    # without a relaxation the normalisation is by the largest value: scale invariant, max 1
+    F0 = M.features(Q, nb, 0.0 * delta)
+    assert np.allclose(M.features(3.7 * Q, nb, 0.0 * delta), F0, rtol=1e-5, atol=1e-7)
     for vi in range(2):
-        blk = np.abs(F[:, vi * 24:(vi + 1) * 24])
-        assert np.all(blk.max(axis=1) <= 1.0) and np.allclose(blk.max(axis=1), 1.0, rtol=1e-5)
-    # a uniform state plus round-off gives features near zero (the floor), not unit-size noise
+        assert np.allclose(np.abs(F0[:, vi * 24:(vi + 1) * 24]).max(axis=1), 1.0, rtol=1e-5)
+    # variations far below delta give features near zero, far above it their normalised shape
+    small = 1e-6 * Q
+    small[:, :, 0] += 1.0
+    assert np.abs(M.features(small, nb, delta)).max() < 1e-3
+    # the tri_delta geometry: h = sqrt(2 |T|) is the lattice spacing of a split unit square
+    xs, ts = np.array([[0, 0], [1, 0], [0, 1]], float), np.array([[0, 1, 2]])
+    assert M.tri_delta(xs, ts, 500.0)[0] == pytest.approx(500.0)
+    # a uniform state plus round-off gives features near zero, not unit-size noise
     U = np.zeros_like(Q)
     U[:, :, 0] = Q[0, :, 0]
     U[:, :, 1:] = 1e-17 * g.standard_normal(U[:, :, 1:].shape)
-    assert np.abs(M.features(U, nb)).max() < 1e-9
+    assert np.abs(M.features(U, nb, 0.0 * delta)).max() < 1e-9
