@@ -54,7 +54,8 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one k_elem launch on the 2D triangle workload from rocprofv3 counters
 # (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid only for the kernel
 # source it was measured on.
-KELEM_TRAFFIC = {"src_sha256": None, "bytes_per_launch": None}
+KELEM_TRAFFIC = {"src_sha256": "2d9c5d923c02d33e6eb27a9caf01a0f6cc31d2ea058293a22ddbb064587cc937",
+                 "bytes_per_launch": 1222619776}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def kernel_src_hash():
@@ -205,6 +206,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-mesh batched leg")
+    ap.add_argument("--batched-only", action="store_true", help="run only the batched leg (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -227,6 +229,10 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_1601_08145_amd import lxw as L
+
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(L, args.steps, args.warmup)}), flush=True)
+        return
 
     xy, tri, Q0 = build_workload()
     mesh = L.Mesh.tri(xy, tri)

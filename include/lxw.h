@@ -80,6 +80,7 @@ enum { LXW_HOST_PTR = 0, LXW_DEVICE_PTR = 1 };
 typedef struct lxw_mesh lxw_mesh;
 typedef struct lxw_solver lxw_solver;
 typedef struct lxw_batch lxw_batch;
+typedef struct lxw_indicator lxw_indicator;
 
 typedef struct lxw_params {
   double gamma;      /* ratio of specific heats, Eq. (eos); > 1 */
@@ -266,6 +267,72 @@ lxw_status lxw_batch_stats(lxw_batch* b, int32_t i, lxw_stats* out);
  * lxw_step, lxw_advance, lxw_set_state, lxw_get_state and lxw_set_debug return
  * LXW_ERR_UNSUPPORTED on it).  Owned by the batch. */
 lxw_solver* lxw_batch_solver(lxw_batch* b);
+
+/* ---- Learned troubled-cell indicator (P2 triangles) ---------------------------------------
+ * The paper detects troubled cells with the shock-capturing limiter it cites (Sec. 1.5 Step 5,
+ * Sec. 4.1).  The learned form keeps that limiter and the positivity limiters of Secs. 3.1-3.3 and
+ * replaces only the detection: a multilayer perceptron 48 -> 64 (ReLU) -> 64 (ReLU) -> 1 (sigmoid)
+ * gives each cell a probability p that the shock-capturing limiter acts on it; cells with
+ * p < tau_lo skip that limiter, cells with p >= tau_hi are flagged and the rest use the plain
+ * detection (both run the limiter, which then acts only where its bounds are violated).
+ * Features (48 per triangle): cells c = (i, n_0, n_1, n_2), n_k the neighbour across local edge k
+ * (i itself on the boundary); for rho and then E the 24 values Q[c][var][l] (c-major, l = 0..5)
+ * with the centre cell's average subtracted from the four mode-1 entries, divided by
+ * (max |value| + delta_i + 1e-6 |centre average| + 1e-30), delta_i = alpha0 h_i^1.5 the
+ * shock-capturing limiter's relaxation (h_i = sqrt(2 |T_i|)).  Parameters: one float32 vector of LXW_IND_NPARAM values W1[48][64],
+ * b1[64], W2[64][64], b2[64], w3[64], b3 (row-major, input index first).  Inference runs the
+ * two hidden layers on the bf16 matrix cores (inputs, weights and hidden activations rounded to
+ * bfloat16, float32 accumulation); training runs in float32.  Random numbers (initial weights,
+ * sample order) come from the caller. */
+enum { LXW_IND_NFEAT = 48, LXW_IND_NPARAM = 7361 };
+
+typedef struct lxw_adam {
+  double lr, beta1, beta2, eps; /* Adam (Kingma & Ba); e.g. 1e-3, 0.9, 0.999, 1e-8 */
+  double w_pos, w_neg;          /* class weights of the cross-entropy (y = 1, y = 0) */
+} lxw_adam;
+
+/* Creates an indicator with parameters params (host, LXW_IND_NPARAM floats) whose kernels run on
+ * stream (a hipStream_t, null for the default stream). */
+lxw_status lxw_indicator_create(const float* params, void* stream, lxw_indicator** out);
+lxw_status lxw_indicator_destroy(lxw_indicator* ind);
+/* Master float32 parameters to / from host memory; setting them resets the Adam state. */
+lxw_status lxw_indicator_get_params(const lxw_indicator* ind, float* out);
+lxw_status lxw_indicator_set_params(lxw_indicator* ind, const float* params);
+/* Binary file: 8-byte tag "LXWIND01", int32 LXW_IND_NPARAM, the float32 parameters. */
+lxw_status lxw_indicator_save(const lxw_indicator* ind, const char* path);
+lxw_status lxw_indicator_load(lxw_indicator* ind, const char* path);
+
+/* Probabilities p[n] of features X[n][48] (device memory, float32) by the inference kernel. */
+lxw_status lxw_indicator_predict(lxw_indicator* ind, const float* X, int32_t n, float* p);
+
+/* Gradient of the class-weighted cross-entropy
+ *   L = -(1/n) sum_i [w_pos y_i log p_i + w_neg (1 - y_i) log(1 - p_i)]
+ * over X[n][48], y[n] (device, float32) by the training kernels: grad[LXW_IND_NPARAM] (host) and
+ * *loss (nullable).  Synchronous. */
+lxw_status lxw_indicator_grad(lxw_indicator* ind, const float* X, const float* y, int32_t n, double w_pos,
+                              double w_neg, float* grad, double* loss);
+
+/* n_updates Adam updates with float32 master weights; update u uses the minibatch of samples
+ * order[u*batch .. (u+1)*batch) of X[n_samples][48], y[n_samples] (all device memory; order
+ * entries outside [0, n_samples) are clamped).  *last_loss (nullable): the last minibatch's loss.
+ * Synchronous; the inference weights follow the new parameters. */
+lxw_status lxw_indicator_train(lxw_indicator* ind, const float* X, const float* y, int32_t n_samples,
+                               const int32_t* order, int32_t n_updates, int32_t batch, const lxw_adam* hp,
+                               double* last_loss);
+
+/* Training data from a solver whose shock-capturing limiter is pending (after lxw_step, with no
+ * state read in between): features X[n_elem][48] (float32) of the state that limiter is about to
+ * see and the factor theta_sc[n_elem] it will apply (1: the cell is left alone), both in the
+ * caller's element order, host or device memory per flags.  Changes nothing.  Single triangle
+ * meshes only (LXW_ERR_UNSUPPORTED else); LXW_ERR_ARG if no limiter is pending. */
+lxw_status lxw_indicator_collect(lxw_solver* s, float* X, double* theta_sc, int32_t flags);
+
+/* Uses ind (which must outlive the solver's use of it) for later steps of s; null restores the
+ * plain limiter everywhere.  Needs 0 <= tau_lo <= tau_hi <= 1.  Resets the decision counts. */
+lxw_status lxw_solver_set_indicator(lxw_solver* s, const lxw_indicator* ind, double tau_lo, double tau_hi);
+/* Decisions since lxw_solver_set_indicator: counts[3] = (skipped, plain detection, flagged), and
+ * (flags nullable) the last decision per element in the caller's order (0, 1, 2).  Synchronous. */
+lxw_status lxw_indicator_decisions(lxw_solver* s, int64_t* counts, uint8_t* flags);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblxw.so")
-SOURCES = [os.path.join(CSRC, "lxw_kernels.hip"), os.path.join(CSRC, "lxw_host.cpp")]
+SOURCES = [os.path.join(CSRC, "lxw_kernels.hip"), os.path.join(CSRC, "lxw_indicator.hip"),
+           os.path.join(CSRC, "lxw_host.cpp")]
 HEADERS = [os.path.join(CSRC, "lxw_internal.hpp"), os.path.join(os.path.dirname(HERE), "include", "lxw.h")]
 
 # Packed FP32 instructions are disabled for all device code (the compiler may otherwise form

@@ -457,6 +457,11 @@ struct lxw_solver {
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool use_graph = true;
+  // learned troubled-cell indicator (triangles): decisions per element, decision counts
+  const lxw_indicator* ind = nullptr;
+  unsigned char* ind_flag = nullptr;
+  unsigned long long* ind_counts = nullptr;
+  float tau_lo = 0.0f, tau_hi = 1.0f;
   ~lxw_solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap) (void)hipStreamDestroy(cap);
@@ -472,6 +477,29 @@ struct lxw_solver {
     bufs.push_back({p, count * sizeof(T)});
     *out = (T*)p;
     return LXW_OK;
+  }
+};
+
+// Learned troubled-cell indicator: FP32 master parameters with Adam moments, and the bf16 /
+// FP32 arrays the inference kernel reads (packed from the master parameters).
+struct lxw_indicator {
+  hipStream_t st = nullptr;
+  float* theta = nullptr;  // [IND_NPARAM]
+  float* m = nullptr;
+  float* v = nullptr;
+  int64_t t = 0;           // Adam updates so far
+  uint16_t* A1 = nullptr;  // [2][3][64][8]
+  uint16_t* A2 = nullptr;  // [2][4][64][8]
+  float* b1p = nullptr;    // [2][2][16]
+  float* b2p = nullptr;
+  float* w3p = nullptr;    // [2][2][16] + b3
+  float* part = nullptr;   // [part_blocks][IND_PART]
+  int part_blocks = 0;
+  float* scal = nullptr;   // [1] loss
+  std::vector<void*> bufs;
+  ~lxw_indicator() {
+    if (st) (void)hipStreamSynchronize(st);
+    for (void* p : bufs) (void)hipFree(p);
   }
 };
 
@@ -586,10 +614,49 @@ hipError_t launch_one(lxw_solver* S, const View<R>& v, KernelId k, double T, int
   return e;
 }
 
+IndW ind_weights(const lxw_solver* S) {
+  const lxw_indicator* I = S->ind;
+  IndW W{};
+  W.A1 = I->A1; W.A2 = I->A2; W.b1 = I->b1p; W.b2 = I->b2p; W.w3 = I->w3p;
+  W.tau_lo = S->tau_lo;
+  W.tau_hi = S->tau_hi;
+  return W;
+}
+
+// The learned indicator's decisions for the pending shock-capturing limiter (triangles only).
+template <class E, class R>
+hipError_t launch_ind_step(lxw_solver* S, const View<R>& v) {
+  if constexpr (E::kind == ElTri::kind) {
+    if (!S->ind) return hipSuccess;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (S->timing) {
+      if (S->ev_used == S->ev_pool.size()) {
+        hipEvent_t x, y;
+        if (hipEventCreate(&x) != hipSuccess || hipEventCreate(&y) != hipSuccess) return hipErrorOutOfMemory;
+        S->ev_pool.push_back({x, y});
+        S->ev_kid.push_back(0);
+      }
+      a = S->ev_pool[S->ev_used].first;
+      b = S->ev_pool[S->ev_used].second;
+      S->ev_kid[S->ev_used] = LXW_K_IND;
+      S->ev_used++;
+      hipError_t e = hipEventRecord(a, S->st);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_indicator<R>(v, ind_weights(S), S->ind_flag, S->ind_counts, S->st);
+    if (e == hipSuccess && S->timing) e = hipEventRecord(b, S->st);
+    return e;
+  } else {
+    (void)S; (void)v;
+    return hipSuccess;
+  }
+}
+
 template <class E, class R>
 lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v, double T) {
   const lxw_mesh& M = *S->M;
   const int V = M.V, ML = M.ML, N = M.N;
+  HIPCHK((launch_ind_step<E, R>(S, v)));
   HIPCHK((launch_one<E, R>(S, v, K_PRE, T, 0)));
   HIPCHK((launch_one<E, R>(S, v, K_DT, T, 0)));
   HIPCHK((launch_one<E, R>(S, v, K_ELEM, T, 0)));
@@ -606,6 +673,7 @@ lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v, double T) {
 
 template <class E, class R>
 lxw_status enqueue_shock_t(lxw_solver* S, const View<R>& v) {
+  HIPCHK((launch_ind_step<E, R>(S, v)));
   HIPCHK((launch_one<E, R>(S, v, K_SHOCK, 0.0, 1)));
   HIPCHK((launch_one<E, R>(S, v, K_FINAL, 0.0, 1)));
   return LXW_OK;
@@ -907,6 +975,97 @@ lxw_status run_steps_impl(lxw_solver* S, int64_t n_steps) {
     if (s) return s;
   }
   for (int64_t k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(S->gexec, S->st));
+  return LXW_OK;
+}
+
+// ---- learned indicator: host helpers ---------------------------------------------------------
+
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+
+// Pack the master parameters into the inference kernel's lane layout (see lxw_indicator.hip).
+lxw_status ind_pack(lxw_indicator* I) {
+  std::vector<float> th(IND_NPARAM);
+  HIPCHK(hipStreamSynchronize(I->st));
+  HIPCHK(hipMemcpy(th.data(), I->theta, IND_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  const float* W1 = &th[IND_OFF_W1];
+  const float* W2 = &th[IND_OFF_W2];
+  std::vector<uint16_t> A1(2 * 3 * 64 * 8), A2(2 * 4 * 64 * 8);
+  for (int mt = 0; mt < 2; ++mt)
+    for (int st = 0; st < 3; ++st)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          const int k = 16 * st + 8 * (l / 32) + e, m = 32 * mt + l % 32;
+          A1[((mt * 3 + st) * 64 + l) * 8 + e] = bf16_bits(W1[k * IND_NH + m]);
+        }
+  for (int mt2 = 0; mt2 < 2; ++mt2)
+    for (int mt = 0; mt < 2; ++mt)
+      for (int g = 0; g < 2; ++g)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e) {
+            const int kin = 32 * mt + 8 * (2 * g + e / 4) + 4 * (l / 32) + e % 4, mout = 32 * mt2 + l % 32;
+            A2[((mt2 * 4 + mt * 2 + g) * 64 + l) * 8 + e] = bf16_bits(W2[kin * IND_NH + mout]);
+          }
+  std::vector<float> b1p(64), b2p(64), w3p(65);
+  for (int mt = 0; mt < 2; ++mt)
+    for (int h = 0; h < 2; ++h)
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * mt + 8 * (r / 4) + 4 * h + r % 4;
+        b1p[(mt * 2 + h) * 16 + r] = th[IND_OFF_B1 + m];
+        b2p[(mt * 2 + h) * 16 + r] = th[IND_OFF_B2 + m];
+        w3p[(mt * 2 + h) * 16 + r] = th[IND_OFF_W3 + m];
+      }
+  w3p[64] = th[IND_OFF_B3];
+  HIPCHK(hipMemcpy(I->A1, A1.data(), A1.size() * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I->A2, A2.data(), A2.size() * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I->b1p, b1p.data(), 64 * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I->b2p, b2p.data(), 64 * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I->w3p, w3p.data(), 65 * 4, hipMemcpyHostToDevice));
+  return LXW_OK;
+}
+
+template <class T>
+lxw_status ind_alloc(lxw_indicator* I, T** p, size_t n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T));
+  if (e != hipSuccess) return fail(LXW_ERR_OOM, "indicator allocation");
+  I->bufs.push_back(q);
+  *p = (T*)q;
+  return LXW_OK;
+}
+
+lxw_status ind_part(lxw_indicator* I, int nblk) {
+  if (nblk <= I->part_blocks) return LXW_OK;
+  lxw_status s = ind_alloc(I, &I->part, (size_t)nblk * IND_PART);
+  if (s) return s;
+  I->part_blocks = nblk;
+  return LXW_OK;
+}
+
+lxw_status ind_set_theta(lxw_indicator* I, const float* p) {
+  for (int j = 0; j < IND_NPARAM; ++j)
+    if (!std::isfinite(p[j])) return fail(LXW_ERR_ARG, "non-finite indicator parameter " + std::to_string(j));
+  std::vector<float> z(IND_NPARAM, 0.0f);
+  HIPCHK(hipStreamSynchronize(I->st));
+  HIPCHK(hipMemcpy(I->theta, p, IND_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I->m, z.data(), IND_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I->v, z.data(), IND_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  I->t = 0;
+  return ind_pack(I);
+}
+
+template <class E, class R>
+lxw_status collect_t(lxw_solver* S, const View<R>& v, float* Xd, double* thd) {
+  HIPCHK(launch_features<R>(v, Xd, S->st));
+  View<R> w = v;
+  w.theta = thd;  // k_pre mode 2 stores the factor there
+  HIPCHK((launch<E, R>(K_SHOCK, w, S->cfg, S->st, S->n_mesh, 0.0, 2)));
+  HIPCHK(hipStreamSynchronize(S->st));
   return LXW_OK;
 }
 
@@ -1504,6 +1663,218 @@ lxw_status lxw_batch_stats(lxw_batch* B, int32_t i, lxw_stats* out) {
   out->t = x.t;
   out->last_dt = x.dt;
   out->last_s = x.s;
+  return LXW_OK;
+}
+
+// ---- learned troubled-cell indicator --------------------------------------------------------
+
+lxw_status lxw_indicator_create(const float* params, void* stream, lxw_indicator** out) {
+  if (!params || !out) return fail(LXW_ERR_ARG, "null argument");
+  *out = nullptr;
+  lxw_status s = ensure_init();
+  if (s) return s;
+  std::unique_ptr<lxw_indicator> I(new (std::nothrow) lxw_indicator);
+  if (!I) return fail(LXW_ERR_OOM, "host allocation");
+  I->st = (hipStream_t)stream;
+  if ((s = ind_alloc(I.get(), &I->theta, IND_NPARAM)) || (s = ind_alloc(I.get(), &I->m, IND_NPARAM)) ||
+      (s = ind_alloc(I.get(), &I->v, IND_NPARAM)) || (s = ind_alloc(I.get(), &I->A1, 2 * 3 * 64 * 8)) ||
+      (s = ind_alloc(I.get(), &I->A2, 2 * 4 * 64 * 8)) || (s = ind_alloc(I.get(), &I->b1p, 64)) ||
+      (s = ind_alloc(I.get(), &I->b2p, 64)) || (s = ind_alloc(I.get(), &I->w3p, 65)) ||
+      (s = ind_alloc(I.get(), &I->scal, 1)))
+    return s;
+  if ((s = ind_set_theta(I.get(), params))) return s;
+  *out = I.release();
+  return LXW_OK;
+}
+
+lxw_status lxw_indicator_destroy(lxw_indicator* ind) {
+  delete ind;
+  return LXW_OK;
+}
+
+lxw_status lxw_indicator_get_params(const lxw_indicator* I, float* out) {
+  if (!I || !out) return fail(LXW_ERR_ARG, "null argument");
+  HIPCHK(hipStreamSynchronize(I->st));
+  HIPCHK(hipMemcpy(out, I->theta, IND_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  return LXW_OK;
+}
+
+lxw_status lxw_indicator_set_params(lxw_indicator* I, const float* p) {
+  if (!I || !p) return fail(LXW_ERR_ARG, "null argument");
+  return ind_set_theta(I, p);
+}
+
+static const char IND_MAGIC[8] = {'L', 'X', 'W', 'I', 'N', 'D', '0', '1'};
+
+lxw_status lxw_indicator_save(const lxw_indicator* I, const char* path) {
+  if (!I || !path) return fail(LXW_ERR_ARG, "null argument");
+  std::vector<float> th(IND_NPARAM);
+  lxw_status s = lxw_indicator_get_params(I, th.data());
+  if (s) return s;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(LXW_ERR_ARG, std::string("cannot open ") + path);
+  const int32_t n = IND_NPARAM;
+  bool ok = std::fwrite(IND_MAGIC, 1, 8, f) == 8 && std::fwrite(&n, 4, 1, f) == 1 &&
+            std::fwrite(th.data(), 4, IND_NPARAM, f) == (size_t)IND_NPARAM;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? LXW_OK : fail(LXW_ERR_ARG, std::string("write failed: ") + path);
+}
+
+lxw_status lxw_indicator_load(lxw_indicator* I, const char* path) {
+  if (!I || !path) return fail(LXW_ERR_ARG, "null argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(LXW_ERR_ARG, std::string("cannot open ") + path);
+  char mg[8];
+  int32_t n = 0;
+  std::vector<float> th(IND_NPARAM);
+  bool ok = std::fread(mg, 1, 8, f) == 8 && std::memcmp(mg, IND_MAGIC, 8) == 0 && std::fread(&n, 4, 1, f) == 1 &&
+            n == IND_NPARAM && std::fread(th.data(), 4, IND_NPARAM, f) == (size_t)IND_NPARAM;
+  std::fclose(f);
+  if (!ok) return fail(LXW_ERR_ARG, std::string("not an indicator parameter file: ") + path);
+  return ind_set_theta(I, th.data());
+}
+
+lxw_status lxw_indicator_predict(lxw_indicator* I, const float* X, int32_t n, float* p) {
+  if (!I || (n > 0 && (!X || !p))) return fail(LXW_ERR_ARG, "null argument");
+  if (n < 0) return fail(LXW_ERR_ARG, "negative sample count");
+  IndW W{};
+  W.A1 = I->A1; W.A2 = I->A2; W.b1 = I->b1p; W.b2 = I->b2p; W.w3 = I->w3p;
+  W.tau_lo = 0.0f; W.tau_hi = 1.0f;
+  HIPCHK(launch_predict(W, X, n, p, I->st));
+  HIPCHK(hipStreamSynchronize(I->st));
+  return LXW_OK;
+}
+
+lxw_status lxw_indicator_grad(lxw_indicator* I, const float* X, const float* y, int32_t n, double w_pos, double w_neg,
+                              float* grad, double* loss) {
+  if (!I || !X || !y || !grad) return fail(LXW_ERR_ARG, "null argument");
+  if (n < 1) return fail(LXW_ERR_ARG, "need at least one sample");
+  const int nblk = mlp_blocks(n);
+  lxw_status s = ind_part(I, nblk);
+  if (s) return s;
+  float* gd = nullptr;
+  HIPCHK(hipMalloc(&gd, IND_NPARAM * sizeof(float)));
+  TrainArgs a{X, y, nullptr, n, 0, n, (float)w_pos, (float)w_neg, 1.0f / (float)n, I->theta, I->part};
+  hipError_t e = launch_mlp_grad(a, I->st);
+  if (e == hipSuccess) e = launch_mlp_reduce(nblk, I->part, I->theta, I->m, I->v, gd, I->scal, 0, 0, 0, 0, 0, 1, 1, I->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(I->st);
+  float lf = 0.0f;
+  if (e == hipSuccess) e = hipMemcpy(grad, gd, IND_NPARAM * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&lf, I->scal, sizeof(float), hipMemcpyDeviceToHost);
+  (void)hipFree(gd);
+  HIPCHK(e);
+  if (loss) *loss = lf;
+  return LXW_OK;
+}
+
+lxw_status lxw_indicator_train(lxw_indicator* I, const float* X, const float* y, int32_t n_samples,
+                               const int32_t* order, int32_t n_updates, int32_t batch, const lxw_adam* hp,
+                               double* last_loss) {
+  if (!I || !X || !y || !order || !hp) return fail(LXW_ERR_ARG, "null argument");
+  if (n_samples < 1 || batch < 1 || n_updates < 0) return fail(LXW_ERR_ARG, "need n_samples >= 1, batch >= 1, n_updates >= 0");
+  if (!(hp->lr > 0) || !(hp->beta1 >= 0 && hp->beta1 < 1) || !(hp->beta2 >= 0 && hp->beta2 < 1) || !(hp->eps > 0) ||
+      !(hp->w_pos > 0) || !(hp->w_neg > 0))
+    return fail(LXW_ERR_ARG, "bad Adam or class-weight parameters");
+  const int nblk = mlp_blocks(batch);
+  lxw_status s = ind_part(I, nblk);
+  if (s) return s;
+  for (int32_t u = 0; u < n_updates; ++u) {
+    TrainArgs a{X, y, order, n_samples, u * batch, batch, (float)hp->w_pos, (float)hp->w_neg, 1.0f / (float)batch,
+                I->theta, I->part};
+    I->t += 1;
+    const double bc1 = 1.0 - std::pow(hp->beta1, (double)I->t), bc2 = 1.0 - std::pow(hp->beta2, (double)I->t);
+    HIPCHK(launch_mlp_grad(a, I->st));
+    HIPCHK(launch_mlp_reduce(nblk, I->part, I->theta, I->m, I->v, nullptr, I->scal, 1, (float)hp->lr, (float)hp->beta1,
+                             (float)hp->beta2, (float)hp->eps, (float)bc1, (float)bc2, I->st));
+  }
+  HIPCHK(hipStreamSynchronize(I->st));
+  if (last_loss) {
+    float lf = 0.0f;
+    HIPCHK(hipMemcpy(&lf, I->scal, sizeof(float), hipMemcpyDeviceToHost));
+    *last_loss = n_updates > 0 ? lf : 0.0;
+  }
+  return ind_pack(I);
+}
+
+lxw_status lxw_indicator_collect(lxw_solver* S, float* X, double* theta_sc, int32_t flags) {
+  if (check_solver(S) || !X || !theta_sc) return fail(LXW_ERR_ARG, "null argument");
+  if (S->M->kind != LXW_TRI || S->batch) return fail(LXW_ERR_UNSUPPORTED, "the indicator is for single triangle meshes");
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  if (!S->hsc.shock_pending || !S->P.shock)
+    return fail(LXW_ERR_ARG, "no shock-capturing limiter pending: take a step first (and read no state in between)");
+  const int N = S->M->N;
+  float* Xd = nullptr;
+  double* td = nullptr;
+  HIPCHK(hipMalloc(&Xd, (size_t)N * IND_NIN * sizeof(float)));
+  if (hipMalloc(&td, (size_t)(N ? N : 1) * sizeof(double)) != hipSuccess) {
+    (void)hipFree(Xd);
+    return fail(LXW_ERR_OOM, "collect buffers");
+  }
+  s = S->fp32 ? collect_t<ElTri, float>(S, S->vf, Xd, td) : collect_t<ElTri, double>(S, S->vd, Xd, td);
+  std::vector<float> xh((size_t)N * IND_NIN);
+  std::vector<double> th(N);
+  hipError_t e = hipSuccess;
+  if (!s) e = hipMemcpy(xh.data(), Xd, xh.size() * sizeof(float), hipMemcpyDeviceToHost);
+  if (!s && e == hipSuccess) e = hipMemcpy(th.data(), td, th.size() * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(Xd);
+  (void)hipFree(td);
+  if (s) return s;
+  HIPCHK(e);
+  std::vector<float> xo(xh.size());
+  std::vector<double> to(N);
+  for (int i = 0; i < N; ++i) {
+    const int c = S->M->perm[i];
+    std::memcpy(&xo[(size_t)c * IND_NIN], &xh[(size_t)i * IND_NIN], IND_NIN * sizeof(float));
+    to[c] = th[i];
+  }
+  if (flags & LXW_DEVICE_PTR) {
+    HIPCHK(hipMemcpy(X, xo.data(), xo.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(theta_sc, to.data(), to.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(X, xo.data(), xo.size() * sizeof(float));
+    std::memcpy(theta_sc, to.data(), to.size() * sizeof(double));
+  }
+  return LXW_OK;
+}
+
+lxw_status lxw_solver_set_indicator(lxw_solver* S, const lxw_indicator* ind, double tau_lo, double tau_hi) {
+  if (check_solver(S)) return LXW_ERR_ARG;
+  if (ind && S->M->kind != LXW_TRI) return fail(LXW_ERR_UNSUPPORTED, "the indicator is for triangle meshes");
+  if (ind && !(tau_lo >= 0.0 && tau_lo <= tau_hi && tau_hi <= 1.0))
+    return fail(LXW_ERR_ARG, "need 0 <= tau_lo <= tau_hi <= 1");
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  if (ind && !S->ind_flag) {
+    if ((s = S->alloc(&S->ind_flag, (size_t)S->M->N))) return s;
+    if ((s = S->alloc(&S->ind_counts, 3))) return s;
+  }
+  if (ind) {
+    const unsigned long long z[3] = {0, 0, 0};
+    HIPCHK(hipMemcpy(S->ind_counts, z, sizeof z, hipMemcpyHostToDevice));
+  }
+  S->ind = ind;
+  S->tau_lo = (float)tau_lo;
+  S->tau_hi = (float)tau_hi;
+  S->vd.ind_flag = ind ? S->ind_flag : nullptr;
+  S->vf.ind_flag = ind ? S->ind_flag : nullptr;
+  drop_graph(S);
+  return LXW_OK;
+}
+
+lxw_status lxw_indicator_decisions(lxw_solver* S, int64_t* counts, uint8_t* flags) {
+  if (check_solver(S) || !counts) return fail(LXW_ERR_ARG, "null argument");
+  if (!S->ind) return fail(LXW_ERR_ARG, "no indicator set on this solver");
+  lxw_status s = sync_check(S);
+  if (s) return s;
+  unsigned long long c[3];
+  HIPCHK(hipMemcpy(c, S->ind_counts, sizeof c, hipMemcpyDeviceToHost));
+  for (int k = 0; k < 3; ++k) counts[k] = (int64_t)c[k];
+  if (flags) {
+    std::vector<unsigned char> f(S->M->N);
+    HIPCHK(hipMemcpy(f.data(), S->ind_flag, f.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < S->M->N; ++i) flags[S->M->perm[i]] = f[i];
+  }
   return LXW_OK;
 }
 

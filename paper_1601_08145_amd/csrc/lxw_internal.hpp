@@ -158,8 +158,7 @@ struct IndW {
   const uint16_t* A2;  // [2 row tiles][4 k-steps][64 lanes][8]
   const float* b1;     // [2 row tiles][2 lane halves][16 accumulator registers]
   const float* b2;     // same layout
-  const float* w3;     // same layout
-  float b3;
+  const float* w3;     // same layout, then b3 at index 64
   float tau_lo, tau_hi;
 };
 
@@ -173,9 +172,10 @@ hipError_t launch_predict(const IndW& W, const float* X, int n, float* p, hipStr
 // order[base + s] (s < n; order null: base + s), then the in-order reduction and, with adam != 0,
 // the Adam update of theta / m / v (bc1 = 1 - beta1^t, bc2 = 1 - beta2^t).
 struct TrainArgs {
-  const float* X;
-  const float* y;
-  const int* order;
+  const float* X;       // [n_samples][48]
+  const float* y;       // [n_samples]
+  const int* order;     // sample indices (clamped to [0, n_samples))
+  int n_samples;
   int base, n;
   float w_pos, w_neg, inv_n;
   const float* theta;

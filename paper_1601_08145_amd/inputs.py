@@ -227,6 +227,58 @@ def sedov_cart_state(nx, ny, box=(-1.0, 1.0, -1.0, 1.0), gamma=1.4, e_total=0.98
     return averages_to_modal(avg, 9)
 
 
+def sedov_tri_state(xy, tri, r0, gamma=1.4, e_total=0.98, p_bg=1e-10):
+    """Sedov-type blast on a triangle mesh: rho = 1, u = 0, p = p_bg background, the total energy
+    e_total spread uniformly over the triangles whose centroid lies within r0 of the origin (cell
+    averages, higher modes zero)."""
+    a = np.asarray(xy)[np.asarray(tri)]
+    cen = a.mean(axis=1)
+    area = 0.5 * np.abs((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1])
+                        - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0]))
+    hot = np.hypot(cen[:, 0], cen[:, 1]) < r0
+    assert hot.any()
+    avg = np.zeros((len(tri), 4))
+    avg[:, 0] = 1.0
+    avg[:, 3] = p_bg / (gamma - 1.0)
+    avg[hot, 3] = e_total / area[hot].sum()
+    return averages_to_modal(avg, 6)
+
+
+def mach_shock_states(mach=10.0, rho1=1.4, p1=1.0, gamma=1.4):
+    """Pre- and post-shock primitive states (rho, u, v, p) of a planar shock of Mach number `mach`
+    moving in +x into gas at rest (Rankine-Hugoniot relations)."""
+    c1 = math.sqrt(gamma * p1 / rho1)
+    W = mach * c1
+    rho2 = rho1 * (gamma + 1) * mach**2 / ((gamma - 1) * mach**2 + 2)
+    p2 = p1 * (2 * gamma * mach**2 - (gamma - 1)) / (gamma + 1)
+    u2 = W * (1 - rho1 / rho2)
+    return np.array([rho1, 0.0, 0.0, p1]), np.array([rho2, u2, 0.0, p2])
+
+
+def ramp_state(xy, tri, x_shock=0.25, mach=10.0, gamma=1.4, m=2):
+    """Cell averages of a Mach `mach` shock at x = x_shock moving into the ramp channel (gas at
+    rest, rho = 1.4, p = 1, ahead of it), higher modes zero; and the inflow state (conserved) for
+    the x = 0 side."""
+    pre, post = mach_shock_states(mach, gamma=gamma)
+
+    def fn(pts):
+        behind = pts[..., 0] < x_shock
+        out = np.empty(pts.shape[:-1] + (4,))
+        out[...] = pre
+        out[behind] = post
+        return out
+
+    Q = averages_to_modal(cell_average_state(fn, tri_sample_points(xy, tri, m), gamma), 6)
+    return Q, prim_to_cons(post[None, :], gamma)[0]
+
+
+def ramp_bc(tags):
+    """Boundary codes of the ramp channel's tags: inflow side -> inflow (3), outflow side and top
+    -> transparent (1), floor and ramp -> reflective wall (2), interior -1."""
+    tags = np.asarray(tags)
+    return np.where(tags == 0, 3, np.where((tags == 1) | (tags == 3), 1, np.where(tags == 2, 2, -1))).astype(np.int32)
+
+
 def four_quadrant_params(seed):
     """Seeded primitive states of the four quadrants: rho, p ~ U[0.05, 1], u, v ~ U[-1, 1]."""
     g = rng(seed)
@@ -330,6 +382,16 @@ def batch_workload_parallel(n_meshes, seed, lo=2000, hi=60000, m=2, workers=8):
     with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
         out = list(ex.map(_batch_case_avg, jobs, chunksize=4))
     return [(xy, tri, averages_to_modal(avg, 6)) for xy, tri, avg in out]
+
+
+def mlp_init(seed, n_in=48, n_h=64):
+    """Initial parameters of the indicator network (flat float32, layout W1, b1, W2, b2, w3, b3):
+    weights uniform in +-sqrt(6 / fan_in), biases uniform in +-0.05, seeded."""
+    g = rng(seed)
+    parts = [g.uniform(-1, 1, n_in * n_h) * math.sqrt(6.0 / n_in), g.uniform(-0.05, 0.05, n_h),
+             g.uniform(-1, 1, n_h * n_h) * math.sqrt(6.0 / n_h), g.uniform(-0.05, 0.05, n_h),
+             g.uniform(-1, 1, n_h) * math.sqrt(6.0 / n_h), g.uniform(-0.05, 0.05, 1)]
+    return np.concatenate(parts).astype(np.float32)
 
 
 def random_modal_state(N, dim, n_modes, seed, amp=0.3, gamma=1.4, p_range=(0.3, 1.5), rough_frac=0.0,

@@ -55,6 +55,11 @@ class Tune(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32 * 8)]
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("w_pos", ctypes.c_double), ("w_neg", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("t", ctypes.c_double), ("last_dt", ctypes.c_double),
                 ("last_s", ctypes.c_double)]
@@ -97,6 +102,18 @@ def _load():
         "lxw_batch_get_state": [P, I32, P, dp, I32],
         "lxw_batch_advance_steps": [P, I64],
         "lxw_batch_stats": [P, I32, ctypes.POINTER(Stats)],
+        "lxw_indicator_create": [P, P, ctypes.POINTER(P)],
+        "lxw_indicator_destroy": [P],
+        "lxw_indicator_get_params": [P, P],
+        "lxw_indicator_set_params": [P, P],
+        "lxw_indicator_save": [P, ctypes.c_char_p],
+        "lxw_indicator_load": [P, ctypes.c_char_p],
+        "lxw_indicator_predict": [P, P, I32, P],
+        "lxw_indicator_grad": [P, P, P, I32, D, D, P, dp],
+        "lxw_indicator_train": [P, P, P, I32, P, I32, I32, ctypes.POINTER(Adam), dp],
+        "lxw_indicator_collect": [P, P, P, I32],
+        "lxw_solver_set_indicator": [P, P, D, D],
+        "lxw_indicator_decisions": [P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -315,6 +332,26 @@ class Solver(_Ops):
     def set_debug(self, on=True):
         _check(_L.lxw_set_debug(self.h, int(on)))
 
+    def set_indicator(self, ind, tau_lo=0.0, tau_hi=1.0):
+        """Learned detection for the shock-capturing limiter (None: plain everywhere)."""
+        self._ind = ind  # the indicator must outlive its use
+        _check(_L.lxw_solver_set_indicator(self.h, ind.h if ind is not None else None, tau_lo, tau_hi))
+
+    def indicator_decisions(self, flags=True):
+        c = np.zeros(3, dtype=np.int64)
+        f = np.zeros(self.mesh.N, dtype=np.uint8) if flags else None
+        _check(_L.lxw_indicator_decisions(self.h, c.ctypes.data_as(ctypes.c_void_p),
+                                          f.ctypes.data_as(ctypes.c_void_p) if flags else None))
+        return c, f
+
+    def collect(self):
+        """Features [N][48] (float32) and the pending shock-capturing limiter's factor [N]."""
+        X = np.zeros((self.mesh.N, NFEAT), dtype=np.float32)
+        th = np.zeros(self.mesh.N)
+        _check(_L.lxw_indicator_collect(self.h, X.ctypes.data_as(ctypes.c_void_p), th.ctypes.data_as(ctypes.c_void_p),
+                                        HOST_PTR))
+        return X, th
+
     def stage(self, stage):
         m = self.mesh
         shapes = {STAGE_QLIM: self.shape, STAGE_QUPD: self.shape, STAGE_VOL: self.shape, STAGE_THETA: (m.N,),
@@ -323,6 +360,81 @@ class Solver(_Ops):
         out = np.zeros(shapes[stage])
         _check(_L.lxw_debug_stage(self.h, stage, _dp(out)))
         return out
+
+
+NFEAT, NPARAM = 48, 7361
+
+
+def _dev(a, dtype):
+    """A contiguous device tensor of dtype holding a (numpy array or tensor)."""
+    if isinstance(a, torch.Tensor):
+        return a.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+class Indicator:
+    """Learned troubled-cell indicator (lxw_indicator_*): inference, gradients and training run in
+    the library's kernels on this object's stream; arrays are passed as device tensors."""
+
+    def __init__(self, params, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (NPARAM,)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(_L.lxw_indicator_create(p.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self, _destroy=_L.lxw_indicator_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def params(self):
+        p = np.zeros(NPARAM, dtype=np.float32)
+        _check(_L.lxw_indicator_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p)))
+        return p
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(_L.lxw_indicator_set_params(self.h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def save(self, path):
+        _check(_L.lxw_indicator_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        _check(_L.lxw_indicator_load(self.h, str(path).encode()))
+
+    def predict(self, X):
+        Xd = _dev(X, torch.float32)
+        n = Xd.shape[0]
+        p = torch.zeros(n, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        _check(_L.lxw_indicator_predict(self.h, ctypes.c_void_p(Xd.data_ptr()), n, ctypes.c_void_p(p.data_ptr())))
+        return p.cpu().numpy()
+
+    def grad(self, X, y, w_pos=1.0, w_neg=1.0):
+        Xd, yd = _dev(X, torch.float32), _dev(y, torch.float32)
+        g = np.zeros(NPARAM, dtype=np.float32)
+        loss = ctypes.c_double(0.0)
+        torch.cuda.synchronize()
+        _check(_L.lxw_indicator_grad(self.h, ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
+                                     Xd.shape[0], w_pos, w_neg, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, X, y, order, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, w_pos=1.0, w_neg=1.0):
+        Xd, yd = _dev(X, torch.float32), _dev(y, torch.float32)
+        od = _dev(order, torch.int32)
+        n_updates = od.shape[0] // batch
+        hp = Adam(lr, beta1, beta2, eps, w_pos, w_neg)
+        loss = ctypes.c_double(0.0)
+        torch.cuda.synchronize()
+        _check(_L.lxw_indicator_train(self.h, ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
+                                      Xd.shape[0], ctypes.c_void_p(od.data_ptr()), n_updates, batch, ctypes.byref(hp),
+                                      ctypes.byref(loss)))
+        return loss.value
 
 
 class Batch(_Ops):

@@ -1,0 +1,186 @@
+"""GPU tests of the learned troubled-cell indicator through the C interface, against the FP64 CPU
+reference of the network (oracle/mlp.py) and the FP64 oracle of the step.
+
+Inference (bf16 matrix cores, float32 accumulation) is compared with the reference evaluated on
+bf16-rounded inputs, weights and hidden activations; gradients (float32 training kernels) with the
+float64 gradient; training data (features, the limiter's factor) with the oracle's; the learned
+step with the oracle step restricted to the cells the indicator left to the limiter."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as M
+from paper_1601_08145_amd import inputs as I
+from tests.helpers import rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1601_08145_amd import lxw
+    return lxw
+
+
+def test_predict_matches_bf16_reference(L):
+    print("[gpu] indicator predict", flush=True)
+    th = I.mlp_init(1)
+    ind = L.Indicator(th)
+    g = np.random.default_rng(2)
+    X = g.uniform(-1, 1, (1000, 48)).astype(np.float32)  # 15 full wavefronts and a ragged one
+    p = ind.predict(X)
+    ref = M.forward(th.astype(np.float64), X.astype(np.float64), bf16=True)
+    d = np.abs(p - ref)
+    print(f"[gpu]   max |p - ref| {d.max():.2e}, 99th percentile {np.percentile(d, 99):.2e}", flush=True)
+    assert np.percentile(d, 99) <= 1e-4 and d.max() <= 5e-3
+    # without the bf16 rounding the network differs visibly: the check above is about the format
+    assert np.abs(M.forward(th.astype(np.float64), X.astype(np.float64)) - ref).max() > 1e-4
+
+
+def test_grad_matches_fp64_reference(L):
+    print("[gpu] indicator gradient", flush=True)
+    th = I.mlp_init(3)
+    ind = L.Indicator(th)
+    g = np.random.default_rng(4)
+    n = 300  # four workgroups and a ragged one
+    X = g.uniform(-1, 1, (n, 48)).astype(np.float32)
+    y = (g.uniform(0, 1, n) < 0.3).astype(np.float32)
+    gg, loss = ind.grad(X, y, w_pos=2.0, w_neg=0.6)
+    ref = M.grad(th.astype(np.float64), X.astype(np.float64), y.astype(np.float64), 2.0, 0.6)
+    lref = M.loss(th.astype(np.float64), X.astype(np.float64), y.astype(np.float64), 2.0, 0.6)
+    err = np.linalg.norm(gg - ref) / np.linalg.norm(ref)
+    print(f"[gpu]   gradient rel. error {err:.2e}, loss {loss:.6f} vs {lref:.6f}", flush=True)
+    assert err <= 1e-5
+    assert loss == pytest.approx(lref, rel=1e-5)
+
+
+def test_adam_updates_match_fp64_reference(L):
+    th0 = I.mlp_init(5)
+    ind = L.Indicator(th0)
+    g = np.random.default_rng(6)
+    n, batch, nu = 500, 128, 6
+    X = g.uniform(-1, 1, (n, 48)).astype(np.float32)
+    y = (X[:, 3] + 0.5 * X[:, 30] > 0.2).astype(np.float32)
+    order = g.integers(0, n, nu * batch).astype(np.int32)
+    ind.train(X, y, order, batch, lr=1e-3, w_pos=1.5, w_neg=0.8)
+    th = th0.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for u in range(nu):
+        idx = order[u * batch:(u + 1) * batch]
+        gr = M.grad(th, X[idx].astype(np.float64), y[idx].astype(np.float64), 1.5, 0.8)
+        th, m, v = M.adam(th, m, v, gr, u + 1, lr=1e-3)
+    d = np.abs(ind.params().astype(np.float64) - th)
+    print(f"[gpu]   Adam: max |dtheta| {d.max():.2e}, 99.9th percentile {np.percentile(d, 99.9):.2e}", flush=True)
+    # Adam's first steps are lr * sign(g): a parameter whose gradient is ~0 may move by lr either
+    # way; all others agree closely
+    assert np.percentile(d, 99.9) <= 1e-5 and d.max() <= 2 * nu * 1e-3
+
+
+def test_training_separates_a_learnable_rule(L):
+    print("[gpu] indicator training", flush=True)
+    ind = L.Indicator(I.mlp_init(7))
+    g = np.random.default_rng(8)
+    n = 8192
+    X = g.uniform(-1, 1, (n, 48)).astype(np.float32)
+    y = ((np.abs(X[:, 1]) > 0.6) | (X[:, 25] * X[:, 26] > 0.3)).astype(np.float32)
+    order = np.concatenate([g.permutation(n) for _ in range(16)]).astype(np.int32)
+    l0 = ind.grad(X, y)[1]
+    l1 = ind.train(X, y, order, 256, lr=3e-3)
+    p = ind.predict(X)
+    acc = np.mean((p > 0.5) == (y > 0.5))
+    print(f"[gpu]   loss {l0:.4f} -> {l1:.4f}, accuracy {acc:.4f}", flush=True)
+    assert l1 < 0.5 * l0 and acc > 0.9
+
+
+def _vortex_case(L, n=26, seed=11, alpha0=0.05):
+    xy, tri = I.lattice_delaunay(n, seed, box=(-5, 5, -5, 5))
+    Q0 = I.averages_to_modal(I.cell_average_state(I.vortex_shock_fn(seed), I.tri_sample_points(xy, tri, 2), 1.4), 6)
+    return xy, tri, Q0, dict(alpha0=alpha0)
+
+
+def test_collect_matches_oracle(L):
+    print("[gpu] indicator training data vs oracle", flush=True)
+    xy, tri, Q0, kw = _vortex_case(L)
+    S = L.Solver(L.Mesh.tri(xy, tri), **kw)
+    S.set_state(Q0)
+    Ob = O.Solver(O.Mesh.tri(xy, tri), **kw)
+    Ob.set_state(Q0)
+    for _ in range(2):
+        S.step()
+        Ob.step()
+    X, th = S.collect()
+    th_o = Ob.stage(O.STAGE_THETA_SC)
+    F_o = M.features(Ob.stage(O.STAGE_QUPD), M.tri_neighbours(tri), M.tri_delta(xy, tri, kw["alpha0"]))
+    assert np.sum(th_o < 1) > 10
+    assert np.abs(th - th_o).max() <= 1e-10
+    assert np.abs(X - F_o).max() <= 1e-6
+    # collecting changed nothing: the next step still matches the oracle
+    S.step()
+    Ob.step()
+    assert max(rel_l1(S.get_state()[0][:, v], Ob.get_state()[0][:, v]) for v in range(4)) <= 1e-12
+
+
+def test_learned_step_matches_masked_oracle(L):
+    print("[gpu] learned step vs masked oracle", flush=True)
+    xy, tri, Q0, kw = _vortex_case(L, n=30, seed=12)
+    th = I.mlp_init(13)
+    ind = L.Indicator(th)
+    S = L.Solver(L.Mesh.tri(xy, tri), **kw)
+    S.set_state(Q0)
+    Ob = O.Solver(O.Mesh.tri(xy, tri), **kw)
+    Ob.set_state(Q0)
+    nb = M.tri_neighbours(tri)
+    dl = M.tri_delta(xy, tri, kw["alpha0"])
+    # thresholds in the middle of this network's outputs, so that both decisions occur
+    S.step()
+    Ob.step()
+    p0 = M.forward(th.astype(np.float64), M.features(Ob.stage(O.STAGE_QUPD), nb, dl), bf16=True)
+    tau = float(np.median(p0))
+    S.set_indicator(ind, tau, min(1.0, tau + 0.1))
+    Ob2 = O.Solver(O.Mesh.tri(xy, tri), **kw)
+    Q1, t1 = S.get_state()  # applies the pending limiter with the indicator's decisions
+    counts, flags = S.indicator_decisions()
+    Ob2.set_state(Q0)
+    Ob2.set_shock_mask(flags != 0)
+    Ob2.step()
+    assert counts[0] > 0 and counts[1] + counts[2] > 0
+    assert max(rel_l1(Q1[:, v], Ob2.get_state()[0][:, v]) for v in range(4)) <= 1e-12
+    # decisions agree with the reference network wherever p is not within 1e-2 of tau
+    pr = M.forward(th.astype(np.float64), M.features(Ob2.stage(O.STAGE_QUPD), nb, dl), bf16=True)
+    clear = np.abs(pr - tau) > 1e-2
+    assert np.array_equal((flags[clear] == 0), (pr[clear] < tau))
+    # further steps with the indicator: each matches the oracle step with the same decisions
+    for _ in range(3):
+        S.step()
+        Qg, _ = S.get_state()
+        _, flags = S.indicator_decisions()
+        Ob2.set_shock_mask(flags != 0)
+        Ob2.step()
+        assert max(rel_l1(Qg[:, v], Ob2.get_state()[0][:, v]) for v in range(4)) <= 1e-12
+
+
+def test_indicator_errors_and_files(L, tmp_path):
+    th = I.mlp_init(14)
+    ind = L.Indicator(th)
+    S = L.Solver(L.Mesh.cart(8, 8, 0, 1, 0, 1, [1, 1, 1, 1]))
+    with pytest.raises(L.LxwError) as e:
+        S.set_indicator(ind, 0.1, 0.5)
+    assert e.value.name == "LXW_ERR_UNSUPPORTED"
+    xy, tri, Q0, kw = _vortex_case(L, n=10)
+    St = L.Solver(L.Mesh.tri(xy, tri))
+    with pytest.raises(L.LxwError) as e:
+        St.set_indicator(ind, 0.6, 0.5)
+    assert e.value.name == "LXW_ERR_ARG"
+    St.set_state(Q0)
+    with pytest.raises(L.LxwError) as e:
+        St.collect()
+    assert e.value.name == "LXW_ERR_ARG"
+    f = tmp_path / "ind.bin"
+    ind.save(f)
+    other = L.Indicator(I.mlp_init(15))
+    other.load(f)
+    assert np.array_equal(other.params(), th)
+    (tmp_path / "bad.bin").write_bytes(b"not a parameter file")
+    with pytest.raises(L.LxwError):
+        other.load(tmp_path / "bad.bin")
