@@ -14,9 +14,12 @@ around every launch inside the timed region give the average duration of the dom
 a bounded sample: one step of the same workload on all host cores.
 
 A second, batched leg advances 512 independent meshes of 2k-60k triangles together (graph replay,
-autotuned launch shapes) and is reported under "batched".
+autotuned launch shapes) and is reported under "batched".  A third leg trains the learned
+troubled-cell indicator with the library's kernels and compares the learned form with the plain
+form ("learned").
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-fp64] [--no-batched]
+                 [--no-learned]
 """
 import argparse
 import json
@@ -197,6 +200,77 @@ def batched_leg(L, steps, warmup):
             "kernels": kt, "roofline": kelem_roofline(kt["k_elem"]["ms_avg"], ntot, traffic_ok=False)}
 
 
+def rel_l1(a, b):
+    return max(float(np.abs(a[:, v] - b[:, v]).sum() / np.abs(b[:, v]).sum()) for v in range(a.shape[1]))
+
+
+def time_steps(L, mesh, Q0, steps, warmup, ind=None, tau=(0.0, 1.0), kw=None):
+    """FP32-mixed steps replayed from the graph (timed), then per-kernel events; returns
+    (ms per step, kernel averages, final state, decision counts)."""
+    S = L.Solver(mesh, precision=L.FP32_MIXED, **(kw or {}))
+    S.set_state(Q0)
+    if ind is not None:
+        S.set_indicator(ind, *tau)
+    S.run_steps(warmup)
+    S.sync()
+    ms = _timed(S, steps)
+    S.set_timing(True)
+    S.run_steps(steps)  # as many steps again, so that states compare with the other legs' after warmup + 2 steps
+    S.sync()
+    kt = {k: v[0] / max(v[1], 1) for k, v in S.kernel_times().items()}
+    S.set_timing(False)
+    Q, _ = S.get_state()
+    counts = S.indicator_decisions(False)[0].tolist() if ind is not None else None
+    return ms / steps, kt, Q, counts
+
+
+def learned_leg(L, steps, warmup, c3_mesh, c3_Q0, fp64_Q=None):
+    """Train the indicator with the library's kernels on plain runs of the four-quadrant and blast
+    families, then run the learned form against the plain form on the 2D triangle workload and on a
+    2M-triangle ramp with a Mach 10 shock (outside the training families)."""
+    from paper_1601_08145_amd import indicator_train as T, inputs as I
+    t0 = time.time()
+    cases = T.family_cases(L, "quadrants", range(2), 200) + T.family_cases(L, "sedov", range(2), 200)
+    X, y, seen, npos = T.collect(L, cases, 40, 4, L.FP32_MIXED)
+    t1 = time.time()
+    ind, loss = T.train(L, X, y, epochs=15)
+    t2 = time.time()
+    tau = T.calibrate(ind.predict(X), y, 0.999)
+    taus = (tau, max(0.5, tau))
+    log(f"[bench] learned: {seen} cells seen, {npos} labelled troubled, {len(y)} training samples; collect "
+        f"{t1 - t0:.1f} s, train {t2 - t1:.1f} s, tau_lo {tau:.3g}")
+    out = {"training": {"families": "four-quadrant and near-vacuum blast, 2 seeds each, 200^2 lattices, 40 steps",
+                        "cells_seen": seen, "positives": npos, "samples": int(len(y)), "final_loss": loss,
+                        "collect_s": t1 - t0, "train_s": t2 - t1, "tau_lo": tau}}
+    ms_p, kt_p, Qp, _ = time_steps(L, c3_mesh, c3_Q0, steps, warmup)
+    ms_l, kt_l, Ql, cnt = time_steps(L, c3_mesh, c3_Q0, steps, warmup, ind, taus)
+    n = c3_mesh.N
+    out["tri_1M"] = {"plain_ms_per_step": ms_p, "learned_ms_per_step": ms_l, "learned_value": n / (ms_l * 1e-3),
+                     "speedup_vs_plain_fp32": ms_p / ms_l, "rel_l1_learned_vs_plain": rel_l1(Ql, Qp),
+                     "skip_fraction": cnt[0] / max(sum(cnt), 1),
+                     "k_pre_us": {"plain": kt_p["k_pre"] * 1e3, "learned": kt_l["k_pre"] * 1e3},
+                     "k_ind_us": kt_l["k_ind"] * 1e3}
+    if fp64_Q is not None:
+        out["tri_1M"]["rel_l1_learned_vs_fp64_plain"] = rel_l1(Ql, fp64_Q)
+    log(f"[bench]   1M triangles: plain {ms_p:.3f} ms, learned {ms_l:.3f} ms per step; rel L1 learned vs plain "
+        f"{out['tri_1M']['rel_l1_learned_vs_plain']:.2e}, skip {out['tri_1M']['skip_fraction']:.3f}")
+    xy, tri, tags = I.ramp_channel(2_000_000, 0)
+    Q0, inflow = I.ramp_state(xy, tri)
+    mesh = L.Mesh.tri(xy, tri, I.ramp_bc(tags))
+    kw = {"inflow": list(inflow)}
+    ms_p, kt_p, Qp, _ = time_steps(L, mesh, Q0, steps, warmup, kw=kw)
+    ms_l, kt_l, Ql, cnt = time_steps(L, mesh, Q0, steps, warmup, ind, taus, kw=kw)
+    out["ramp_mach10"] = {"n_elem": mesh.N, "plain_ms_per_step": ms_p, "learned_ms_per_step": ms_l,
+                          "plain_value": mesh.N / (ms_p * 1e-3), "learned_value": mesh.N / (ms_l * 1e-3),
+                          "speedup_vs_plain_fp32": ms_p / ms_l, "rel_l1_learned_vs_plain": rel_l1(Ql, Qp),
+                          "skip_fraction": cnt[0] / max(sum(cnt), 1),
+                          "k_pre_us": {"plain": kt_p["k_pre"] * 1e3, "learned": kt_l["k_pre"] * 1e3},
+                          "k_ind_us": kt_l["k_ind"] * 1e3}
+    log(f"[bench]   ramp {mesh.N} triangles: plain {ms_p:.3f} ms, learned {ms_l:.3f} ms per step; rel L1 learned vs "
+        f"plain {out['ramp_mach10']['rel_l1_learned_vs_plain']:.2e}, skip {out['ramp_mach10']['skip_fraction']:.3f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +281,7 @@ def main():
     ap.add_argument("--no-kernel-events", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-mesh batched leg")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched leg (for profiling)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-indicator leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -281,6 +356,9 @@ def main():
 
     if not args.no_batched:
         out["batched"] = batched_leg(L, args.steps, args.warmup)
+
+    if not args.no_learned:
+        out["learned"] = learned_leg(L, args.steps, args.warmup, mesh, Q0, f64["Q"] if not args.no_fp64 else None)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle, one step)")

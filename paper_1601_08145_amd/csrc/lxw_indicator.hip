@@ -13,6 +13,8 @@
 // var*24 + c*6 + l.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lxw_internal.hpp"
 
 namespace lxw {
@@ -49,9 +51,9 @@ __device__ __forceinline__ void cell_features(const View<R>& v, int i, float (&F
     for (int x = 0; x < 24; ++x) mx = fmaxf(mx, fabsf(vals[x]));
     // floor: the shock-capturing limiter's relaxation delta_i (variations far below it give
     // features near zero) and a relative 1e-6 (a uniform region's round-off stays near zero)
-    const float sc = mx + float(v.delta[i] + 1e-6 * fabs(avg)) + 1e-30f;
+    const float rs = 1.0f / (mx + float(v.delta[i] + 1e-6 * fabs(avg)) + 1e-30f);
 #pragma unroll
-    for (int x = 0; x < 24; ++x) F[g * 24 + x] = vals[x] / sc;
+    for (int x = 0; x < 24; ++x) F[g * 24 + x] = vals[x] * rs;
   }
 }
 
@@ -87,8 +89,28 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, w);
 }
 
+// The packed weights, staged in LDS once per workgroup (14.8 KB).
+struct IndLds {
+  uint16_t A1[2 * 3 * 64 * 8];
+  uint16_t A2[2 * 4 * 64 * 8];
+  float b1[64], b2[64], w3[65];
+};
+
+__device__ __forceinline__ void stage_weights(IndLds& L, const IndW& W) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const i32x4* a1 = reinterpret_cast<const i32x4*>(W.A1);
+  const i32x4* a2 = reinterpret_cast<const i32x4*>(W.A2);
+  i32x4* l1 = reinterpret_cast<i32x4*>(L.A1);
+  i32x4* l2 = reinterpret_cast<i32x4*>(L.A2);
+  for (int x = t; x < 2 * 3 * 64 * 8 / 8; x += nt) l1[x] = a1[x];
+  for (int x = t; x < 2 * 4 * 64 * 8 / 8; x += nt) l2[x] = a2[x];
+  for (int x = t; x < 64; x += nt) { L.b1[x] = W.b1[x]; L.b2[x] = W.b2[x]; }
+  for (int x = t; x < 65; x += nt) L.w3[x] = W.w3[x];
+  __syncthreads();
+}
+
 // Logit of the lane's own cell (all 64 lanes must call this together).
-__device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndW& W) {
+__device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndLds& W) {
   const int l = threadIdx.x & 63, h = l >> 5;
   bf16x8 own[3], other[3];
 #pragma unroll
@@ -112,7 +134,7 @@ __device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndW
       f32x16 a = {};
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        const bf16x8 A = load_bf16x8(W.A1 + ((size_t)(mt * 3 + s) * 64 + l) * 8);
+        const bf16x8 A = load_bf16x8(W.A1 + ((mt * 3 + s) * 64 + l) * 8);
         const bf16x8 B = (t == h) ? own[s] : other[s];
         a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, a, 0, 0, 0);
       }
@@ -141,7 +163,7 @@ __device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndW
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
-          const bf16x8 A = load_bf16x8(W.A2 + ((size_t)(mt2 * 4 + mt * 2 + g) * 64 + l) * 8);
+          const bf16x8 A = load_bf16x8(W.A2 + ((mt2 * 4 + mt * 2 + g) * 64 + l) * 8);
           a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, H[mt][t][g], a, 0, 0, 0);
         }
       // layer 3 on the lane's 16 hidden units of this row tile
@@ -157,37 +179,52 @@ __device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndW
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
 
 // Decisions for the solver's elements: 0 skip the shock-capturing limiter (p < tau_lo), 2 flagged
-// (p >= tau_hi), 1 otherwise; counts[3] accumulates the decisions.
+// (p >= tau_hi), 1 otherwise; counts[3] accumulates the decisions.  Workgroups of 256 lanes stage
+// the weights once and then walk over chunks of 256 elements (every lane of a workgroup runs the
+// same number of chunks, as the matrix instructions need full wavefronts).
 template <class R>
 __global__ __launch_bounds__(256) void k_ind(View<R> v, IndW W, unsigned char* flag, unsigned long long* counts) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < v.N;
-  float F[IND_NIN];
-  if (valid) {
-    cell_features<R>(v, i, F);
-  } else {
+  __shared__ IndLds Ls;
+  stage_weights(Ls, W);
+  const int nchunk = (v.N + 255) / 256;
+  unsigned long long n0 = 0, n1 = 0, n2 = 0;
+  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int i = ch * 256 + threadIdx.x;
+    const bool valid = i < v.N;
+    float F[IND_NIN];
+    if (valid) {
+      cell_features<R>(v, i, F);
+    } else {
 #pragma unroll
-    for (int f = 0; f < IND_NIN; ++f) F[f] = 0.0f;
+      for (int f = 0; f < IND_NIN; ++f) F[f] = 0.0f;
+    }
+    const float p = sigmoidf(mlp_logit(F, Ls));
+    const int d = p < W.tau_lo ? 0 : (p >= W.tau_hi ? 2 : 1);
+    if (valid) flag[i] = (unsigned char)d;
+    n0 += __popcll(__ballot(valid && d == 0));
+    n1 += __popcll(__ballot(valid && d == 1));
+    n2 += __popcll(__ballot(valid && d == 2));
   }
-  const float p = sigmoidf(mlp_logit(F, W));
-  const int d = p < W.tau_lo ? 0 : (p >= W.tau_hi ? 2 : 1);
-  if (valid) flag[i] = (unsigned char)d;
-  const unsigned long long b0 = __ballot(valid && d == 0), b1 = __ballot(valid && d == 1), b2 = __ballot(valid && d == 2);
   if ((threadIdx.x & 63) == 0) {
-    if (b0) atomicAdd(&counts[0], (unsigned long long)__popcll(b0));
-    if (b1) atomicAdd(&counts[1], (unsigned long long)__popcll(b1));
-    if (b2) atomicAdd(&counts[2], (unsigned long long)__popcll(b2));
+    if (n0) atomicAdd(&counts[0], n0);
+    if (n1) atomicAdd(&counts[1], n1);
+    if (n2) atomicAdd(&counts[2], n2);
   }
 }
 
 __global__ __launch_bounds__(256) void k_predict(IndW W, const float* X, int n, float* p) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
-  float F[IND_NIN];
+  __shared__ IndLds Ls;
+  stage_weights(Ls, W);
+  const int nchunk = (n + 255) / 256;
+  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int i = ch * 256 + threadIdx.x;
+    const bool valid = i < n;
+    float F[IND_NIN];
 #pragma unroll
-  for (int f = 0; f < IND_NIN; ++f) F[f] = valid ? X[(size_t)i * IND_NIN + f] : 0.0f;
-  const float z = mlp_logit(F, W);
-  if (valid) p[i] = sigmoidf(z);
+    for (int f = 0; f < IND_NIN; ++f) F[f] = valid ? X[(size_t)i * IND_NIN + f] : 0.0f;
+    const float z = mlp_logit(F, Ls);
+    if (valid) p[i] = sigmoidf(z);
+  }
 }
 
 // ---- training: one wavefront of 64 samples per workgroup --------------------------------------
@@ -335,7 +372,7 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(int nblk, const float* part,
 template <class R>
 hipError_t launch_indicator(const View<R>& v, const IndW& W, unsigned char* flag, unsigned long long* counts,
                             hipStream_t st) {
-  if (v.N > 0) hipLaunchKernelGGL(k_ind<R>, dim3((v.N + 255) / 256), dim3(256), 0, st, v, W, flag, counts);
+  if (v.N > 0) hipLaunchKernelGGL(k_ind<R>, dim3(std::min((v.N + 255) / 256, 2048)), dim3(256), 0, st, v, W, flag, counts);
   return hipGetLastError();
 }
 
@@ -346,7 +383,7 @@ hipError_t launch_features(const View<R>& v, float* X, hipStream_t st) {
 }
 
 hipError_t launch_predict(const IndW& W, const float* X, int n, float* p, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_predict, dim3((n + 255) / 256), dim3(256), 0, st, W, X, n, p);
+  if (n > 0) hipLaunchKernelGGL(k_predict, dim3(std::min((n + 255) / 256, 2048)), dim3(256), 0, st, W, X, n, p);
   return hipGetLastError();
 }
 

@@ -310,8 +310,11 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
     // ---- shock-capturing limiter on the primitive variables (bounds from the edge neighbours'
     // averages relaxed by alpha0 h^1.5; velocity and pressure sampled where the density is positive)
     double th_sc = 1.0;
+    double rmin = INFINITY;  // smallest point density of the unlimited state, from the shock pass
+    bool have_rmin = false;
     const bool detect = mode == 2 || !v.ind_flag || v.ind_flag[i] != 0;
     if (v.shock && v.sc[mid].shock_pending && ok && detect) {
+      have_rmin = true;
       double wb[V], Mx[V], Mn[V];
       wb[0] = qb[0];
 #pragma unroll
@@ -362,6 +365,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
         for (int c = 0; c < V; ++c) q[c] = qb[c] + point_dev<E, R>(T, Qh, p, c);
         wmax[0] = fmax(wmax[0], q[0]);
         wmin[0] = fmin(wmin[0], q[0]);
+        rmin = fmin(rmin, q[0]);
         if (q[0] > 0.0) {
           const double r = 1.0 / q[0];
 #pragma unroll
@@ -397,19 +401,31 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
       // ---- moment limiter (Sec. 3.1): Step 0 flattens cells below eps0 or with p_bar <= 0;
       // Step 1 density (closed form of the largest theta); Step 2 pressure by concavity, target
       // eps_p = min(eps0, p_bar).
+      // When neither the shock limiter nor the density step limits (the common case), the point
+      // states of the density, pressure and wave-speed passes are the same; those passes then share
+      // one loop.  Every value is computed by the same operations as in the separate passes.
       double th = 1.0;
+      double smax1 = 0.0;
+      bool fused = false;
       if (!ok) {
         th = 0.0;
       } else {
         double thr = 1.0;
+        if (have_rmin && th_sc == 1.0) {
+          // the density factor is a decreasing function of the point density: its minimum over
+          // the points is its value at the smallest point density
+          if (rmin < eps0) thr = fmin(thr, (qb[0] - eps0) / (qb[0] - rmin));
+        } else {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const double rm = qb[0] + th_sc * point_dev<E, R>(T, Qh, p, 0);
-          if (rm < eps0) thr = fmin(thr, (qb[0] - eps0) / (qb[0] - rm));
+          for (int p = 0; p < NP; ++p) {
+            const double rm = qb[0] + th_sc * point_dev<E, R>(T, Qh, p, 0);
+            if (rm < eps0) thr = fmin(thr, (qb[0] - eps0) / (qb[0] - rm));
+          }
         }
         const double epsp = fmin(eps0, pb);
         const double ts = thr * th_sc;
         th = thr;
+        fused = ts == 1.0;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
           double q[V];
@@ -417,13 +433,16 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
           for (int c = 0; c < V; ++c) q[c] = qb[c] + ts * point_dev<E, R>(T, Qh, p, c);
           const double pt = pressure_r<DIM>(q, 1.0 / q[0], gam);
           if (pt < epsp) th = fmin(th, thr * (pb - epsp) / (pb - pt));
+          if (fused) smax1 = fmax(smax1, speed_r<DIM>(q, gam));
         }
       }
       const double tt = th_sc * th;
       v.theta[i] = tt;
       if (finite && qb[0] > 0.0 && pb > 0.0) {
         smax = speed_r<DIM>(qb, gam);
-        if (tt > 0.0) {
+        if (fused && tt == 1.0) {
+          smax = fmax(smax, smax1);
+        } else if (tt > 0.0) {
 #pragma unroll
           for (int p = 0; p < NP; ++p) {
             double q[V];

@@ -184,3 +184,50 @@ def test_indicator_errors_and_files(L, tmp_path):
     (tmp_path / "bad.bin").write_bytes(b"not a parameter file")
     with pytest.raises(L.LxwError):
         other.load(tmp_path / "bad.bin")
+
+
+def test_learned_indicator_gain(L):
+    """Train the indicator with the library's kernels on plain runs of the four-quadrant and blast
+    families (labels from the plain shock-capturing limiter), then compare the learned form with the
+    plain form on held-out seeds: it skips the limiter on most cells while the solutions stay close
+    (the plain limiter is the judge).  Outside the training families (Mach 10 ramp) the difference
+    is reported; positivity holds either way (every step is checked by the library)."""
+    from paper_1601_08145_amd import indicator_train as T
+    print("[gpu] learned indicator: collect, train, evaluate", flush=True)
+    cases = T.family_cases(L, "quadrants", range(2), 140) + T.family_cases(L, "sedov", range(2), 140)
+    X, y, seen, npos = T.collect(L, cases, 30, 3, L.FP32_MIXED)
+    assert npos > 500
+    ind, loss = T.train(L, X, y, epochs=15)
+    p = ind.predict(X)
+    tau = T.calibrate(p, y, 0.999)
+    assert np.mean(p[y > 0.5] >= tau) >= 0.999
+    print(f"[gpu]   {seen} cells, {npos} positive, loss {loss:.4f}, tau_lo {tau:.3g}", flush=True)
+
+    def run(mesh, Q0, steps, with_ind, kw=None):
+        S = L.Solver(mesh, precision=L.FP32_MIXED, **(kw or {}))
+        S.set_state(Q0)
+        if with_ind:
+            S.set_indicator(ind, tau, max(0.5, tau))
+        S.run_steps(steps)
+        Q, _ = S.get_state()
+        c = S.indicator_decisions(False)[0] if with_ind else None
+        return Q, c
+
+    for kind in ("quadrants", "sedov"):
+        mesh, Q0, _ = T.family_cases(L, kind, [9], 140)[0]
+        Qp, _ = run(mesh, Q0, 30, False)
+        Ql, c = run(mesh, Q0, 30, True)
+        d = max(rel_l1(Ql[:, v], Qp[:, v]) for v in range(4))
+        skip = c[0] / c.sum()
+        print(f"[gpu]   held-out {kind}: rel L1 learned vs plain {d:.2e}, limiter skipped on {skip:.3f} of cells",
+              flush=True)
+        assert skip > 0.9 and d < 5e-3
+    xy, tri, tags = I.ramp_channel(60000, 1)
+    Q0, inflow = I.ramp_state(xy, tri)
+    mesh = L.Mesh.tri(xy, tri, I.ramp_bc(tags))
+    Qp, _ = run(mesh, Q0, 40, False, {"inflow": list(inflow)})
+    Ql, c = run(mesh, Q0, 40, True, {"inflow": list(inflow)})
+    d = max(rel_l1(Ql[:, v], Qp[:, v]) for v in range(4))
+    print(f"[gpu]   ramp (outside the training families): rel L1 learned vs plain {d:.2e}, skip {c[0] / c.sum():.3f}",
+          flush=True)
+    assert np.all(Ql[:, 0, 0] > 0)
