@@ -235,8 +235,8 @@ def learned_leg(L, steps, warmup, c3_mesh, c3_Q0, fp64_Q=None):
     t1 = time.time()
     ind, loss = T.train(L, X, y, epochs=15)
     t2 = time.time()
-    tau = T.calibrate(ind.predict(X), y, 0.999)
-    taus = (tau, max(0.5, tau))
+    tau = T.TAU_LO
+    taus = (T.TAU_LO, T.TAU_HI)
     log(f"[bench] learned: {seen} cells seen, {npos} labelled troubled, {len(y)} training samples; collect "
         f"{t1 - t0:.1f} s, train {t2 - t1:.1f} s, tau_lo {tau:.3g}")
     out = {"training": {"families": "four-quadrant and near-vacuum blast, 2 seeds each, 200^2 lattices, 40 steps",

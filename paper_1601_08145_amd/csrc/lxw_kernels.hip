@@ -307,13 +307,19 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
     }
     const bool ok = finite && qb[0] >= eps0 && pb > 0.0;
 
-    // ---- shock-capturing limiter on the primitive variables (bounds from the edge neighbours'
-    // averages relaxed by alpha0 h^1.5; velocity and pressure sampled where the density is positive)
+    // ---- one pass over the points of the unlimited state: the shock-capturing limiter on the
+    // primitive variables (bounds from the edge neighbours' averages relaxed by alpha0 h^1.5;
+    // velocity and pressure sampled where the density is positive) when it is due, and the
+    // smallest point density and pressure and the largest wave speed, which settle the moment
+    // limiter and the wave speed at once when nothing needs limiting
     double th_sc = 1.0;
-    double rmin = INFINITY;  // smallest point density of the unlimited state, from the shock pass
+    double rmin = INFINITY;  // smallest point density of the unlimited state
+    double pmin = INFINITY;  // smallest point pressure of the unlimited state (points with rho > 0)
+    double smax0 = 0.0;      // largest point wave speed of the unlimited state (points with rho > 0)
     bool have_rmin = false;
     const bool detect = mode == 2 || !v.ind_flag || v.ind_flag[i] != 0;
-    if (v.shock && v.sc[mid].shock_pending && ok && detect) {
+    const bool shock_on = v.shock && v.sc[mid].shock_pending && ok && detect;
+    if (shock_on || (mode == 0 && ok)) {
       have_rmin = true;
       double wb[V], Mx[V], Mn[V];
       wb[0] = qb[0];
@@ -324,7 +330,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
 #pragma unroll
       for (int c = 0; c < V; ++c) { Mx[c] = wb[c] + dl; Mn[c] = wb[c] - dl; }
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
+      for (int k = 0; k < K && shock_on; ++k) {
         double qn[V], wn[V];
         const int j = v.nbr[k * N + i];
         if (j >= 0) {
@@ -368,23 +374,29 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
         rmin = fmin(rmin, q[0]);
         if (q[0] > 0.0) {
           const double r = 1.0 / q[0];
+          double u2 = 0.0;
 #pragma unroll
           for (int d = 0; d < DIM; ++d) {
             const double u = q[1 + d] * r;
             wmax[1 + d] = fmax(wmax[1 + d], u);
             wmin[1 + d] = fmin(wmin[1 + d], u);
+            u2 += u * u;
           }
           const double pp = pressure_r<DIM>(q, r, gam);
           wmax[DIM + 1] = fmax(wmax[DIM + 1], pp);
           wmin[DIM + 1] = fmin(wmin[DIM + 1], pp);
+          pmin = fmin(pmin, pp);
+          smax0 = fmax(smax0, sqrt(u2) + sqrt(gam * pp * r));  // = speed_r of this point
         }
       }
+      if (shock_on) {
 #pragma unroll
-      for (int c = 0; c < V; ++c) {
-        if (wmax[c] > Mx[c]) th_sc = fmin(th_sc, (Mx[c] - wb[c]) / (wmax[c] - wb[c]));
-        if (wmin[c] < Mn[c]) th_sc = fmin(th_sc, (wb[c] - Mn[c]) / (wb[c] - wmin[c]));
+        for (int c = 0; c < V; ++c) {
+          if (wmax[c] > Mx[c]) th_sc = fmin(th_sc, (Mx[c] - wb[c]) / (wmax[c] - wb[c]));
+          if (wmin[c] < Mn[c]) th_sc = fmin(th_sc, (wb[c] - Mn[c]) / (wb[c] - wmin[c]));
+        }
+        th_sc = fmax(0.0, fmin(1.0, th_sc));
       }
-      th_sc = fmax(0.0, fmin(1.0, th_sc));
     }
 
     if (mode == 2) {
@@ -409,6 +421,10 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
       bool fused = false;
       if (!ok) {
         th = 0.0;
+      } else if (have_rmin && th_sc == 1.0 && rmin >= eps0 && pmin >= fmin(eps0, pb)) {
+        // nothing limits: the shock pass already evaluated every point's pressure and speed
+        fused = true;
+        smax1 = smax0;
       } else {
         double thr = 1.0;
         if (have_rmin && th_sc == 1.0) {

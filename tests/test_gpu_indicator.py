@@ -199,7 +199,7 @@ def test_learned_indicator_gain(L):
     assert npos > 500
     ind, loss = T.train(L, X, y, epochs=15)
     p = ind.predict(X)
-    tau = T.calibrate(p, y, 0.999)
+    tau = T.TAU_LO
     assert np.mean(p[y > 0.5] >= tau) >= 0.999
     print(f"[gpu]   {seen} cells, {npos} positive, loss {loss:.4f}, tau_lo {tau:.3g}", flush=True)
 
@@ -207,7 +207,7 @@ def test_learned_indicator_gain(L):
         S = L.Solver(mesh, precision=L.FP32_MIXED, **(kw or {}))
         S.set_state(Q0)
         if with_ind:
-            S.set_indicator(ind, tau, max(0.5, tau))
+            S.set_indicator(ind, tau, T.TAU_HI)
         S.run_steps(steps)
         Q, _ = S.get_state()
         c = S.indicator_decisions(False)[0] if with_ind else None
@@ -230,4 +230,4 @@ def test_learned_indicator_gain(L):
     d = max(rel_l1(Ql[:, v], Qp[:, v]) for v in range(4))
     print(f"[gpu]   ramp (outside the training families): rel L1 learned vs plain {d:.2e}, skip {c[0] / c.sum():.3f}",
           flush=True)
-    assert np.all(Ql[:, 0, 0] > 0)
+    assert np.all(Ql[:, 0, 0] > 0) and d < 5e-2
