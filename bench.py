@@ -57,8 +57,8 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one k_elem launch on the 2D triangle workload from rocprofv3 counters
 # (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid only for the kernel
 # source it was measured on.
-KELEM_TRAFFIC = {"src_sha256": "2d9c5d923c02d33e6eb27a9caf01a0f6cc31d2ea058293a22ddbb064587cc937",
-                 "bytes_per_launch": 1222619776}  # profiles/lxw_kernels_tri_c3_counters.md
+KELEM_TRAFFIC = {"src_sha256": "da8678a0ea0d5e3257b94c5eb4f8bb2fcf4fc3aed1be4975454a5ed752213aea",
+                 "bytes_per_launch": 1221234688}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def kernel_src_hash():
@@ -117,7 +117,20 @@ def time_gpu(L, mesh, Q0, precision, steps, warmup, kernel_events=True):
     return {"ms_total": ms, "ms_graph": ms_graph, "kernels": kt, "Q": Q, "t": t}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(xy, tri, Q0):
+    """The oracle (FP64, OpenMP over elements and edges) on the host cores: one step of the full
+    workload on all threads, and one step of a 200^2-lattice mesh of the same kind on one thread."""
     import oracle as O
     m = O.Mesh.tri(xy, tri)
     S = O.Solver(m)
@@ -125,8 +138,22 @@ def cpu_baseline(xy, tri, Q0):
     t0 = time.perf_counter()
     S.step()
     dt = time.perf_counter() - t0
-    return {"value": len(tri) / dt, "unit": "element-updates/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"one step of the same {len(tri)}-triangle workload (FP64 oracle, {dt:.1f} s)"}
+    cores = O.num_threads()
+    from paper_1601_08145_amd import inputs as I
+    xs, ts = I.lattice_delaunay(200, 0)
+    Qs = I.averages_to_modal(I.cell_average_state(I.four_quadrant_fn(0), I.tri_sample_points(xs, ts, 2), 1.4), 6)
+    O.set_num_threads(1)
+    S1 = O.Solver(O.Mesh.tri(xs, ts))
+    S1.set_state(Qs)
+    t1 = time.perf_counter()
+    S1.step()
+    dt1 = time.perf_counter() - t1
+    O.set_num_threads(cores)
+    return {"value": len(tri) / dt, "unit": "element-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one step of the same {len(tri)}-triangle workload (FP64 oracle, {dt:.1f} s on {cores} threads)",
+            "one_thread": {"value": len(ts) / dt1, "sample": f"one step of a {len(ts)}-triangle mesh of the same "
+                                                             f"kind on 1 thread ({dt1:.1f} s)"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def kelem_roofline(kavg_ms, n_elem, traffic_ok):
@@ -268,6 +295,42 @@ def learned_leg(L, steps, warmup, c3_mesh, c3_Q0, fp64_Q=None):
                           "k_ind_us": kt_l["k_ind"] * 1e3}
     log(f"[bench]   ramp {mesh.N} triangles: plain {ms_p:.3f} ms, learned {ms_l:.3f} ms per step; rel L1 learned vs "
         f"plain {out['ramp_mach10']['rel_l1_learned_vs_plain']:.2e}, skip {out['ramp_mach10']['skip_fraction']:.3f}")
+    return out, ind, taus
+
+
+def equal_l1_leg(L, ind, taus, n=256, T=0.5):
+    """Each form on an exact solution (Shu's isentropic vortex advected by (1, 1) on a periodic
+    [-5,5]^2 Delaunay mesh), to time T: L1 error of the cell averages against the exact ones (both
+    from the library's 7-point projection) and the rate, so that the forms are compared at equal
+    L1 error."""
+    from paper_1601_08145_amd import inputs as I
+    xy, tri = I.lattice_delaunay(n, 5, box=(-5.0, 5.0, -5.0, 5.0), periodic=True)
+    tags = I.boundary_tags(xy, tri, (-5.0, 5.0, -5.0, 5.0), [0, 0, 0, 0])
+    mesh = L.Mesh.tri(xy, tri, tags, (10.0, 10.0))
+    pts = mesh.quad_points()
+    Q0 = mesh.project(I.prim_to_cons(I.vortex_fn(0.0)(pts), 1.4))
+    ex = mesh.project(I.prim_to_cons(I.vortex_fn(T)(pts), 1.4))[:, :, 0]
+    a = xy[tri]
+    area = 0.5 * np.abs((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0]))
+    out = {"workload": f"isentropic vortex (strength 5) advected by (1,1) to t = {T}, periodic [-5,5]^2, "
+                       f"{mesh.N}-triangle jittered-lattice Delaunay mesh, CFL 0.08", "n_elem": mesh.N, "forms": {}}
+    for name, prec, use_ind in (("fp64_plain", L.FP64, False), ("fp32_mixed", L.FP32_MIXED, False),
+                                ("fp32_mixed_learned", L.FP32_MIXED, True)):
+        if use_ind and ind is None:
+            continue
+        S = L.Solver(mesh, precision=prec)
+        S.set_state(Q0)
+        if use_ind:
+            S.set_indicator(ind, *taus)
+        t0 = time.perf_counter()
+        st = S.advance(T)
+        wall = time.perf_counter() - t0
+        Q, t = S.get_state()
+        err = float(np.sum(np.abs(Q[:, 0, 0] - ex[:, 0]) * area) / np.sum(area))
+        errv = max(float(np.sum(np.abs(Q[:, v, 0] - ex[:, v]) * area) / np.sum(np.abs(ex[:, v]) * area)) for v in range(4))
+        out["forms"][name] = {"l1_rho": err, "rel_l1_max_var": errv, "steps": st.steps,
+                              "element_updates_per_s_incl_sync": mesh.N * st.steps / wall}
+        log(f"[bench]   equal-L1 vortex {name}: L1(rho) {err:.4e}, max rel L1 {errv:.3e}, {st.steps} steps")
     return out
 
 
@@ -282,6 +345,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-mesh batched leg")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched leg (for profiling)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-indicator leg")
+    ap.add_argument("--no-equal-l1", action="store_true", help="skip the equal-L1 comparison on the vortex")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -357,13 +421,20 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_leg(L, args.steps, args.warmup)
 
+    ind, taus = None, None
     if not args.no_learned:
-        out["learned"] = learned_leg(L, args.steps, args.warmup, mesh, Q0, f64["Q"] if not args.no_fp64 else None)
+        out["learned"], ind, taus = learned_leg(L, args.steps, args.warmup, mesh, Q0,
+                                                f64["Q"] if not args.no_fp64 else None)
+    if not args.no_equal_l1:
+        log("[bench] equal-L1 comparison on an exact solution")
+        out["equal_l1"] = equal_l1_leg(L, ind, taus)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle, one step)")
         out["cpu_baseline"] = cpu_baseline(xy, tri, Q0)
-        log(f"[bench]   {out['cpu_baseline']['value']:.4e} element-updates/s on {out['cpu_baseline']['cores']} threads")
+        cb = out["cpu_baseline"]
+        log(f"[bench]   {cb['value']:.4e} element-updates/s on {cb['cores']} threads, {cb['one_thread']['value']:.4e} on 1 "
+            f"({cb['cpu_model']})")
 
     print(json.dumps(out), flush=True)
 

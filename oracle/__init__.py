@@ -50,6 +50,7 @@ def lib():
         sig = {
             "ora_mesh_1d": (P, [i, d, d, i, i]),
             "ora_num_threads": (i, []),
+            "ora_set_num_threads": (None, [i]),
             "ora_mesh_cart": (P, [i, i, d, d, d, d, ip]),
             "ora_mesh_tri": (P, [i, dp, i, ip, ip, dp]),
             "ora_last_error": (ctypes.c_char_p, []),
@@ -264,6 +265,11 @@ class Solver:
 
 def num_threads():
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n):
+    """OpenMP threads of the oracle's loops (results do not depend on it)."""
+    lib().ora_set_num_threads(int(n))
 
 
 def flux(q, d=0, gamma=1.4):

@@ -1105,6 +1105,9 @@ extern "C" {
 
 void* ora_mesh_1d(int n, double x0, double x1, int bcl, int bcr) { return mesh_1d(n, x0, x1, bcl, bcr); }
 // Number of threads the element and edge loops run on.
+void ora_set_num_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
 int ora_num_threads() {
 #ifdef _OPENMP
   return omp_get_max_threads();

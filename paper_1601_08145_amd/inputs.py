@@ -301,6 +301,24 @@ def four_quadrant_fn(seed, xc=0.5, yc=0.5):
     return fn
 
 
+def vortex_fn(t=0.0, eps=5.0, uinf=(1.0, 1.0), center=(0.0, 0.0), period=(10.0, 10.0), gamma=1.4):
+    """Shu's isentropic vortex (strength eps) on the free stream (rho, u, v, p) = (1, uinf, 1),
+    advected to time t (an exact solution of the Euler equations), nearest periodic image:
+    primitive variables at points (..., 2)."""
+    def fn(pts):
+        xr = pts[..., 0] - center[0] - uinf[0] * t
+        yr = pts[..., 1] - center[1] - uinf[1] * t
+        if period is not None:
+            xr = (xr + 0.5 * period[0]) % period[0] - 0.5 * period[0]
+            yr = (yr + 0.5 * period[1]) % period[1] - 0.5 * period[1]
+        f = np.exp(0.5 * (1.0 - xr * xr - yr * yr))
+        T = 1.0 - (gamma - 1) * eps**2 / (8 * gamma * math.pi**2) * f * f
+        rho = T ** (1.0 / (gamma - 1))
+        return np.stack([rho, uinf[0] - eps / (2 * math.pi) * f * yr, uinf[1] + eps / (2 * math.pi) * f * xr,
+                         rho * T], axis=-1)
+    return fn
+
+
 def vortex_shock_fn(seed, gamma=1.4, eps=5.0, box=(-5.0, 5.0, -5.0, 5.0)):
     """Isentropic vortex (strength eps) on the free stream (rho, u, v, p) = (1, 0, 0, 1),
     overlaid with a planar shock of random normal angle, position and Mach number U[1.5, 3]
