@@ -247,7 +247,7 @@ lxw_status ensure_init() {
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
-// Mesh: connectivity in the caller's order, then a Morton (Z-order) renumbering of 2D elements by
+// Mesh: connectivity in the caller's order, then a Hilbert-curve renumbering of 2D elements by
 // centroid for locality, then edges numbered in the new element order (i_e = the first element
 // to visit the edge), geometry and the per-element edge slots.
 // ---------------------------------------------------------------------------------------------
@@ -275,17 +275,24 @@ int bc_to_slot(int bc) {
   }
 }
 
-uint64_t morton2(uint32_t x, uint32_t y) {
-  auto spread = [](uint64_t v) {
-    v &= 0xffffffffull;
-    v = (v | (v << 16)) & 0x0000ffff0000ffffull;
-    v = (v | (v << 8)) & 0x00ff00ff00ff00ffull;
-    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0full;
-    v = (v | (v << 2)) & 0x3333333333333333ull;
-    v = (v | (v << 1)) & 0x5555555555555555ull;
-    return v;
-  };
-  return spread(x) | (spread(y) << 1);
+// Index of (x, y) along a Hilbert curve over a 2^16 x 2^16 grid: consecutive indices are grid
+// neighbours, so elements close in the order are close in space (fewer long jumps than a Z-order).
+uint64_t hilbert2(uint32_t x, uint32_t y) {
+  uint64_t d = 0;
+  for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += (uint64_t)s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {  // rotate the quadrant (bits below s) so the sub-curve is traversed in order
+      if (rx == 1) {
+        x = s - 1 - (x & (s - 1)) + (x & ~(s - 1));
+        y = s - 1 - (y & (s - 1)) + (y & ~(s - 1));
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
 }
 
 // Finish a mesh given, in caller order: vertex coordinates cvx (N x nv x dim), neighbours cnb /
@@ -315,7 +322,7 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
         double f = (hi[d] > lo[d]) ? (cen[2 * i + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
         q[d] = (uint32_t)std::min(65535.0, std::max(0.0, f * 65535.0));
       }
-      code[i] = morton2(q[0], q[1]);
+      code[i] = hilbert2(q[0], q[1]);
     }
     std::stable_sort(M->perm.begin(), M->perm.end(), [&](int a, int b) { return code[a] < code[b]; });
   }

@@ -775,6 +775,21 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
       }
   }
 
+  // Sec. 2.3 Step 3 / Sec. 3.3 Step 6, volume part: Q^(l) += dt V_l for l >= 2.  Stored before the
+  // edge points (which use the modes held in registers), so the accumulators are free for them.
+#pragma unroll
+  for (int c = 0; c < V; ++c)
+#pragma unroll
+    for (int l = 1; l < ML; ++l) v.Qh[(c * (ML - 1) + l - 1) * N + i] = thR * Qr[c][l - 1] + dt * vol[c][l - 1];
+  if (v.dbg_vol) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      v.dbg_vol[(c * ML) * N + i] = 0.0;
+#pragma unroll
+      for (int l = 1; l < ML; ++l) v.dbg_vol[(c * ML + l) * N + i] = double(vol[c][l - 1]);
+    }
+  }
+
   // edge points: traces q and n_out . F_T (and the ghost side on boundary edges)
   for (int k = 0; k < K; ++k) {
     const int slot = v.eslot[k * N + i];
@@ -835,19 +850,6 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
     }
   }
 
-  // Sec. 2.3 Step 3 / Sec. 3.3 Step 6, volume part: Q^(l) += dt V_l for l >= 2
-#pragma unroll
-  for (int c = 0; c < V; ++c)
-#pragma unroll
-    for (int l = 1; l < ML; ++l) v.Qh[(c * (ML - 1) + l - 1) * N + i] = thR * Qr[c][l - 1] + dt * vol[c][l - 1];
-  if (v.dbg_vol) {
-#pragma unroll
-    for (int c = 0; c < V; ++c) {
-      v.dbg_vol[(c * ML) * N + i] = 0.0;
-#pragma unroll
-      for (int l = 1; l < ML; ++l) v.dbg_vol[(c * ML + l) * N + i] = double(vol[c][l - 1]);
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------------------------
