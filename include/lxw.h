@@ -151,8 +151,10 @@ lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w,
 
 /* Creates a solver on device 0 for mesh m (which must outlive it).  stream: a hipStream_t (null
  * for the default stream); every kernel of the solver runs on it.  Allocates all device memory
- * the step needs.  Errors: LXW_ERR_ARG / LXW_ERR_UNSUPPORTED for bad parameters, LXW_ERR_OOM,
- * LXW_ERR_DEVICE. */
+ * the step needs.  Device arrays use 32-bit indices: n_var * n_modes * n_elem and
+ * 2 * q * n_var * n_edges (q = 3 edge points in 2D, 1 in 1D) must not exceed 2^31 - 1 (about 89
+ * million P2 triangles or 59 million Q2 quadrilaterals per solver).  Errors: LXW_ERR_ARG / LXW_ERR_UNSUPPORTED for bad parameters or a
+ * mesh above that size, LXW_ERR_OOM, LXW_ERR_DEVICE. */
 lxw_status lxw_solver_create(const lxw_mesh* m, const lxw_params* p, void* stream, lxw_solver** out);
 lxw_status lxw_solver_destroy(lxw_solver* s);
 
@@ -209,7 +211,9 @@ lxw_status lxw_sync(lxw_solver* s);
  *   LXW_STAGE_THETA_SC shock-limiter theta applied after the update [N]
  *   LXW_STAGE_SDT      {s, dt} [2]
  * Per-kernel timing: lxw_set_timing(s, 1) records HIP events around every kernel of later steps;
- * lxw_kernel_times returns, per kernel id (LXW_K_*), the summed milliseconds and launch counts. */
+ * lxw_kernel_times returns, per kernel id (LXW_K_*), the summed milliseconds and launch counts.
+ * A step ends inside the LXW_K_UPDATE kernel; LXW_K_FINAL counts only the kernel that closes a
+ * state read-out which applied the pending shock-capturing limiter. */
 enum {
   LXW_STAGE_QLIM = 0, LXW_STAGE_THETA = 1, LXW_STAGE_VOL = 2, LXW_STAGE_FLXW = 3, LXW_STAGE_FLXF = 4,
   LXW_STAGE_C = 6, LXW_STAGE_LAME = 7, LXW_STAGE_QUPD = 8, LXW_STAGE_THETA_SC = 9, LXW_STAGE_SDT = 10

@@ -674,7 +674,6 @@ lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v, double T) {
     HIPCHK(hipMemcpyAsync(S->dq_upd_bar, v.Qbar, (size_t)V * N * sizeof(double), hipMemcpyDeviceToDevice, S->st));
     HIPCHK(hipMemcpyAsync(S->dq_upd_h, v.Qh, (size_t)V * (ML - 1) * N * sizeof(R), hipMemcpyDeviceToDevice, S->st));
   }
-  HIPCHK((launch_one<E, R>(S, v, K_FINAL, T, 0)));
   return LXW_OK;
 }
 
@@ -936,6 +935,13 @@ lxw_status create_solver(const lxw_mesh* m, const lxw_params* p, void* stream, B
   lxw_status s = check_params(p);
   if (s) return s;
   if ((s = ensure_init())) return s;
+  {
+    // device arrays are indexed with 32-bit integers: the largest per-element array has V*ML
+    // columns of N entries, the largest per-edge array 3*V columns of E entries
+    const int64_t nqe = m->kind == LXW_LINE ? 1 : 3;
+    if ((int64_t)m->V * m->ML * m->N > INT32_MAX || 2 * nqe * m->V * (int64_t)m->E > INT32_MAX)
+      return fail(LXW_ERR_ARG, "mesh too large for one solver (32-bit device indices)");
+  }
   std::unique_ptr<lxw_solver> S(new (std::nothrow) lxw_solver);
   if (!S) return fail(LXW_ERR_OOM, "host allocation");
   S->M = m;

@@ -14,8 +14,9 @@
 //   k_flim   per element, float64: the flux limiter of Sec. 3.3 Steps 4-5 (Gamma, Lambda_ik, the
 //            corner states and the damping-factor solve mu_c), one candidate per (element, edge);
 //   k_update per element: Lambda_e = min over the two sides, the blended cell-average update and
-//            the higher-moment update of Sec. 3.3 Step 6, and the positivity check;
-//   k_final  per mesh: t += dt.
+//            the higher-moment update of Sec. 3.3 Step 6, and the positivity check; the first
+//            element of each mesh then ends the mesh's step (t += dt);
+//   k_final  per mesh, after a state read-out applied the pending shock limiter: marks it done.
 // Thread-per-element (or per-edge) mapping; reference tables sit in __constant__ memory and are
 // read through the scalar cache (every lane of a wave reads the same entry).  State is stored as
 // structure-of-arrays: cell averages Qbar[V][N] (float64) and higher modes Qh[V][ML-1][N].
@@ -211,6 +212,20 @@ __device__ __forceinline__ void inflow_state(const double* inflow, T* out) {
 template <class R>
 __device__ __forceinline__ int mesh_id(const int* mesh_of, int i) { return mesh_of ? mesh_of[i] : 0; }
 
+// Entry i of a structure-of-arrays column that starts at `col` (a pointer the whole wavefront
+// shares).  The byte offset is formed in 32 bits (i < 2^29, and no column reaches 4 GiB), so the
+// address is the shared base plus the lane's offset: without this the compiler keeps one 64-bit
+// vector address per column live across a burst of loads, which costs more registers than the
+// data itself.
+template <class T>
+__device__ __forceinline__ T& at(T* col, int i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(col) + (unsigned)i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* col, int i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(col) + (unsigned)i * (unsigned)sizeof(T));
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Elements (and
 // edges, numbered in element order) are in space-filling-curve order, so neighbouring work items
 // share data; give every XCD one contiguous range of blocks (the grid is padded to a multiple of 8
@@ -276,8 +291,10 @@ __device__ __forceinline__ double point_dev(const RefTab<E, double>& T, const R 
   return acc;
 }
 
-template <class E, class R>
-__global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
+// The mode is a template argument: each mode's kernel holds only its own path, so the read-out and
+// collection paths do not raise the register allocation of the per-step kernel.
+template <class E, class R, int mode>
+__global__ __launch_bounds__(256) void k_pre(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
   const RefTab<E, double>& T = TabSel<E, double>::get();
   const int N = v.N;
@@ -292,9 +309,9 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
     R Qh[V][ML - 1];
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      qb[c] = v.Qbar[c * N + i];
+      qb[c] = at(v.Qbar + (size_t)c * N, i);
 #pragma unroll
-      for (int l = 0; l < ML - 1; ++l) Qh[c][l] = v.Qh[(c * (ML - 1) + l) * N + i];
+      for (int l = 0; l < ML - 1; ++l) Qh[c][l] = at(v.Qh + (size_t)(c * (ML - 1) + l) * N, i);
     }
     const double rb = 1.0 / qb[0];
     const double pb = pressure_r<DIM>(qb, rb, gam);
@@ -317,7 +334,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
     double pmin = INFINITY;  // smallest point pressure of the unlimited state (points with rho > 0)
     double smax0 = 0.0;      // largest point wave speed of the unlimited state (points with rho > 0)
     bool have_rmin = false;
-    const bool detect = mode == 2 || !v.ind_flag || v.ind_flag[i] != 0;
+    const bool detect = mode == 2 || !v.ind_flag || at(v.ind_flag, i) != 0;
     const bool shock_on = v.shock && v.sc[mid].shock_pending && ok && detect;
     if (shock_on || (mode == 0 && ok)) {
       have_rmin = true;
@@ -326,22 +343,22 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) wb[1 + d] = qb[1 + d] * rb;
       wb[DIM + 1] = pb;
-      const double dl = v.delta[i];
+      const double dl = at(v.delta, i);
 #pragma unroll
       for (int c = 0; c < V; ++c) { Mx[c] = wb[c] + dl; Mn[c] = wb[c] - dl; }
 #pragma unroll
       for (int k = 0; k < K && shock_on; ++k) {
         double qn[V], wn[V];
-        const int j = v.nbr[k * N + i];
+        const int j = at(v.nbr + (size_t)k * N, i);
         if (j >= 0) {
 #pragma unroll
-          for (int c = 0; c < V; ++c) qn[c] = v.Qbar[c * N + j];
+          for (int c = 0; c < V; ++c) qn[c] = at(v.Qbar + (size_t)c * N, j);
         } else {
-          const int bc = v.eslot[k * N + i] & 3;
+          const int bc = at(v.eslot + (size_t)k * N, i) & 3;
           if (bc == SB_REFLECTIVE) {
             double nh[DIM], len2 = 0.0;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) { nh[d] = double(v.nout[(k * DIM + d) * N + i]); len2 += nh[d] * nh[d]; }
+            for (int d = 0; d < DIM; ++d) { nh[d] = double(at(v.nout + (size_t)(k * DIM + d) * N, i)); len2 += nh[d] * nh[d]; }
             const double il = 1.0 / sqrt(len2);
 #pragma unroll
             for (int d = 0; d < DIM; ++d) nh[d] *= il;
@@ -400,13 +417,13 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
     }
 
     if (mode == 2) {
-      v.theta[i] = th_sc;  // the factor the limiter would apply; the state is left as it is
+      at(v.theta, i) = th_sc;  // the factor the limiter would apply; the state is left as it is
     } else if (mode == 1) {
       if (th_sc < 1.0) {
 #pragma unroll
         for (int c = 0; c < V; ++c)
 #pragma unroll
-          for (int l = 0; l < ML - 1; ++l) v.Qh[(c * (ML - 1) + l) * N + i] = R(th_sc * double(Qh[c][l]));
+          for (int l = 0; l < ML - 1; ++l) at(v.Qh + (size_t)(c * (ML - 1) + l) * N, i) = R(th_sc * double(Qh[c][l]));
       }
       if (v.dbg_theta_sc && v.shock && v.sc[mid].shock_pending) v.dbg_theta_sc[i] = th_sc;
     } else {
@@ -453,7 +470,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v, int mode) {
         }
       }
       const double tt = th_sc * th;
-      v.theta[i] = tt;
+      at(v.theta, i) = tt;
       if (finite && qb[0] > 0.0 && pb > 0.0) {
         smax = speed_r<DIM>(qb, gam);
         if (fused && tt == 1.0) {
@@ -864,15 +881,15 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   const int NE = v.E, N = v.N;
   const int e = xcd_item();
   if (e >= NE) return;
-  const int mid = v.e_mesh ? v.e_mesh[e] : 0;
+  const int mid = v.e_mesh ? at(v.e_mesh, e) : 0;
   const double s = v.sc[mid].s;
   const double gam = v.gamma;
   double n[DIM], len2 = 0.0;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) { n[d] = v.e_n[d * NE + e]; len2 += n[d] * n[d]; }
+  for (int d = 0; d < DIM; ++d) { n[d] = at(v.e_n + (size_t)d * NE, e); len2 += n[d] * n[d]; }
   const double len = sqrt(len2);
   const R hs = R(0.5 * s * len);
-  const int ie = v.e_i[e], je = v.e_j[e];
+  const int ie = at(v.e_i, e), je = at(v.e_j, e);
   double W[V];
 #pragma unroll
   for (int c = 0; c < V; ++c) W[c] = 0.0;
@@ -880,27 +897,27 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   for (int jj = 0; jj < NQE; ++jj) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      const R qm = v.tq[((size_t)(0 * NQE + jj) * V + c) * NE + e];
-      const R fm = v.tf[((size_t)(0 * NQE + jj) * V + c) * NE + e];
-      const R qp = v.tq[((size_t)(1 * NQE + jj) * V + c) * NE + e];
-      const R fp = -v.tf[((size_t)(1 * NQE + jj) * V + c) * NE + e];
+      const R qm = at(v.tq + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
+      const R fm = at(v.tf + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
+      const R qp = at(v.tq + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
+      const R fp = -at(v.tf + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
       const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
-      v.fstar[(jj * V + c) * NE + e] = fs;
+      at(v.fstar + (size_t)(jj * V + c) * NE, e) = fs;
       W[c] += 0.5 * double(T.om[jj]) * double(fs);
     }
   }
 #pragma unroll
-  for (int c = 0; c < V; ++c) v.fLxW[c * NE + e] = W[c];
+  for (int c = 0; c < V; ++c) at(v.fLxW + (size_t)c * NE, e) = W[c];
 
   const int i = ie, j = je;
   double qi[V], qj[V];
 #pragma unroll
-  for (int c = 0; c < V; ++c) qi[c] = v.Qbar[c * N + i];
+  for (int c = 0; c < V; ++c) qi[c] = at(v.Qbar + (size_t)c * N, i);
   if (j >= 0) {
 #pragma unroll
-    for (int c = 0; c < V; ++c) qj[c] = v.Qbar[c * N + j];
+    for (int c = 0; c < V; ++c) qj[c] = at(v.Qbar + (size_t)c * N, j);
   } else {
-    const int bc = v.e_bc[e];
+    const int bc = at(v.e_bc, e);
     if (bc == SB_REFLECTIVE) {
       double nh[DIM];
 #pragma unroll
@@ -927,7 +944,7 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
     for (int c = 0; c < V; ++c) Lf[c] += 0.5 * n[d] * (Fj[c] + Fi[c]);
   }
 #pragma unroll
-  for (int c = 0; c < V; ++c) v.fLxF[c * NE + e] = Lf[c] - 0.5 * s * len * (qj[c] - qi[c]);
+  for (int c = 0; c < V; ++c) at(v.fLxF + (size_t)c * NE, e) = Lf[c] - 0.5 * s * len * (qj[c] - qi[c]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -984,24 +1001,24 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   const int mid = mesh_id<R>(v.mesh_of, i);
   const double dt = v.sc[mid].dt;
   const double gam = v.gamma;
-  const double area = v.area[i];
+  const double area = at(v.area, i);
   const double r = dt / area;
   double qb[V];
 #pragma unroll
-  for (int c = 0; c < V; ++c) qb[c] = v.Qbar[c * N + i];
+  for (int c = 0; c < V; ++c) qb[c] = at(v.Qbar + (size_t)c * N, i);
   double fW[K][V], fF[K][V], df[K];
   int eidx[K], sd[K];
   double Gam = area * qb[0] / dt;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int slot = v.eslot[k * N + i];
+    const int slot = at(v.eslot + (size_t)k * N, i);
     eidx[k] = slot >> 3;
     sd[k] = (slot >> 2) & 1;
     const double ep = sd[k] ? -1.0 : 1.0;
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      fW[k][c] = ep * v.fLxW[c * NE + eidx[k]];
-      fF[k][c] = ep * v.fLxF[c * NE + eidx[k]];
+      fW[k][c] = ep * at(v.fLxW + (size_t)c * NE, eidx[k]);
+      fF[k][c] = ep * at(v.fLxF + (size_t)c * NE, eidx[k]);
     }
     Gam -= fF[k][0];
     df[k] = fF[k][0] - fW[k][0];
@@ -1047,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   }
   if (bad) report(v.err, E_CFL, i);
 #pragma unroll
-  for (int k = 0; k < K; ++k) v.cedge[sd[k] * NE + eidx[k]] = Lam[k] * mm[k];
+  for (int k = 0; k < K; ++k) at(v.cedge, sd[k] * NE + eidx[k]) = Lam[k] * mm[k];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1066,31 +1083,31 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   const double dt = v.sc[mid].dt;
-  const double r = dt / v.area[i];
+  const double r = dt / at(v.area, i);
   double qb[V];
   R Qh[V][ML - 1];
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    qb[c] = v.Qbar[c * N + i];
+    qb[c] = at(v.Qbar + (size_t)c * N, i);
 #pragma unroll
-    for (int l = 0; l < ML - 1; ++l) Qh[c][l] = v.Qh[(c * (ML - 1) + l) * N + i];
+    for (int l = 0; l < ML - 1; ++l) Qh[c][l] = at(v.Qh + (size_t)(c * (ML - 1) + l) * N, i);
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int slot = v.eslot[k * N + i];
+    const int slot = at(v.eslot + (size_t)k * N, i);
     const int e = slot >> 3, side = (slot >> 2) & 1;
     const double ep = side ? -1.0 : 1.0;
-    const double th = fmin(1.0, fmin(v.cedge[e], v.cedge[NE + e]));
+    const double th = fmin(1.0, fmin(at(v.cedge, e), at(v.cedge + NE, e)));
     if (v.dbg_lame) v.dbg_lame[k * N + i] = th;
 #pragma unroll
-    for (int c = 0; c < V; ++c) qb[c] -= r * ep * (th * v.fLxW[c * NE + e] + (1.0 - th) * v.fLxF[c * NE + e]);
+    for (int c = 0; c < V; ++c) qb[c] -= r * ep * (th * at(v.fLxW + (size_t)c * NE, e) + (1.0 - th) * at(v.fLxF + (size_t)c * NE, e));
     const R re = R(r * ep);
 #pragma unroll
     for (int jl = 0; jl < NQE; ++jl) {
       const int jj = side ? (NQE - 1 - jl) : jl;
 #pragma unroll
       for (int c = 0; c < V; ++c) {
-        const R fs = re * v.fstar[(jj * V + c) * NE + e];
+        const R fs = re * at(v.fstar + (size_t)(jj * V + c) * NE, e);
 #pragma unroll
         for (int l = 1; l < ML; ++l) Qh[c][l - 1] -= T.ephi[k][jl][l] * fs;
       }
@@ -1099,29 +1116,31 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   bool finite = true;
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    v.Qbar[c * N + i] = qb[c];
+    at(v.Qbar + (size_t)c * N, i) = qb[c];
     finite = finite && isfinite(qb[c]);
 #pragma unroll
-    for (int l = 0; l < ML - 1; ++l) v.Qh[(c * (ML - 1) + l) * N + i] = Qh[c][l];
+    for (int l = 0; l < ML - 1; ++l) at(v.Qh + (size_t)(c * (ML - 1) + l) * N, i) = Qh[c][l];
   }
   if (!finite) report(v.err, E_NONFINITE, i);
   else if (!(qb[0] > 0.0) || !(pressure<DIM>(qb, v.gamma) > 0.0)) report(v.err, E_POSITIVITY, i);
-}
-
-// k_final: mode 0 ends a step (t += dt, reset s, shock limiter now due); mode 1 marks the pending
-// shock limiter as applied (after a state read-out applied it).
-__global__ void k_final(Scalars* sc, int n_mesh, int shock, int mode) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_mesh) return;
-  Scalars& S = sc[m];
-  if (mode == 0) {
-    S.t += S.dt;
+  // The first element of each mesh ends the mesh's step: t += dt, the wave-speed maximum is reset
+  // and the shock-capturing limiter becomes due.  Every lane has read dt above and no kernel of
+  // this step reads the fields written here.
+  if (i == 0 || (v.mesh_of && at(v.mesh_of, i - 1) != mid)) {
+    Scalars& S = v.sc[mid];
+    S.t += dt;
     S.steps += 1;
     S.s_bits = 0ull;
-    S.shock_pending = shock ? 1 : 0;
-  } else {
-    S.shock_pending = 0;
+    S.shock_pending = v.shock ? 1 : 0;
   }
+}
+
+// k_final: marks the pending shock-capturing limiter as applied (after a state read-out applied
+// it).
+__global__ void k_final(Scalars* sc, int n_mesh) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_mesh) return;
+  sc[m].shock_pending = 0;
 }
 
 template <class E, class R>
@@ -1133,10 +1152,14 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
   if (tunable(k == K_SHOCK ? K_PRE : k) && bs != 64 && bs != 128 && bs != 256) return hipErrorInvalidConfiguration;
   switch (k) {
     case K_PRE:
-      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v, 0);
+      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R, 0>), egrid(v.N, bs), dim3(bs), 0, st, v);
       break;
     case K_SHOCK:
-      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v, mode);
+      if (mode != 1 && mode != 2) return hipErrorInvalidValue;
+      if (v.N > 0) {
+        if (mode == 1) hipLaunchKernelGGL((k_pre<E, R, 1>), egrid(v.N, bs), dim3(bs), 0, st, v);
+        else hipLaunchKernelGGL((k_pre<E, R, 2>), egrid(v.N, bs), dim3(bs), 0, st, v);
+      }
       break;
     case K_IND:
       return hipErrorInvalidValue;  // launched through launch_indicator
@@ -1158,7 +1181,8 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
       if (v.N > 0) hipLaunchKernelGGL((k_update<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v);
       break;
     case K_FINAL:
-      hipLaunchKernelGGL(k_final, grid(n_mesh, 64), dim3(64), 0, st, v.sc, n_mesh, v.shock, mode);
+      if (mode != 1) return hipErrorInvalidValue;  // the step itself ends in k_update
+      hipLaunchKernelGGL(k_final, grid(n_mesh, 64), dim3(64), 0, st, v.sc, n_mesh);
       break;
   }
   return hipGetLastError();
