@@ -1860,12 +1860,9 @@ lxw_status lxw_solver_set_indicator(lxw_solver* S, const lxw_indicator* ind, dou
   if (s) return s;
   if (ind && !S->ind_flag) {
     if ((s = S->alloc(&S->ind_flag, (size_t)S->M->N))) return s;
-    if ((s = S->alloc(&S->ind_counts, 3))) return s;
+    if ((s = S->alloc(&S->ind_counts, (size_t)3 * IND_GRID_MAX))) return s;
   }
-  if (ind) {
-    const unsigned long long z[3] = {0, 0, 0};
-    HIPCHK(hipMemcpy(S->ind_counts, z, sizeof z, hipMemcpyHostToDevice));
-  }
+  if (ind) HIPCHK(hipMemset(S->ind_counts, 0, sizeof(unsigned long long) * 3 * IND_GRID_MAX));
   S->ind = ind;
   S->tau_lo = (float)tau_lo;
   S->tau_hi = (float)tau_hi;
@@ -1880,9 +1877,13 @@ lxw_status lxw_indicator_decisions(lxw_solver* S, int64_t* counts, uint8_t* flag
   if (!S->ind) return fail(LXW_ERR_ARG, "no indicator set on this solver");
   lxw_status s = sync_check(S);
   if (s) return s;
-  unsigned long long c[3];
-  HIPCHK(hipMemcpy(c, S->ind_counts, sizeof c, hipMemcpyDeviceToHost));
-  for (int k = 0; k < 3; ++k) counts[k] = (int64_t)c[k];
+  std::vector<unsigned long long> c((size_t)3 * IND_GRID_MAX);
+  HIPCHK(hipMemcpy(c.data(), S->ind_counts, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  for (int k = 0; k < 3; ++k) {
+    unsigned long long t = 0;
+    for (int b = 0; b < IND_GRID_MAX; ++b) t += c[(size_t)b * 3 + k];
+    counts[k] = (int64_t)t;
+  }
   if (flags) {
     std::vector<unsigned char> f(S->M->N);
     HIPCHK(hipMemcpy(f.data(), S->ind_flag, f.size(), hipMemcpyDeviceToHost));

@@ -31,27 +31,27 @@ __device__ __forceinline__ void cell_features(const View<R>& v, int i, float (&F
   int cells[4] = {i, i, i, i};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int j = v.nbr[k * N + i];
+    const int j = at(v.nbr + (size_t)k * N, i);
     cells[k + 1] = j >= 0 ? j : i;
   }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int c = g == 0 ? 0 : 3;  // rho, E
-    const double avg = v.Qbar[c * N + i];
+    const double avg = at(v.Qbar + (size_t)c * N, i);
     float vals[24];
     float mx = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int cell = cells[q];
-      vals[q * 6] = float(v.Qbar[c * N + cell] - avg);
+      vals[q * 6] = float(at(v.Qbar + (size_t)c * N, cell) - avg);
 #pragma unroll
-      for (int l = 1; l < ML; ++l) vals[q * 6 + l] = float(v.Qh[(c * (ML - 1) + l - 1) * N + cell]);
+      for (int l = 1; l < ML; ++l) vals[q * 6 + l] = float(at(v.Qh + (size_t)(c * (ML - 1) + l - 1) * N, cell));
     }
 #pragma unroll
     for (int x = 0; x < 24; ++x) mx = fmaxf(mx, fabsf(vals[x]));
     // floor: the shock-capturing limiter's relaxation delta_i (variations far below it give
     // features near zero) and a relative 1e-6 (a uniform region's round-off stays near zero)
-    const float rs = 1.0f / (mx + float(v.delta[i] + 1e-6 * fabs(avg)) + 1e-30f);
+    const float rs = 1.0f / (mx + float(at(v.delta, i) + 1e-6 * fabs(avg)) + 1e-30f);
 #pragma unroll
     for (int x = 0; x < 24; ++x) F[g * 24 + x] = vals[x] * rs;
   }
@@ -125,10 +125,12 @@ __device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndL
     own[s] = mine;
     other[s] = swap_halves(send);  // the partner cell's features for this lane's k range
   }
-  // layer 1
-  f32x16 acc[2][2];
+  // layer 1, one 32 x 32 tile at a time, each followed by its bias, ReLU and bf16 rounding (the
+  // second layer's B operands): only one accumulator tile is live
+  bf16x8 H[2][2][2];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < 2; ++mt) {
+    const float* bb = W.b1 + (mt * 2 + h) * 16;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       f32x16 a = {};
@@ -138,21 +140,13 @@ __device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndL
         const bf16x8 B = (t == h) ? own[s] : other[s];
         a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, a, 0, 0, 0);
       }
-      acc[mt][t] = a;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) H[mt][t][r >> 3][r & 7] = (__bf16)fmaxf(a[r] + bb[r], 0.0f);
     }
-  // bias, ReLU, bf16: the second layer's B operands
-  bf16x8 H[2][2][2];
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
-    const float* bb = W.b1 + (mt * 2 + h) * 16;
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) H[mt][t][r >> 3][r & 7] = (__bf16)fmaxf(acc[mt][t][r] + bb[r], 0.0f);
   }
   // layer 2
   float part[2] = {0.0f, 0.0f};
-#pragma unroll
+#pragma unroll 1  // unrolled, the two row tiles' weight, bias and output loads all stay live
   for (int mt2 = 0; mt2 < 2; ++mt2) {
     const float* bb = W.b2 + (mt2 * 2 + h) * 16;
     const float* ww = W.w3 + (mt2 * 2 + h) * 16;
@@ -179,11 +173,14 @@ __device__ __forceinline__ float mlp_logit(const float (&F)[IND_NIN], const IndL
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
 
 // Decisions for the solver's elements: 0 skip the shock-capturing limiter (p < tau_lo), 2 flagged
-// (p >= tau_hi), 1 otherwise; counts[3] accumulates the decisions.  Workgroups of 256 lanes stage
-// the weights once and then walk over chunks of 256 elements (every lane of a workgroup runs the
-// same number of chunks, as the matrix instructions need full wavefronts).
+// (p >= tau_hi), 1 otherwise.  Workgroups of 256 lanes stage the weights once and then walk over
+// chunks of 256 elements (every lane of a workgroup runs the same number of chunks, as the matrix
+// instructions need full wavefronts).  Workgroup b adds its decision counts to row b of
+// counts[][3]: atomics of every wavefront on three shared counters serialise (about 8 ns each,
+// over 100 us at a million cells).
+// Three wavefronts per SIMD (168 registers, no spills): the feature gathers are latency-bound.
 template <class R>
-__global__ __launch_bounds__(256) void k_ind(View<R> v, IndW W, unsigned char* flag, unsigned long long* counts) {
+__global__ __launch_bounds__(256, 3) void k_ind(View<R> v, IndW W, unsigned char* flag, unsigned long long* counts) {
   __shared__ IndLds Ls;
   stage_weights(Ls, W);
   const int nchunk = (v.N + 255) / 256;
@@ -205,14 +202,18 @@ __global__ __launch_bounds__(256) void k_ind(View<R> v, IndW W, unsigned char* f
     n1 += __popcll(__ballot(valid && d == 1));
     n2 += __popcll(__ballot(valid && d == 2));
   }
-  if ((threadIdx.x & 63) == 0) {
-    if (n0) atomicAdd(&counts[0], n0);
-    if (n1) atomicAdd(&counts[1], n1);
-    if (n2) atomicAdd(&counts[2], n2);
+  __shared__ unsigned long long red[4][3];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[w][0] = n0; red[w][1] = n1; red[w][2] = n2; }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long s = 0;
+    for (int x = 0; x < (int)(blockDim.x >> 6); ++x) s += red[x][threadIdx.x];
+    counts[blockIdx.x * 3 + threadIdx.x] += s;
   }
 }
 
-__global__ __launch_bounds__(256) void k_predict(IndW W, const float* X, int n, float* p) {
+__global__ __launch_bounds__(256, 3) void k_predict(IndW W, const float* X, int n, float* p) {
   __shared__ IndLds Ls;
   stage_weights(Ls, W);
   const int nchunk = (n + 255) / 256;
@@ -372,7 +373,8 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(int nblk, const float* part,
 template <class R>
 hipError_t launch_indicator(const View<R>& v, const IndW& W, unsigned char* flag, unsigned long long* counts,
                             hipStream_t st) {
-  if (v.N > 0) hipLaunchKernelGGL(k_ind<R>, dim3(std::min((v.N + 255) / 256, 2048)), dim3(256), 0, st, v, W, flag, counts);
+  if (v.N > 0)
+    hipLaunchKernelGGL(k_ind<R>, dim3(std::min((v.N + 255) / 256, IND_GRID_MAX)), dim3(256), 0, st, v, W, flag, counts);
   return hipGetLastError();
 }
 

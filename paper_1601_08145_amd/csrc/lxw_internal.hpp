@@ -111,6 +111,20 @@ struct View {
   double* dbg_qlim;       // [V][ML][N] limited state at the start of the step
 };
 
+// Entry i of a structure-of-arrays column that starts at `col` (a pointer the whole wavefront
+// shares).  The byte offset is formed in 32 bits (i < 2^29, and no column reaches 4 GiB), so the
+// address is the shared base plus the lane's offset: without this the compiler keeps one 64-bit
+// vector address per column live across a burst of loads, which costs more registers than the
+// data itself.
+template <class T>
+__device__ __forceinline__ T& at(T* col, int i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(col) + (unsigned)i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* col, int i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(col) + (unsigned)i * (unsigned)sizeof(T));
+}
+
 // All reference tables in both precisions (built on the host by lxw_host.cpp).
 struct HostTabs {
   RefTab<ElLine, double> line_d;
@@ -162,6 +176,10 @@ struct IndW {
   float tau_lo, tau_hi;
 };
 
+// Inference over the solver's elements: decisions flag[N] and per-workgroup decision counts
+// counts[IND_GRID_MAX][3], each workgroup adding to its own row (no two workgroups share a
+// counter); the caller sums the rows.
+constexpr int IND_GRID_MAX = 2048;
 template <class R>
 hipError_t launch_indicator(const View<R>& v, const IndW& W, unsigned char* flag, unsigned long long* counts,
                             hipStream_t st);

@@ -212,20 +212,6 @@ __device__ __forceinline__ void inflow_state(const double* inflow, T* out) {
 template <class R>
 __device__ __forceinline__ int mesh_id(const int* mesh_of, int i) { return mesh_of ? mesh_of[i] : 0; }
 
-// Entry i of a structure-of-arrays column that starts at `col` (a pointer the whole wavefront
-// shares).  The byte offset is formed in 32 bits (i < 2^29, and no column reaches 4 GiB), so the
-// address is the shared base plus the lane's offset: without this the compiler keeps one 64-bit
-// vector address per column live across a burst of loads, which costs more registers than the
-// data itself.
-template <class T>
-__device__ __forceinline__ T& at(T* col, int i) {
-  return *reinterpret_cast<T*>(reinterpret_cast<char*>(col) + (unsigned)i * (unsigned)sizeof(T));
-}
-template <class T>
-__device__ __forceinline__ const T& at(const T* col, int i) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(col) + (unsigned)i * (unsigned)sizeof(T));
-}
-
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Elements (and
 // edges, numbered in element order) are in space-filling-curve order, so neighbouring work items
 // share data; give every XCD one contiguous range of blocks (the grid is padded to a multiple of 8
