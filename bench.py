@@ -57,8 +57,8 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one k_elem launch on the 2D triangle workload from rocprofv3 counters
 # (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid only for the kernel
 # source it was measured on.
-KELEM_TRAFFIC = {"src_sha256": "aa0d693bdb881aef0aefbed2c8fe089464349ce1ea92e6d8147067e79e953c51",
-                 "bytes_per_launch": 936000102}  # profiles/lxw_kernels_tri_c3_counters.md
+KELEM_TRAFFIC = {"src_sha256": "76f30a9098654c76ec9f6c9a271bf7d894985681571d0be04af693b7b3ae75b5",
+                 "bytes_per_launch": 974027776}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def kernel_src_hash():
@@ -154,6 +154,27 @@ def cpu_baseline(xy, tri, Q0):
             "one_thread": {"value": len(ts) / dt1, "sample": f"one step of a {len(ts)}-triangle mesh of the same "
                                                              f"kind on 1 thread ({dt1:.1f} s)"},
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def copy_rate(nbytes=1 << 30, reps=5):
+    """Bytes read + written per second of a device-to-device copy of nbytes (fastest of reps): the
+    rate a plain streaming kernel reaches, beside which the memory-bound step kernels are read."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    del a, b
+    return 2 * nbytes / (best * 1e-3)
 
 
 def kelem_roofline(kavg_ms, n_elem, traffic_ok):
@@ -358,10 +379,17 @@ def main():
         n = args.copy_probe // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
+        ms = []
         for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        # bytes read + written per copy over the fastest of the three
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3, "ms": ms,
+                          "GBs_read_plus_write": 2 * n * 4 / (min(ms) * 1e-3) / 1e9}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the LxW-DG step here is a "
@@ -407,6 +435,11 @@ def main():
         kt = {k: {"ms_avg": v[0] / max(v[1], 1), "launches": v[1]} for k, v in mix["kernels"].items()}
         out["kernels"] = kt
         out["roofline"] = kelem_roofline(kt["k_elem"]["ms_avg"], N, traffic_ok=True)
+
+    cr = copy_rate()
+    out["hbm_copy_probe"] = {"GBs": cr / 1e9, "frac_of_peak": cr / 1e9 / PEAK_HBM_GBS,
+                             "note": "device copy of 1 GiB, bytes read + written, fastest of 5"}
+    log(f"[bench] 1 GiB device copy: {cr / 1e12:.2f} TB/s read + write")
 
     if not args.no_fp64:
         log(f"[bench] FP64 plain: {args.warmup} warm-up + {args.steps} timed steps")
