@@ -141,6 +141,8 @@ def test_learned_step_matches_masked_oracle(L):
     Ob2 = O.Solver(O.Mesh.tri(xy, tri), **kw)
     Q1, t1 = S.get_state()  # applies the pending limiter with the indicator's decisions
     counts, flags = S.indicator_decisions()
+    # one inference since the indicator was set: the per-workgroup counts add up to its decisions
+    assert np.array_equal(counts, np.bincount(flags, minlength=3))
     Ob2.set_state(Q0)
     Ob2.set_shock_mask(flags != 0)
     Ob2.step()
@@ -256,6 +258,10 @@ def test_full_size_ramp_learned_step_vs_masked_oracle(L):
         if learned:
             S.set_indicator(ind, T.TAU_LO, T.TAU_HI)
         S.step()
+        if learned:
+            # one inference over 2M cells (workgroups walk several chunks each): counts = decisions
+            c1, f1 = S.indicator_decisions()
+            assert np.array_equal(c1, np.bincount(f1, minlength=3)) and c1.sum() == len(tri)
         Qg, tg = S.get_state()
         Ob = O.Solver(om, inflow=list(inflow))
         Ob.set_state(Q0)
