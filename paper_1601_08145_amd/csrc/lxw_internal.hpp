@@ -90,10 +90,12 @@ struct View {
   R* tq;                  // [2][NQE][V][E] traces q (side 0 = i_e, side 1 = j_e or the ghost state),
                           //   points in i_e's order along the edge
   R* tf;                  // [2][NQE][V][E] traces n_out . F_T of that side
-  R* fstar;               // [NQE][V][E] F*_T . n_e at the edge points
-  double* fLxW;           // [V][E]
-  double* fLxF;           // [V][E]
-  double* cedge;          // [2][E] damping candidate of each side (1 on a ghost side)
+  // Per-edge records (array of structures): the element kernels gather them by edge index, and
+  // one record spans one or two cache lines instead of one line per component.
+  R* fstar;               // [E][NQE][V] F*_T . n_e at the edge points
+  double* fLxW;           // [E][2][V]: f^LxW of edge e at fLxW[e * 2V + c]
+  double* fLxF;           // = fLxW + V: f^LxF of edge e at fLxF[e * 2V + c] (same records)
+  double* cedge;          // [E][2] damping candidate of each side (1 on a ghost side)
   const unsigned char* ind_flag;  // [N] learned indicator decision (0: the shock-capturing limiter
                                  //   is skipped) or null (plain detection everywhere)
   Scalars* sc;

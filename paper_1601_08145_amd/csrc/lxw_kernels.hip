@@ -332,6 +332,36 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
       const double dl = at(v.delta, i);
 #pragma unroll
       for (int c = 0; c < V; ++c) { Mx[c] = wb[c] + dl; Mn[c] = wb[c] - dl; }
+      // the point pass before the neighbours' bounds: the neighbour states are then not live
+      // across it (135 instead of 165 registers)
+      double wmax[V], wmin[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) { wmax[c] = wb[c]; wmin[c] = wb[c]; }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        double q[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) q[c] = qb[c] + point_dev<E, R>(T, Qh, p, c);
+        wmax[0] = fmax(wmax[0], q[0]);
+        wmin[0] = fmin(wmin[0], q[0]);
+        rmin = fmin(rmin, q[0]);
+        if (q[0] > 0.0) {
+          const double r = 1.0 / q[0];
+          double u2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            const double u = q[1 + d] * r;
+            wmax[1 + d] = fmax(wmax[1 + d], u);
+            wmin[1 + d] = fmin(wmin[1 + d], u);
+            u2 += u * u;
+          }
+          const double pp = pressure_r<DIM>(q, r, gam);
+          wmax[DIM + 1] = fmax(wmax[DIM + 1], pp);
+          wmin[DIM + 1] = fmin(wmin[DIM + 1], pp);
+          pmin = fmin(pmin, pp);
+          smax0 = fmax(smax0, sqrt(u2) + sqrt(gam * pp * r));  // = speed_r of this point
+        }
+      }
 #pragma unroll
       for (int k = 0; k < K && shock_on; ++k) {
         double qn[V], wn[V];
@@ -363,34 +393,6 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
         wn[DIM + 1] = pressure_r<DIM>(qn, rn, gam);
 #pragma unroll
         for (int c = 0; c < V; ++c) { Mx[c] = fmax(Mx[c], wn[c]); Mn[c] = fmin(Mn[c], wn[c]); }
-      }
-      double wmax[V], wmin[V];
-#pragma unroll
-      for (int c = 0; c < V; ++c) { wmax[c] = wb[c]; wmin[c] = wb[c]; }
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        double q[V];
-#pragma unroll
-        for (int c = 0; c < V; ++c) q[c] = qb[c] + point_dev<E, R>(T, Qh, p, c);
-        wmax[0] = fmax(wmax[0], q[0]);
-        wmin[0] = fmin(wmin[0], q[0]);
-        rmin = fmin(rmin, q[0]);
-        if (q[0] > 0.0) {
-          const double r = 1.0 / q[0];
-          double u2 = 0.0;
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            const double u = q[1 + d] * r;
-            wmax[1 + d] = fmax(wmax[1 + d], u);
-            wmin[1 + d] = fmin(wmin[1 + d], u);
-            u2 += u * u;
-          }
-          const double pp = pressure_r<DIM>(q, r, gam);
-          wmax[DIM + 1] = fmax(wmax[DIM + 1], pp);
-          wmin[DIM + 1] = fmin(wmin[DIM + 1], pp);
-          pmin = fmin(pmin, pp);
-          smax0 = fmax(smax0, sqrt(u2) + sqrt(gam * pp * r));  // = speed_r of this point
-        }
       }
       if (shock_on) {
 #pragma unroll
@@ -860,77 +862,107 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
 // (Eq. (LLF) with the scaled normal), f^LxW_e = (1/2) sum_j omega_j F*_j (float64 sum), and
 // f^LxF_e = (1/2) n_e.(F(q_bar_j) + F(q_bar_i)) - (s |n_e| / 2)(q_bar_j - q_bar_i) in float64.
 // ---------------------------------------------------------------------------------------------
+// Copies nbytes (a multiple of 4) from LDS to global memory with the whole workgroup, 16 bytes per
+// lane and store where both ends allow it: consecutive lanes write consecutive addresses.
+template <int ALIGN16>
+__device__ __forceinline__ void lds_to_global(unsigned char* dst, const unsigned char* src, int nbytes) {
+  if constexpr (ALIGN16) {
+    for (int o = (int)threadIdx.x * 16; o < nbytes; o += (int)blockDim.x * 16)
+      *reinterpret_cast<uint4*>(dst + o) = *reinterpret_cast<const uint4*>(src + o);
+  } else {
+    for (int o = (int)threadIdx.x * 4; o < nbytes; o += (int)blockDim.x * 4)
+      *reinterpret_cast<unsigned*>(dst + o) = *reinterpret_cast<const unsigned*>(src + o);
+  }
+}
+
 template <class E, class R>
 __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE;
+  // per-edge records: F* at the edge points, and (f^LxW, f^LxF); each lane writes its edge's
+  // records into LDS as it computes them
+  constexpr int FS = NQE * V * (int)sizeof(R), FL = 2 * V * (int)sizeof(double);
+  __shared__ __align__(16) unsigned char rec_fs[256 * FS];
+  __shared__ __align__(16) unsigned char rec_fl[256 * FL];
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const int NE = v.E, N = v.N;
   const int e = xcd_item();
-  if (e >= NE) return;
-  const int mid = v.e_mesh ? at(v.e_mesh, e) : 0;
-  const double s = v.sc[mid].s;
-  const double gam = v.gamma;
-  double n[DIM], len2 = 0.0;
+  const bool valid = e < NE;
+  const int e0 = e - (int)threadIdx.x;  // first edge of the workgroup (its edges are consecutive)
+  const int nrec = max(0, min((int)blockDim.x, NE - e0));
+  R* fsr = reinterpret_cast<R*>(rec_fs + threadIdx.x * FS);
+  double* flr = reinterpret_cast<double*>(rec_fl + threadIdx.x * FL);
+  if (valid) {
+    const int mid = v.e_mesh ? at(v.e_mesh, e) : 0;
+    const double s = v.sc[mid].s;
+    const double gam = v.gamma;
+    double n[DIM], len2 = 0.0;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) { n[d] = at(v.e_n + (size_t)d * NE, e); len2 += n[d] * n[d]; }
-  const double len = sqrt(len2);
-  const R hs = R(0.5 * s * len);
-  const int ie = at(v.e_i, e), je = at(v.e_j, e);
-  double W[V];
+    for (int d = 0; d < DIM; ++d) { n[d] = at(v.e_n + (size_t)d * NE, e); len2 += n[d] * n[d]; }
+    const double len = sqrt(len2);
+    const R hs = R(0.5 * s * len);
+    const int ie = at(v.e_i, e), je = at(v.e_j, e);
+    double W[V];
 #pragma unroll
-  for (int c = 0; c < V; ++c) W[c] = 0.0;
+    for (int c = 0; c < V; ++c) W[c] = 0.0;
 #pragma unroll
-  for (int jj = 0; jj < NQE; ++jj) {
+    for (int jj = 0; jj < NQE; ++jj) {
 #pragma unroll
-    for (int c = 0; c < V; ++c) {
-      const R qm = at(v.tq + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
-      const R fm = at(v.tf + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
-      const R qp = at(v.tq + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
-      const R fp = -at(v.tf + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
-      const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
-      at(v.fstar + (size_t)(jj * V + c) * NE, e) = fs;
-      W[c] += 0.5 * double(T.om[jj]) * double(fs);
+      for (int c = 0; c < V; ++c) {
+        const R qm = at(v.tq + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
+        const R fm = at(v.tf + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
+        const R qp = at(v.tq + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
+        const R fp = -at(v.tf + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
+        const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
+        fsr[jj * V + c] = fs;
+        W[c] += 0.5 * double(T.om[jj]) * double(fs);
+      }
     }
-  }
 #pragma unroll
-  for (int c = 0; c < V; ++c) at(v.fLxW + (size_t)c * NE, e) = W[c];
+    for (int c = 0; c < V; ++c) flr[c] = W[c];
 
-  const int i = ie, j = je;
-  double qi[V], qj[V];
+    const int i = ie, j = je;
+    double qi[V], qj[V];
 #pragma unroll
-  for (int c = 0; c < V; ++c) qi[c] = at(v.Qbar + (size_t)c * N, i);
-  if (j >= 0) {
+    for (int c = 0; c < V; ++c) qi[c] = at(v.Qbar + (size_t)c * N, i);
+    if (j >= 0) {
 #pragma unroll
-    for (int c = 0; c < V; ++c) qj[c] = at(v.Qbar + (size_t)c * N, j);
-  } else {
-    const int bc = at(v.e_bc, e);
-    if (bc == SB_REFLECTIVE) {
-      double nh[DIM];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) nh[d] = n[d] / len;
-      reflect<DIM, double>(qi, nh, qj);
-    } else if (bc == SB_INFLOW) {
-      inflow_state<DIM, double>(v.inflow, qj);
+      for (int c = 0; c < V; ++c) qj[c] = at(v.Qbar + (size_t)c * N, j);
     } else {
+      const int bc = at(v.e_bc, e);
+      if (bc == SB_REFLECTIVE) {
+        double nh[DIM];
 #pragma unroll
-      for (int c = 0; c < V; ++c) qj[c] = qi[c];
+        for (int d = 0; d < DIM; ++d) nh[d] = n[d] / len;
+        reflect<DIM, double>(qi, nh, qj);
+      } else if (bc == SB_INFLOW) {
+        inflow_state<DIM, double>(v.inflow, qj);
+      } else {
+#pragma unroll
+        for (int c = 0; c < V; ++c) qj[c] = qi[c];
+      }
     }
+    St<DIM, double> si = base_state<DIM, double>(qi, gam - 1.0);
+    St<DIM, double> sj = base_state<DIM, double>(qj, gam - 1.0);
+    double Lf[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) Lf[c] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      double Fi[V], Fj[V];
+      flux<DIM, double>(si, d, Fi);
+      flux<DIM, double>(sj, d, Fj);
+#pragma unroll
+      for (int c = 0; c < V; ++c) Lf[c] += 0.5 * n[d] * (Fj[c] + Fi[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < V; ++c) flr[V + c] = Lf[c] - 0.5 * s * len * (qj[c] - qi[c]);
   }
-  St<DIM, double> si = base_state<DIM, double>(qi, gam - 1.0);
-  St<DIM, double> sj = base_state<DIM, double>(qj, gam - 1.0);
-  double Lf[V];
-#pragma unroll
-  for (int c = 0; c < V; ++c) Lf[c] = 0.0;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    double Fi[V], Fj[V];
-    flux<DIM, double>(si, d, Fi);
-    flux<DIM, double>(sj, d, Fj);
-#pragma unroll
-    for (int c = 0; c < V; ++c) Lf[c] += 0.5 * n[d] * (Fj[c] + Fi[c]);
-  }
-#pragma unroll
-  for (int c = 0; c < V; ++c) at(v.fLxF + (size_t)c * NE, e) = Lf[c] - 0.5 * s * len * (qj[c] - qi[c]);
+  // The records of the workgroup's edges are one contiguous range: staged in LDS, they are written
+  // with coalesced stores (written straight from the lanes, every store instruction would touch a
+  // cache line per lane).
+  __syncthreads();
+  lds_to_global<FS % 16 == 0>(reinterpret_cast<unsigned char*>(v.fstar) + (size_t)max(e0, 0) * FS, rec_fs, nrec * FS);
+  lds_to_global<FL % 16 == 0>(reinterpret_cast<unsigned char*>(v.fLxW) + (size_t)max(e0, 0) * FL, rec_fl, nrec * FL);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -981,7 +1013,7 @@ __device__ double mu_solve(const double* qL, const double* qa, double gam, doubl
 template <class E, class R>
 __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   constexpr int V = E::V, DIM = E::DIM, K = E::K;
-  const int N = v.N, NE = v.E;
+  const int N = v.N;
   const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
@@ -1003,8 +1035,8 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
     const double ep = sd[k] ? -1.0 : 1.0;
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      fW[k][c] = ep * at(v.fLxW + (size_t)c * NE, eidx[k]);
-      fF[k][c] = ep * at(v.fLxF + (size_t)c * NE, eidx[k]);
+      fW[k][c] = ep * v.fLxW[(size_t)eidx[k] * (2 * V) + c];
+      fF[k][c] = ep * v.fLxW[(size_t)eidx[k] * (2 * V) + V + c];
     }
     Gam -= fF[k][0];
     df[k] = fF[k][0] - fW[k][0];
@@ -1050,7 +1082,7 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   }
   if (bad) report(v.err, E_CFL, i);
 #pragma unroll
-  for (int k = 0; k < K; ++k) at(v.cedge, sd[k] * NE + eidx[k]) = Lam[k] * mm[k];
+  for (int k = 0; k < K; ++k) v.cedge[(size_t)eidx[k] * 2 + sd[k]] = Lam[k] * mm[k];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1064,7 +1096,7 @@ template <class E, class R>
 __global__ __launch_bounds__(256) void k_update(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, K = E::K, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
-  const int N = v.N, NE = v.E;
+  const int N = v.N;
   const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
@@ -1083,17 +1115,18 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
     const int slot = at(v.eslot + (size_t)k * N, i);
     const int e = slot >> 3, side = (slot >> 2) & 1;
     const double ep = side ? -1.0 : 1.0;
-    const double th = fmin(1.0, fmin(at(v.cedge, e), at(v.cedge + NE, e)));
+    const double th = fmin(1.0, fmin(v.cedge[(size_t)e * 2], v.cedge[(size_t)e * 2 + 1]));
     if (v.dbg_lame) v.dbg_lame[k * N + i] = th;
 #pragma unroll
-    for (int c = 0; c < V; ++c) qb[c] -= r * ep * (th * at(v.fLxW + (size_t)c * NE, e) + (1.0 - th) * at(v.fLxF + (size_t)c * NE, e));
+    for (int c = 0; c < V; ++c)
+      qb[c] -= r * ep * (th * v.fLxW[(size_t)e * (2 * V) + c] + (1.0 - th) * v.fLxW[(size_t)e * (2 * V) + V + c]);
     const R re = R(r * ep);
 #pragma unroll
     for (int jl = 0; jl < NQE; ++jl) {
       const int jj = side ? (NQE - 1 - jl) : jl;
 #pragma unroll
       for (int c = 0; c < V; ++c) {
-        const R fs = re * at(v.fstar + (size_t)(jj * V + c) * NE, e);
+        const R fs = re * v.fstar[(size_t)e * (NQE * V) + jj * V + c];
 #pragma unroll
         for (int l = 1; l < ML; ++l) Qh[c][l - 1] -= T.ephi[k][jl][l] * fs;
       }
