@@ -763,18 +763,17 @@ lxw_status load_state(lxw_solver* S, const lxw_mesh& Mloc, int off, const double
       return fail(LXW_ERR_STATE, buf);
     }
   }
-  std::vector<double> qbar((size_t)V * N);
+  std::vector<double> qbar((size_t)V * N);  // [N][V]
   std::vector<double> qh((size_t)V * (ML - 1) * N);
   for (int i = 0; i < N; ++i) {
     const double* q = &h[(size_t)Mloc.perm[i] * V * ML];
     for (int v = 0; v < V; ++v) {
-      qbar[(size_t)v * N + i] = q[v * ML];
+      qbar[(size_t)i * V + v] = q[v * ML];
       for (int l = 1; l < ML; ++l) qh[((size_t)v * (ML - 1) + l - 1) * N + i] = q[v * ML + l];
     }
   }
   double* dbar = S->fp32 ? S->vf.Qbar : S->vd.Qbar;
-  for (int v = 0; v < V; ++v)
-    HIPCHK(hipMemcpy(dbar + (size_t)v * Nt + off, &qbar[(size_t)v * N], N * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dbar + (size_t)off * V, qbar.data(), qbar.size() * sizeof(double), hipMemcpyHostToDevice));
   const int rows = V * (ML - 1);
   if (S->fp32) {
     std::vector<float> f(qh.begin(), qh.end());
@@ -806,8 +805,7 @@ lxw_status store_state(lxw_solver* S, const lxw_mesh& Mloc, int off, bool upd_co
   std::vector<double> qbar((size_t)V * N), qh((size_t)V * (ML - 1) * N);
   const double* src_bar = upd_copy ? S->dq_upd_bar : (S->fp32 ? S->vf.Qbar : S->vd.Qbar);
   const char* src_h = (const char*)(upd_copy ? S->dq_upd_h : (S->fp32 ? (const void*)S->vf.Qh : (const void*)S->vd.Qh));
-  for (int v = 0; v < V; ++v)
-    HIPCHK(hipMemcpy(&qbar[(size_t)v * N], src_bar + (size_t)v * Nt + off, N * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(qbar.data(), src_bar + (size_t)off * V, qbar.size() * sizeof(double), hipMemcpyDeviceToHost));
   const int rows = V * (ML - 1);
   if (S->fp32) {
     std::vector<float> f(qh.size());
@@ -822,7 +820,7 @@ lxw_status store_state(lxw_solver* S, const lxw_mesh& Mloc, int off, bool upd_co
   for (int i = 0; i < N; ++i) {
     double* q = &out[(size_t)Mloc.perm[i] * V * ML];
     for (int v = 0; v < V; ++v) {
-      q[v * ML] = qbar[(size_t)v * N + i];
+      q[v * ML] = qbar[(size_t)i * V + v];
       for (int l = 1; l < ML; ++l) q[v * ML + l] = qh[((size_t)v * (ML - 1) + l - 1) * N + i];
     }
   }
@@ -1429,7 +1427,7 @@ lxw_status lxw_debug_stage(lxw_solver* S, int32_t stage, double* out) {
       for (int i = 0; i < N; ++i) {
         double* q = &out[(size_t)M.perm[i] * V * ML];
         for (int v = 0; v < V; ++v) {
-          q[v * ML] = qbar[(size_t)v * N + i];
+          q[v * ML] = qbar[(size_t)i * V + v];
           for (int l = 1; l < ML; ++l) q[v * ML + l] = qh[((size_t)v * (ML - 1) + l - 1) * N + i];
         }
       }

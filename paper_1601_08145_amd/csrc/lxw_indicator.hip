@@ -37,13 +37,13 @@ __device__ __forceinline__ void cell_features(const View<R>& v, int i, float (&F
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int c = g == 0 ? 0 : 3;  // rho, E
-    const double avg = at(v.Qbar + (size_t)c * N, i);
+    const double avg = v.Qbar[(size_t)i * ElTri::V + c];
     float vals[24];
     float mx = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int cell = cells[q];
-      vals[q * 6] = float(at(v.Qbar + (size_t)c * N, cell) - avg);
+      vals[q * 6] = float(v.Qbar[(size_t)cell * ElTri::V + c] - avg);
 #pragma unroll
       for (int l = 1; l < ML; ++l) vals[q * 6 + l] = float(at(v.Qh + (size_t)(c * (ML - 1) + l - 1) * N, cell));
     }

@@ -83,7 +83,9 @@ struct View {
   const double* e_n;      // [DIM][E] n_e, |n_e| = edge length
   const int* e_mesh;      // [E] mesh index or null
   // state
-  double* Qbar;           // [V][N] cell averages
+  double* Qbar;           // [N][V] cell averages (array of structures: the kernels also gather
+                          //   them by neighbour index, and one element's averages then share
+                          //   a cache line)
   R* Qh;                  // [V][ML-1][N] modes 2..ML
   // work
   double* theta;          // [N] limiter factor of the step (shock x moment), applied by k_elem

@@ -19,7 +19,8 @@
 //   k_final  per mesh, after a state read-out applied the pending shock limiter: marks it done.
 // Thread-per-element (or per-edge) mapping; reference tables sit in __constant__ memory and are
 // read through the scalar cache (every lane of a wave reads the same entry).  State is stored as
-// structure-of-arrays: cell averages Qbar[V][N] (float64) and higher modes Qh[V][ML-1][N].
+// cell averages Qbar[N][V] (float64, one record per element: also gathered by neighbour index) and
+// higher modes as structure-of-arrays Qh[V][ML-1][N].
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
     R Qh[V][ML - 1];
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      qb[c] = at(v.Qbar + (size_t)c * N, i);
+      qb[c] = v.Qbar[(size_t)i * V + c];
 #pragma unroll
       for (int l = 0; l < ML - 1; ++l) Qh[c][l] = at(v.Qh + (size_t)(c * (ML - 1) + l) * N, i);
     }
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
         const int j = at(v.nbr + (size_t)k * N, i);
         if (j >= 0) {
 #pragma unroll
-          for (int c = 0; c < V; ++c) qn[c] = at(v.Qbar + (size_t)c * N, j);
+          for (int c = 0; c < V; ++c) qn[c] = v.Qbar[(size_t)j * V + c];
         } else {
           const int bc = at(v.eslot + (size_t)k * N, i) & 3;
           if (bc == SB_REFLECTIVE) {
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
   R Qr[V][ML - 1];
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    qb[c] = v.Qbar[c * N + i];
+    qb[c] = v.Qbar[(size_t)i * V + c];
 #pragma unroll
     for (int l = 1; l < ML; ++l) Qr[c][l - 1] = v.Qh[(c * (ML - 1) + l - 1) * N + i];
   }
@@ -884,7 +885,7 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   __shared__ __align__(16) unsigned char rec_fs[256 * FS];
   __shared__ __align__(16) unsigned char rec_fl[256 * FL];
   const RefTab<E, R>& T = TabSel<E, R>::get();
-  const int NE = v.E, N = v.N;
+  const int NE = v.E;
   const int e = xcd_item();
   const bool valid = e < NE;
   const int e0 = e - (int)threadIdx.x;  // first edge of the workgroup (its edges are consecutive)
@@ -923,10 +924,10 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
     const int i = ie, j = je;
     double qi[V], qj[V];
 #pragma unroll
-    for (int c = 0; c < V; ++c) qi[c] = at(v.Qbar + (size_t)c * N, i);
+    for (int c = 0; c < V; ++c) qi[c] = v.Qbar[(size_t)i * V + c];
     if (j >= 0) {
 #pragma unroll
-      for (int c = 0; c < V; ++c) qj[c] = at(v.Qbar + (size_t)c * N, j);
+      for (int c = 0; c < V; ++c) qj[c] = v.Qbar[(size_t)j * V + c];
     } else {
       const int bc = at(v.e_bc, e);
       if (bc == SB_REFLECTIVE) {
@@ -1023,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   const double r = dt / area;
   double qb[V];
 #pragma unroll
-  for (int c = 0; c < V; ++c) qb[c] = at(v.Qbar + (size_t)c * N, i);
+  for (int c = 0; c < V; ++c) qb[c] = v.Qbar[(size_t)i * V + c];
   double fW[K][V], fF[K][V], df[K];
   int eidx[K], sd[K];
   double Gam = area * qb[0] / dt;
@@ -1106,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   R Qh[V][ML - 1];
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    qb[c] = at(v.Qbar + (size_t)c * N, i);
+    qb[c] = v.Qbar[(size_t)i * V + c];
 #pragma unroll
     for (int l = 0; l < ML - 1; ++l) Qh[c][l] = at(v.Qh + (size_t)(c * (ML - 1) + l) * N, i);
   }
@@ -1135,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   bool finite = true;
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    at(v.Qbar + (size_t)c * N, i) = qb[c];
+    v.Qbar[(size_t)i * V + c] = qb[c];
     finite = finite && isfinite(qb[c]);
 #pragma unroll
     for (int l = 0; l < ML - 1; ++l) at(v.Qh + (size_t)(c * (ML - 1) + l) * N, i) = Qh[c][l];
