@@ -559,6 +559,22 @@ __global__ void k_dt(Scalars* sc, DevError* err, int n_mesh, double T) {
 // ---------------------------------------------------------------------------------------------
 // Waves per SIMD the register allocation of k_elem targets: two for float32 triangles (measured
 // faster: latency of the trace stores is hidden), one elsewhere (float64 would spill at two).
+// Stores V values of one record (consecutive, 16-byte aligned when V values fill whole 16-byte
+// words) with vector stores.
+template <class R, int V>
+__device__ __forceinline__ void store_rec(R* p, const R (&x)[V]) {
+  if constexpr ((V * sizeof(R)) % 16 == 0) {
+    typedef R vec __attribute__((ext_vector_type(V)));
+    vec t;
+#pragma unroll
+    for (int c = 0; c < V; ++c) t[c] = x[c];
+    *reinterpret_cast<vec*>(p) = t;
+  } else {
+#pragma unroll
+    for (int c = 0; c < V; ++c) p[c] = x[c];
+  }
+}
+
 template <class E, class R>
 struct ElemOcc { static constexpr int waves = (E::kind == ElTri::kind && sizeof(R) == 4) ? 2 : 1; };
 
@@ -808,14 +824,15 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
       const int jj = side ? (NQE - 1 - jl) : jl;  // point order of i_e along the edge
       R q[V], qt[V], qtt[V], FT[DIM][V];
       point(p, q, qt, qtt, FT);
+      R fn[V];
 #pragma unroll
       for (int c = 0; c < V; ++c) {
-        R fn = R(0);
+        fn[c] = R(0);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) fn += n[d] * FT[d][c];
-        v.tq[((size_t)(side * NQE + jj) * V + c) * NE + e] = q[c];
-        v.tf[((size_t)(side * NQE + jj) * V + c) * NE + e] = fn;
+        for (int d = 0; d < DIM; ++d) fn[c] += n[d] * FT[d][c];
       }
+      store_rec<R, V>(v.tq + (((size_t)side * NE + e) * NQE + jj) * V, q);
+      store_rec<R, V>(v.tf + (((size_t)side * NE + e) * NQE + jj) * V, fn);
       if (bc != SB_INTERIOR) {
         R qg[V], FTg[DIM][V];
         if (bc == SB_TRANSPARENT) {
@@ -844,14 +861,16 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
           inflow_state<DIM, R>(v.inflow, qg);
           ft_from<DIM, R>(qg, z, z, gm1, dt, FTg);
         }
+        R fg[V];
 #pragma unroll
         for (int c = 0; c < V; ++c) {
           R fn = R(0);
 #pragma unroll
           for (int d = 0; d < DIM; ++d) fn += n[d] * FTg[d][c];
-          v.tq[((size_t)(NQE + jj) * V + c) * NE + e] = qg[c];
-          v.tf[((size_t)(NQE + jj) * V + c) * NE + e] = -fn;
+          fg[c] = -fn;
         }
+        store_rec<R, V>(v.tq + (((size_t)NE + e) * NQE + jj) * V, qg);
+        store_rec<R, V>(v.tf + (((size_t)NE + e) * NQE + jj) * V, fg);
       }
     }
   }
@@ -909,10 +928,10 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
     for (int jj = 0; jj < NQE; ++jj) {
 #pragma unroll
       for (int c = 0; c < V; ++c) {
-        const R qm = at(v.tq + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
-        const R fm = at(v.tf + ((size_t)(0 * NQE + jj) * V + c) * NE, e);
-        const R qp = at(v.tq + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
-        const R fp = -at(v.tf + ((size_t)(1 * NQE + jj) * V + c) * NE, e);
+        const R qm = v.tq[((size_t)e * NQE + jj) * V + c];
+        const R fm = v.tf[((size_t)e * NQE + jj) * V + c];
+        const R qp = v.tq[(((size_t)NE + e) * NQE + jj) * V + c];
+        const R fp = -v.tf[(((size_t)NE + e) * NQE + jj) * V + c];
         const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
         fsr[jj * V + c] = fs;
         W[c] += 0.5 * double(T.om[jj]) * double(fs);
