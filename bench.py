@@ -57,8 +57,8 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one k_elem launch on the 2D triangle workload from rocprofv3 counters
 # (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid only for the kernel
 # source it was measured on.
-KELEM_TRAFFIC = {"src_sha256": "76f30a9098654c76ec9f6c9a271bf7d894985681571d0be04af693b7b3ae75b5",
-                 "bytes_per_launch": 974027776}  # profiles/lxw_kernels_tri_c3_counters.md
+KELEM_TRAFFIC = {"src_sha256": "90a2c67c2a7e37c8abec0a3a570c32b389309e50b6b0c90f40fea3d7c551e702",
+                 "bytes_per_launch": 674563276}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def kernel_src_hash():
