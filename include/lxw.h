@@ -267,7 +267,9 @@ lxw_status lxw_batch_advance_steps(lxw_batch* b, int64_t n_steps);
 /* Waits, then reports mesh i: steps since its state was set, t, last dt and last s. */
 lxw_status lxw_batch_stats(lxw_batch* b, int32_t i, lxw_stats* out);
 /* The solver that runs the batch, for lxw_sync, lxw_set_tune / lxw_get_tune / lxw_autotune,
- * lxw_set_graph, lxw_set_timing and lxw_kernel_times (the per-mesh calls above handle state;
+ * lxw_set_graph, lxw_set_timing, lxw_kernel_times, and (triangle meshes) lxw_solver_set_indicator
+ * and lxw_indicator_decisions, whose flags then follow the meshes' caller orders one after
+ * another (the per-mesh calls above handle state;
  * lxw_step, lxw_advance, lxw_set_state, lxw_get_state and lxw_set_debug return
  * LXW_ERR_UNSUPPORTED on it).  Owned by the batch. */
 lxw_solver* lxw_batch_solver(lxw_batch* b);

@@ -276,6 +276,20 @@ class _Ops:
         _check(_L.lxw_autotune(self._sh(), trial_steps, ctypes.byref(t)))
         return {KERNEL_NAMES[k]: int(t.block[k]) for k in range(K_COUNT)}
 
+    def set_indicator(self, ind, tau_lo=0.0, tau_hi=1.0):
+        """Learned detection for the shock-capturing limiter (None: plain everywhere)."""
+        self._ind = ind  # the indicator must outlive its use
+        _check(_L.lxw_solver_set_indicator(self._sh(), ind.h if ind is not None else None, tau_lo, tau_hi))
+
+    def indicator_decisions(self, flags=True):
+        """(counts of skipped / plain / flagged decisions since set_indicator, last decision per
+        element in the caller's order; for a batch, the meshes' caller orders one after another)."""
+        c = np.zeros(3, dtype=np.int64)
+        f = np.zeros(self.n_elem, dtype=np.uint8) if flags else None
+        _check(_L.lxw_indicator_decisions(self._sh(), c.ctypes.data_as(ctypes.c_void_p),
+                                          f.ctypes.data_as(ctypes.c_void_p) if flags else None))
+        return c, f
+
 
 class Solver(_Ops):
     def __init__(self, mesh, stream=None, **params):
@@ -296,6 +310,10 @@ class Solver(_Ops):
 
     def _sh(self):
         return self.h
+
+    @property
+    def n_elem(self):
+        return self.mesh.N
 
     @property
     def shape(self):
@@ -331,18 +349,6 @@ class Solver(_Ops):
 
     def set_debug(self, on=True):
         _check(_L.lxw_set_debug(self.h, int(on)))
-
-    def set_indicator(self, ind, tau_lo=0.0, tau_hi=1.0):
-        """Learned detection for the shock-capturing limiter (None: plain everywhere)."""
-        self._ind = ind  # the indicator must outlive its use
-        _check(_L.lxw_solver_set_indicator(self.h, ind.h if ind is not None else None, tau_lo, tau_hi))
-
-    def indicator_decisions(self, flags=True):
-        c = np.zeros(3, dtype=np.int64)
-        f = np.zeros(self.mesh.N, dtype=np.uint8) if flags else None
-        _check(_L.lxw_indicator_decisions(self.h, c.ctypes.data_as(ctypes.c_void_p),
-                                          f.ctypes.data_as(ctypes.c_void_p) if flags else None))
-        return c, f
 
     def collect(self):
         """Features [N][48] (float32) and the pending shock-capturing limiter's factor [N]."""
@@ -460,6 +466,10 @@ class Batch(_Ops):
 
     def _sh(self):
         return _L.lxw_batch_solver(self.h)
+
+    @property
+    def n_elem(self):
+        return sum(m.N for m in self.meshes)
 
     def shape(self, i):
         m = self.meshes[i]

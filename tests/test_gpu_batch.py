@@ -225,3 +225,44 @@ def test_batch_of_cartesian_meshes(L):
         Qs, ts = S.get_state()
         Qb, tb = B.get_state(b)
         assert tb == ts and np.array_equal(Qb, Qs)
+
+
+def test_batch_with_learned_indicator(L):
+    """The learned indicator on a batch of triangle meshes: the same decisions and the same states
+    as each mesh's own solver with that indicator, bit for bit; the batch's decision flags follow
+    the meshes' caller orders one after another."""
+    print("[gpu] batch with the learned indicator vs single solvers", flush=True)
+    cases, meshes = small_batch(L, sizes=(9, 14, 6, 21), seed=7)
+    ind = L.Indicator(I.mlp_init(21))
+    # thresholds at the median of this network's outputs on these states, so both decisions occur
+    ps = []
+    for b, (_, _, Q) in enumerate(cases):
+        S = L.Solver(meshes[b], precision=1)
+        S.set_state(Q)
+        S.step()
+        X, _ = S.collect()
+        ps.append(ind.predict(X))
+    tau = float(np.median(np.concatenate(ps)))
+    tau_hi = min(1.0, tau + 0.1)
+    B = L.Batch(meshes, precision=1)
+    for b, (_, _, Q) in enumerate(cases):
+        B.set_state(b, Q)
+    B.set_indicator(ind, tau, tau_hi)
+    singles = []
+    for b, (_, _, Q) in enumerate(cases):
+        S = L.Solver(meshes[b], precision=1)
+        S.set_state(Q)
+        S.set_indicator(ind, tau, tau_hi)
+        singles.append(S)
+    B.advance_steps(5)
+    for S in singles:
+        S.run_steps(5)
+    cb, fb = B.indicator_decisions()
+    dec = [S.indicator_decisions() for S in singles]
+    assert np.array_equal(fb, np.concatenate([f for _, f in dec]))
+    assert np.array_equal(cb, np.sum([c for c, _ in dec], axis=0))
+    assert cb[0] > 0 and cb[1] + cb[2] > 0
+    for b, S in enumerate(singles):
+        Qb, tb = B.get_state(b)
+        Qs, ts = S.get_state()
+        assert tb == ts and np.array_equal(Qb, Qs), (b, np.abs(Qb - Qs).max())
