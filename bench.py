@@ -54,11 +54,16 @@ def kelem_bytes_per_elem(rsize):
     return 4 * 8 + 20 * rsize + 8 + 10 * rsize + 12 + 20 * rsize + 72 * rsize
 
 
-# HBM traffic of one k_elem launch on the 2D triangle workload from rocprofv3 counters
-# (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid only for the kernel
-# source it was measured on.
-KELEM_TRAFFIC = {"src_sha256": "90a2c67c2a7e37c8abec0a3a570c32b389309e50b6b0c90f40fea3d7c551e702",
-                 "bytes_per_launch": 674563276}  # profiles/lxw_kernels_tri_c3_counters.md
+# HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
+# rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
+# only for the kernel source it was measured on.
+TRAFFIC = {"src_sha256": "90a2c67c2a7e37c8abec0a3a570c32b389309e50b6b0c90f40fea3d7c551e702",
+           "bytes_per_launch": {"k_pre": 139244339, "k_elem": 674563276, "k_edge": 525932544,
+                                "k_flim": 173558272, "k_update": 466318336}}  # profiles/lxw_kernels_tri_c3_counters.md
+
+
+def traffic_valid():
+    return TRAFFIC["src_sha256"] == kernel_src_hash()
 
 
 def kernel_src_hash():
@@ -181,8 +186,8 @@ def kelem_roofline(kavg_ms, n_elem, traffic_ok):
     achieved = KELEM_FLOPS_PER_ELEM * n_elem / (kavg_ms * 1e-3) / 1e12
     bytes_ = kelem_bytes_per_elem(4) * n_elem
     traffic = None
-    if traffic_ok and KELEM_TRAFFIC["bytes_per_launch"] and KELEM_TRAFFIC["src_sha256"] == kernel_src_hash():
-        traffic = KELEM_TRAFFIC["bytes_per_launch"]
+    if traffic_ok and traffic_valid():
+        traffic = TRAFFIC["bytes_per_launch"]["k_elem"]
     return {"kernel": "k_elem", "bound": "alu", "achieved": achieved, "peak": PEAK_VECTOR_NONPACKED_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_VECTOR_NONPACKED_TFLOPS, "traffic": traffic,
             "kernel_ms": kavg_ms, "flops_per_elem": KELEM_FLOPS_PER_ELEM,
@@ -440,6 +445,14 @@ def main():
     out["hbm_copy_probe"] = {"GBs": cr / 1e9, "frac_of_peak": cr / 1e9 / PEAK_HBM_GBS,
                              "note": "device copy of 1 GiB, bytes read + written, fastest of 5"}
     log(f"[bench] 1 GiB device copy: {cr / 1e12:.2f} TB/s read + write")
+    if mix["kernels"] and traffic_valid():
+        # measured HBM bytes per launch over this run's per-kernel times
+        hk = {}
+        for k, b in TRAFFIC["bytes_per_launch"].items():
+            gbs = b / (out["kernels"][k]["ms_avg"] * 1e-3) / 1e9
+            hk[k] = {"traffic_bytes": b, "achieved_GBs": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS,
+                     "frac_of_copy_probe": gbs / (cr / 1e9)}
+        out["hbm_kernels"] = hk
 
     if not args.no_fp64:
         log(f"[bench] FP64 plain: {args.warmup} warm-up + {args.steps} timed steps")
