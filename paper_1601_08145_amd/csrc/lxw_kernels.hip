@@ -4,8 +4,10 @@
 // One step is six launches on one stream (grid-wide dependencies separate them):
 //   k_pre    per element: pending shock-capturing limiter of the previous step (Sec. 1.5 Step 5),
 //            moment limiter (Sec. 3.1), cell-average checks, and the global wave speed s
-//            (wavefront max, one atomic max per wavefront);
-//   k_dt     per mesh: dt = CFL / (s max_i |dT_i|/(2|T_i|)), clipped to reach T;
+//            (one partial maximum per workgroup for a single mesh; in a batch one atomic maximum
+//            per wavefront and mesh);
+//   k_dt     per mesh: dt = CFL / (s max_i |dT_i|/(2|T_i|)), clipped to reach T (for a single
+//            mesh it first reduces the workgroup partials);
 //   k_elem   per element: Galerkin projection of F (Sec. 2.3 Step 1), the time-averaged flux F_T
 //            of Eq. (taylor3-flux) at every interior and edge point (Sec. 2.2, 2.3 Step 2), the
 //            volume term (Sec. 2.3 Step 3) added to the higher modes, and the edge traces;

@@ -331,7 +331,8 @@ def test_advance_reaches_T_exactly(L):
 @pytest.mark.skipif(os.environ.get("LXW_SKIP_FULL") == "1", reason="full-size case skipped on request")
 def test_full_size_c3_one_step(L):
     """The 2D triangle workload at full size (999,698 triangles, four-quadrant Riemann data): one
-    step of the FP64 library against one step of the oracle, and the FP32-mixed form."""
+    step of the FP64 library against one step of the oracle, and the FP32-mixed form; then the two
+    forms against each other after 100 steps."""
     print("[gpu] full-size C3 one step (mesh generation, oracle step)", flush=True)
     xy, tri = I.lattice_delaunay(708, 0)
     assert len(tri) == 999698
@@ -349,6 +350,18 @@ def test_full_size_c3_one_step(L):
         err = per_var_rel_l1(Qg, Qo)
         print(f"[gpu]   precision {prec}: rel L1 {err:.3e}", flush=True)
         assert err <= tol
+    # 100 steps of both forms, replayed from the step graph as bench.py times them: the FP32-mixed
+    # form stays within the FP32 bound of the FP64 form (which itself follows the oracle step by step)
+    out = {}
+    for prec in (L.FP64, L.FP32_MIXED):
+        S = L.Solver(lm, precision=prec)
+        S.set_state(Q0)
+        S.run_steps(100)
+        S.sync()
+        out[prec] = S.get_state()
+    d = per_var_rel_l1(out[L.FP32_MIXED][0], out[L.FP64][0])
+    print(f"[gpu]   FP32-mixed vs FP64 after 100 steps: rel L1 {d:.3e}", flush=True)
+    assert d <= 1e-5 and out[L.FP32_MIXED][1] == pytest.approx(out[L.FP64][1], rel=1e-6)
 
 
 @pytest.mark.skipif(os.environ.get("LXW_SKIP_FULL") == "1", reason="full-size case skipped on request")
