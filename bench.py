@@ -57,9 +57,9 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "90a2c67c2a7e37c8abec0a3a570c32b389309e50b6b0c90f40fea3d7c551e702",
-           "bytes_per_launch": {"k_pre": 139244339, "k_elem": 674563276, "k_edge": 525932544,
-                                "k_flim": 173558272, "k_update": 466318336}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "4423e2017d8c91249b1e080f9ede8d9d020ec89e38b35d9f51018afbb292c4fb",
+           "bytes_per_launch": {"k_pre": 139300136, "k_elem": 675929497, "k_edge": 525948928,
+                                "k_flim": 173555916, "k_update": 466214912}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
