@@ -289,6 +289,33 @@ def test_device_pointer_state(L):
     assert np.array_equal(Qd.cpu().numpy(), Qh)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_smallest_meshes(L, prec):
+    """Degenerate sizes: one triangle (every edge a boundary edge), two 1D cells, 2 x 2 Cartesian
+    cells with walls; each workgroup is almost all tail.  Five steps against the oracle."""
+    print(f"[gpu] smallest meshes, precision {prec}", flush=True)
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    tri = np.array([[0, 1, 2]], dtype=np.int32)
+    cases = [(L.Mesh.tri(xy, tri), O.Mesh.tri(xy, tri), I.random_modal_state(1, 2, 6, seed=31, amp=0.2)),
+             (L.Mesh.line(2, 0, 1, 1, 2), O.Mesh.line(2, 0, 1, 1, 2), I.random_modal_state(2, 1, 3, seed=32, amp=0.2)),
+             (L.Mesh.cart(2, 2, 0, 1, 0, 1, [2, 2, 2, 2]), O.Mesh.cart(2, 2, 0, 1, 0, 1, [2, 2, 2, 2]),
+              I.random_modal_state(4, 2, 9, seed=33, amp=0.2))]
+    for lm, om, Q0 in cases:
+        S = L.Solver(lm, precision=prec)
+        S.set_state(Q0)
+        Ob = O.Solver(om)
+        Ob.set_state(Q0)
+        for _ in range(5):
+            S.step()
+            Ob.step()
+        Qg, tg = S.get_state()
+        Qo, to = Ob.get_state()
+        err = per_var_rel_l1(Qg, Qo)
+        print(f"[gpu]   {len(Q0)} elements: rel L1 after 5 steps {err:.3e}", flush=True)
+        assert err <= (5 * TOL if prec == 0 else 1e-5), err
+        assert tg == pytest.approx(to, rel=1e-12 if prec == 0 else 1e-6)
+
+
 def test_error_paths(L):
     lm, om, Q0, kw = make_case(L, "tri-transparent")
     S = L.Solver(lm)
