@@ -515,9 +515,9 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
 // ---------------------------------------------------------------------------------------------
 // k_dt: per mesh, dt from the CFL condition (reading of Sec. 4.1, "CFL 0.08"), clipped to T.
 // ---------------------------------------------------------------------------------------------
-// Single mesh: one block reduces the per-block maxima of k_pre.
-__global__ __launch_bounds__(256) void k_dt_single(Scalars* sc, DevError* err, const double* spart, int nparts, double T) {
-  __shared__ double red[4];
+// Single mesh: one workgroup of 1024 lanes reduces the per-workgroup maxima of k_pre.
+__global__ __launch_bounds__(1024) void k_dt_single(Scalars* sc, DevError* err, const double* spart, int nparts, double T) {
+  __shared__ double red[16];
   double x = 0.0;
   for (int b = threadIdx.x; b < nparts; b += blockDim.x) x = fmax(x, spart[b]);
 #pragma unroll
@@ -525,7 +525,8 @@ __global__ __launch_bounds__(256) void k_dt_single(Scalars* sc, DevError* err, c
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double s = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  double s = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, red[w]);
   Scalars& S = sc[0];
   S.s = s;
   if (!(s > 0.0) || !isfinite(s)) {
@@ -1206,7 +1207,7 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
       return hipErrorInvalidValue;  // launched through launch_indicator
     case K_DT:
       if (v.mesh_of) hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh, T);
-      else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(256), 0, st, v.sc, v.err, v.spart,
+      else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(1024), 0, st, v.sc, v.err, v.spart,
                               v.N > 0 ? egrid_blocks(v.N, cfg.bs[K_PRE]) : 0, T);
       break;
     case K_ELEM:
