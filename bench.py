@@ -57,9 +57,9 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "4423e2017d8c91249b1e080f9ede8d9d020ec89e38b35d9f51018afbb292c4fb",
-           "bytes_per_launch": {"k_pre": 139300136, "k_elem": 675929497, "k_edge": 525948928,
-                                "k_flim": 173555916, "k_update": 466214912}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "ea583b38301f1cd6be418c50b239d8346d93ffe9819ea8cd4bc11c76d8137d92",
+           "bytes_per_launch": {"k_pre": 139141089, "k_elem": 679146086, "k_edge": 525963264,
+                                "k_flim": 173616025, "k_update": 465843200}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
