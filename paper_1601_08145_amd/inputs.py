@@ -137,6 +137,116 @@ def ramp_channel(n_target, seed, angle_deg=30.0, length=4.0, height=1.5, ramp_x=
     return np.ascontiguousarray(xy), tri, tags
 
 
+# Shock-diffraction domains of Sec. 4 (the block step and the 120-degree wedge).  Both are the box
+# [0, 13] x [0, 11] minus a solid: the step removes [0, 1] x [0, 6]; the wedge removes the triangle
+# (0, 0), (0, 6), (3.4, 6), whose slanted face and the top y = 6 meet at an angle of about 120
+# degrees.  The gas enters above the solid (x = 0, 6 <= y <= 11); the solid's surface is a wall;
+# every other side is transparent.
+DIFFRACTION = {
+    "step": {"solid": [(0.0, 0.0), (1.0, 0.0), (1.0, 6.0), (0.0, 6.0)], "x_shock": 1.0, "mach": 5.09, "t_end": 2.3},
+    "wedge": {"solid": [(0.0, 0.0), (3.4, 6.0), (0.0, 6.0)], "x_shock": 3.4, "mach": 10.0, "t_end": 0.9},
+}
+
+
+def _in_polygon(pts, poly):
+    """Points strictly inside a convex polygon given counter-clockwise (margin 1e-9)."""
+    inside = np.ones(len(pts), dtype=bool)
+    for k in range(len(poly)):
+        (ax, ay), (bx, by) = poly[k], poly[(k + 1) % len(poly)]
+        inside &= (bx - ax) * (pts[:, 1] - ay) - (by - ay) * (pts[:, 0] - ax) > 1e-9
+    return inside
+
+
+def _dist_to_polygon_edges(pts, poly):
+    d = np.full(len(pts), np.inf)
+    for k in range(len(poly)):
+        a, b = np.array(poly[k]), np.array(poly[(k + 1) % len(poly)])
+        ab = b - a
+        t = np.clip(((pts - a) @ ab) / (ab @ ab), 0.0, 1.0)
+        d = np.minimum(d, np.linalg.norm(pts - (a + t[:, None] * ab), axis=1))
+    return d
+
+
+def diffraction_domain(kind, n_target, seed, jitter=0.25, box=(13.0, 11.0)):
+    """Triangle mesh of the `kind` ("step" or "wedge") shock-diffraction domain with about n_target
+    triangles: a jittered lattice of spacing h, the solid's points removed, points placed every
+    about h along the solid's surface (lattice points closer than 0.55 h to it dropped), Delaunay
+    triangulation, triangles inside the solid removed.  Returns (xy, tri, tags) with tags per
+    triangle edge (edge k joins vertices k and k+1): 0 on the inflow side (x = 0 above the solid),
+    2 on the solid's surface, 1 on the other sides, -1 for interior edges."""
+    spec = DIFFRACTION[kind]
+    solid = spec["solid"]
+    W, H = box
+    sx, sy = np.array(solid).T
+    solid_area = 0.5 * abs(np.dot(sx, np.roll(sy, -1)) - np.dot(sy, np.roll(sx, -1)))
+    area = W * H - solid_area
+    h = math.sqrt(2.0 * area / n_target)
+    g = rng(seed)
+    nx, ny = int(round(W / h)) + 1, int(round(H / h)) + 1
+    X, Y = np.meshgrid(np.linspace(0.0, W, nx), np.linspace(0.0, H, ny), indexing="ij")
+    hx, hy = W / (nx - 1), H / (ny - 1)
+    dx = g.uniform(-jitter * hx, jitter * hx, X.shape)
+    dy = g.uniform(-jitter * hy, jitter * hy, X.shape)
+    dx[0, :] = dx[-1, :] = 0.0
+    dy[:, 0] = dy[:, -1] = 0.0
+    dx[:, 0] = dx[:, -1] = 0.0
+    dy[0, :] = dy[-1, :] = 0.0
+    pts = np.stack([(X + dx).ravel(), (Y + dy).ravel()], axis=1)
+    keep = ~_in_polygon(pts, solid) & (_dist_to_polygon_edges(pts, solid) > 0.55 * min(hx, hy))
+    pts = pts[keep]
+    # points along the solid's surface (its edges that lie inside the box), spacing about h
+    surf = []
+    for k in range(len(solid)):
+        a, b = np.array(solid[k]), np.array(solid[(k + 1) % len(solid)])
+        if (a[0] == 0.0 and b[0] == 0.0) or (a[1] == 0.0 and b[1] == 0.0):
+            continue  # on the box boundary: the solid's back, not in contact with the gas
+        m = max(1, int(round(np.linalg.norm(b - a) / min(hx, hy))))
+        surf.append(a[None, :] + np.linspace(0.0, 1.0, m + 1)[:, None] * (b - a)[None, :])
+    surf = np.concatenate(surf)
+    xy = np.concatenate([pts, surf])
+    xy = np.unique(np.round(xy, 12), axis=0)
+    tri = Delaunay(xy).simplices.astype(np.int32)
+    c = xy[tri].mean(axis=1)
+    tri = tri[~_in_polygon(c, solid)]
+    a = xy[tri]
+    cross = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0])
+    tri[cross < 0] = tri[cross < 0][:, [0, 2, 1]]
+    tri = np.ascontiguousarray(tri)
+    tot = 0.5 * np.abs(cross).sum()
+    assert abs(tot - area) < 1e-8 * area, ("triangulation does not fill the domain", tot, area)
+    # nodes no triangle uses (the solid's back corners) are dropped
+    used = np.unique(tri)
+    remap = -np.ones(len(xy), np.int64)
+    remap[used] = np.arange(len(used))
+    xy, tri = xy[used], remap[tri].astype(np.int32)
+    e = np.concatenate([np.sort(np.stack([tri[:, k], tri[:, (k + 1) % 3]], 1), 1) for k in range(3)], 0)
+    key = e[:, 0].astype(np.int64) * len(xy) + e[:, 1]
+    _, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    on_bnd = (cnt[inv] == 1).reshape(3, -1).T
+    tags = np.full(tri.shape, -1, np.int32)
+    tol = 1e-9
+    for k in range(3):
+        pa, pb = xy[tri[:, k]], xy[tri[:, (k + 1) % 3]]
+        mid = 0.5 * (pa + pb)
+        t = np.full(len(tri), 2, np.int32)  # the solid's surface unless on a side of the box
+        on_box = ((np.abs(pa[:, 0]) < tol) & (np.abs(pb[:, 0]) < tol)) | \
+                 ((np.abs(pa[:, 0] - W) < tol) & (np.abs(pb[:, 0] - W) < tol)) | \
+                 ((np.abs(pa[:, 1]) < tol) & (np.abs(pb[:, 1]) < tol)) | \
+                 ((np.abs(pa[:, 1] - H) < tol) & (np.abs(pb[:, 1] - H) < tol))
+        t[on_box] = 1
+        t[on_box & (np.abs(mid[:, 0]) < tol)] = 0  # x = 0: only above the solid is gas
+        tags[on_bnd[:, k], k] = t[on_bnd[:, k]]
+    return np.ascontiguousarray(xy), tri, tags
+
+
+def diffraction_state(xy, tri, kind, gamma=1.4, m=2):
+    """Cell averages of the kind's shock (Mach 5.09 at x = 1 for the step, Mach 10 at x = 3.4 for
+    the wedge) moving in +x into gas at rest (rho = 1.4, p = 1), higher modes zero; and the inflow
+    state (conserved, the post-shock state)."""
+    spec = DIFFRACTION[kind]
+    return ramp_state(xy, tri, x_shock=spec["x_shock"], mach=spec["mach"], gamma=gamma, m=m)
+
+
 # ---------------------------------------------------------------------------------------------
 # Initial states
 # ---------------------------------------------------------------------------------------------
