@@ -180,7 +180,10 @@ typedef struct lxw_stats {
   double last_s;     /* global wave speed of the last step */
 } lxw_stats;
 
-/* Steps until t == T (the last dt is clipped) or max_steps steps.  Synchronous. */
+/* Steps until t == T (the last dt is clipped) or max_steps steps.  Synchronous.  The end time is
+ * kept on the device, where every step is clipped to it and a step at t == T changes nothing;
+ * the steps are enqueued in chunks (replays of the captured step graph, as lxw_run_steps) with
+ * one synchronisation per chunk, and the result equals that of single lxw_step calls to T. */
 lxw_status lxw_advance(lxw_solver* s, double T, int64_t max_steps, lxw_stats* out);
 
 /* Enqueues n_steps steps with no final time (dt from the CFL condition each step) on the

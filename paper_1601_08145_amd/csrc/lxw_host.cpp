@@ -468,6 +468,7 @@ struct lxw_solver {
   const lxw_indicator* ind = nullptr;
   unsigned char* ind_flag = nullptr;
   unsigned long long* ind_counts = nullptr;
+  double t_end = std::numeric_limits<double>::infinity();  // end time last set on the device
   float tau_lo = 0.0f, tau_hi = 1.0f;
   ~lxw_solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -598,7 +599,7 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
 }
 
 template <class E, class R>
-hipError_t launch_one(lxw_solver* S, const View<R>& v, KernelId k, double T, int mode) {
+hipError_t launch_one(lxw_solver* S, const View<R>& v, KernelId k, int mode) {
   const int pub = (k == K_SHOCK) ? LXW_K_PRE : (int)k;
   hipEvent_t a = nullptr, b = nullptr;
   if (S->timing) {
@@ -615,7 +616,7 @@ hipError_t launch_one(lxw_solver* S, const View<R>& v, KernelId k, double T, int
     hipError_t e = hipEventRecord(a, S->st);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = launch<E, R>(k, v, S->cfg, S->st, S->n_mesh, T, mode);
+  hipError_t e = launch<E, R>(k, v, S->cfg, S->st, S->n_mesh, mode);
   if (e != hipSuccess) return e;
   if (S->timing) e = hipEventRecord(b, S->st);
   return e;
@@ -632,7 +633,7 @@ IndW ind_weights(const lxw_solver* S) {
 
 // The learned indicator's decisions for the pending shock-capturing limiter (triangles only).
 template <class E, class R>
-hipError_t launch_ind_step(lxw_solver* S, const View<R>& v) {
+hipError_t launch_ind_step(lxw_solver* S, const View<R>& v, bool in_step) {
   if constexpr (E::kind == ElTri::kind) {
     if (!S->ind) return hipSuccess;
     hipEvent_t a = nullptr, b = nullptr;
@@ -650,7 +651,7 @@ hipError_t launch_ind_step(lxw_solver* S, const View<R>& v) {
       hipError_t e = hipEventRecord(a, S->st);
       if (e != hipSuccess) return e;
     }
-    hipError_t e = launch_indicator<R>(v, ind_weights(S), S->ind_flag, S->ind_counts, S->st);
+    hipError_t e = launch_indicator<R>(v, ind_weights(S), S->ind_flag, S->ind_counts, in_step, S->st);
     if (e == hipSuccess && S->timing) e = hipEventRecord(b, S->st);
     return e;
   } else {
@@ -660,16 +661,16 @@ hipError_t launch_ind_step(lxw_solver* S, const View<R>& v) {
 }
 
 template <class E, class R>
-lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v, double T) {
+lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v) {
   const lxw_mesh& M = *S->M;
   const int V = M.V, ML = M.ML, N = M.N;
-  HIPCHK((launch_ind_step<E, R>(S, v)));
-  HIPCHK((launch_one<E, R>(S, v, K_PRE, T, 0)));
-  HIPCHK((launch_one<E, R>(S, v, K_DT, T, 0)));
-  HIPCHK((launch_one<E, R>(S, v, K_ELEM, T, 0)));
-  HIPCHK((launch_one<E, R>(S, v, K_EDGE, T, 0)));
-  HIPCHK((launch_one<E, R>(S, v, K_FLIM, T, 0)));
-  HIPCHK((launch_one<E, R>(S, v, K_UPDATE, T, 0)));
+  HIPCHK((launch_ind_step<E, R>(S, v, true)));
+  HIPCHK((launch_one<E, R>(S, v, K_PRE, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_DT, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_ELEM, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_EDGE, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_FLIM, 0)));
+  HIPCHK((launch_one<E, R>(S, v, K_UPDATE, 0)));
   if (S->debug) {
     HIPCHK(hipMemcpyAsync(S->dq_upd_bar, v.Qbar, (size_t)V * N * sizeof(double), hipMemcpyDeviceToDevice, S->st));
     HIPCHK(hipMemcpyAsync(S->dq_upd_h, v.Qh, (size_t)V * (ML - 1) * N * sizeof(R), hipMemcpyDeviceToDevice, S->st));
@@ -679,17 +680,17 @@ lxw_status enqueue_step_t(lxw_solver* S, const View<R>& v, double T) {
 
 template <class E, class R>
 lxw_status enqueue_shock_t(lxw_solver* S, const View<R>& v) {
-  HIPCHK((launch_ind_step<E, R>(S, v)));
-  HIPCHK((launch_one<E, R>(S, v, K_SHOCK, 0.0, 1)));
-  HIPCHK((launch_one<E, R>(S, v, K_FINAL, 0.0, 1)));
+  HIPCHK((launch_ind_step<E, R>(S, v, false)));
+  HIPCHK((launch_one<E, R>(S, v, K_SHOCK, 1)));
+  HIPCHK((launch_one<E, R>(S, v, K_FINAL, 1)));
   return LXW_OK;
 }
 
-lxw_status enqueue_step(lxw_solver* S, double T) {
+lxw_status enqueue_step(lxw_solver* S) {
   switch (S->M->kind) {
-    case LXW_LINE: return S->fp32 ? enqueue_step_t<ElLine, float>(S, S->vf, T) : enqueue_step_t<ElLine, double>(S, S->vd, T);
-    case LXW_QUAD: return S->fp32 ? enqueue_step_t<ElQuad, float>(S, S->vf, T) : enqueue_step_t<ElQuad, double>(S, S->vd, T);
-    default: return S->fp32 ? enqueue_step_t<ElTri, float>(S, S->vf, T) : enqueue_step_t<ElTri, double>(S, S->vd, T);
+    case LXW_LINE: return S->fp32 ? enqueue_step_t<ElLine, float>(S, S->vf) : enqueue_step_t<ElLine, double>(S, S->vd);
+    case LXW_QUAD: return S->fp32 ? enqueue_step_t<ElQuad, float>(S, S->vf) : enqueue_step_t<ElQuad, double>(S, S->vd);
+    default: return S->fp32 ? enqueue_step_t<ElTri, float>(S, S->vf) : enqueue_step_t<ElTri, double>(S, S->vd);
   }
 }
 
@@ -792,7 +793,9 @@ lxw_status reset_scalars(lxw_solver* S, int b, double t0) {
   z.geo = S->geo_m[b];
   z.cfl = S->P.cfl;
   z.t = t0;
+  z.T = std::numeric_limits<double>::infinity();
   HIPCHK(hipMemcpy(S->sc + b, &z, sizeof z, hipMemcpyHostToDevice));
+  S->t_end = z.T;
   if ((int)S->hscv.size() != S->n_mesh) S->hscv.assign(S->n_mesh, Scalars{});
   S->hscv[b] = z;
   S->hsc = S->hscv[0];
@@ -833,7 +836,7 @@ lxw_status capture_step(lxw_solver* S) {
   HIPCHK(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
   hipStream_t user = S->st;
   S->st = S->cap;
-  lxw_status s = enqueue_step(S, std::numeric_limits<double>::infinity());
+  lxw_status s = enqueue_step(S);
   S->st = user;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(S->cap, &g);
@@ -970,13 +973,20 @@ lxw_status create_solver(const lxw_mesh* m, const lxw_params* p, void* stream, B
   return LXW_OK;
 }
 
-lxw_status run_steps_impl(lxw_solver* S, int64_t n_steps) {
-  if (n_steps < 0) return fail(LXW_ERR_ARG, "negative step count");
-  if (n_steps == 0) return LXW_OK;
+// Sets the end time on the device if it differs from the one last set (stream-ordered).
+lxw_status set_end_time(lxw_solver* S, double T) {
+  if (S->t_end == T) return LXW_OK;
+  HIPCHK(launch_set_end(S->sc, S->n_mesh, T, S->st));
+  S->t_end = T;
+  return LXW_OK;
+}
+
+// Enqueues n steps: replays of the captured step graph, or eager launches while timing, stage
+// read-out or graphs are off.
+lxw_status replay_steps(lxw_solver* S, int64_t n_steps) {
   if (S->timing || S->debug || !S->use_graph) {
-    const double inf = std::numeric_limits<double>::infinity();
     for (int64_t k = 0; k < n_steps; ++k) {
-      lxw_status s = enqueue_step(S, inf);
+      lxw_status s = enqueue_step(S);
       if (s) return s;
     }
     return LXW_OK;
@@ -987,6 +997,14 @@ lxw_status run_steps_impl(lxw_solver* S, int64_t n_steps) {
   }
   for (int64_t k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(S->gexec, S->st));
   return LXW_OK;
+}
+
+lxw_status run_steps_impl(lxw_solver* S, int64_t n_steps) {
+  if (n_steps < 0) return fail(LXW_ERR_ARG, "negative step count");
+  if (n_steps == 0) return LXW_OK;
+  lxw_status s = set_end_time(S, std::numeric_limits<double>::infinity());
+  if (s) return s;
+  return replay_steps(S, n_steps);
 }
 
 // ---- learned indicator: host helpers ---------------------------------------------------------
@@ -1075,7 +1093,7 @@ lxw_status collect_t(lxw_solver* S, const View<R>& v, float* Xd, double* thd) {
   HIPCHK(launch_features<R>(v, Xd, S->st));
   View<R> w = v;
   w.theta = thd;  // k_pre mode 2 stores the factor there
-  HIPCHK((launch<E, R>(K_SHOCK, w, S->cfg, S->st, S->n_mesh, 0.0, 2)));
+  HIPCHK((launch<E, R>(K_SHOCK, w, S->cfg, S->st, S->n_mesh, 2)));
   HIPCHK(hipStreamSynchronize(S->st));
   return LXW_OK;
 }
@@ -1324,7 +1342,8 @@ lxw_status lxw_step(lxw_solver* S, double T, double* dt_taken) {
   if (check_solver(S)) return LXW_ERR_ARG;
   if (S->batch) return fail(LXW_ERR_UNSUPPORTED, "a batch advances by step counts (lxw_batch_advance_steps)");
   if (!(S->hsc.t < T)) return fail(LXW_ERR_ARG, "t >= T");
-  lxw_status s = enqueue_step(S, T);
+  lxw_status s = set_end_time(S, T);
+  if (!s) s = enqueue_step(S);
   if (s) return s;
   s = sync_check(S);
   if (dt_taken) *dt_taken = S->hsc.dt;
@@ -1334,13 +1353,22 @@ lxw_status lxw_step(lxw_solver* S, double T, double* dt_taken) {
 lxw_status lxw_advance(lxw_solver* S, double T, int64_t max_steps, lxw_stats* out) {
   if (check_solver(S)) return LXW_ERR_ARG;
   if (S->batch) return fail(LXW_ERR_UNSUPPORTED, "a batch advances by step counts (lxw_batch_advance_steps)");
-  int64_t n = 0;
-  lxw_status s = LXW_OK;
-  while (S->hsc.t < T && n < max_steps) {
-    s = enqueue_step(S, T);
+  // Steps in chunks (graph replays) with one synchronisation per chunk: the end time sits on
+  // the device, every step is clipped to it and a step at t = T changes nothing, so a chunk may
+  // run past T.  Chunks grow to 256 steps and shrink to the number the last dt predicts.
+  const int64_t steps0 = S->hsc.steps;
+  int64_t n = 0, chunk = 1;
+  lxw_status s = set_end_time(S, T);
+  while (!s && S->hsc.t < T && n < max_steps) {
+    int64_t k = std::min(chunk, max_steps - n);
+    if (S->hsc.dt > 0.0) {
+      const double est = std::ceil((T - S->hsc.t) / S->hsc.dt);
+      if (est >= 1.0 && est < (double)k) k = (int64_t)est;
+    }
+    s = replay_steps(S, k);
     if (!s) s = sync_check(S);
-    if (s) break;
-    ++n;
+    n = S->hsc.steps - steps0;
+    chunk = std::min<int64_t>(2 * chunk, 256);
   }
   if (out) { out->steps = n; out->t = S->hsc.t; out->last_dt = S->hsc.dt; out->last_s = S->hsc.s; }
   return s;
@@ -1565,11 +1593,11 @@ lxw_status lxw_autotune(lxw_solver* S, int32_t trial_steps, lxw_tune* out) {
     for (int bs : sizes) {
       S->cfg = best;
       S->cfg.bs[k] = bs;
-      s = enqueue_step(S, inf);  // warm-up with this shape
+      s = enqueue_step(S);  // warm-up with this shape
       if (!s) s = sync_check(S);
       S->kms[k] = 0.0;
       S->kcount[k] = 0;
-      for (int t = 0; t < trial_steps && !s; ++t) s = enqueue_step(S, inf);
+      for (int t = 0; t < trial_steps && !s; ++t) s = enqueue_step(S);
       if (!s) s = sync_check(S);
       if (s) break;
       const double ms = S->kms[k] / (double)std::max<int64_t>(S->kcount[k], 1);

@@ -180,7 +180,10 @@ __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(
 // over 100 us at a million cells).
 // Three wavefronts per SIMD (168 registers, no spills): the feature gathers are latency-bound.
 template <class R>
-__global__ __launch_bounds__(256, 3) void k_ind(View<R> v, IndW W, unsigned char* flag, unsigned long long* counts) {
+__global__ __launch_bounds__(256, 3) void k_ind(View<R> v, IndW W, unsigned char* flag, unsigned long long* counts,
+                                                int in_step) {
+  // a step of a single mesh at its end time changes nothing (the state read-out still decides)
+  if (in_step && !v.mesh_of && !(v.sc[0].t < v.sc[0].T)) return;
   __shared__ IndLds Ls;
   stage_weights(Ls, W);
   const int nchunk = (v.N + 255) / 256;
@@ -372,9 +375,10 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(int nblk, const float* part,
 // ---- launchers --------------------------------------------------------------------------------
 template <class R>
 hipError_t launch_indicator(const View<R>& v, const IndW& W, unsigned char* flag, unsigned long long* counts,
-                            hipStream_t st) {
+                            bool in_step, hipStream_t st) {
   if (v.N > 0)
-    hipLaunchKernelGGL(k_ind<R>, dim3(std::min((v.N + 255) / 256, IND_GRID_MAX)), dim3(256), 0, st, v, W, flag, counts);
+    hipLaunchKernelGGL(k_ind<R>, dim3(std::min((v.N + 255) / 256, IND_GRID_MAX)), dim3(256), 0, st, v, W, flag, counts,
+                       in_step ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -402,9 +406,9 @@ hipError_t launch_mlp_reduce(int nblk, const float* part, float* theta, float* m
   return hipGetLastError();
 }
 
-template hipError_t launch_indicator<double>(const View<double>&, const IndW&, unsigned char*, unsigned long long*,
+template hipError_t launch_indicator<double>(const View<double>&, const IndW&, unsigned char*, unsigned long long*, bool,
                                              hipStream_t);
-template hipError_t launch_indicator<float>(const View<float>&, const IndW&, unsigned char*, unsigned long long*,
+template hipError_t launch_indicator<float>(const View<float>&, const IndW&, unsigned char*, unsigned long long*, bool,
                                             hipStream_t);
 template hipError_t launch_features<double>(const View<double>&, float*, hipStream_t);
 template hipError_t launch_features<float>(const View<float>&, float*, hipStream_t);

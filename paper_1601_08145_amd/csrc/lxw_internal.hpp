@@ -46,11 +46,12 @@ struct RefTab {
 // Per-mesh device scalars (one record per mesh; the batched form holds many).
 struct Scalars {
   unsigned long long s_bits;  // global wave speed as the bit pattern of a non-negative double
-  double s, dt, t, T;
+  double s, dt, t;
+  double T;                   // end time: dt is clipped to reach it; at t >= T a step changes nothing
   double geo;                 // max_i |dT_i| / (2|T_i|)
   double cfl;
   int shock_pending;          // the shock-capturing limiter of the previous step is still due
-  int pad;
+  int idle;                   // set by k_dt when t >= T: the rest of the step changes nothing
   long long steps;
 };
 
@@ -143,6 +144,8 @@ struct HostTabs {
 
 // ---- host-side launchers implemented in lxw_kernels.hip -----------------------------------
 hipError_t upload_tables(const HostTabs& t);
+// End time of every mesh (stream-ordered): steps are clipped to reach it and change nothing after.
+hipError_t launch_set_end(Scalars* sc, int n_mesh, double T, hipStream_t st);
 
 enum KernelId { K_PRE = 0, K_DT = 1, K_ELEM = 2, K_EDGE = 3, K_FLIM = 4, K_UPDATE = 5, K_FINAL = 6, K_IND = 7,
                 K_SHOCK = 8 };
@@ -160,7 +163,7 @@ inline bool tunable(int k) { return k == K_PRE || k == K_ELEM || k == K_EDGE || 
 inline int egrid_blocks(int n, int bs) { return ((n + bs - 1) / bs + 7) / 8 * 8; }
 
 template <class E, class R>
-hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_t st, int n_mesh, double T, int mode);
+hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_t st, int n_mesh, int mode);
 
 // ---- learned troubled-cell indicator (lxw_indicator.hip) ------------------------------------
 // Network 48 -> 64 (ReLU) -> 64 (ReLU) -> 1 (sigmoid); flat FP32 parameters W1[48][64], b1[64],
@@ -188,7 +191,7 @@ struct IndW {
 constexpr int IND_GRID_MAX = 2048;
 template <class R>
 hipError_t launch_indicator(const View<R>& v, const IndW& W, unsigned char* flag, unsigned long long* counts,
-                            hipStream_t st);
+                            bool in_step, hipStream_t st);
 template <class R>
 hipError_t launch_features(const View<R>& v, float* X, hipStream_t st);
 hipError_t launch_predict(const IndW& W, const float* X, int n, float* p, hipStream_t st);

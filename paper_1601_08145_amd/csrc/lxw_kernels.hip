@@ -285,6 +285,8 @@ __device__ __forceinline__ double point_dev(const RefTab<E, double>& T, const R 
 template <class E, class R, int mode>
 __global__ __launch_bounds__(256) void k_pre(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
+  // a single mesh at its end time: the step changes nothing (every lane leaves together)
+  if (mode == 0 && !v.mesh_of && !(v.sc[0].t < v.sc[0].T)) return;
   const RefTab<E, double>& T = TabSel<E, double>::get();
   const int N = v.N;
   const int i = xcd_item();
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
 // k_dt: per mesh, dt from the CFL condition (reading of Sec. 4.1, "CFL 0.08"), clipped to T.
 // ---------------------------------------------------------------------------------------------
 // Single mesh: one workgroup of 1024 lanes reduces the per-workgroup maxima of k_pre.
-__global__ __launch_bounds__(1024) void k_dt_single(Scalars* sc, DevError* err, const double* spart, int nparts, double T) {
+__global__ __launch_bounds__(1024) void k_dt_single(Scalars* sc, DevError* err, const double* spart, int nparts) {
   __shared__ double red[16];
   double x = 0.0;
   for (int b = threadIdx.x; b < nparts; b += blockDim.x) x = fmax(x, spart[b]);
@@ -528,6 +530,8 @@ __global__ __launch_bounds__(1024) void k_dt_single(Scalars* sc, DevError* err, 
   double s = red[0];
   for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, red[w]);
   Scalars& S = sc[0];
+  S.idle = !(S.t < S.T);  // the end time is reached: this step changes nothing
+  if (S.idle) return;
   S.s = s;
   if (!(s > 0.0) || !isfinite(s)) {
     report(err, E_NONFINITE, -1);
@@ -535,14 +539,16 @@ __global__ __launch_bounds__(1024) void k_dt_single(Scalars* sc, DevError* err, 
     return;
   }
   double dt = S.cfl / (s * S.geo);
-  if (S.t + dt > T) dt = T - S.t;
+  if (S.t + dt > S.T) dt = S.T - S.t;
   S.dt = dt;
 }
 
-__global__ void k_dt(Scalars* sc, DevError* err, int n_mesh, double T) {
+__global__ void k_dt(Scalars* sc, DevError* err, int n_mesh) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_mesh) return;
   Scalars& S = sc[m];
+  S.idle = !(S.t < S.T);
+  if (S.idle) return;
   const double s = __longlong_as_double((long long)S.s_bits);
   S.s = s;
   if (!(s > 0.0) || !isfinite(s)) {
@@ -551,7 +557,7 @@ __global__ void k_dt(Scalars* sc, DevError* err, int n_mesh, double T) {
     return;
   }
   double dt = S.cfl / (s * S.geo);
-  if (S.t + dt > T) dt = T - S.t;
+  if (S.t + dt > S.T) dt = S.T - S.t;
   S.dt = dt;
 }
 
@@ -590,6 +596,7 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
   const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
+  if (v.sc[mid].idle) return;  // end time reached: nothing changes
   const R dt = R(v.sc[mid].dt);
   const R gm1 = R(v.gamma - 1.0);
 
@@ -1123,6 +1130,7 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
+  if (v.sc[mid].idle) return;  // end time reached: nothing changes
   const double dt = v.sc[mid].dt;
   const double r = dt / at(v.area, i);
   double qb[V];
@@ -1177,6 +1185,18 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   }
 }
 
+// Sets the end time of every mesh (a kernel, so that it is ordered on the stream and may be
+// captured).
+__global__ void k_set_end(Scalars* sc, int n_mesh, double T) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < n_mesh) sc[m].T = T;
+}
+
+hipError_t launch_set_end(Scalars* sc, int n_mesh, double T, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_end, dim3((unsigned)((n_mesh + 63) / 64)), dim3(64), 0, st, sc, n_mesh, T);
+  return hipGetLastError();
+}
+
 // k_final: marks the pending shock-capturing limiter as applied (after a state read-out applied
 // it).
 __global__ void k_final(Scalars* sc, int n_mesh) {
@@ -1186,7 +1206,7 @@ __global__ void k_final(Scalars* sc, int n_mesh) {
 }
 
 template <class E, class R>
-hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_t st, int n_mesh, double T, int mode) {
+hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_t st, int n_mesh, int mode) {
   auto grid = [](int n, int b) { return dim3((unsigned)((n + b - 1) / b)); };
   // element and edge kernels: grid padded to a multiple of 8 blocks (XCD-contiguous block order)
   auto egrid = [](int n, int b) { return dim3((unsigned)egrid_blocks(n, b)); };
@@ -1206,9 +1226,9 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
     case K_IND:
       return hipErrorInvalidValue;  // launched through launch_indicator
     case K_DT:
-      if (v.mesh_of) hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh, T);
+      if (v.mesh_of) hipLaunchKernelGGL(k_dt, grid(n_mesh, 64), dim3(64), 0, st, v.sc, v.err, n_mesh);
       else hipLaunchKernelGGL(k_dt_single, dim3(1), dim3(1024), 0, st, v.sc, v.err, v.spart,
-                              v.N > 0 ? egrid_blocks(v.N, cfg.bs[K_PRE]) : 0, T);
+                              v.N > 0 ? egrid_blocks(v.N, cfg.bs[K_PRE]) : 0);
       break;
     case K_ELEM:
       if (v.N > 0) hipLaunchKernelGGL((k_elem<E, R>), egrid(v.N, bs), dim3(bs), 0, st, v);
@@ -1230,11 +1250,11 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
   return hipGetLastError();
 }
 
-template hipError_t launch<ElLine, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, double, int);
-template hipError_t launch<ElLine, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, double, int);
-template hipError_t launch<ElQuad, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, double, int);
-template hipError_t launch<ElQuad, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, double, int);
-template hipError_t launch<ElTri, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, double, int);
-template hipError_t launch<ElTri, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, double, int);
+template hipError_t launch<ElLine, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElLine, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElQuad, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElQuad, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElTri, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElTri, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
 
 }  // namespace lxw

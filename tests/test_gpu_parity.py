@@ -355,6 +355,47 @@ def test_advance_reaches_T_exactly(L):
     assert per_var_rel_l1(Qg, Qo) <= 1e-11
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_advance_in_chunks_equals_single_steps(L, graph):
+    """lxw_advance enqueues steps in chunks (graph replays) with the end time on the device: the
+    result equals single lxw_step calls to the same end time bit for bit, with the same step
+    count; a second advance to the same time takes no step and changes nothing; run_steps
+    afterwards is not clipped.  Also with the learned indicator, whose step launches at the end
+    time change nothing while the state read-out still decides."""
+    print(f"[gpu] advance in chunks vs single steps (graph {graph})", flush=True)
+    xy, tri, Q0, kw = _tri_case_small()
+    T = 0.02
+    for with_ind in (False, True):
+        a = L.Solver(L.Mesh.tri(xy, tri), **kw)
+        b = L.Solver(L.Mesh.tri(xy, tri), **kw)
+        a.set_graph(graph)
+        ind = L.Indicator(I.mlp_init(5)) if with_ind else None
+        for S in (a, b):
+            S.set_state(Q0)
+            if with_ind:
+                S.set_indicator(ind, 0.3, 0.6)
+        st = a.advance(T)
+        n = 0
+        while b.get_state()[1] < T:
+            b.step(T)
+            n += 1
+        Qa, ta = a.get_state()
+        Qb, tb = b.get_state()
+        assert st.steps == n and ta == tb == T and np.array_equal(Qa, Qb), (with_ind, st.steps, n)
+        st2 = a.advance(T)
+        assert st2.steps == 0 and np.array_equal(a.get_state()[0], Qa)
+        a.run_steps(3)
+        a.sync()
+        Qc, tc = a.get_state()
+        assert tc > T and not np.array_equal(Qc, Qa)
+
+
+def _tri_case_small():
+    xy, tri = I.lattice_delaunay(20, 9, box=(-5.0, 5.0, -5.0, 5.0))
+    Q0 = I.averages_to_modal(I.cell_average_state(I.vortex_shock_fn(4), I.tri_sample_points(xy, tri), 1.4), 6)
+    return xy, tri, Q0, {}
+
+
 @pytest.mark.skipif(os.environ.get("LXW_SKIP_FULL") == "1", reason="full-size case skipped on request")
 def test_full_size_c3_one_step(L):
     """The 2D triangle workload at full size (999,698 triangles, four-quadrant Riemann data): one
