@@ -596,7 +596,9 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
   const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
-  if (v.sc[mid].idle) return;  // end time reached: nothing changes
+  // At the end time the step changes nothing: the stored modes are written back as they were.
+  // The flag is applied at the store (not by an early return), so its load overlaps the others.
+  const bool idle = v.sc[mid].idle;
   const R dt = R(v.sc[mid].dt);
   const R gm1 = R(v.gamma - 1.0);
 
@@ -812,7 +814,8 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
 #pragma unroll
   for (int c = 0; c < V; ++c)
 #pragma unroll
-    for (int l = 1; l < ML; ++l) v.Qh[(c * (ML - 1) + l - 1) * N + i] = thR * Qr[c][l - 1] + dt * vol[c][l - 1];
+    for (int l = 1; l < ML; ++l)
+      v.Qh[(c * (ML - 1) + l - 1) * N + i] = idle ? Qr[c][l - 1] : thR * Qr[c][l - 1] + dt * vol[c][l - 1];
   if (v.dbg_vol) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
@@ -1048,6 +1051,7 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   const double dt = v.sc[mid].dt;
+  const bool idle = v.sc[mid].idle;  // at the end time nothing is reported (the step is discarded)
   const double gam = v.gamma;
   const double area = at(v.area, i);
   const double r = dt / area;
@@ -1110,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
     for (int k = 0; k < K; ++k)
       if ((a >> k) & 1) mm[k] = fmin(mm[k], mu);
   }
-  if (bad) report(v.err, E_CFL, i);
+  if (bad && !idle) report(v.err, E_CFL, i);
 #pragma unroll
   for (int k = 0; k < K; ++k) v.cedge[(size_t)eidx[k] * 2 + sd[k]] = Lam[k] * mm[k];
 }
@@ -1130,7 +1134,8 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
   const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
-  if (v.sc[mid].idle) return;  // end time reached: nothing changes
+  // at the end time the step changes nothing: the flag is read here and applied at the stores
+  const bool idle = v.sc[mid].idle;
   const double dt = v.sc[mid].dt;
   const double r = dt / at(v.area, i);
   double qb[V];
@@ -1163,6 +1168,7 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
       }
     }
   }
+  if (idle) return;
   bool finite = true;
 #pragma unroll
   for (int c = 0; c < V; ++c) {
