@@ -324,6 +324,44 @@ def learned_leg(L, steps, warmup, c3_mesh, c3_Q0, fp64_Q=None):
     return out, ind, taus
 
 
+def diffraction_leg(L):
+    """The paper's shock-diffraction problems (block step to t = 2.3, 120-degree wedge to t = 0.9)
+    on unstructured meshes of the paper's size, whole runs through lxw_advance in both forms:
+    steps, wall time, element-updates/s, and the density and pressure ranges against the paper's
+    plots, with the shock-capturing limiter's relaxation factor 5 (500 lets spurious maxima grow on
+    these domains; reported once per problem for comparison)."""
+    import torch
+    from paper_1601_08145_amd import inputs as I
+    out = {}
+    paper = {"step": {"rho": [0.066227, 7.0668], "p": [0.091, 37.0]}, "wedge": {"rho": [0.0665, 8.1], "p": [0.5, 118.0]}}
+    for kind, n in (("step", 126018), ("wedge", 122046)):
+        spec = I.DIFFRACTION[kind]
+        xy, tri, tags = I.diffraction_domain(kind, n, 0)
+        Q0, inflow = I.diffraction_state(xy, tri, kind)
+        mesh = L.Mesh.tri(xy, tri, I.ramp_bc(tags))
+        runs = []
+        for prec, a0 in ((L.FP32_MIXED, 5.0), (L.FP64, 5.0), (L.FP32_MIXED, 500.0)):
+            S = L.Solver(mesh, precision=prec, inflow=list(inflow), alpha0=a0)
+            S.set_state(Q0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = S.advance(spec["t_end"])
+            wall = time.perf_counter() - t0
+            Q, t = S.get_state()
+            rho = Q[:, 0, 0]
+            p = 0.4 * (Q[:, 3, 0] - 0.5 * (Q[:, 1, 0] ** 2 + Q[:, 2, 0] ** 2) / rho)
+            runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "relaxation_factor": a0,
+                         "steps": int(st.steps), "t": t, "wall_s": wall,
+                         "element_updates_per_s": len(tri) * st.steps / wall,
+                         "rho": [float(rho.min()), float(rho.max())], "p": [float(p.min()), float(p.max())]})
+            log(f"[bench]   {kind} ({len(tri)} triangles), {runs[-1]['precision']}, factor {a0:g}: {st.steps} steps "
+                f"to t = {t:g} in {wall:.2f} s ({runs[-1]['element_updates_per_s']:.3e} element-updates/s); "
+                f"rho {rho.min():.4g}..{rho.max():.4g}, p {p.min():.4g}..{p.max():.4g}")
+        out[kind] = {"n_elem": len(tri), "t_end": spec["t_end"], "mach": spec["mach"], "paper_plot_ranges": paper[kind],
+                     "runs": runs}
+    return out
+
+
 def equal_l1_leg(L, ind, taus, sizes=(48, 96, 192), T=1.0):
     """Each form on an exact solution (Shu's isentropic vortex advected by (1, 1) on a periodic
     [-5,5]^2 Delaunay mesh), to time T, at three resolutions: L1 error of the cell averages against
@@ -376,6 +414,7 @@ def main():
     ap.add_argument("--batched-only", action="store_true", help="run only the batched leg (for profiling)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-indicator leg")
     ap.add_argument("--no-equal-l1", action="store_true", help="skip the equal-L1 comparison on the vortex")
+    ap.add_argument("--no-diffraction", action="store_true", help="skip the shock-diffraction runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -475,6 +514,9 @@ def main():
     if not args.no_learned:
         out["learned"], ind, taus = learned_leg(L, args.steps, args.warmup, mesh, Q0,
                                                 f64["Q"] if not args.no_fp64 else None)
+    if not args.no_diffraction:
+        log("[bench] shock diffraction (whole runs)")
+        out["diffraction"] = diffraction_leg(L)
     if not args.no_equal_l1:
         log("[bench] equal-L1 comparison on an exact solution")
         out["equal_l1"] = equal_l1_leg(L, ind, taus)
