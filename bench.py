@@ -57,9 +57,9 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "ea583b38301f1cd6be418c50b239d8346d93ffe9819ea8cd4bc11c76d8137d92",
-           "bytes_per_launch": {"k_pre": 139141089, "k_elem": 679146086, "k_edge": 525963264,
-                                "k_flim": 173616025, "k_update": 465843200}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "5b4038ed3be1453f824d657b334f6cc85c7398c0b8c98169639e23ad2e372280",
+           "bytes_per_launch": {"k_pre": 139128012, "k_elem": 685711155, "k_edge": 525942784,
+                                "k_flim": 173576089, "k_update": 459812864}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
@@ -326,7 +326,8 @@ def learned_leg(L, steps, warmup, c3_mesh, c3_Q0, fp64_Q=None):
 
 def diffraction_leg(L):
     """The paper's shock-diffraction problems (block step to t = 2.3, 120-degree wedge to t = 0.9)
-    on unstructured meshes of the paper's size, whole runs through lxw_advance in both forms:
+    on unstructured meshes of the paper's size, and the block step on its 390 x 330 Cartesian mesh;
+    whole runs through lxw_advance in both forms:
     steps, wall time, element-updates/s, and the density and pressure ranges against the paper's
     plots, with the shock-capturing limiter's relaxation factor 5 (500 lets spurious maxima grow on
     these domains; reported once per problem for comparison)."""
@@ -359,6 +360,28 @@ def diffraction_leg(L):
                 f"rho {rho.min():.4g}..{rho.max():.4g}, p {p.min():.4g}..{p.max():.4g}")
         out[kind] = {"n_elem": len(tri), "t_end": spec["t_end"], "mach": spec["mach"], "paper_plot_ranges": paper[kind],
                      "runs": runs}
+    # the block step on the paper's 390 x 330 Cartesian mesh (Q2), the solid's cells removed
+    nx, ny, box, bc, keep, Q0, inflow = I.diffraction_cart()
+    mesh = L.Mesh.cart(nx, ny, *box, bc, keep=keep)
+    runs = []
+    for prec in (L.FP32_MIXED, L.FP64):
+        S = L.Solver(mesh, precision=prec, inflow=list(inflow), alpha0=5.0)
+        S.set_state(Q0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.advance(2.3)
+        wall = time.perf_counter() - t0
+        Q, t = S.get_state()
+        rho = Q[:, 0, 0]
+        p = 0.4 * (Q[:, 3, 0] - 0.5 * (Q[:, 1, 0] ** 2 + Q[:, 2, 0] ** 2) / rho)
+        runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "relaxation_factor": 5.0,
+                     "steps": int(st.steps), "t": t, "wall_s": wall, "element_updates_per_s": len(Q0) * st.steps / wall,
+                     "rho": [float(rho.min()), float(rho.max())], "p": [float(p.min()), float(p.max())]})
+        log(f"[bench]   Cartesian step ({nx} x {ny}, {len(Q0)} cells), {runs[-1]['precision']}: {st.steps} steps to "
+            f"t = {t:g} in {wall:.2f} s ({runs[-1]['element_updates_per_s']:.3e} element-updates/s); "
+            f"rho {rho.min():.4g}..{rho.max():.4g}, p {p.min():.4g}..{p.max():.4g}")
+    out["cartesian_step"] = {"nx": nx, "ny": ny, "n_elem": len(Q0), "t_end": 2.3, "mach": 5.09,
+                             "paper_plot_ranges": paper["step"], "runs": runs}
     return out
 
 

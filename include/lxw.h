@@ -115,6 +115,18 @@ lxw_status lxw_mesh_create_1d(int32_t n, double x0, double x1, int32_t bc_left, 
 lxw_status lxw_mesh_create_cart(int32_t nx, int32_t ny, double x0, double x1, double y0, double y1,
                                 const int32_t bc[4], lxw_mesh** out);
 
+/* Cartesian mesh with cells removed (the solid of the paper's Cartesian shock-diffraction problem
+ * over a step, Sec. 4): as lxw_mesh_create_cart, where keep[nx*ny] (host, read during the call;
+ * cell (i, j) at i + nx*j) is 0 for a removed cell.  The kept cells are numbered in that
+ * row-major order (the caller's element index), and their edges facing a removed cell get the
+ * boundary type wall_bc (LXW_BC_REFLECTIVE, LXW_BC_TRANSPARENT or LXW_BC_INFLOW); a periodic
+ * partner that is removed counts as such a face.  keep == NULL keeps every cell.  Errors: as
+ * lxw_mesh_create_cart; LXW_ERR_ARG for a wall_bc that is not one of those three or a mask that
+ * keeps no cell. */
+lxw_status lxw_mesh_create_cart_masked(int32_t nx, int32_t ny, double x0, double x1, double y0, double y1,
+                                       const int32_t bc[4], const uint8_t* keep, int32_t wall_bc,
+                                       lxw_mesh** out);
+
 /* Unstructured triangle mesh: xy[n_nodes][2] node coordinates, tri[n_tri][3] counter-clockwise
  * vertex indices.  bnd_tag (nullable, [n_tri][3]) gives the LXW_BC_* code of local edge k of
  * each triangle when that edge is on the boundary (ignored inside; transparent when null).

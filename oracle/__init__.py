@@ -46,12 +46,13 @@ def lib():
         P = ctypes.c_void_p
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
         i, d = ctypes.c_int, ctypes.c_double
         sig = {
             "ora_mesh_1d": (P, [i, d, d, i, i]),
             "ora_num_threads": (i, []),
             "ora_set_num_threads": (None, [i]),
-            "ora_mesh_cart": (P, [i, i, d, d, d, d, ip]),
+            "ora_mesh_cart": (P, [i, i, d, d, d, d, ip, u8p, i]),
             "ora_mesh_tri": (P, [i, dp, i, ip, ip, dp]),
             "ora_last_error": (ctypes.c_char_p, []),
             "ora_mesh_free": (None, [P]),
@@ -150,9 +151,18 @@ class Mesh:
         return Mesh(lib().ora_mesh_1d(n, x0, x1, bc_left, bc_right))
 
     @staticmethod
-    def cart(nx, ny, x0, x1, y0, y1, bc):
+    def cart(nx, ny, x0, x1, y0, y1, bc, keep=None, wall_bc=2):
+        """Cartesian Q2 mesh; keep (nx*ny flags, cell (i, j) at i + nx*j) removes cells, whose
+        faces become boundaries of type wall_bc (reflective by default)."""
         b = i32(bc)
-        return Mesh(lib().ora_mesh_cart(nx, ny, x0, x1, y0, y1, _i(b)))
+        k = None
+        if keep is not None:
+            k = np.ascontiguousarray(np.asarray(keep, dtype=np.uint8).reshape(-1))
+            if k.size != nx * ny:
+                raise ValueError("keep needs nx * ny flags")
+        return Mesh(lib().ora_mesh_cart(nx, ny, x0, x1, y0, y1, _i(b),
+                                        k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if k is not None else None,
+                                        int(wall_bc)))
 
     @staticmethod
     def tri(xy, tri, bnd=None, period=None):

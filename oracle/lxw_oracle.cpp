@@ -366,17 +366,25 @@ static Mesh* mesh_1d(int n, double x0, double x1, int bcl, int bcr) {
   return M;
 }
 
-// bc[4] = {x-low, x-high, y-low, y-high}
-static Mesh* mesh_cart(int nx, int ny, double x0, double x1, double y0, double y1, const int* bc) {
+// bc[4] = {x-low, x-high, y-low, y-high}.  keep (nullable, nx*ny flags, cell (i, j) at i + nx*j)
+// removes the cells whose flag is 0: the remaining cells are numbered in that row-major order and
+// their edges facing a removed cell get the boundary type wall_bc (the solid of the paper's
+// Cartesian step problem, Sec. 4).
+static Mesh* mesh_cart(int nx, int ny, double x0, double x1, double y0, double y1, const int* bc,
+                       const unsigned char* keep, int wall_bc) {
   Mesh* M = new Mesh;
   M->R = make_ref(QUAD);
-  int N = nx * ny;
+  std::vector<int> id(nx * ny, -1);
+  int N = 0;
+  for (int c = 0; c < nx * ny; ++c)
+    if (!keep || keep[c]) id[c] = N++;
   M->N = N;
   double hx = (x1 - x0) / nx, hy = (y1 - y0) / ny;
   M->nbr.assign(4 * N, -1); M->nbr_k.assign(4 * N, -1); M->ebc.assign(4 * N, BC_INTERIOR);
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      int e = i + nx * j;
+      int e = id[i + nx * j];
+      if (e < 0) continue;
       double xa = x0 + i * hx, xb = x0 + (i + 1) * hx, ya = y0 + j * hy, yb = y0 + (j + 1) * hy;
       double v[8] = {xa, ya, xb, ya, xb, yb, xa, yb};
       for (double c : v) M->vx.push_back(c);
@@ -385,7 +393,9 @@ static Mesh* mesh_cart(int nx, int ny, double x0, double x1, double y0, double y
         bool out = (ii < 0 || ii >= nx || jj < 0 || jj >= ny);
         if (out && bcode != BC_PERIODIC) { M->ebc[4 * e + k] = bcode; return; }
         ii = (ii + nx) % nx; jj = (jj + ny) % ny;
-        M->nbr[4 * e + k] = ii + nx * jj; M->nbr_k[4 * e + k] = kk;
+        int n = id[ii + nx * jj];
+        if (n < 0) { M->ebc[4 * e + k] = wall_bc; return; }
+        M->nbr[4 * e + k] = n; M->nbr_k[4 * e + k] = kk;
       };
       link(0, i, j - 1, 2, bc[2]);
       link(1, i + 1, j, 3, bc[1]);
@@ -1115,8 +1125,9 @@ int ora_num_threads() {
   return 1;
 #endif
 }
-void* ora_mesh_cart(int nx, int ny, double x0, double x1, double y0, double y1, const int* bc) {
-  return mesh_cart(nx, ny, x0, x1, y0, y1, bc);
+void* ora_mesh_cart(int nx, int ny, double x0, double x1, double y0, double y1, const int* bc,
+                    const unsigned char* keep, int wall_bc) {
+  return mesh_cart(nx, ny, x0, x1, y0, y1, bc, keep, wall_bc);
 }
 static std::string g_err;
 void* ora_mesh_tri(int nn, const double* xy, int nt, const int* tri, const int* bnd, const double* period) {

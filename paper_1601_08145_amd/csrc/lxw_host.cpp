@@ -1152,23 +1152,37 @@ lxw_status lxw_mesh_create_1d(int32_t n, double x0, double x1, int32_t bcl, int3
 
 lxw_status lxw_mesh_create_cart(int32_t nx, int32_t ny, double x0, double x1, double y0, double y1, const int32_t bc[4],
                                 lxw_mesh** out) {
+  return lxw_mesh_create_cart_masked(nx, ny, x0, x1, y0, y1, bc, nullptr, LXW_BC_REFLECTIVE, out);
+}
+
+lxw_status lxw_mesh_create_cart_masked(int32_t nx, int32_t ny, double x0, double x1, double y0, double y1,
+                                       const int32_t bc[4], const uint8_t* keep, int32_t wall_bc, lxw_mesh** out) {
   if (!out || !bc) return fail(LXW_ERR_ARG, "null argument");
   *out = nullptr;
   if (nx < 2 || ny < 2 || !(x1 > x0) || !(y1 > y0)) return fail(LXW_ERR_ARG, "need nx, ny >= 2 and a non-empty box");
+  if ((int64_t)nx * ny > INT32_MAX) return fail(LXW_ERR_ARG, "too many cells");
   for (int s = 0; s < 4; ++s)
     if (bc[s] < 0 || bc[s] > 3) return fail(LXW_ERR_ARG, "bad boundary code");
   if ((bc[0] == LXW_BC_PERIODIC) != (bc[1] == LXW_BC_PERIODIC) || (bc[2] == LXW_BC_PERIODIC) != (bc[3] == LXW_BC_PERIODIC))
     return fail(LXW_ERR_ARG, "periodic must be set on both sides of a direction");
+  if (wall_bc != LXW_BC_REFLECTIVE && wall_bc != LXW_BC_TRANSPARENT && wall_bc != LXW_BC_INFLOW)
+    return fail(LXW_ERR_ARG, "wall_bc must be reflective, transparent or inflow");
+  // caller index of every kept cell, -1 for a removed one
+  std::vector<int> id((size_t)nx * ny, -1);
+  int N = 0;
+  for (size_t c = 0; c < id.size(); ++c)
+    if (!keep || keep[c]) id[c] = N++;
+  if (N == 0) return fail(LXW_ERR_ARG, "the mask keeps no cell");
   std::unique_ptr<lxw_mesh> M(new (std::nothrow) lxw_mesh);
   if (!M) return fail(LXW_ERR_OOM, "host allocation");
-  const int N = nx * ny;
   M->kind = LXW_QUAD; M->dim = 2; M->N = N; M->K = 4; M->V = 4; M->ML = 9;
   const double hx = (x1 - x0) / nx, hy = (y1 - y0) / ny;
   std::vector<double> cvx((size_t)N * 8);
   std::vector<int> nb((size_t)N * 4, -1), nk((size_t)N * 4, -1), bcv((size_t)N * 4, -1);
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      const int e = i + nx * j;
+      const int e = id[(size_t)i + (size_t)nx * j];
+      if (e < 0) continue;
       const double xa = x0 + i * hx, xb = (i == nx - 1) ? x1 : x0 + (i + 1) * hx;
       const double ya = y0 + j * hy, yb = (j == ny - 1) ? y1 : y0 + (j + 1) * hy;
       const double v[8] = {xa, ya, xb, ya, xb, yb, xa, yb};
@@ -1179,7 +1193,9 @@ lxw_status lxw_mesh_create_cart(int32_t nx, int32_t ny, double x0, double x1, do
         const bool outside = l.ii < 0 || l.ii >= nx || l.jj < 0 || l.jj >= ny;
         if (outside && l.code != LXW_BC_PERIODIC) { bcv[(size_t)e * 4 + l.k] = l.code; continue; }
         const int ii = (l.ii + nx) % nx, jj = (l.jj + ny) % ny;
-        nb[(size_t)e * 4 + l.k] = ii + nx * jj;
+        const int n = id[(size_t)ii + (size_t)nx * jj];
+        if (n < 0) { bcv[(size_t)e * 4 + l.k] = wall_bc; continue; }  // face of a removed cell
+        nb[(size_t)e * 4 + l.k] = n;
         nk[(size_t)e * 4 + l.k] = l.kk;
       }
     }

@@ -251,6 +251,30 @@ def diffraction_state(xy, tri, kind, gamma=1.4, m=2):
 # Initial states
 # ---------------------------------------------------------------------------------------------
 
+def diffraction_cart(nx=390, ny=330, box=(13.0, 11.0), gamma=1.4):
+    """The shock-diffraction problem over the block step (Sec. 4) on an nx x ny Cartesian mesh of
+    [0, W] x [0, H] (the paper: 390 x 330, h = 1/30): the cells whose centre lies in the solid
+    [0, 1] x [0, 6] are removed (their faces are reflective walls), inflow at x = 0, transparent
+    elsewhere.  Returns (nx, ny, (x0, x1, y0, y1), bc, keep, Q0, inflow) with keep the nx*ny
+    row-major cell flags, Q0[n_kept][4][9] the Mach 5.09 shock at x = 1 (a cell face when
+    nx / W * 1 is whole) moving into gas at rest (rho = 1.4, p = 1) as cell averages (higher modes
+    zero), and inflow the post-shock conserved state."""
+    spec = DIFFRACTION["step"]
+    W, H = box
+    (sx0, sy0), (sx1, sy1) = spec["solid"][0], spec["solid"][2]
+    xc = (np.arange(nx) + 0.5) * (W / nx)
+    yc = (np.arange(ny) + 0.5) * (H / ny)
+    X, Y = np.meshgrid(xc, yc, indexing="xy")
+    solid = (X > sx0) & (X < sx1) & (Y > sy0) & (Y < sy1)
+    keep = (~solid).ravel().astype(np.uint8)
+    pre, post = mach_shock_states(spec["mach"], gamma=gamma)
+    behind = (X < spec["x_shock"]).ravel()[keep != 0]
+    prim = np.where(behind[:, None], post[None, :], pre[None, :])
+    Q0 = averages_to_modal(prim_to_cons(prim, gamma), 9)
+    bc = [3, 1, 1, 1]  # x-low inflow (only above the solid), x-high, y-low, y-high transparent
+    return nx, ny, (0.0, W, 0.0, H), bc, keep, Q0, prim_to_cons(post[None, :], gamma)[0]
+
+
 def prim_to_cons(prim, gamma):
     """(rho, u[, v], p) -> (rho, rho u[, rho v], E) along the last axis, Eq. (eos)."""
     prim = np.asarray(prim, dtype=np.float64)

@@ -76,6 +76,8 @@ def _load():
         "lxw_params_default": [ctypes.POINTER(Params)],
         "lxw_mesh_create_1d": [I32, D, D, I32, I32, ctypes.POINTER(P)],
         "lxw_mesh_create_cart": [I32, I32, D, D, D, D, ip, ctypes.POINTER(P)],
+        "lxw_mesh_create_cart_masked": [I32, I32, D, D, D, D, ip, ctypes.POINTER(ctypes.c_uint8), I32,
+                                        ctypes.POINTER(P)],
         "lxw_mesh_create_tri": [I32, dp, I32, ip, ip, dp, ctypes.POINTER(P)],
         "lxw_mesh_destroy": [P],
         "lxw_mesh_get_info": [P, ctypes.POINTER(MeshInfo)],
@@ -195,14 +197,25 @@ class Mesh:
         return Mesh(h, LINE, np.stack([xs[:-1], xs[1:]], 1)[:, :, None])
 
     @staticmethod
-    def cart(nx, ny, x0, x1, y0, y1, bc):
+    def cart(nx, ny, x0, x1, y0, y1, bc, keep=None, wall_bc=BC_REFLECTIVE):
+        """Cartesian Q2 mesh; keep (nx*ny flags, cell (i, j) at i + nx*j) removes the cells whose flag
+        is 0, their faces becoming boundaries of type wall_bc; the kept cells keep row-major order."""
         b = np.ascontiguousarray(bc, dtype=np.int32)
         h = ctypes.c_void_p()
-        _check(_L.lxw_mesh_create_cart(nx, ny, x0, x1, y0, y1, _ip(b), ctypes.byref(h)))
-        xs = np.linspace(x0, x1, nx + 1)
-        ys = np.linspace(y0, y1, ny + 1)
         i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
         i, j = i.ravel(), j.ravel()
+        if keep is None:
+            _check(_L.lxw_mesh_create_cart(nx, ny, x0, x1, y0, y1, _ip(b), ctypes.byref(h)))
+        else:
+            k = np.ascontiguousarray(np.asarray(keep).reshape(-1) != 0, dtype=np.uint8)
+            if k.size != nx * ny:
+                raise ValueError("keep needs nx * ny flags")
+            _check(_L.lxw_mesh_create_cart_masked(nx, ny, x0, x1, y0, y1, _ip(b),
+                                                  k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(wall_bc),
+                                                  ctypes.byref(h)))
+            i, j = i[k != 0], j[k != 0]
+        xs = np.linspace(x0, x1, nx + 1)
+        ys = np.linspace(y0, y1, ny + 1)
         v = np.stack([np.stack([xs[i], ys[j]], 1), np.stack([xs[i + 1], ys[j]], 1),
                       np.stack([xs[i + 1], ys[j + 1]], 1), np.stack([xs[i], ys[j + 1]], 1)], 1)
         return Mesh(h, QUAD, v)

@@ -49,3 +49,24 @@ def test_diffraction_state(kind):
     assert np.allclose(Q[ahead, 0, 0], pre[0]) and np.allclose(Q[behind, 0, 0], post[0])
     assert np.allclose(Q[:, :, 1:], 0.0)
     assert inflow[0] == pytest.approx(post[0])
+
+
+def test_diffraction_cartesian_step():
+    """The block step on the paper's 390 x 330 Cartesian mesh (h = 1/30): the 30 x 180 cells of the
+    solid removed, the domain's area filled exactly, the shock on the cell face x = 1 with the
+    post-shock state behind it, and the same counts in the oracle's mesh."""
+    import oracle as O
+    nx, ny, box, bc, keep, Q0, inflow = I.diffraction_cart()
+    assert (nx, ny) == (390, 330) and nx * ny - keep.sum() == 30 * 180
+    M = O.Mesh.cart(nx, ny, *box, bc, keep=keep, wall_bc=O.BC_REFLECTIVE)
+    assert M.N == len(Q0) == 123300 and M.area.sum() == pytest.approx(13.0 * 11.0 - 6.0, rel=1e-12)
+    # edges: 4 per cell, the boundary ones counted once (walls 180 + 30, inflow 150, x-high 330,
+    # y-low 360, y-high 390)
+    assert M.E == (4 * M.N + 210 + 150 + 330 + 360 + 390) // 2
+    assert (M.nbr < 0).sum() == 210 + 150 + 330 + 360 + 390
+    pre, post = I.mach_shock_states(5.09)
+    cons = I.prim_to_cons(np.stack([pre, post]), 1.4)
+    jj, ii = np.nonzero(keep.reshape(ny, nx))
+    behind = ii < 30
+    assert np.allclose(Q0[behind, :, 0], cons[1]) and np.allclose(Q0[~behind, :, 0], cons[0])
+    assert np.all(jj[behind] >= 180) and np.allclose(inflow, cons[1]) and np.all(Q0[:, :, 1:] == 0)

@@ -51,6 +51,17 @@ def test_refelem_tables_match_the_oracle(L, kind):
     assert a == b
 
 
+def test_masked_cartesian_mesh_counts(L):
+    """The library's masked Cartesian mesh (the block step's solid removed) has the oracle's cell
+    and edge counts, and rejects a mask that keeps nothing."""
+    nx, ny, box, bc, keep, Q0, _ = I.diffraction_cart(78, 66)
+    m = L.Mesh.cart(nx, ny, *box, bc, keep=keep)
+    mo = O.Mesh.cart(nx, ny, *box, bc, keep=keep)
+    assert (m.N, m.E) == (mo.N, mo.E) == (len(Q0), mo.E)
+    with pytest.raises(Exception):
+        L.Mesh.cart(nx, ny, *box, bc, keep=np.zeros(nx * ny, np.uint8))
+
+
 def test_mesh_connectivity_counts(L):
     xy, tri = I.lattice_delaunay(15, 2)
     m = L.Mesh.tri(xy, tri)

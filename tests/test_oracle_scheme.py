@@ -257,3 +257,73 @@ def test_reflective_wall_mirror_symmetry():
     a, _ = Sh.get_state()
     b, _ = Sf.get_state()
     assert np.allclose(a, b[:n], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_masked_cells_act_as_walls(axis):
+    """Removed cells of a masked Cartesian mesh turn their neighbours' faces into boundaries of the
+    given type: a 2n x m box whose upper half (in x or in y) is removed runs bit for bit like the
+    n x m box with a reflective wall on that side (same cell order, same coordinates)."""
+    n, m = 10, 7
+    if axis == "x":
+        keep = (np.arange(2 * n)[None, :] < n) & np.ones((m, 1), bool)
+        Mm = O.Mesh.cart(2 * n, m, 0, 2, 0, 1, [O.BC_TRANSPARENT, O.BC_TRANSPARENT, O.BC_PERIODIC, O.BC_PERIODIC],
+                         keep=keep, wall_bc=O.BC_REFLECTIVE)
+        Mp = O.Mesh.cart(n, m, 0, 1, 0, 1, [O.BC_TRANSPARENT, O.BC_REFLECTIVE, O.BC_PERIODIC, O.BC_PERIODIC])
+    else:
+        keep = (np.arange(2 * m)[:, None] < m) & np.ones((1, n), bool)
+        Mm = O.Mesh.cart(n, 2 * m, 0, 1, 0, 2, [O.BC_PERIODIC, O.BC_PERIODIC, O.BC_TRANSPARENT, O.BC_TRANSPARENT],
+                         keep=keep, wall_bc=O.BC_REFLECTIVE)
+        Mp = O.Mesh.cart(n, m, 0, 1, 0, 1, [O.BC_PERIODIC, O.BC_PERIODIC, O.BC_TRANSPARENT, O.BC_REFLECTIVE])
+    assert (Mm.N, Mm.E) == (Mp.N, Mp.E) == (n * m, Mp.E)
+    Q = I.random_modal_state(n * m, 2, 9, seed=11, amp=0.3, rough_frac=0.1, rough_amp=2.0, p_range=(1e-3, 1.0))
+    out = []
+    for M in (Mm, Mp):
+        S = O.Solver(M)
+        S.set_state(Q)
+        for _ in range(5):
+            S.step()
+        out.append(S.get_state())
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+def test_masked_walls_conserve_mass_and_energy():
+    """A periodic box with a block of cells removed (reflective faces) and a notch across the
+    periodic seam: mass and energy stay constant to round-off over ten steps (no mass or energy
+    crosses a reflective face), while the x-momentum does not (the walls push), and a uniform
+    flow stays uniform except next to the walls after one step (every other cell sees the same
+    flux on opposite faces)."""
+    nx, ny = 24, 20
+    keep = np.ones((ny, nx), bool)
+    keep[7:12, 9:15] = False        # block
+    keep[3:6, 0:2] = False          # notch at the x-low side: its x-high partner faces it periodically
+    M = O.Mesh.cart(nx, ny, 0, 2.4, 0, 2.0, [O.BC_PERIODIC] * 4, keep=keep, wall_bc=O.BC_REFLECTIVE)
+    assert M.N == keep.sum() and M.area.sum() == pytest.approx(2.4 * 2.0 * keep.mean(), rel=1e-13)
+    Q = I.random_modal_state(M.N, 2, 9, seed=12, amp=0.5, rough_frac=0.2, rough_amp=3.0, p_range=(1e-5, 1.0))
+    mx = Q[:, 1, 0] + 0.5 * Q[:, 0, 0]  # a mean flow into the walls, pressure unchanged
+    Q[:, 3, 0] += 0.5 * (mx**2 - Q[:, 1, 0] ** 2) / Q[:, 0, 0]
+    Q[:, 1, 0] = mx
+    S = O.Solver(M)
+    S.set_state(Q)
+    tot0 = np.sum(Q[:, :, 0] * M.area[:, None], axis=0)
+    for _ in range(10):
+        S.step()
+    Qn, _ = S.get_state()
+    tot = np.sum(Qn[:, :, 0] * M.area[:, None], axis=0)
+    scale = np.sum(np.abs(Q[:, :, 0]) * M.area[:, None], axis=0)
+    assert abs(tot[0] - tot0[0]) <= 1e-13 * scale[0] and abs(tot[3] - tot0[3]) <= 1e-13 * scale[3]
+    assert abs(tot[1] - tot0[1]) > 1e-6 * scale[1]
+    # uniform flow: one step changes only the cells with a face on a removed cell
+    U = I.averages_to_modal(I.prim_to_cons(np.tile([1.0, 0.7, 0.4, 1.0], (M.N, 1)), 1.4), 9)
+    S = O.Solver(M)
+    S.set_state(U)
+    S.step()
+    Un, _ = S.get_state()
+    changed = np.abs(Un[:, :, 0] - U[:, :, 0]).max(axis=1) > 1e-12
+    ids = -np.ones(nx * ny, int)
+    ids[keep.ravel()] = np.arange(M.N)
+    jj, ii = np.nonzero(keep)
+    walled = np.zeros(M.N, bool)
+    for dj, di in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        walled |= ~keep[(jj + dj) % ny, (ii + di) % nx]
+    assert np.array_equal(changed[ids[keep.ravel()]], walled)
