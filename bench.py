@@ -385,6 +385,71 @@ def diffraction_leg(L):
     return out
 
 
+def sedov_leg(L):
+    """The paper's Sedov blasts, whole runs through lxw_advance in both forms: 1D (dx = 1/100, to
+    t = 0.001) and 2D on the disk of radius 1.1 with about 136,270 triangles (to t = 0.1): steps,
+    wall time, element-updates/s, the L1 density error against the similarity solution and the
+    radius of the density maximum against the exact shock radius."""
+    import torch
+    from paper_1601_08145_amd import inputs as I
+    from tests.exact_sedov import Sedov
+    out = {}
+    dx, T = 0.01, 1e-3
+    n, x0, x1, Q0 = I.sedov_1d(dx)
+    ex = Sedov(1, E=3.2e6)
+    xc = x0 + (np.arange(n) + 0.5) * dx
+    xs = xc[:, None] + ((np.arange(16) + 0.5) / 16 - 0.5)[None, :] * dx
+    rho_e = ex.state(xs, T)[0].mean(axis=1)
+    mesh = L.Mesh.line(n, x0, x1, L.BC_TRANSPARENT, L.BC_TRANSPARENT)
+    runs = []
+    for prec in (L.FP32_MIXED, L.FP64):
+        S = L.Solver(mesh, precision=prec, cfl=0.1)
+        S.set_state(Q0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.advance(T)
+        wall = time.perf_counter() - t0
+        Q, t = S.get_state()
+        l1 = float(np.abs(Q[:, 0, 0] - rho_e).sum() / np.abs(rho_e - 1.0).sum())
+        runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "steps": int(st.steps), "t": t,
+                     "wall_s": wall, "element_updates_per_s": n * st.steps / wall, "l1_rho_vs_similarity": l1,
+                     "peak_x": float(abs(xc[np.argmax(Q[:, 0, 0])])), "rho_max": float(Q[:, 0, 0].max())})
+        log(f"[bench]   Sedov 1D ({n} cells), {runs[-1]['precision']}: {st.steps} steps in {wall:.2f} s; "
+            f"L1(rho) vs similarity solution {l1:.4f}, peak at |x| = {runs[-1]['peak_x']:.3f} (exact shock {ex.radius(T):.3f})")
+    out["1d"] = {"n_elem": n, "dx": dx, "t_end": T, "exact_shock_x": ex.radius(T), "runs": runs}
+    xy, tri = I.sedov_disk()
+    Q0 = I.sedov_disk_state(xy, tri)
+    ex = Sedov(2, E=0.979264)
+    a = xy[tri]
+    w = np.array([[0.5, 0.5, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5],
+                  [2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
+    pts = np.einsum("pk,nkd->npd", w, a)
+    T2 = 0.1
+    rho_e = ex.state(np.hypot(pts[..., 0], pts[..., 1]), T2)[0].mean(axis=1)
+    area = 0.5 * np.abs((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0]))
+    r = np.hypot(a.mean(axis=1)[:, 0], a.mean(axis=1)[:, 1])
+    mesh = L.Mesh.tri(xy, tri)
+    runs = []
+    for prec in (L.FP32_MIXED, L.FP64):
+        S = L.Solver(mesh, precision=prec)
+        S.set_state(Q0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.advance(T2)
+        wall = time.perf_counter() - t0
+        Q, t = S.get_state()
+        rho = Q[:, 0, 0]
+        l1 = float(np.sum(np.abs(rho - rho_e) * area) / np.sum(np.abs(rho_e - 1.0) * area))
+        runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "steps": int(st.steps), "t": t,
+                     "wall_s": wall, "element_updates_per_s": len(tri) * st.steps / wall, "l1_rho_vs_similarity": l1,
+                     "peak_r": float(r[np.argmax(rho)]), "rho_max": float(rho.max())})
+        log(f"[bench]   Sedov 2D ({len(tri)} triangles), {runs[-1]['precision']}: {st.steps} steps in {wall:.2f} s "
+            f"({runs[-1]['element_updates_per_s']:.3e} element-updates/s); L1(rho) vs similarity solution {l1:.4f}, "
+            f"peak {rho.max():.3f} at r = {runs[-1]['peak_r']:.4f} (exact shock {ex.radius(T2):.4f})")
+    out["2d_disk"] = {"n_elem": len(tri), "t_end": T2, "exact_shock_r": ex.radius(T2), "runs": runs}
+    return out
+
+
 def equal_l1_leg(L, ind, taus, sizes=(48, 96, 192), T=1.0):
     """Each form on an exact solution (Shu's isentropic vortex advected by (1, 1) on a periodic
     [-5,5]^2 Delaunay mesh), to time T, at three resolutions: L1 error of the cell averages against
@@ -438,6 +503,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-indicator leg")
     ap.add_argument("--no-equal-l1", action="store_true", help="skip the equal-L1 comparison on the vortex")
     ap.add_argument("--no-diffraction", action="store_true", help="skip the shock-diffraction runs")
+    ap.add_argument("--no-sedov", action="store_true", help="skip the Sedov blast runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -540,6 +606,9 @@ def main():
     if not args.no_diffraction:
         log("[bench] shock diffraction (whole runs)")
         out["diffraction"] = diffraction_leg(L)
+    if not args.no_sedov:
+        log("[bench] Sedov blasts (whole runs)")
+        out["sedov"] = sedov_leg(L)
     if not args.no_equal_l1:
         log("[bench] equal-L1 comparison on an exact solution")
         out["equal_l1"] = equal_l1_leg(L, ind, taus)

@@ -251,6 +251,70 @@ def diffraction_state(xy, tri, kind, gamma=1.4, m=2):
 # Initial states
 # ---------------------------------------------------------------------------------------------
 
+def sedov_1d(dx=0.01, half_width=2.0, e_total=3.2e6, e_bg=1e-12):
+    """The 1D Sedov blast (Sec. 4.2.2): cells of width dx (the paper: 1/100) on
+    [-(half_width + dx/2), half_width + dx/2], an odd count so that one cell is centred at 0;
+    rho = 1, u = 0, E = e_bg everywhere except the centre cell, which holds E = e_total / dx.
+    Returns (n, x0, x1, Q0[n][3][3]) (cell averages, higher modes zero)."""
+    n = 2 * int(round(half_width / dx)) + 1
+    x1 = n * dx / 2
+    avg = np.zeros((n, 3))
+    avg[:, 0] = 1.0
+    avg[:, 2] = e_bg
+    avg[n // 2, 2] = e_total / dx
+    return n, -x1, x1, averages_to_modal(avg, 3)
+
+
+def sedov_disk(n_target=136270, seed=0, radius=1.1, jitter=0.25):
+    """Triangle mesh of the disk of the given radius (the 2D Sedov blast on an unstructured mesh,
+    Sec. 4.3.2, with about n_target triangles): a jittered square lattice of spacing h inside
+    radius - 0.55 h, points every about h on the circle, Delaunay.  Returns (xy, tri)."""
+    g = rng(seed)
+    area = math.pi * radius * radius
+    h = math.sqrt(2.0 * area / n_target)
+    for _ in range(6):
+        m = int(math.ceil(radius / h)) + 1
+        ax = np.arange(-m, m + 1) * h
+        X, Y = np.meshgrid(ax, ax, indexing="xy")
+        pts = np.stack([X.ravel(), Y.ravel()], 1)
+        pts = pts + g.uniform(-jitter * h, jitter * h, pts.shape)
+        pts = pts[np.hypot(pts[:, 0], pts[:, 1]) < radius - 0.55 * h]
+        nb = int(round(2.0 * math.pi * radius / h))
+        th = 2.0 * math.pi * np.arange(nb) / nb
+        xy = np.concatenate([pts, radius * np.stack([np.cos(th), np.sin(th)], 1)], 0)
+        n_tri = 2 * len(xy) - nb - 2  # triangles of a Delaunay triangulation with nb hull points
+        if abs(n_tri - n_target) <= 0.002 * n_target:
+            break
+        h *= math.sqrt(n_tri / n_target)
+    tri = Delaunay(xy).simplices.astype(np.int32)
+    a = xy[tri]
+    cross = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0])
+    tri[cross < 0] = tri[cross < 0][:, [0, 2, 1]]
+    return xy, tri
+
+
+def sedov_disk_state(xy, tri, radius=1.1, e_total=0.979264, e_bg=1e-12):
+    """Initial data of the 2D Sedov blast (Sec. 4.3.2): rho = 1, u = 0, E = e_bg, and the energy
+    e_total released within r_d = sqrt(pi radius^2 / n_cells) of the centre.  Reading: the
+    energy is deposited on the triangles whose centroid lies within r_d, uniformly per area and
+    with the exact total e_total (the quantity the blast's similarity solution depends on),
+    rather than as the point function's projection.  Returns Q0[n][4][6] (cell averages, higher
+    modes zero)."""
+    a = np.asarray(xy)[np.asarray(tri)]
+    cen = a.mean(axis=1)
+    area = 0.5 * np.abs((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1])
+                        - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0]))
+    r_d = math.sqrt(math.pi * radius * radius / len(tri))
+    hot = np.hypot(cen[:, 0], cen[:, 1]) < r_d
+    if not hot.any():
+        hot[np.argmin(np.hypot(cen[:, 0], cen[:, 1]))] = True
+    avg = np.zeros((len(tri), 4))
+    avg[:, 0] = 1.0
+    avg[:, 3] = e_bg
+    avg[hot, 3] += e_total / area[hot].sum()
+    return averages_to_modal(avg, 6)
+
+
 def diffraction_cart(nx=390, ny=330, box=(13.0, 11.0), gamma=1.4):
     """The shock-diffraction problem over the block step (Sec. 4) on an nx x ny Cartesian mesh of
     [0, W] x [0, H] (the paper: 390 x 330, h = 1/30): the cells whose centre lies in the solid

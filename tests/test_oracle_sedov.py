@@ -1,0 +1,89 @@
+"""The Sedov blast problems (Sec. 4.2.2 in 1D, Sec. 4.3.2 on an unstructured disk): the
+similarity solution used as their reference is pinned first (its energy integral, Taylor's
+constant), then the oracle's runs are checked against it."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_08145_amd import inputs as I
+from tests import helpers as H
+from tests.exact_sedov import Sedov
+
+
+@pytest.mark.parametrize("j", [1, 2, 3])
+def test_similarity_solution_energy_integral(j):
+    """The integrated profiles satisfy the algebraic energy integral (which follows from energy
+    conservation alone, not from the ODEs integrated) and the strong-shock values at lam = 1;
+    the density vanishes at the centre."""
+    S = Sedov(j)
+    assert S.energy_integral_residual() < 1e-6
+    assert S.g[-1] == pytest.approx(6.0, rel=1e-12) and S.f[-1] == pytest.approx(1 / 1.2, rel=1e-12)
+    big = S.g > 1e-9  # below, the values are at the integrator's absolute tolerance
+    assert S.g[0] < 1e-5 and np.all(np.diff(S.g[big]) > 0)
+
+
+def test_similarity_solution_constants():
+    """Spherical, gamma = 1.4: R = 1.033 (E/rho0)^(1/5) t^(2/5) (Taylor's constant).  Cylindrical:
+    the energy 0.979264 of the 2D problem puts the shock at r = 1 at t = 1."""
+    assert Sedov(3).alpha ** (-1 / 5) == pytest.approx(1.033, abs=1e-3)
+    assert Sedov(2, E=0.979264).radius(1.0) == pytest.approx(1.0, abs=2e-3)
+
+
+def sedov_1d_run(dx, T=1e-3):
+    n, x0, x1, Q0 = I.sedov_1d(dx)
+    M = O.Mesh.line(n, x0, x1, O.BC_TRANSPARENT, O.BC_TRANSPARENT)
+    S = O.Solver(M, cfl=0.1)
+    S.set_state(Q0)
+    S.advance(T)
+    Q, t = S.get_state()
+    return n, x0, Q0, Q, t
+
+
+def cell_avg_exact_1d(ex, x0, n, dx, T, sub=16):
+    xc = x0 + (np.arange(n) + 0.5) * dx
+    xs = xc[:, None] + ((np.arange(sub) + 0.5) / sub - 0.5)[None, :] * dx
+    return xc, ex.state(xs, T)[0].mean(axis=1)
+
+
+def test_sedov_1d_against_similarity_solution():
+    """1D Sedov blast of the paper (E = 3.2e6/dx in the centre cell, dx = 1/100), on
+    [-2.005, 2.005] to t = 0.001 (reading: the paper gives neither; at that time the planar
+    similarity solution has its shock at |x| = 1.437): positivity, energy conserved to round-off,
+    the density peak within three cells behind the exact shock and above 0.8 of its value 6, and the
+    L1 density error against the similarity solution small and falling under refinement."""
+    ex = Sedov(1, E=3.2e6)
+    T = 1e-3
+    errs = []
+    for dx in (0.02, 0.01):
+        n, x0, Q0, Q, t = sedov_1d_run(dx, T)
+        assert t == pytest.approx(T, rel=1e-14)
+        assert np.all(Q[:, 0, 0] > 0) and np.all(H.pressure(Q[:, :, 0]) > 0)
+        E0, E1 = Q0[:, 2, 0].sum(), Q[:, 2, 0].sum()
+        assert abs(E1 - E0) <= 1e-12 * E0
+        xc, rho_e = cell_avg_exact_1d(ex, x0, n, dx, T)
+        errs.append(np.abs(Q[:, 0, 0] - rho_e).sum() / np.abs(rho_e - 1.0).sum())
+        for side in (xc < 0, xc > 0):
+            k = np.argmax(np.where(side, Q[:, 0, 0], 0.0))
+            assert ex.radius(T) - 3 * dx <= abs(xc[k]) <= ex.radius(T) + dx
+            assert Q[k, 0, 0] > 0.8 * 6.0
+    assert errs[1] < errs[0] and errs[1] < 0.15, errs
+
+
+def test_sedov_disk_input():
+    """The 2D problem's disk (radius 1.1) with about the paper's 136,270 triangles, counter-clockwise,
+    filling the inscribed polygon; the released energy is exactly 0.979264 on a few central
+    triangles."""
+    xy, tri = I.sedov_disk()
+    assert abs(len(tri) - 136270) < 0.005 * 136270
+    a = xy[tri]
+    cross = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0])
+    assert np.all(cross > 0)
+    nb = np.sum(np.isclose(np.hypot(xy[:, 0], xy[:, 1]), 1.1, rtol=0, atol=1e-12))
+    assert 0.5 * cross.sum() == pytest.approx(0.5 * nb * 1.1 ** 2 * math.sin(2 * math.pi / nb), rel=1e-12)
+    Q = I.sedov_disk_state(xy, tri)
+    hot = Q[:, 3, 0] > 1.0
+    assert 1 <= hot.sum() <= 10 and np.all(Q[~hot, 3, 0] == 1e-12) and np.all(Q[:, 0, 0] == 1.0)
+    assert np.sum((Q[:, 3, 0] - 1e-12) * 0.5 * cross) == pytest.approx(0.979264, rel=1e-12)
+
