@@ -402,8 +402,8 @@ def sedov_leg(L):
     rho_e = ex.state(xs, T)[0].mean(axis=1)
     mesh = L.Mesh.line(n, x0, x1, L.BC_TRANSPARENT, L.BC_TRANSPARENT)
     runs = []
-    for prec in (L.FP32_MIXED, L.FP64):
-        S = L.Solver(mesh, precision=prec, cfl=0.1)
+    for prec, exact in ((L.FP32_MIXED, 0), (L.FP64, 0), (L.FP64, 1)):
+        S = L.Solver(mesh, precision=prec, cfl=0.1, theta_exact=exact)
         S.set_state(Q0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -411,10 +411,12 @@ def sedov_leg(L):
         wall = time.perf_counter() - t0
         Q, t = S.get_state()
         l1 = float(np.abs(Q[:, 0, 0] - rho_e).sum() / np.abs(rho_e - 1.0).sum())
-        runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "steps": int(st.steps), "t": t,
+        runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "theta_exact": exact,
+                     "steps": int(st.steps), "t": t,
                      "wall_s": wall, "element_updates_per_s": n * st.steps / wall, "l1_rho_vs_similarity": l1,
                      "peak_x": float(abs(xc[np.argmax(Q[:, 0, 0])])), "rho_max": float(Q[:, 0, 0].max())})
-        log(f"[bench]   Sedov 1D ({n} cells), {runs[-1]['precision']}: {st.steps} steps in {wall:.2f} s; "
+        log(f"[bench]   Sedov 1D ({n} cells), {runs[-1]['precision']}{', exact factor' if exact else ''}: "
+            f"{st.steps} steps in {wall:.2f} s; "
             f"L1(rho) vs similarity solution {l1:.4f}, peak at |x| = {runs[-1]['peak_x']:.3f} (exact shock {ex.radius(T):.3f})")
     out["1d"] = {"n_elem": n, "dx": dx, "t_end": T, "exact_shock_x": ex.radius(T), "runs": runs}
     xy, tri = I.sedov_disk()
@@ -430,8 +432,8 @@ def sedov_leg(L):
     r = np.hypot(a.mean(axis=1)[:, 0], a.mean(axis=1)[:, 1])
     mesh = L.Mesh.tri(xy, tri)
     runs = []
-    for prec in (L.FP32_MIXED, L.FP64):
-        S = L.Solver(mesh, precision=prec)
+    for prec, exact in ((L.FP32_MIXED, 0), (L.FP64, 0), (L.FP32_MIXED, 1)):
+        S = L.Solver(mesh, precision=prec, theta_exact=exact)
         S.set_state(Q0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -440,10 +442,12 @@ def sedov_leg(L):
         Q, t = S.get_state()
         rho = Q[:, 0, 0]
         l1 = float(np.sum(np.abs(rho - rho_e) * area) / np.sum(np.abs(rho_e - 1.0) * area))
-        runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "steps": int(st.steps), "t": t,
+        runs.append({"precision": "FP32_MIXED" if prec == L.FP32_MIXED else "FP64", "theta_exact": exact,
+                     "steps": int(st.steps), "t": t,
                      "wall_s": wall, "element_updates_per_s": len(tri) * st.steps / wall, "l1_rho_vs_similarity": l1,
                      "peak_r": float(r[np.argmax(rho)]), "rho_max": float(rho.max())})
-        log(f"[bench]   Sedov 2D ({len(tri)} triangles), {runs[-1]['precision']}: {st.steps} steps in {wall:.2f} s "
+        log(f"[bench]   Sedov 2D ({len(tri)} triangles), {runs[-1]['precision']}{', exact factor' if exact else ''}: "
+            f"{st.steps} steps in {wall:.2f} s "
             f"({runs[-1]['element_updates_per_s']:.3e} element-updates/s); L1(rho) vs similarity solution {l1:.4f}, "
             f"peak {rho.max():.3f} at r = {runs[-1]['peak_r']:.4f} (exact shock {ex.radius(T2):.4f})")
     out["2d_disk"] = {"n_elem": len(tri), "t_end": T2, "exact_shock_r": ex.radius(T2), "runs": runs}
@@ -504,6 +508,7 @@ def main():
     ap.add_argument("--no-equal-l1", action="store_true", help="skip the equal-L1 comparison on the vortex")
     ap.add_argument("--no-diffraction", action="store_true", help="skip the shock-diffraction runs")
     ap.add_argument("--no-sedov", action="store_true", help="skip the Sedov blast runs")
+    ap.add_argument("--no-exact-theta", action="store_true", help="skip the exact moment-limiter factor leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -595,6 +600,17 @@ def main():
         out["mixed_vs_fp64"] = {"speedup": value / v64, "rel_l1_state_diff": rel,
                                 "note": f"states after {args.warmup + 2 * args.steps} steps from the same input"}
         log(f"[bench]   FP64 {v64:.4e} element-updates/s; mixed/FP64 {value / v64:.2f}x; rel L1 diff {rel:.2e}")
+
+    if not args.no_exact_theta:
+        # the moment limiter with the exact pressure factor, on the same workload
+        ms_p, kt_p, Qp, _ = time_steps(L, mesh, Q0, args.steps, args.warmup)
+        ms_e, kt_e, Qe, _ = time_steps(L, mesh, Q0, args.steps, args.warmup, kw={"theta_exact": 1})
+        out["exact_theta"] = {"ms_per_step": ms_e, "plain_ms_per_step": ms_p, "k_pre_ms": kt_e.get("k_pre"),
+                              "plain_k_pre_ms": kt_p.get("k_pre"), "rel_l1_vs_plain": rel_l1(Qe, Qp),
+                              "note": f"FP32-mixed, states after {args.warmup + 2 * args.steps} steps"}
+        log(f"[bench] exact moment-limiter factor: {ms_e:.3f} ms/step (plain {ms_p:.3f}), k_pre "
+            f"{kt_e.get('k_pre', 0) * 1e3:.1f} us (plain {kt_p.get('k_pre', 0) * 1e3:.1f}); rel L1 vs plain "
+            f"{out['exact_theta']['rel_l1_vs_plain']:.2e}")
 
     if not args.no_batched:
         out["batched"] = batched_leg(L, args.steps, args.warmup)

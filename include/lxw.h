@@ -93,10 +93,15 @@ typedef struct lxw_params {
   int32_t shock;     /* LXW_SHOCK_OFF or LXW_SHOCK_PLAIN */
   double inflow[4];  /* inflow state for LXW_BC_INFLOW edges: (rho, Mx, My, E); 1D uses
                         (rho, Mx, -, E) */
+  int32_t theta_exact; /* 0: the moment limiter's pressure factor by the concavity bound of
+                        Sec. 3.1 (the paper's method); 1: by the exact root of the quadratic
+                        rho p = (gamma-1)(a theta^2 + b theta + c) of Sec. 3.1 (the optimal factor the
+                        paper mentions), moved inside by a relative 1e-10 and checked in float64,
+                        never below the concavity value */
 } lxw_params;
 
 /* Fills p with the paper's defaults: gamma 1.4, degree 2, CFL 0.08, eps0 1e-12, alpha0 500,
- * FP64, plain shock limiter, inflow (1, 0, 0, 2.5). */
+ * FP64, plain shock limiter, inflow (1, 0, 0, 2.5), concavity bound (theta_exact 0). */
 lxw_status lxw_params_default(lxw_params* p);
 
 /* Message of the last failure on this thread (never null; empty when none). */

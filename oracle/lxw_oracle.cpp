@@ -486,6 +486,7 @@ struct Params {
   int shock = 1;
   double inflow[4] = {1, 0, 0, 1};
   double force_theta = -1.0;  // test hook: when >= 0, every Lambda_e is replaced by this value
+  int exact_theta = 0;        // moment limiter Step 2 by the exact root instead of concavity
 };
 
 enum Status { OK = 0, ERR_ARG = -1, ERR_STATE = -4, ERR_POSITIVITY = -5, ERR_NONFINITE = -6, ERR_CFL = -7 };
@@ -580,6 +581,44 @@ static std::vector<std::vector<double>> limiter_points(const RefElem& R) {
 //  Step 2 reading: pressure target eps_p = min(eps0, p_bar); by concavity of p in theta,
 //  theta_m = theta^rho if p(q_bar + theta^rho q~_m) >= eps_p, otherwise
 //  theta^rho (p_bar - eps_p)/(p_bar - p(q_bar + theta^rho q~_m)); theta = min_m theta_m.
+//  Exact variant (the paper notes the optimal theta could be computed at the cost of more
+//  arithmetic): along the segment q(s) = q_bar + s D, D = q(theta^rho) - q_bar, the function
+//  g(s) = rho (p - eps_p) = (gamma-1)(E rho - |M|^2/2) - eps_p rho is the quadratic A s^2 + B s + C,
+//    A = (gamma-1)(D_E D_rho - |D_M|^2/2),
+//    B = (gamma-1)(D_E rho_bar + E_bar D_rho - D_M . M_bar) - eps_p D_rho,
+//    C = (gamma-1)(E_bar rho_bar - |M_bar|^2/2) - eps_p rho_bar,
+//  (the paper's a_m, b_m and c of the quadratic in theta, shifted by the target eps_p) is
+//  non-negative at s = 0 and negative at s = 1; its root in (0, 1) is taken in the
+//  cancellation-free form s* = 2C / (-B + sqrt(B^2 - 4AC)) (s* = 0 when C <= 0) and moved inside
+//  by a relative 1e-10, so that p(q(s)) >= eps_p holds in floating point with a margin; where
+//  that check still fails the concavity value is kept.  theta_m = theta^rho max(s_c, s).
+static double exact_segment_root(int dim, double gam, const double* qbar, const double* qt, double eps_p,
+                                 double s_c) {
+  const int V = dim + 2;
+  double D[4];
+  for (int v = 0; v < V; ++v) D[v] = qt[v] - qbar[v];
+  const double gm1 = gam - 1.0;
+  double dMdM = 0.0, dMM = 0.0, MM = 0.0;
+  for (int d = 0; d < dim; ++d) {
+    dMdM += D[1 + d] * D[1 + d];
+    dMM += D[1 + d] * qbar[1 + d];
+    MM += qbar[1 + d] * qbar[1 + d];
+  }
+  const double A = gm1 * (D[V - 1] * D[0] - 0.5 * dMdM);
+  const double B = gm1 * (D[V - 1] * qbar[0] + qbar[V - 1] * D[0] - dMM) - eps_p * D[0];
+  const double C = gm1 * (qbar[V - 1] * qbar[0] - 0.5 * MM) - eps_p * qbar[0];
+  double sr = 0.0;
+  if (C > 0.0) {
+    const double den = -B + std::sqrt(std::max(B * B - 4.0 * A * C, 0.0));
+    sr = den > 0.0 ? 2.0 * C / den : 1.0;
+  }
+  sr = std::min(sr, 1.0) * (1.0 - 1e-10);
+  double q[4];
+  for (int v = 0; v < V; ++v) q[v] = qbar[v] + sr * D[v];
+  if (!(q[0] > 0.0) || !(pressure(dim, gam, q) >= eps_p)) return s_c;
+  return std::max(s_c, sr);
+}
+
 static double moment_limit(const Mesh& M, const Params& P, double* Qi) {
   const RefElem& R = M.R;
   int V = NVAR(M), ML = R.ML, dim = R.dim;
@@ -612,7 +651,10 @@ static double moment_limit(const Mesh& M, const Params& P, double* Qi) {
       for (int v = 0; v < V; ++v) qt[v] = qbar[v] + th_rho * d[v];
       double pt = pressure(dim, P.gamma, qt);
       double thm = th_rho;
-      if (pt < eps_p) thm = th_rho * (pbar - eps_p) / (pbar - pt);
+      if (pt < eps_p) {
+        const double s_c = (pbar - eps_p) / (pbar - pt);
+        thm = P.exact_theta ? th_rho * exact_segment_root(dim, P.gamma, qbar, qt, eps_p, s_c) : th_rho * s_c;
+      }
       theta = std::min(theta, thm);
     }
   }
@@ -1159,6 +1201,7 @@ void* ora_solver_new(void* m, double gamma, double cfl, double eps0, double alph
 }
 void ora_solver_free(void* s) { delete (Solver*)s; }
 void ora_force_theta(void* s, double th) { ((Solver*)s)->P.force_theta = th; }
+void ora_set_exact_theta(void* s, int on) { ((Solver*)s)->P.exact_theta = on; }
 void ora_set_shock_mask(void* s, const unsigned char* mask) {
   Solver* S = (Solver*)s;
   if (mask) S->shock_mask.assign(mask, mask + S->M->N);

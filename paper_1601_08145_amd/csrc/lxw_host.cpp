@@ -595,6 +595,7 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   v.eps0 = S->P.eps0;
   for (int c = 0; c < 4; ++c) v.inflow[c] = S->P.inflow[c];
   v.shock = S->P.shock;
+  v.theta_exact = S->P.theta_exact;
   return LXW_OK;
 }
 
@@ -865,6 +866,7 @@ lxw_status check_params(const lxw_params* p) {
     return fail(LXW_ERR_ARG, "need gamma > 1, 0 < cfl <= 1, eps0 > 0, alpha0 >= 0");
   if (p->precision != LXW_FP64 && p->precision != LXW_FP32_MIXED) return fail(LXW_ERR_ARG, "bad precision");
   if (p->shock != LXW_SHOCK_OFF && p->shock != LXW_SHOCK_PLAIN) return fail(LXW_ERR_UNSUPPORTED, "bad shock-limiter mode");
+  if (p->theta_exact != 0 && p->theta_exact != 1) return fail(LXW_ERR_ARG, "theta_exact must be 0 or 1");
   return LXW_OK;
 }
 
@@ -1119,6 +1121,7 @@ lxw_status lxw_params_default(lxw_params* p) {
   p->alpha0 = 500.0;
   p->precision = LXW_FP64;
   p->shock = LXW_SHOCK_PLAIN;
+  p->theta_exact = 0;
   p->inflow[0] = 1.0; p->inflow[1] = 0.0; p->inflow[2] = 0.0; p->inflow[3] = 2.5;
   return LXW_OK;
 }

@@ -110,6 +110,7 @@ struct View {
   double gamma, eps0;
   double inflow[4];
   int shock;
+  int theta_exact;        // moment limiter Step 2 by the exact root (k_pre mode 3) instead of concavity
   // diagnostics (null unless requested)
   double* dbg_theta;      // [N]
   double* dbg_theta_sc;   // [N]

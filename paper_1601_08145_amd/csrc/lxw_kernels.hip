@@ -280,13 +280,54 @@ __device__ __forceinline__ double point_dev(const RefTab<E, double>& T, const R 
   return acc;
 }
 
+// Exact variant of the moment limiter's pressure step (Sec. 3.1; the paper notes the optimal factor
+// could be computed at the cost of more arithmetic).  Along the segment q(s) = qb + s D from the
+// average to the point state at the density factor, D = q - qb, g(s) = rho (p - eps_p) =
+// (gamma-1)(E rho - |M|^2/2) - eps_p rho is the quadratic A s^2 + B s + C (the paper's a_m, b_m, c
+// shifted by the target eps_p), with g(0) >= 0 > g(1).  Its root in (0, 1) in the cancellation-free
+// form 2C / (-B + sqrt(B^2 - 4AC)) (0 when C <= 0), moved inside by a relative 1e-10 and accepted
+// only where p(q(s)) >= eps_p then holds in float64; the result is never below the concavity
+// value s_c.
+template <int DIM>
+__device__ __noinline__ double exact_segment(const double* qb, const double* q, double epsp, double gam, double s_c) {
+  constexpr int V = DIM + 2;
+  double D[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) D[c] = q[c] - qb[c];
+  const double gm1 = gam - 1.0;
+  double dMdM = 0.0, dMM = 0.0, MM = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    dMdM += D[1 + d] * D[1 + d];
+    dMM += D[1 + d] * qb[1 + d];
+    MM += qb[1 + d] * qb[1 + d];
+  }
+  const double A = gm1 * (D[V - 1] * D[0] - 0.5 * dMdM);
+  const double B = gm1 * (D[V - 1] * qb[0] + qb[V - 1] * D[0] - dMM) - epsp * D[0];
+  const double C = gm1 * (qb[V - 1] * qb[0] - 0.5 * MM) - epsp * qb[0];
+  double sr = 0.0;
+  if (C > 0.0) {
+    const double den = -B + sqrt(fmax(B * B - 4.0 * A * C, 0.0));
+    sr = den > 0.0 ? 2.0 * C / den : 1.0;
+  }
+  sr = fmin(sr, 1.0) * (1.0 - 1e-10);
+  double qs[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) qs[c] = qb[c] + sr * D[c];
+  if (!(qs[0] > 0.0) || !(pressure<DIM>(qs, gam) >= epsp)) return s_c;
+  return fmax(s_c, sr);
+}
+
 // The mode is a template argument: each mode's kernel holds only its own path, so the read-out and
-// collection paths do not raise the register allocation of the per-step kernel.
+// collection paths do not raise the register allocation of the per-step kernel.  Modes: 0 step,
+// 1 read-out (pending shock-capturing limiter applied), 2 collection (its factor recorded), 3 step
+// with the exact pressure factor of the moment limiter.
 template <class E, class R, int mode>
 __global__ __launch_bounds__(256) void k_pre(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
+  constexpr bool kStep = mode == 0 || mode == 3;
   // a single mesh at its end time: the step changes nothing (every lane leaves together)
-  if (mode == 0 && !v.mesh_of && !(v.sc[0].t < v.sc[0].T)) return;
+  if (kStep && !v.mesh_of && !(v.sc[0].t < v.sc[0].T)) return;
   const RefTab<E, double>& T = TabSel<E, double>::get();
   const int N = v.N;
   const int i = xcd_item();
@@ -309,7 +350,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
     bool finite = true;
 #pragma unroll
     for (int c = 0; c < V; ++c) finite = finite && isfinite(qb[c]);
-    if (mode == 0) {
+    if (kStep) {
       if (!finite) report(v.err, E_NONFINITE, i);
       else if (!(qb[0] > 0.0) || !(pb > 0.0)) report(v.err, E_POSITIVITY, i);
     }
@@ -327,7 +368,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
     bool have_rmin = false;
     const bool detect = mode == 2 || !v.ind_flag || at(v.ind_flag, i) != 0;
     const bool shock_on = v.shock && v.sc[mid].shock_pending && ok && detect;
-    if (shock_on || (mode == 0 && ok)) {
+    if (shock_on || (kStep && ok)) {
       have_rmin = true;
       double wb[V], Mx[V], Mn[V];
       wb[0] = qb[0];
@@ -458,7 +499,10 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
 #pragma unroll
           for (int c = 0; c < V; ++c) q[c] = qb[c] + ts * point_dev<E, R>(T, Qh, p, c);
           const double pt = pressure_r<DIM>(q, 1.0 / q[0], gam);
-          if (pt < epsp) th = fmin(th, thr * (pb - epsp) / (pb - pt));
+          if (pt < epsp) {
+            if (mode == 3) th = fmin(th, thr * exact_segment<DIM>(qb, q, epsp, gam, (pb - epsp) / (pb - pt)));
+            else th = fmin(th, thr * (pb - epsp) / (pb - pt));
+          }
           if (fused) smax1 = fmax(smax1, speed_r<DIM>(q, gam));
         }
       }
@@ -494,7 +538,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
       }
     }
   }
-  if (mode == 0) {
+  if (kStep) {
     if (v.mesh_of) {
       atomic_max_per_mesh(v.sc, mid, smax, valid);
     } else {
@@ -1220,7 +1264,10 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
   if (tunable(k == K_SHOCK ? K_PRE : k) && bs != 64 && bs != 128 && bs != 256) return hipErrorInvalidConfiguration;
   switch (k) {
     case K_PRE:
-      if (v.N > 0) hipLaunchKernelGGL((k_pre<E, R, 0>), egrid(v.N, bs), dim3(bs), 0, st, v);
+      if (v.N > 0) {
+        if (v.theta_exact) hipLaunchKernelGGL((k_pre<E, R, 3>), egrid(v.N, bs), dim3(bs), 0, st, v);
+        else hipLaunchKernelGGL((k_pre<E, R, 0>), egrid(v.N, bs), dim3(bs), 0, st, v);
+      }
       break;
     case K_SHOCK:
       if (mode != 1 && mode != 2) return hipErrorInvalidValue;

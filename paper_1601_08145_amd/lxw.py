@@ -42,7 +42,7 @@ class LxwError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("degree", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("eps0", ctypes.c_double), ("alpha0", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("shock", ctypes.c_int32), ("inflow", ctypes.c_double * 4)]
+                ("shock", ctypes.c_int32), ("inflow", ctypes.c_double * 4), ("theta_exact", ctypes.c_int32)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -155,8 +155,10 @@ def default_params(**kw):
         if k == "inflow":
             for c in range(4):
                 p.inflow[c] = float(v[c])
-        else:
+        elif k in dict(Params._fields_):
             setattr(p, k, v)
+        else:
+            raise TypeError(f"unknown solver parameter {k!r}")
     return p
 
 

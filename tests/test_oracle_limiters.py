@@ -77,6 +77,64 @@ def test_moment_limiter_density_theta_is_maximal():
     assert checked > 30
 
 
+def _pressure_root_brute(qbar, D, eps_p, n=4001):
+    """Largest s in [0, 1] with p(qbar + s' D) >= eps_p for every s' in [0, s], by dense sampling
+    refined by bisection (pure numpy, no quadratic formula)."""
+    s = np.linspace(0.0, 1.0, n)
+    p = H.pressure(qbar[None, :] + s[:, None] * D[None, :])
+    bad = np.nonzero(~(p >= eps_p))[0]
+    if len(bad) == 0:
+        return 1.0
+    lo, hi = s[bad[0] - 1], s[bad[0]]
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        if H.pressure(qbar + mid * D) >= eps_p:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+@pytest.mark.parametrize("kind", [O.LINE, O.QUAD, O.TRI])
+def test_moment_limiter_exact_theta(kind):
+    """The exact variant of Step 2: for every cell theta is the largest factor that keeps the
+    pressure at or above eps_p = min(eps0, p_bar) at every limiter point (found here by sampling and
+    bisection along each point's segment, to 1e-8), it never limits more than the concavity form,
+    the density step and the averages are unchanged, and every point keeps p >= eps_p."""
+    R = O.RefElem(kind)
+    mesh = {O.LINE: lambda: O.Mesh.line(4, 0, 1, 1, 1), O.QUAD: lambda: O.Mesh.cart(2, 2, 0, 1, 0, 1, [1] * 4),
+            O.TRI: lambda: O.Mesh.tri(*I.lattice_delaunay(3, 0))}[kind]()
+    Sp = O.Solver(mesh)
+    Se = O.Solver(mesh, exact_theta=True)
+    pts = limiter_pts(R)
+    Q = I.random_modal_state(300, R.dim, R.ML, seed=12, amp=0.3, rough_frac=0.5, rough_amp=3.0, p_range=(1e-6, 1.0))
+    n_gain = n_p = 0
+    for Qi in Q:
+        th_p, _ = Sp.moment_limit(Qi)
+        th_e, Ql = Se.moment_limit(Qi)
+        assert th_e >= th_p and np.array_equal(Ql[:, 0], Qi[:, 0])
+        qbar = Qi[:, 0]
+        pbar = H.pressure(qbar)
+        if not (qbar[0] >= 1e-12 and pbar > 0):
+            assert th_e == 0.0
+            continue
+        eps_p = min(1e-12, pbar)
+        q = eval_at(R, Qi, pts)
+        dev = q - qbar[None, :]
+        th_rho = min([1.0] + [(qbar[0] - 1e-12) / (-d) for d in dev[:, 0] if qbar[0] + d < 1e-12])
+        th_true = th_rho
+        for d in dev:
+            qt = qbar + th_rho * d
+            if H.pressure(qt) < eps_p:
+                th_true = min(th_true, th_rho * _pressure_root_brute(qbar, qt - qbar, eps_p))
+                n_p += 1
+        assert th_e == pytest.approx(th_true, rel=1e-8, abs=1e-12)
+        ql = eval_at(R, Ql, pts)
+        assert np.all(H.pressure(ql) >= eps_p * (1 - 1e-9) - 1e-15)
+        n_gain += th_e > th_p * (1 + 1e-6)
+    assert n_p > 20 and n_gain > 10
+
+
 def _step(mesh, Q, **kw):
     S = O.Solver(mesh, **kw)
     S.set_state(Q)

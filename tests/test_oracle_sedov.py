@@ -31,10 +31,10 @@ def test_similarity_solution_constants():
     assert Sedov(2, E=0.979264).radius(1.0) == pytest.approx(1.0, abs=2e-3)
 
 
-def sedov_1d_run(dx, T=1e-3):
+def sedov_1d_run(dx, T=1e-3, exact_theta=False):
     n, x0, x1, Q0 = I.sedov_1d(dx)
     M = O.Mesh.line(n, x0, x1, O.BC_TRANSPARENT, O.BC_TRANSPARENT)
-    S = O.Solver(M, cfl=0.1)
+    S = O.Solver(M, cfl=0.1, exact_theta=exact_theta)
     S.set_state(Q0)
     S.advance(T)
     Q, t = S.get_state()
@@ -87,3 +87,18 @@ def test_sedov_disk_input():
     assert 1 <= hot.sum() <= 10 and np.all(Q[~hot, 3, 0] == 1e-12) and np.all(Q[:, 0, 0] == 1.0)
     assert np.sum((Q[:, 3, 0] - 1e-12) * 0.5 * cross) == pytest.approx(0.979264, rel=1e-12)
 
+
+
+def test_sedov_1d_exact_theta():
+    """The same blast with the moment limiter's exact pressure factor: positive, energy conserved,
+    and as close to the similarity solution as the concavity form (within 10% of its L1 error)."""
+    ex = Sedov(1, E=3.2e6)
+    T, dx = 1e-3, 0.01
+    out = []
+    for exact in (False, True):
+        n, x0, Q0, Q, t = sedov_1d_run(dx, T, exact_theta=exact)
+        assert np.all(Q[:, 0, 0] > 0) and np.all(H.pressure(Q[:, :, 0]) > 0)
+        assert abs(Q[:, 2, 0].sum() - Q0[:, 2, 0].sum()) <= 1e-12 * Q0[:, 2, 0].sum()
+        xc, rho_e = cell_avg_exact_1d(ex, x0, n, dx, T)
+        out.append(np.abs(Q[:, 0, 0] - rho_e).sum() / np.abs(rho_e - 1.0).sum())
+    assert abs(out[1] - out[0]) <= 0.1 * out[0], out
