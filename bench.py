@@ -57,9 +57,9 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "5b4038ed3be1453f824d657b334f6cc85c7398c0b8c98169639e23ad2e372280",
-           "bytes_per_launch": {"k_pre": 139128012, "k_elem": 685711155, "k_edge": 525942784,
-                                "k_flim": 173576089, "k_update": 459812864}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "cf3eaf1c77aaa74d9e540cce62677bac07531904c970955695ad830e233ca2a5",
+           "bytes_per_launch": {"k_pre": 139132313, "k_elem": 684642304, "k_edge": 525920256,
+                                "k_flim": 173594316, "k_update": 460254208}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
