@@ -792,6 +792,10 @@ static double mu_solve(int dim, double gam, double eps_p, const double* qL, cons
   double b = (gam - 1.0) * (qL[0] * d[iE] + d[0] * qL[iE] - mLd) - eps_p * d[0];
   double c = (gam - 1.0) * (qL[0] * qL[iE] - 0.5 * mL2) - eps_p * qL[0];
   if (!(c > 0.0)) return 0.0;
+  // The target is the LxF corner's own pressure (p(q^LxF) <= eps0): c vanishes in exact
+  // arithmetic, g(mu) = mu (a mu + b), and with b <= 0 no mu > 0 keeps p >= eps_p; c > 0 here
+  // is rounding, and the ulp search below would only end at 0.
+  if (b <= 0.0 && pressure(dim, gam, qL) <= eps_p) return 0.0;
   double disc = std::max(0.0, b * b - 4.0 * a * c);
   double den = -b + std::sqrt(disc);
   double mu = (den > 0.0) ? 2.0 * c / den : 0.0;

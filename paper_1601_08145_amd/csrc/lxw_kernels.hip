@@ -1072,6 +1072,9 @@ __device__ double mu_solve(const double* qL, const double* qa, double gam, doubl
   const double b = g1 * (qL[0] * dq[V - 1] + dq[0] * qL[V - 1] - mLd) - epsp * dq[0];
   const double c = g1 * (qL[0] * qL[V - 1] - 0.5 * mL2) - epsp * qL[0];
   if (!(c > 0.0)) return 0.0;
+  // target equal to the LxF corner's own pressure (p(q^LxF) <= eps0): c is zero up to rounding,
+  // g(mu) = mu (a mu + b), and with b <= 0 only mu = 0 is feasible (the ulp search would end there)
+  if (b <= 0.0 && pressure<DIM>(qL, gam) <= epsp) return 0.0;
   const double den = -b + sqrt(fmax(0.0, b * b - 4.0 * a * c));
   double mu = den > 0.0 ? 2.0 * c / den : 0.0;
   mu = fmin(1.0, fmax(0.0, mu));
