@@ -169,3 +169,32 @@ def test_mu_solve_is_the_largest_positive_fraction():
                 lo, hi = (mid, hi) if ok(mid) else (lo, mid)
             assert mu == pytest.approx(lo, abs=1e-12)
     assert n_lim > 20
+
+
+def test_mu_solve_target_at_the_lxf_pressure():
+    """Near vacuum the target is the LxF corner's own pressure (p(q^LxF) <= eps0): the quadratic's
+    constant term vanishes, and where the pressure falls along the segment no fraction above 0
+    keeps it (every sampled mu > 0 fails), so mu = 0; where it rises, mu is positive and keeps it."""
+    rng = np.random.default_rng(6)
+    n_fall = n_rise = 0
+    for _ in range(200):
+        rho = rng.uniform(1e-4, 1e-2)
+        u = rng.normal(size=2)
+        pL = rng.uniform(1e-14, 1e-12)
+        qL = np.array([rho, rho * u[0], rho * u[1], pL / (G - 1) + 0.5 * rho * (u @ u)])
+        qa = qL + rng.normal(size=4) * np.array([0.3 * rho, rho, rho, 1e-12])
+        eps_p = min(1e-12, (G - 1) * (qL[3] - 0.5 * (qL[1] ** 2 + qL[2] ** 2) / qL[0]))
+        mu = O.mu_solve(qL, qa, eps_p)
+
+        def p_at(m):
+            q = qL + m * (qa - qL)
+            return (G - 1) * (q[3] - 0.5 * (q[1] ** 2 + q[2] ** 2) / q[0]) if q[0] > 0 else -np.inf
+
+        small = [p_at(m) for m in (1e-9, 1e-6, 1e-3)]
+        if all(p < eps_p for p in small):
+            assert mu == 0.0
+            n_fall += 1
+        elif mu > 0.0:
+            assert p_at(mu) >= eps_p
+            n_rise += 1
+    assert n_fall > 20 and n_rise > 20
