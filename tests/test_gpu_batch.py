@@ -227,6 +227,32 @@ def test_batch_of_cartesian_meshes(L):
         assert tb == ts and np.array_equal(Qb, Qs)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_masked_meshes_exact_theta(L, prec):
+    """Masked Cartesian meshes (the block step's solid at two resolutions, and a box with a
+    removed block and periodic sides) with the exact moment-limiter factor advance together
+    exactly as they do alone."""
+    nx, ny, box, bc, keep, Q0, inflow = I.diffraction_cart(52, 44)
+    keep2 = np.ones((20, 26), bool)
+    keep2[6:12, 8:14] = False
+    Q2 = I.random_modal_state(int(keep2.sum()), 2, 9, seed=9, amp=0.3, rough_frac=0.2, rough_amp=3.0,
+                              p_range=(1e-4, 1))
+    specs = [(L.Mesh.cart(nx, ny, *box, bc, keep=keep), Q0),
+             (L.Mesh.cart(26, 20, 0, 2.6, 0, 2.0, [0, 0, 0, 0], keep=keep2), Q2)]
+    kw = dict(precision=prec, theta_exact=1, inflow=list(inflow))
+    B = L.Batch([m for m, _ in specs], **kw)
+    for b, (_, Q) in enumerate(specs):
+        B.set_state(b, Q)
+    B.advance_steps(8)
+    for b, (m, Q) in enumerate(specs):
+        S = L.Solver(m, **kw)
+        S.set_state(Q)
+        S.run_steps(8)
+        Qs, ts = S.get_state()
+        Qb, tb = B.get_state(b)
+        assert tb == ts and np.array_equal(Qb, Qs), (b, np.abs(Qb - Qs).max())
+
+
 def test_batch_with_learned_indicator(L):
     """The learned indicator on a batch of triangle meshes: the same decisions and the same states
     as each mesh's own solver with that indicator, bit for bit; the batch's decision flags follow
