@@ -74,6 +74,9 @@ enum {
 /* Shock-capturing limiter modes. */
 enum { LXW_SHOCK_OFF = 0, LXW_SHOCK_PLAIN = 1 };
 
+/* Where the global wave speed s is measured (lxw_params.wave_speed). */
+enum { LXW_SPEED_POINTS = 0, LXW_SPEED_AVERAGES = 1 };
+
 /* State transfer flags. */
 enum { LXW_HOST_PTR = 0, LXW_DEVICE_PTR = 1 };
 
@@ -98,10 +101,16 @@ typedef struct lxw_params {
                         rho p = (gamma-1)(a theta^2 + b theta + c) of Sec. 3.1 (the optimal factor the
                         paper mentions), moved inside by a relative 1e-10 and checked in float64,
                         never below the concavity value */
+  int32_t wave_speed;  /* the global wave speed s (Sec. 4.1: an estimate of the largest speed):
+                        LXW_SPEED_POINTS (default) the largest |u| + c over the cell averages and
+                        every limited point; LXW_SPEED_AVERAGES over the cell averages only (the
+                        speeds the Lax-Friedrichs fluxes of the positivity argument need; near
+                        vacuum the limited points' speeds can exceed them a hundredfold) */
 } lxw_params;
 
 /* Fills p with the paper's defaults: gamma 1.4, degree 2, CFL 0.08, eps0 1e-12, alpha0 500,
- * FP64, plain shock limiter, inflow (1, 0, 0, 2.5), concavity bound (theta_exact 0). */
+ * FP64, plain shock limiter, inflow (1, 0, 0, 2.5), concavity bound (theta_exact 0), wave speed
+ * over the limited points (LXW_SPEED_POINTS). */
 lxw_status lxw_params_default(lxw_params* p);
 
 /* Message of the last failure on this thread (never null; empty when none). */

@@ -62,6 +62,7 @@ def lib():
             "ora_solver_free": (None, [P]),
             "ora_force_theta": (None, [P, d]),
             "ora_set_exact_theta": (None, [P, i]),
+            "ora_set_s_avg": (None, [P, i]),
             "ora_set_shock_mask": (None, [P, P]),
             "ora_set_state": (None, [P, dp, d]),
             "ora_get_state": (None, [P, dp, dp]),
@@ -196,13 +197,15 @@ class OracleError(RuntimeError):
 
 class Solver:
     def __init__(self, mesh, gamma=1.4, cfl=0.08, eps0=1e-12, alpha0=500.0, shock=True, inflow=None,
-                 exact_theta=False):
+                 exact_theta=False, s_from_averages=False):
         self.mesh = mesh
         inf = f64(inflow) if inflow is not None else None
         self.h = lib().ora_solver_new(mesh.h, gamma, cfl, eps0, alpha0, int(bool(shock)),
                                       _d(inf) if inf is not None else None)
         if exact_theta:
             lib().ora_set_exact_theta(self.h, 1)
+        if s_from_averages:
+            lib().ora_set_s_avg(self.h, 1)
         self.gamma = gamma
 
     def __del__(self):

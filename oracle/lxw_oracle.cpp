@@ -487,6 +487,7 @@ struct Params {
   double inflow[4] = {1, 0, 0, 1};
   double force_theta = -1.0;  // test hook: when >= 0, every Lambda_e is replaced by this value
   int exact_theta = 0;        // moment limiter Step 2 by the exact root instead of concavity
+  int s_avg = 0;              // global wave speed from the cell averages only
 };
 
 enum Status { OK = 0, ERR_ARG = -1, ERR_STATE = -4, ERR_POSITIVITY = -5, ERR_NONFINITE = -6, ERR_CFL = -7 };
@@ -844,7 +845,9 @@ static int step(Solver& S, double T) {
   S.Qlim = S.Q;
 
   // ---- Global wave speed s and the time step (reading of Sec. 4.1: CFL 0.08 means
-  //      dt * s * max_i |dT_i| / (2|T_i|) = CFL; the last step is clipped to reach T) -----------
+  //      dt * s * max_i |dT_i| / (2|T_i|) = CFL; the last step is clipped to reach T).  s is the
+  //      largest |u| + c over the cell averages and every limited point, or over the cell
+  //      averages only when s_avg is set -------------------------------------------------------
   auto pts = limiter_points(R);
   double s = 0.0, geo = 0.0;
 #pragma omp parallel for reduction(max : s, geo) schedule(static)
@@ -853,7 +856,7 @@ static int step(Solver& S, double T) {
     double qbar[4] = {0.0, 0.0, 0.0, 0.0};
     for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML];
     double si = wave_speed(dim, gam, qbar);
-    for (auto& x : pts) {
+    if (!S.P.s_avg) for (auto& x : pts) {
       double q[4];
       eval_q(M, Qi, x.data(), q);
       si = std::max(si, wave_speed(dim, gam, q));
@@ -1206,6 +1209,7 @@ void* ora_solver_new(void* m, double gamma, double cfl, double eps0, double alph
 void ora_solver_free(void* s) { delete (Solver*)s; }
 void ora_force_theta(void* s, double th) { ((Solver*)s)->P.force_theta = th; }
 void ora_set_exact_theta(void* s, int on) { ((Solver*)s)->P.exact_theta = on; }
+void ora_set_s_avg(void* s, int on) { ((Solver*)s)->P.s_avg = on; }
 void ora_set_shock_mask(void* s, const unsigned char* mask) {
   Solver* S = (Solver*)s;
   if (mask) S->shock_mask.assign(mask, mask + S->M->N);

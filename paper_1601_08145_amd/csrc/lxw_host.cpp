@@ -596,6 +596,7 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   for (int c = 0; c < 4; ++c) v.inflow[c] = S->P.inflow[c];
   v.shock = S->P.shock;
   v.theta_exact = S->P.theta_exact;
+  v.s_avg = S->P.wave_speed;
   return LXW_OK;
 }
 
@@ -867,6 +868,8 @@ lxw_status check_params(const lxw_params* p) {
   if (p->precision != LXW_FP64 && p->precision != LXW_FP32_MIXED) return fail(LXW_ERR_ARG, "bad precision");
   if (p->shock != LXW_SHOCK_OFF && p->shock != LXW_SHOCK_PLAIN) return fail(LXW_ERR_UNSUPPORTED, "bad shock-limiter mode");
   if (p->theta_exact != 0 && p->theta_exact != 1) return fail(LXW_ERR_ARG, "theta_exact must be 0 or 1");
+  if (p->wave_speed != LXW_SPEED_POINTS && p->wave_speed != LXW_SPEED_AVERAGES)
+    return fail(LXW_ERR_ARG, "wave_speed must be LXW_SPEED_POINTS or LXW_SPEED_AVERAGES");
   return LXW_OK;
 }
 
@@ -1122,6 +1125,7 @@ lxw_status lxw_params_default(lxw_params* p) {
   p->precision = LXW_FP64;
   p->shock = LXW_SHOCK_PLAIN;
   p->theta_exact = 0;
+  p->wave_speed = LXW_SPEED_POINTS;
   p->inflow[0] = 1.0; p->inflow[1] = 0.0; p->inflow[2] = 0.0; p->inflow[3] = 2.5;
   return LXW_OK;
 }

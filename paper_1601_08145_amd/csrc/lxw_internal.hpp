@@ -110,7 +110,8 @@ struct View {
   double gamma, eps0;
   double inflow[4];
   int shock;
-  int theta_exact;        // moment limiter Step 2 by the exact root (k_pre mode 3) instead of concavity
+  int theta_exact;        // moment limiter Step 2 by the exact root (k_pre modes 3, 5) instead of concavity
+  int s_avg;              // global wave speed from the cell averages only (k_pre modes 4, 5)
   // diagnostics (null unless requested)
   double* dbg_theta;      // [N]
   double* dbg_theta_sc;   // [N]

@@ -321,11 +321,14 @@ __device__ __noinline__ double exact_segment(const double* qb, const double* q, 
 // The mode is a template argument: each mode's kernel holds only its own path, so the read-out and
 // collection paths do not raise the register allocation of the per-step kernel.  Modes: 0 step,
 // 1 read-out (pending shock-capturing limiter applied), 2 collection (its factor recorded), 3 step
-// with the exact pressure factor of the moment limiter.
+// with the exact pressure factor of the moment limiter, 4 step with the wave speed from the cell
+// averages only, 5 both.
 template <class E, class R, int mode>
 __global__ __launch_bounds__(256) void k_pre(View<R> v) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
-  constexpr bool kStep = mode == 0 || mode == 3;
+  constexpr bool kStep = mode == 0 || mode >= 3;
+  constexpr bool kExact = mode == 3 || mode == 5;  // exact pressure factor of the moment limiter
+  constexpr bool kSavg = mode >= 4;                // wave speed from the cell averages only
   // a single mesh at its end time: the step changes nothing (every lane leaves together)
   if (kStep && !v.mesh_of && !(v.sc[0].t < v.sc[0].T)) return;
   const RefTab<E, double>& T = TabSel<E, double>::get();
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
           for (int c = 0; c < V; ++c) q[c] = qb[c] + ts * point_dev<E, R>(T, Qh, p, c);
           const double pt = pressure_r<DIM>(q, 1.0 / q[0], gam);
           if (pt < epsp) {
-            if (mode == 3) th = fmin(th, thr * exact_segment<DIM>(qb, q, epsp, gam, (pb - epsp) / (pb - pt)));
+            if (kExact) th = fmin(th, thr * exact_segment<DIM>(qb, q, epsp, gam, (pb - epsp) / (pb - pt)));
             else th = fmin(th, thr * (pb - epsp) / (pb - pt));
           }
           if (fused) smax1 = fmax(smax1, speed_r<DIM>(q, gam));
@@ -510,7 +513,9 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
       at(v.theta, i) = tt;
       if (finite && qb[0] > 0.0 && pb > 0.0) {
         smax = speed_r<DIM>(qb, gam);
-        if (fused && tt == 1.0) {
+        if (kSavg) {
+          // the cell average's speed only
+        } else if (fused && tt == 1.0) {
           smax = fmax(smax, smax1);
         } else if (tt > 0.0) {
 #pragma unroll
@@ -1268,8 +1273,12 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
   switch (k) {
     case K_PRE:
       if (v.N > 0) {
-        if (v.theta_exact) hipLaunchKernelGGL((k_pre<E, R, 3>), egrid(v.N, bs), dim3(bs), 0, st, v);
-        else hipLaunchKernelGGL((k_pre<E, R, 0>), egrid(v.N, bs), dim3(bs), 0, st, v);
+        switch ((v.theta_exact ? 1 : 0) + (v.s_avg ? 2 : 0)) {
+          case 0: hipLaunchKernelGGL((k_pre<E, R, 0>), egrid(v.N, bs), dim3(bs), 0, st, v); break;
+          case 1: hipLaunchKernelGGL((k_pre<E, R, 3>), egrid(v.N, bs), dim3(bs), 0, st, v); break;
+          case 2: hipLaunchKernelGGL((k_pre<E, R, 4>), egrid(v.N, bs), dim3(bs), 0, st, v); break;
+          default: hipLaunchKernelGGL((k_pre<E, R, 5>), egrid(v.N, bs), dim3(bs), 0, st, v); break;
+        }
       }
       break;
     case K_SHOCK:

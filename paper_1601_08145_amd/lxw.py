@@ -21,6 +21,7 @@ ERRORS = {-1: "LXW_ERR_ARG", -2: "LXW_ERR_UNSUPPORTED", -3: "LXW_ERR_MESH", -4: 
           -5: "LXW_ERR_POSITIVITY", -6: "LXW_ERR_NONFINITE", -7: "LXW_ERR_CFL", -8: "LXW_ERR_DEVICE",
           -9: "LXW_ERR_OOM"}
 BC_PERIODIC, BC_TRANSPARENT, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
+SPEED_POINTS, SPEED_AVERAGES = 0, 1
 LINE, QUAD, TRI = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 SHOCK_OFF, SHOCK_PLAIN = 0, 1
@@ -42,7 +43,8 @@ class LxwError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("degree", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("eps0", ctypes.c_double), ("alpha0", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("shock", ctypes.c_int32), ("inflow", ctypes.c_double * 4), ("theta_exact", ctypes.c_int32)]
+                ("shock", ctypes.c_int32), ("inflow", ctypes.c_double * 4), ("theta_exact", ctypes.c_int32),
+                ("wave_speed", ctypes.c_int32)]
 
 
 class MeshInfo(ctypes.Structure):

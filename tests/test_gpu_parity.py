@@ -187,6 +187,37 @@ def test_exact_theta_stage_parity(L, name):
     assert np.array_equal(A.get_state()[0], B.get_state()[0])
 
 
+@pytest.mark.parametrize("name", ["line-walls", "quad-mixed", "tri-transparent", "tri-ramp"])
+def test_wave_speed_from_averages_stage_parity(L, name):
+    """The global wave speed over the cell averages only (solver parameter wave_speed): every
+    stage of six FP64 steps against the oracle's same option, alone and together with the exact
+    moment-limiter factor; s and dt are those of the averages, never above the default's."""
+    print(f"[gpu] averages-only wave speed stage parity {name}", flush=True)
+    lm, om, Q0, kw = make_case(L, name)
+    for exact in (0, 1):
+        S = L.Solver(lm, wave_speed=L.SPEED_AVERAGES, theta_exact=exact, **kw)
+        S.set_debug(True)
+        S.set_state(Q0)
+        Ob = O.Solver(om, inflow=kw.get("inflow"), exact_theta=bool(exact), s_from_averages=True)
+        Ob.set_state(Q0)
+        for k in range(6):
+            S.step()
+            Ob.step()
+            compare_stages(S, Ob, L, tol=TOL if not exact else 1e-9, s_tol=1e-11 if not exact else 1e-9)
+            Qg, tg = S.get_state()
+            Qo, to = Ob.get_state()
+            assert per_var_rel_l1(Qg, Qo) <= (TOL if not exact else 1e-9), (name, exact, k)
+    D = L.Solver(lm, **kw)
+    D.set_debug(True)
+    D.set_state(Q0)
+    D.step()
+    A = L.Solver(lm, wave_speed=L.SPEED_AVERAGES, **kw)
+    A.set_debug(True)
+    A.set_state(Q0)
+    A.step()
+    assert A.stage(L.STAGE_SDT)[0] <= D.stage(L.STAGE_SDT)[0]
+
+
 @pytest.mark.parametrize("name", ["line-walls", "quad-mixed", "quad-masked", "tri-ramp"])
 def test_fp64_multistep_without_readout(L, name):
     """Steps taken back to back (the shock-capturing limiter of each step is then applied at the

@@ -327,3 +327,32 @@ def test_masked_walls_conserve_mass_and_energy():
     for dj, di in ((-1, 0), (1, 0), (0, -1), (0, 1)):
         walled |= ~keep[(jj + dj) % ny, (ii + di) % nx]
     assert np.array_equal(changed[ids[keep.ravel()]], walled)
+
+
+@pytest.mark.parametrize("mesh_kind", ["line", "cart", "tri"])
+def test_wave_speed_from_averages(mesh_kind):
+    """With the wave speed taken over the cell averages only, s is the largest |u| + c of the
+    averages and dt = CFL / (s max_i |dT_i| / (2 |T_i|)) (|dT_i| = 2 in 1D, where the factor is
+    1/dx), recomputed here from the state and the mesh; and s never exceeds the default s, which
+    also takes the limited points."""
+    if mesh_kind == "cart":
+        M = O.Mesh.cart(12, 10, 0, 1.2, 0, 1, [O.BC_PERIODIC] * 4)
+    elif mesh_kind == "line":
+        M = O.Mesh.line(40, 0, 1, O.BC_TRANSPARENT, O.BC_TRANSPARENT)
+    else:
+        M = O.Mesh.tri(*I.lattice_delaunay(12, 5))
+    Q = I.random_modal_state(M.N, M.dim, M.ML, seed=4, amp=0.5, rough_frac=0.2, rough_amp=3.0, p_range=(1e-5, 1.0))
+    A = O.Solver(M, s_from_averages=True)
+    A.set_state(Q)
+    A.step()
+    s_a, dt_a = A.stage(O.STAGE_SDT)
+    q = Q[:, :, 0]
+    speed = np.hypot.reduce(q[:, 1:-1] / q[:, :1], axis=1) if M.dim == 2 else np.abs(q[:, 1] / q[:, 0])
+    speed = speed + np.sqrt(1.4 * H.pressure(q) / q[:, 0])
+    assert s_a == pytest.approx(speed.max(), rel=1e-13)
+    geo = (M.perim / (2 * M.area)).max() if M.dim == 2 else (1.0 / M.area).max()
+    assert dt_a == pytest.approx(0.08 / (s_a * geo), rel=1e-13)
+    B = O.Solver(M)
+    B.set_state(Q)
+    B.step()
+    assert B.stage(O.STAGE_SDT)[0] >= s_a
