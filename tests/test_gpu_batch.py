@@ -227,11 +227,11 @@ def test_batch_of_cartesian_meshes(L):
         assert tb == ts and np.array_equal(Qb, Qs)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_batch_masked_meshes_exact_theta(L, prec):
-    """Masked Cartesian meshes (the block step's solid at two resolutions, and a box with a
-    removed block and periodic sides) with the exact moment-limiter factor advance together
-    exactly as they do alone."""
+@pytest.mark.parametrize("prec,speed", [(0, 0), (1, 0), (1, 1)])
+def test_batch_masked_meshes_exact_theta(L, prec, speed):
+    """Masked Cartesian meshes (the block step's solid, and a box with a removed block and
+    periodic sides) with the exact moment-limiter factor, and with either wave speed, advance
+    together exactly as they do alone."""
     nx, ny, box, bc, keep, Q0, inflow = I.diffraction_cart(52, 44)
     keep2 = np.ones((20, 26), bool)
     keep2[6:12, 8:14] = False
@@ -239,7 +239,7 @@ def test_batch_masked_meshes_exact_theta(L, prec):
                               p_range=(1e-4, 1))
     specs = [(L.Mesh.cart(nx, ny, *box, bc, keep=keep), Q0),
              (L.Mesh.cart(26, 20, 0, 2.6, 0, 2.0, [0, 0, 0, 0], keep=keep2), Q2)]
-    kw = dict(precision=prec, theta_exact=1, inflow=list(inflow))
+    kw = dict(precision=prec, theta_exact=1, wave_speed=speed, inflow=list(inflow))
     B = L.Batch([m for m, _ in specs], **kw)
     for b, (_, Q) in enumerate(specs):
         B.set_state(b, Q)
