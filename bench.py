@@ -494,6 +494,23 @@ def sedov_leg(L, t2=0.1):
     return out
 
 
+def sedov_disk_steps(L, steps, warmup, t_start=0.05):
+    """The 2D Sedov blast (136k triangles, FP32-mixed), advanced to t_start, then `warmup` and
+    `steps` steps replayed from the graph: the near-vacuum core keeps the flux and moment limiters
+    busy."""
+    from paper_1601_08145_amd import inputs as I
+    xy, tri = I.sedov_disk()
+    S = L.Solver(L.Mesh.tri(xy, tri), precision=L.FP32_MIXED)
+    S.set_state(I.sedov_disk_state(xy, tri))
+    st = S.advance(t_start)
+    S.run_steps(warmup)
+    S.sync()
+    ms = _timed(S, steps)
+    log(f"[bench] Sedov disk ({len(tri)} triangles) from t = {t_start} ({st.steps} steps): "
+        f"{ms / steps:.4f} ms/step over {steps} steps")
+    return {"n_elem": len(tri), "t_start": t_start, "steps_to_start": int(st.steps), "ms_per_step": ms / steps}
+
+
 def equal_l1_leg(L, ind, taus, sizes=(48, 96, 192), T=1.0):
     """Each form on an exact solution (Shu's isentropic vortex advected by (1, 1) on a periodic
     [-5,5]^2 Delaunay mesh), to time T, at three resolutions: L1 error of the cell averages against
@@ -544,6 +561,8 @@ def main():
     ap.add_argument("--no-kernel-events", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-mesh batched leg")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched leg (for profiling)")
+    ap.add_argument("--sedov-disk-only", action="store_true",
+                    help="only steps of the 2D Sedov blast mid-run (near-vacuum limiting; for profiling)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-indicator leg")
     ap.add_argument("--no-equal-l1", action="store_true", help="skip the equal-L1 comparison on the vortex")
     ap.add_argument("--no-diffraction", action="store_true", help="skip the shock-diffraction runs")
@@ -582,6 +601,9 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched": batched_leg(L, args.steps, args.warmup)}), flush=True)
+        return
+    if args.sedov_disk_only:
+        print(json.dumps({"sedov_disk": sedov_disk_steps(L, args.steps, args.warmup)}), flush=True)
         return
 
     xy, tri, Q0 = build_workload()
