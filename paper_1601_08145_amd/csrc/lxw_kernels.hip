@@ -289,7 +289,7 @@ __device__ __forceinline__ double point_dev(const RefTab<E, double>& T, const R 
 // only where p(q(s)) >= eps_p then holds in float64; the result is never below the concavity
 // value s_c.
 template <int DIM>
-__device__ __noinline__ double exact_segment(const double* qb, const double* q, double epsp, double gam, double s_c) {
+__device__ __forceinline__ double exact_segment(const double* qb, const double* q, double epsp, double gam, double s_c) {
   constexpr int V = DIM + 2;
   double D[V];
 #pragma unroll
