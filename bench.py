@@ -494,6 +494,31 @@ def sedov_leg(L, t2=0.1):
     return out
 
 
+def cartesian_blast_leg(L, n=512, steps=100, warmup=5):
+    """The Cartesian Q2 workload: a near-vacuum blast (rho = 1, u = 0, p = 1e-10, energy 0.98 in
+    the four centre cells) on a periodic n x n mesh of [-1, 1]^2, both forms: ms per step from
+    graph replay after `warmup` steps, per-kernel times from HIP events, and the FP32-mixed form's
+    relative L1 difference to FP64 after the same steps."""
+    from paper_1601_08145_amd import inputs as I
+    mesh = L.Mesh.cart(n, n, -1, 1, -1, 1, [0, 0, 0, 0])
+    Q0 = I.sedov_cart_state(n, n)
+    out = {"n_elem": n * n, "steps": steps}
+    res = {}
+    for prec, name in ((L.FP32_MIXED, "FP32_MIXED"), (L.FP64, "FP64")):
+        r = time_gpu(L, mesh, Q0, prec, steps, warmup)
+        res[name] = r
+        rho = r["Q"][:, 0, 0]
+        out[name] = {"ms_per_step": r["ms_graph"] / steps, "element_updates_per_s": n * n * steps / (r["ms_graph"] * 1e-3),
+                     "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in r["kernels"].items() if v[1]},
+                     "rho_min": float(rho.min()), "t": r["t"]}
+        log(f"[bench]   Cartesian blast {n}^2, {name}: {r['ms_graph'] / steps:.3f} ms/step "
+            f"({out[name]['element_updates_per_s']:.3e} element-updates/s); kernels "
+            f"{ {k: round(v * 1e3, 1) for k, v in out[name]['kernels_ms'].items()} } us")
+    out["rel_l1_fp32_vs_fp64"] = rel_l1(res["FP32_MIXED"]["Q"], res["FP64"]["Q"])
+    log(f"[bench]   FP32-mixed vs FP64 after {warmup + 2 * steps} steps: rel L1 {out['rel_l1_fp32_vs_fp64']:.2e}")
+    return out
+
+
 def sedov_disk_steps(L, steps, warmup, t_start=0.05):
     """The 2D Sedov blast (136k triangles, FP32-mixed), advanced to t_start, then `warmup` and
     `steps` steps replayed from the graph: the near-vacuum core keeps the flux and moment limiters
@@ -569,6 +594,7 @@ def main():
     ap.add_argument("--no-sedov", action="store_true", help="skip the Sedov blast runs")
     ap.add_argument("--sedov-2d-end", type=float, default=0.1, help="end time of the 2D Sedov run (default 0.1)")
     ap.add_argument("--no-exact-theta", action="store_true", help="skip the exact moment-limiter factor leg")
+    ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian Q2 blast leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -685,6 +711,9 @@ def main():
     if not args.no_diffraction:
         log("[bench] shock diffraction (whole runs)")
         out["diffraction"] = diffraction_leg(L)
+    if not args.no_cartesian:
+        log("[bench] Cartesian Q2 near-vacuum blast")
+        out["cartesian_blast"] = cartesian_blast_leg(L)
     if not args.no_sedov:
         log("[bench] Sedov blasts (whole runs)")
         out["sedov"] = sedov_leg(L, args.sedov_2d_end)
