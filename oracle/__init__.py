@@ -79,6 +79,7 @@ def lib():
             "ora_ft": (None, [i, d, d, dp, dp, dp, dp]),
             "ora_mu_solve": (d, [i, d, d, dp, dp]),
             "ora_moment_limit": (d, [P, dp]),
+            "ora_shock_limit": (d, [P, dp, i, dp]),
             "ora_quad_points": (None, [P, dp]),
             "ora_project": (None, [P, dp, dp]),
             "ora_eval": (None, [P, i, dp, dp, dp]),
@@ -268,6 +269,15 @@ class Solver:
     def moment_limit(self, Qi):
         Qi = f64(Qi).copy()
         th = lib().ora_moment_limit(self.h, _d(Qi))
+        return th, Qi
+
+    def shock_limit(self, Qall, i, Qi=None):
+        """The shock-capturing limiter on element i: its coefficients Qi (default Qall[i]), the
+        neighbours' averages from Qall.  Returns (theta, limited coefficients)."""
+        Qall = f64(Qall)
+        assert Qall.shape == (self.mesh.N, self.mesh.V, self.mesh.ML)
+        Qi = f64(Qall[i] if Qi is None else Qi).copy()
+        th = lib().ora_shock_limit(self.h, _d(Qall), int(i), _d(Qi))
         return th, Qi
 
     def eval_points(self, xi):

@@ -1304,6 +1304,15 @@ double ora_moment_limit(void* s, double* Qi) {
   return moment_limit(*S->M, S->P, Qi);
 }
 
+// Shock-capturing limiter on one element's coefficients Qi (V x ML), with the neighbours' averages
+// taken from Qall (N x V x ML), for tests.  Returns theta.
+double ora_shock_limit(void* s, const double* Qall, int i, double* Qi) {
+  Solver* S = (Solver*)s;
+  const RefElem& R = S->M->R;
+  std::vector<double> Q(Qall, Qall + (size_t)S->M->N * NVAR(*S->M) * R.ML);
+  return shock_limit(*S, Q, i, Qi);
+}
+
 // Physical coordinates of the interior quadrature points of every element (N x NI x dim) and
 // the L2 projection of point values there (N x NI x V) onto the basis (N x V x ML).
 void ora_quad_points(void* m, double* xq) {
