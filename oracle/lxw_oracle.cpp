@@ -824,13 +824,16 @@ static int step(Solver& S, double T) {
   const double gam = S.P.gamma;
   const size_t QS = (size_t)V * ML;
   S.err_elem = -1; S.err.clear();
+  // threads only where the loops are long enough to pay for them (results do not depend on it)
+  const bool par = N >= 4096;
+  (void)par;
   for (double x : S.Q)
     if (!std::isfinite(x)) return set_err(S, ERR_NONFINITE, -1, "non-finite state");
 
   // ---- Element loop, Step 1: moment limiter (Sec. 3.1) -------------------------------------
   S.theta_mom.assign(N, 1.0);
   int bad = -1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     double* Qi = &S.Q[i * QS];
     double qbar[4] = {0.0, 0.0, 0.0, 0.0};
@@ -850,7 +853,7 @@ static int step(Solver& S, double T) {
   //      averages only when s_avg is set -------------------------------------------------------
   auto pts = limiter_points(R);
   double s = 0.0, geo = 0.0;
-#pragma omp parallel for reduction(max : s, geo) schedule(static)
+#pragma omp parallel for reduction(max : s, geo) schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     const double* Qi = &S.Q[i * QS];
     double qbar[4] = {0.0, 0.0, 0.0, 0.0};
@@ -879,7 +882,7 @@ static int step(Solver& S, double T) {
   std::vector<Trace> tr((size_t)N * K * NQE);
   S.Vol.assign((size_t)N * QS, 0.0);
   S.qderiv.assign((size_t)N * NI * 2 * V, 0.0);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     const double* Qi = &S.Q[i * QS];
     double Fh[2][4][9];
@@ -958,7 +961,7 @@ static int step(Solver& S, double T) {
   //      f^LxW_e = (1/2) sum omega F^*.n_e, f^LxF_e from the cell averages, Lambda_e = 1 --------
   const int E = M.E;
   std::vector<double> Fstar((size_t)E * NQE * V), fLxW((size_t)E * V), fLxF((size_t)E * V), Lam_e(E, 1.0);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par)
   for (int e = 0; e < E; ++e) {
     int i = M.e_i[e], ki = M.e_ki[e], j = M.e_j[e], kj = M.e_kj[e];
     const double* n = &M.e_n[2 * e];
@@ -1096,7 +1099,7 @@ static int step(Solver& S, double T) {
   S.fLxF_ik.assign((size_t)N * K * V, 0.0);
   S.Lam_e_ik.assign((size_t)N * K, 1.0);
   std::vector<double> Qnew(S.Q.size());
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     const double* Qi = &S.Q[i * QS];
     double* Qn = &Qnew[i * QS];
@@ -1133,7 +1136,7 @@ static int step(Solver& S, double T) {
   S.theta_sc.assign(N, 1.0);
   if (S.P.shock) {
     std::vector<double> Qs = Qnew;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par)
     for (int i = 0; i < N; ++i)
       if (S.shock_mask.empty() || S.shock_mask[i]) S.theta_sc[i] = shock_limit(S, Qnew, i, &Qs[i * QS]);
     Qnew.swap(Qs);
