@@ -34,13 +34,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DG element-updates/s at P2 2D tri; mixed/learned vs FP64 plain at equal L1"
 
-# MI355X published peaks and the rates they imply (256 CUs at 2.4 GHz): 157.3 TFLOP/s fp32 vector
-# counts packed fp32 (128 fp32 FMA lanes per CU per clock); this library is built with packed fp32
-# instructions disabled, so its fp32 (and fp64) vector rate is 64 FMA lanes x 2 flops x 256 CUs x
-# 2.4 GHz = 78.6 TFLOP/s.
+# MI355X published peaks: HBM3E 8 TB/s; fp32 vector 157.3 TFLOP/s (256 CUs x 2.4 GHz x 128 fp32 FMA
+# lanes x 2 flops, counting packed fp32).  This library is built with packed fp32 instructions
+# disabled, so the fp32 (and fp64) vector rate its kernels can reach is 64 FMA lanes x 2 flops x 256
+# CUs x 2.4 GHz = 78.6 TFLOP/s; roofline fractions are given against the published peak, with the
+# non-packed fraction beside it.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_VECTOR_NONPACKED_TFLOPS = 78.6
+# Algorithmic bytes of one whole step per triangle, FP32 bulk (state of 6 modes x 4 variables read
+# and written, 96 B each way, plus the mesh: 3 neighbour ids and orientation 16 B, Jinv and |T|
+# 20 B): 96 + 96 + 36 = 228 B.  The minimum a step must move; the kernels' traces, edge records and
+# limiter factors are intermediates on top of it.
+STEP_BYTES_PER_ELEM = 228
 
 # Arithmetic of k_elem per triangle (P2, FP32-mixed): projection of F at 7 points, q, grad q,
 # div F^h, grad div F^h and F_T at 16 points, volume term, traces.  Counted from the kernel's
@@ -187,19 +193,34 @@ def copy_rate(nbytes=1 << 30, reps=5):
     return 2 * nbytes / (best * 1e-3)
 
 
-def kelem_roofline(kavg_ms, n_elem, traffic_ok):
+def kelem_roofline(kavg_ms, n_elem, traffic_ok, ms_per_step=None):
+    """Roofline of the dominant kernel k_elem (fp32 vector arithmetic) against the published fp32
+    peak; with ms_per_step, the whole step's algorithmic bytes against the HBM peak and the counted
+    traffic of the step's kernels against those bytes."""
     achieved = KELEM_FLOPS_PER_ELEM * n_elem / (kavg_ms * 1e-3) / 1e12
     bytes_ = kelem_bytes_per_elem(4) * n_elem
     traffic = None
     if traffic_ok and traffic_valid():
         traffic = TRAFFIC["bytes_per_launch"]["k_elem"]
-    return {"kernel": "k_elem", "bound": "alu", "achieved": achieved, "peak": PEAK_VECTOR_NONPACKED_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_VECTOR_NONPACKED_TFLOPS, "traffic": traffic,
-            "kernel_ms": kavg_ms, "flops_per_elem": KELEM_FLOPS_PER_ELEM,
-            "frac_of_packed_fp32_peak": achieved / PEAK_FP32_VECTOR_TFLOPS,
-            "hbm_view": {"achieved_GBs": bytes_ / (kavg_ms * 1e-3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
-                         "frac": bytes_ / (kavg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                         "bytes_per_elem": kelem_bytes_per_elem(4)}}
+    out = {"kernel": "k_elem", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+           "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+           "kernel_ms": kavg_ms, "flops_per_elem": KELEM_FLOPS_PER_ELEM, "units_per_launch": n_elem,
+           "frac_of_nonpacked_fp32_peak": achieved / PEAK_VECTOR_NONPACKED_TFLOPS,
+           "nonpacked_fp32_peak": PEAK_VECTOR_NONPACKED_TFLOPS,
+           "hbm_view": {"achieved_GBs": bytes_ / (kavg_ms * 1e-3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
+                        "frac": bytes_ / (kavg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                        "bytes_per_elem": kelem_bytes_per_elem(4)}}
+    if ms_per_step is not None:
+        sb = STEP_BYTES_PER_ELEM * n_elem
+        step = {"bytes_per_elem": STEP_BYTES_PER_ELEM, "algorithmic_bytes": sb, "ms_per_step": ms_per_step,
+                "achieved_GBs": sb / (ms_per_step * 1e-3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
+                "frac": sb / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        if traffic_ok and traffic_valid():
+            counted = sum(TRAFFIC["bytes_per_launch"].values())
+            step["counted_traffic_bytes"] = counted
+            step["counted_over_algorithmic"] = counted / sb
+        out["step_hbm"] = step
+    return out
 
 
 def time_batch_graph(B, steps):
@@ -661,7 +682,7 @@ def main():
     if mix["kernels"]:
         kt = {k: {"ms_avg": v[0] / max(v[1], 1), "launches": v[1]} for k, v in mix["kernels"].items()}
         out["kernels"] = kt
-        out["roofline"] = kelem_roofline(kt["k_elem"]["ms_avg"], N, traffic_ok=True)
+        out["roofline"] = kelem_roofline(kt["k_elem"]["ms_avg"], N, traffic_ok=True, ms_per_step=ms_step)
 
     cr = copy_rate()
     out["hbm_copy_probe"] = {"GBs": cr / 1e9, "frac_of_peak": cr / 1e9 / PEAK_HBM_GBS,

@@ -77,8 +77,8 @@ enum { LXW_SHOCK_OFF = 0, LXW_SHOCK_PLAIN = 1 };
 /* Where the global wave speed s is measured (lxw_params.wave_speed). */
 enum { LXW_SPEED_POINTS = 0, LXW_SPEED_AVERAGES = 1 };
 
-/* State transfer flags. */
-enum { LXW_HOST_PTR = 0, LXW_DEVICE_PTR = 1 };
+/* State transfer flags (LXW_STATE_UNCHECKED may be or-ed with either pointer kind). */
+enum { LXW_HOST_PTR = 0, LXW_DEVICE_PTR = 1, LXW_STATE_UNCHECKED = 2 };
 
 typedef struct lxw_mesh lxw_mesh;
 typedef struct lxw_solver lxw_solver;
@@ -185,8 +185,12 @@ lxw_status lxw_solver_create(const lxw_mesh* m, const lxw_params* p, void* strea
 lxw_status lxw_solver_destroy(lxw_solver* s);
 
 /* Sets the state: Q as described above (host or device memory per flags) and the time t0.
- * Checks rho_bar >= eps0, p_bar > 0 and finiteness of every cell average (LXW_ERR_STATE, naming
- * the first bad element in the caller's order).  Synchronous. */
+ * Checks rho_bar >= eps0, p_bar > 0 and finiteness of every coefficient (LXW_ERR_STATE, naming
+ * the first bad element in the caller's order).  With LXW_STATE_UNCHECKED in flags these host-side
+ * checks are skipped (a state the caller already trusts, e.g. one read back from a solver of the
+ * same mesh); the device-side checks of the next step still report a cell average that is not
+ * positive (LXW_ERR_POSITIVITY) or not finite (LXW_ERR_NONFINITE), naming the element.
+ * Synchronous. */
 lxw_status lxw_set_state(lxw_solver* s, const double* Q, double t0, int32_t flags);
 
 /* Copies the state after the last completed step (shock-capturing limiter applied) into Q and

@@ -752,7 +752,7 @@ lxw_status load_state(lxw_solver* S, const lxw_mesh& Mloc, int off, const double
   } else {
     std::memcpy(h.data(), Q, n * sizeof(double));
   }
-  for (int c = 0; c < N; ++c) {
+  for (int c = 0; c < N && !(flags & LXW_STATE_UNCHECKED); ++c) {
     const double* q = &h[(size_t)c * V * ML];
     double qb[4];
     bool fin = true;

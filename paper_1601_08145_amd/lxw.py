@@ -25,7 +25,7 @@ SPEED_POINTS, SPEED_AVERAGES = 0, 1
 LINE, QUAD, TRI = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 SHOCK_OFF, SHOCK_PLAIN = 0, 1
-HOST_PTR, DEVICE_PTR = 0, 1
+HOST_PTR, DEVICE_PTR, STATE_UNCHECKED = 0, 1, 2
 STAGE_QLIM, STAGE_THETA, STAGE_VOL, STAGE_FLXW, STAGE_FLXF = 0, 1, 2, 3, 4
 STAGE_C, STAGE_LAME, STAGE_QUPD, STAGE_THETA_SC, STAGE_SDT = 6, 7, 8, 9, 10
 K_PRE, K_DT, K_ELEM, K_EDGE, K_FLIM, K_UPDATE, K_FINAL, K_IND, K_COUNT = 0, 1, 2, 3, 4, 5, 6, 7, 8
@@ -336,14 +336,15 @@ class Solver(_Ops):
     def shape(self):
         return (self.mesh.N, self.mesh.V, self.mesh.ML)
 
-    def set_state(self, Q, t0=0.0):
+    def set_state(self, Q, t0=0.0, checked=True):
+        extra = 0 if checked else STATE_UNCHECKED
         if isinstance(Q, torch.Tensor) and Q.is_cuda:
             assert Q.dtype == torch.float64 and Q.is_contiguous() and tuple(Q.shape) == self.shape
-            _check(_L.lxw_set_state(self.h, ctypes.c_void_p(Q.data_ptr()), t0, DEVICE_PTR))
+            _check(_L.lxw_set_state(self.h, ctypes.c_void_p(Q.data_ptr()), t0, DEVICE_PTR | extra))
         else:
             Q = np.ascontiguousarray(Q, dtype=np.float64)
             assert Q.shape == self.shape, (Q.shape, self.shape)
-            _check(_L.lxw_set_state(self.h, Q.ctypes.data_as(ctypes.c_void_p), t0, HOST_PTR))
+            _check(_L.lxw_set_state(self.h, Q.ctypes.data_as(ctypes.c_void_p), t0, HOST_PTR | extra))
 
     def get_state(self, out=None):
         t = ctypes.c_double(0.0)
@@ -492,10 +493,11 @@ class Batch(_Ops):
         m = self.meshes[i]
         return (m.N, m.V, m.ML)
 
-    def set_state(self, i, Q, t0=0.0):
+    def set_state(self, i, Q, t0=0.0, checked=True):
         Q = np.ascontiguousarray(Q, dtype=np.float64)
         assert Q.shape == self.shape(i), (Q.shape, self.shape(i))
-        _check(_L.lxw_batch_set_state(self.h, i, Q.ctypes.data_as(ctypes.c_void_p), t0, HOST_PTR))
+        _check(_L.lxw_batch_set_state(self.h, i, Q.ctypes.data_as(ctypes.c_void_p), t0,
+                                      HOST_PTR | (0 if checked else STATE_UNCHECKED)))
 
     def get_state(self, i):
         t = ctypes.c_double(0.0)
