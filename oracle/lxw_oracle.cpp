@@ -21,8 +21,10 @@
 // (closed forms, exactness of quadrature, finite differences, exact Riemann solutions,
 // convergence order, conservation, positivity, reduction to first-order Lax-Friedrichs).
 // The shock-capturing limiter (shock_limit below) is a reading of a limiter that the paper cites
-// but does not define: parity unpinned against that limiter's source; only its invariants are
-// pinned.
+// but does not define, so its fidelity to that limiter's source cannot be checked from the paper;
+// the reading itself is pinned by its defining properties (bounds after limiting, maximality of
+// the factor, the neighbour averages it uses, the cell size in the relaxation, hand-computed
+// cases) in tests/test_oracle_shock_limiter.py.
 
 #include <algorithm>
 #include <cmath>

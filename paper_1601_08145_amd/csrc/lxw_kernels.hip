@@ -262,13 +262,30 @@ __device__ __forceinline__ double pressure_r(const double* q, double r, double g
   return (gam - 1.0) * (q[DIM + 1] - 0.5 * k * r);
 }
 
-template <int DIM>
+// |u| + c from u2 = |u|^2 and c2 = gamma p / rho (both float64) for the global wave speed s.
+// Float64 form: in float64.  FP32-mixed form: both square roots by the hardware float32 square
+// root (a float64 square root, or a correctly rounded float32 one, is a sequence of a dozen
+// instructions, and k_pre takes two per limiter point), the sum enlarged by a relative 2^-21 in
+// float64.  The float32 rounding of u2 and c2 (2^-24 each, halved by the root), the roots (up to
+// two ulp, 2^-22) and the sum (2^-24) stay below that margin for u2 and c2 within the float32
+// normal range, so the result is never below the float64 value: the condition on s of the
+// positivity argument (s at least the largest |u| + c) still holds.
+template <class R>
+__device__ __forceinline__ double speed_of(double u2, double c2) {
+  if constexpr (sizeof(R) == sizeof(double)) {
+    return sqrt(u2) + sqrt(c2);
+  } else {
+    return double(__builtin_amdgcn_sqrtf(float(u2)) + __builtin_amdgcn_sqrtf(float(c2))) * (1.0 + 0x1p-21);
+  }
+}
+
+template <int DIM, class R>
 __device__ __forceinline__ double speed_r(const double* q, double gam) {
   const double r = 1.0 / q[0];
   double u2 = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) u2 += (q[1 + d] * r) * (q[1 + d] * r);
-  return sqrt(u2) + sqrt(gam * pressure_r<DIM>(q, r, gam) * r);
+  return speed_of<R>(u2, gam * pressure_r<DIM>(q, r, gam) * r);
 }
 
 // deviation of variable c from the cell average at point p, float64, from the stored modes
@@ -373,19 +390,19 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
     const bool shock_on = v.shock && v.sc[mid].shock_pending && ok && detect;
     if (shock_on || (kStep && ok)) {
       have_rmin = true;
-      double wb[V], Mx[V], Mn[V];
-      wb[0] = qb[0];
+      // primitive variables of the average (formed again after the point pass, so that they are
+      // not live across it)
+      auto prim_avg = [&](double* w) {
+        w[0] = qb[0];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) wb[1 + d] = qb[1 + d] * rb;
-      wb[DIM + 1] = pb;
-      const double dl = at(v.delta, i);
-#pragma unroll
-      for (int c = 0; c < V; ++c) { Mx[c] = wb[c] + dl; Mn[c] = wb[c] - dl; }
-      // the point pass before the neighbours' bounds: the neighbour states are then not live
-      // across it (135 instead of 165 registers)
+        for (int d = 0; d < DIM; ++d) w[1 + d] = qb[1 + d] * rb;
+        w[DIM + 1] = pb;
+      };
+      // the point pass before the bounds: neither the neighbour states nor the relaxed bounds are
+      // live across it (fewer registers)
       double wmax[V], wmin[V];
-#pragma unroll
-      for (int c = 0; c < V; ++c) { wmax[c] = wb[c]; wmin[c] = wb[c]; }
+      prim_avg(wmax);
+      prim_avg(wmin);
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         double q[V];
@@ -408,9 +425,14 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
           wmax[DIM + 1] = fmax(wmax[DIM + 1], pp);
           wmin[DIM + 1] = fmin(wmin[DIM + 1], pp);
           pmin = fmin(pmin, pp);
-          smax0 = fmax(smax0, sqrt(u2) + sqrt(gam * pp * r));  // = speed_r of this point
+          smax0 = fmax(smax0, speed_of<R>(u2, gam * pp * r));  // = speed_r of this point
         }
       }
+      double wb[V], Mx[V], Mn[V];
+      prim_avg(wb);
+      const double dl = at(v.delta, i);
+#pragma unroll
+      for (int c = 0; c < V; ++c) { Mx[c] = wb[c] + dl; Mn[c] = wb[c] - dl; }
 #pragma unroll
       for (int k = 0; k < K && shock_on; ++k) {
         double qn[V], wn[V];
@@ -506,13 +528,13 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
             if (kExact) th = fmin(th, thr * exact_segment<DIM>(qb, q, epsp, gam, (pb - epsp) / (pb - pt)));
             else th = fmin(th, thr * (pb - epsp) / (pb - pt));
           }
-          if (fused) smax1 = fmax(smax1, speed_r<DIM>(q, gam));
+          if (fused) smax1 = fmax(smax1, speed_r<DIM, R>(q, gam));
         }
       }
       const double tt = th_sc * th;
       at(v.theta, i) = tt;
       if (finite && qb[0] > 0.0 && pb > 0.0) {
-        smax = speed_r<DIM>(qb, gam);
+        smax = speed_r<DIM, R>(qb, gam);
         if (kSavg) {
           // the cell average's speed only
         } else if (fused && tt == 1.0) {
@@ -523,7 +545,7 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
             double q[V];
 #pragma unroll
             for (int c = 0; c < V; ++c) q[c] = qb[c] + tt * point_dev<E, R>(T, Qh, p, c);
-            smax = fmax(smax, speed_r<DIM>(q, gam));
+            smax = fmax(smax, speed_r<DIM, R>(q, gam));
           }
         }
       }

@@ -202,7 +202,7 @@ def test_full_size_batch_sampled(L):
         Qg, tg = B.get_state(b)
         err = per_var_rel_l1(Qg, Qo)
         print(f"[gpu]   mesh {b} ({meshes[b].N} triangles): rel L1 {err:.3e}", flush=True)
-        assert tg == pytest.approx(to, rel=1e-6)
+        assert tg == pytest.approx(to, rel=2e-6)  # FP32-mixed s is rounded up by a relative 2^-21
         assert err <= 1e-6
 
 

@@ -26,15 +26,17 @@ def vortex(x, t):
 
 @pytest.mark.parametrize("kind", ["cart", "tri"])
 def test_vortex_convergence(L, kind):
-    """FP64: the L1 error of the cell-average density falls at order above 2.5 between the two
-    finest meshes (Cartesian 32^2 -> 128^2, triangles on 33^2 -> 129^2 lattices); the FP32-mixed
+    """FP64: the L1 error of the cell-average density and the L2 error of the density fall at the
+    orders asserted below between the two finest meshes (Cartesian 32^2 -> 128^2, triangles on
+    33^2 -> 257^2 lattices); the FP32-mixed
     form is within 10% of the FP64 error on the coarsest mesh, where the discretisation error is
     far above float32 rounding, and exceeds 1.1 x the FP64 error by at most its rounding floor on
     the others (5e-7; measured 1.5e-7 on Cartesian and 4e-7 on triangle meshes, densities of
     order 1)."""
     T = 0.5
     errs = {L.FP64: [], L.FP32_MIXED: []}
-    sizes = [32, 64, 128] if kind == "cart" else [33, 65, 129]
+    l2 = []
+    sizes = [32, 64, 128] if kind == "cart" else [33, 65, 129, 257]
     for n in sizes:
         if kind == "cart":
             lm = L.Mesh.cart(n, n, -5, 5, -5, 5, [0, 0, 0, 0])
@@ -53,10 +55,86 @@ def test_vortex_convergence(L, kind):
             Q, t = S.get_state()
             assert t == T
             errs[prec].append(float(np.sum(np.abs(Q[:, 0, 0] - ref) * om.area) / om.area.sum()))
+            if prec == L.FP64:
+                So = O.Solver(om)
+                So.set_state(Q)
+                l2.append(H.l2_error(So, O.RefElem(O.QUAD if kind == "cart" else O.TRI), lambda x: vortex(x, T)))
     orders = [math.log2(errs[L.FP64][i] / errs[L.FP64][i + 1]) for i in range(len(sizes) - 1)]
+    o2 = [math.log2(l2[i] / l2[i + 1]) for i in range(len(sizes) - 1)]
     print(f"[gpu] vortex {kind}: L1(rho) FP64 {['%.3e' % e for e in errs[L.FP64]]}, orders "
-          f"{['%.2f' % o for o in orders]}; FP32-mixed {['%.3e' % e for e in errs[L.FP32_MIXED]]}", flush=True)
-    assert orders[-1] > 2.5
+          f"{['%.2f' % o for o in orders]}; L2(rho) {['%.3e' % e for e in l2]}, orders {['%.2f' % o for o in o2]}; "
+          f"FP32-mixed {['%.3e' % e for e in errs[L.FP32_MIXED]]}", flush=True)
+    if kind == "cart":
+        # the cell averages superconverge (3.65, 3.82); the full solution's L2 error falls at 2.37,
+        # 2.46 (as in the oracle's convergence test on coarser meshes)
+        assert orders[-1] > 2.5 and o2[-1] > 2.3
+    else:
+        # jittered triangles: L2 orders 2.61, 2.73, 2.85 up to the 257^2 lattice (still rising); the
+        # cell-average L1 error follows at 2.60, 2.73, 2.72
+        assert o2[-1] >= 2.8 and orders[-1] > 2.65
     assert abs(errs[L.FP32_MIXED][0] - errs[L.FP64][0]) <= 0.1 * errs[L.FP64][0]
     for e32, e64 in zip(errs[L.FP32_MIXED], errs[L.FP64]):
         assert e32 <= 1.1 * e64 + 5e-7
+
+
+def e3(x, t, a=0.9999):
+    rho = 1 - a * np.sin(2 * np.pi * (x[..., 0] - t)) * np.sin(2 * np.pi * x[..., 1])
+    one = np.ones_like(rho)
+    return H.cons(np.stack([rho, one, 0 * one, one], -1))
+
+
+def golden_e3():
+    rows = [ln.split() for ln in open("tests/golden/e3_convergence_table.txt") if ln.strip() and not ln.startswith("#")]
+    return {(k, int(n)): float(e) for k, n, e in rows}
+
+
+@pytest.mark.parametrize("kind", ["cart", "tri"])
+def test_e3_near_vacuum_convergence(L, kind):
+    """The paper's smooth near-vacuum advection (Sec. 4.3.1) at the sizes of its convergence table:
+    Cartesian 28^2 .. 212^2 (the table's cell counts) and periodic jittered-lattice triangle meshes
+    of the table's triangle counts (2 (n-1)^2 for n = 102 .. 301; the paper's meshes are not given).
+    L2 error of rho against the exact solution at t = 0.02, FP64.
+
+    No limiter acts on this problem (density and pressure stay far above the cutoffs; the oracle's
+    stages show no limited cell or edge), so it measures the unlimited step with the Lax-Friedrichs
+    edge flux of Eq. (LLF), whose dissipation uses the global wave speed s.  Here s (60-120, the
+    sound speed where rho ~ 1e-4) is 30-60 times the flow speed over most of the domain, and with
+    that penalty the errors fall at order 2.0-2.2 over the table's sizes, 7-30 times above the
+    paper's printed values beyond 28^2 (within 1.6 times at 28^2).  The same code with the
+    near-vacuum amplitude 0.9999 -> 0.9 (s about 5) converges at order 3: asserted here at 2.9
+    between the two finest Cartesian meshes, and at 2.8 on the triangle sizes."""
+    T = 0.02
+    gold = golden_e3()
+    sizes = [28, 42, 63, 94, 141, 212] if kind == "cart" else [102, 146, 175, 209, 251, 301]
+    res = {}
+    for a in (0.9999, 0.9):
+        errs = []
+        for n in (sizes if a == 0.9999 else sizes[-2:]):
+            if kind == "cart":
+                lm = L.Mesh.cart(n, n, 0, 1, 0, 1, [0, 0, 0, 0])
+                om = O.Mesh.cart(n, n, 0, 1, 0, 1, [O.BC_PERIODIC] * 4)
+            else:
+                xy, tri = I.lattice_delaunay(n, 5, box=(0.0, 1.0, 0.0, 1.0), periodic=True)
+                tags = I.boundary_tags(xy, tri, (0, 1, 0, 1), [0, 0, 0, 0])
+                lm, om = L.Mesh.tri(xy, tri, tags, (1.0, 1.0)), O.Mesh.tri(xy, tri, tags, (1.0, 1.0))
+            S = L.Solver(lm)
+            S.set_state(om.project(e3(om.quad_points(), 0.0, a)))
+            S.advance(T)
+            Q, t = S.get_state()
+            assert t == T and np.all(Q[:, 0, 0] > 0)
+            So = O.Solver(om)
+            So.set_state(Q)
+            errs.append((om.N, H.l2_error(So, O.RefElem(O.QUAD if kind == "cart" else O.TRI), lambda x: e3(x, T, a))))
+        res[a] = errs
+    h = lambda N: N ** -0.5
+    orders = {a: [math.log(e[i][1] / e[i + 1][1]) / math.log(h(e[i][0]) / h(e[i + 1][0])) for i in range(len(e) - 1)]
+              for a, e in res.items()}
+    # each mesh against the table's entry of the nearest cell count (within 0.1%)
+    ratio = [e / g for N, e in res[0.9999] for (k, Ng), g in gold.items() if k == kind and abs(Ng - N) <= 1e-3 * N]
+    print(f"[gpu] E3 {kind}: L2 {[('%d' % N, '%.3e' % e) for N, e in res[0.9999]]}, orders "
+          f"{['%.2f' % o for o in orders[0.9999]]}; over the paper's values {['%.1f' % r for r in ratio]}; "
+          f"amplitude 0.9: {[('%d' % N, '%.3e' % e) for N, e in res[0.9]]}, order {orders[0.9][-1]:.2f}", flush=True)
+    assert min(orders[0.9999]) > 1.9
+    assert orders[0.9][-1] > (2.9 if kind == "cart" else 2.8)
+    if kind == "cart":
+        assert 0.5 < ratio[0] < 2.0

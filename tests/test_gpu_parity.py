@@ -285,7 +285,8 @@ def test_fp32_mixed_after_100_steps(L):
     Qo, to = Ob.get_state()
     err = per_var_rel_l1(Qg, Qo)
     print(f"[gpu]   rel L1 after 100 steps {err:.3e}, t {tg:.6g} vs {to:.6g}", flush=True)
-    assert err <= 1e-5 and tg == pytest.approx(to, rel=1e-6)
+    # the FP32-mixed wave speed is rounded up by a relative 2^-21, so its time lags by about that
+    assert err <= 1e-5 and tg == pytest.approx(to, rel=2e-6)
 
 
 @pytest.mark.parametrize("name", ["line-walls", "quad-mixed", "quad-masked", "tri-ramp"])
@@ -527,15 +528,17 @@ def test_full_size_c3_one_step(L):
         out[prec] = S.get_state()
     d = per_var_rel_l1(out[L.FP32_MIXED][0], out[L.FP64][0])
     print(f"[gpu]   FP32-mixed vs FP64 after 100 steps: rel L1 {d:.3e}", flush=True)
-    assert d <= 1e-5 and out[L.FP32_MIXED][1] == pytest.approx(out[L.FP64][1], rel=1e-6)
+    # the FP32-mixed wave speed is rounded up by a relative 2^-21 (never below the float64 value):
+    # its time lags by about that much
+    assert d <= 1e-5 and out[L.FP32_MIXED][1] == pytest.approx(out[L.FP64][1], rel=2e-6)
 
 
 @pytest.mark.skipif(os.environ.get("LXW_SKIP_FULL") == "1", reason="full-size case skipped on request")
 def test_quarter_size_c3_100_steps_vs_oracle(L):
     """The 2D triangle workload's generator at a quarter of its size (354^2 lattice, 249,218
     triangles, four-quadrant Riemann data seed 0): 100 steps of the FP32-mixed form within 1e-5
-    relative L1 of 100 oracle steps, and of the FP64 form within the round-off the 100 steps
-    accumulate.  A quarter size keeps the oracle's 100 steps near a minute on the host's cores; the
+    relative L1 of 100 oracle steps (measured 3.3e-7), and of the FP64 form within the round-off
+    the 100 steps accumulate (measured 5.8e-11, bound 1e-10).  A quarter size keeps the oracle's 100 steps near a minute on the host's cores; the
     full size is compared with the oracle over one step (test_full_size_c3_one_step)."""
     print("[gpu] quarter-size C3, 100 oracle steps", flush=True)
     xy, tri = I.lattice_delaunay(354, 0)
@@ -557,7 +560,9 @@ def test_quarter_size_c3_100_steps_vs_oracle(L):
         Qg, tg = S.get_state()
         err = per_var_rel_l1(Qg, Qo)
         print(f"[gpu]   precision {prec}: rel L1 after 100 steps {err:.3e}, t {tg:.9g} (oracle {to:.9g})", flush=True)
-        assert err <= tol and tg == pytest.approx(to, rel=1e-9)
+        # the FP32-mixed form's wave speed comes from float32 point states and is rounded up by a
+        # relative 2^-21: its time lags by about that much
+        assert err <= tol and tg == pytest.approx(to, rel=1e-12 if prec == L.FP64 else 2e-6)
 
 
 @pytest.mark.skipif(os.environ.get("LXW_SKIP_FULL") == "1", reason="full-size case skipped on request")
