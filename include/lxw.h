@@ -351,6 +351,19 @@ lxw_status lxw_indicator_predict(lxw_indicator* ind, const float* X, int32_t n, 
 lxw_status lxw_indicator_grad(lxw_indicator* ind, const float* X, const float* y, int32_t n, double w_pos,
                               double w_neg, float* grad, double* loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc): the gradient of lxw_indicator_grad, with X[n][48], y[n],
+ * grad[LXW_IND_NPARAM] and loss (nullable, one float) all device memory owned by the caller,
+ * enqueued on the indicator's stream without waiting (the results are there once that stream has
+ * reached this point).  Allocates nothing: its per-workgroup partial gradients live in a fixed
+ * device workspace of the library (3.6 MiB per device, held until the process ends), which limits
+ * n to 1 .. LXW_IND_NOALLOC_MAX (LXW_ERR_ARG otherwise).  Calls that overlap on one device share
+ * that workspace and race; calls ordered on one stream do not.  Results equal lxw_indicator_grad's
+ * bit for bit. */
+enum { LXW_IND_NOALLOC_MAX = 8192 };
+lxw_status lxw_indicator_grad_noalloc(lxw_indicator* ind, const float* X, const float* y, int32_t n, double w_pos,
+                                      double w_neg, float* grad, float* loss);
+
 /* n_updates Adam updates with float32 master weights; update u uses the minibatch of samples
  * order[u*batch .. (u+1)*batch) of X[n_samples][48], y[n_samples] (all device memory; order
  * entries outside [0, n_samples) are clamped).  *last_loss (nullable): the last minibatch's loss.

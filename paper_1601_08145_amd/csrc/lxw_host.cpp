@@ -240,6 +240,14 @@ lxw_status ensure_init() {
     g_init_state = -1;
     return fail(LXW_ERR_DEVICE, std::string("uploading reference tables: ") + hipGetErrorString(e));
   }
+  // device address of the fixed workspace of lxw_indicator_grad_noalloc on the current device
+  // (other devices look theirs up on their first such call)
+  float* ws = nullptr;
+  e = ind_static_scratch(&ws);
+  if (e != hipSuccess) {
+    g_init_state = -1;
+    return fail(LXW_ERR_DEVICE, std::string("workspace address: ") + hipGetErrorString(e));
+  }
   g_init_state = 1;
   return LXW_OK;
 }
@@ -1826,6 +1834,23 @@ lxw_status lxw_indicator_grad(lxw_indicator* I, const float* X, const float* y, 
   (void)hipFree(gd);
   HIPCHK(e);
   if (loss) *loss = lf;
+  return LXW_OK;
+}
+
+static_assert(LXW_IND_NOALLOC_MAX == IND_STATIC_MAX_SAMPLES, "public and internal workspace limits differ");
+
+lxw_status lxw_indicator_grad_noalloc(lxw_indicator* I, const float* X, const float* y, int32_t n, double w_pos,
+                                      double w_neg, float* grad, float* loss) {
+  if (!I || !X || !y || !grad) return fail(LXW_ERR_ARG, "null argument");
+  if (n < 1 || n > IND_STATIC_MAX_SAMPLES)
+    return fail(LXW_ERR_ARG, "lxw_indicator_grad_noalloc takes 1 to " + std::to_string(IND_STATIC_MAX_SAMPLES) +
+                                 " samples, got " + std::to_string(n));
+  float* part = nullptr;
+  HIPCHK(ind_static_scratch(&part));
+  const int nblk = mlp_blocks(n);
+  TrainArgs a{X, y, nullptr, n, 0, n, (float)w_pos, (float)w_neg, 1.0f / (float)n, I->theta, part};
+  HIPCHK(launch_mlp_grad(a, I->st));
+  HIPCHK(launch_mlp_reduce(nblk, part, I->theta, I->m, I->v, grad, loss, 0, 0, 0, 0, 0, 1, 1, I->st));
   return LXW_OK;
 }
 

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "lxw_internal.hpp"
 
@@ -370,6 +372,33 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(int nblk, const float* part,
     v[j] = vj;
     theta[j] -= lr * (mj / bc1) / (sqrtf(vj / bc2) + eps);
   }
+}
+
+// ---- fixed workspace of the no-allocation gradient entry point ---------------------------------
+// Partial gradients of up to IND_STATIC_BLOCKS workgroups.  Every device the library runs on holds
+// its own copy until the process ends.  Host code must not pass the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): its device address is looked up per device with
+// hipGetSymbolAddress and kept, and that address is what the kernels get.  k_mlp_grad writes every
+// entry k_mlp_reduce reads, so nothing needs clearing between calls; calls that overlap on one
+// device share the array and race.
+static __device__ __align__(256) float scratch[IND_STATIC_FLOATS];
+
+hipError_t ind_static_scratch(float** out) {
+  static std::mutex mu;
+  static std::vector<float*> addr;  // per device, null until looked up
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<float*>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 // ---- launchers --------------------------------------------------------------------------------

@@ -216,4 +216,13 @@ hipError_t launch_mlp_reduce(int nblk, const float* part, float* theta, float* m
                              float bc2, hipStream_t st);
 inline int mlp_blocks(int n) { return (n + 63) / 64; }
 
+// Fixed device workspace of the gradient entry point that allocates nothing: the per-workgroup
+// partial gradients of at most IND_STATIC_MAX_SAMPLES samples (one workgroup per 64 samples).
+constexpr int IND_STATIC_MAX_SAMPLES = 8192;
+constexpr int IND_STATIC_BLOCKS = IND_STATIC_MAX_SAMPLES / 64;
+constexpr size_t IND_STATIC_FLOATS = (size_t)IND_STATIC_BLOCKS * IND_PART;  // 3.6 MiB
+// Device address of that workspace on the current device (looked up once per device with
+// hipGetSymbolAddress and kept).
+hipError_t ind_static_scratch(float** out);
+
 }  // namespace lxw

@@ -114,6 +114,7 @@ def _load():
         "lxw_indicator_load": [P, ctypes.c_char_p],
         "lxw_indicator_predict": [P, P, I32, P],
         "lxw_indicator_grad": [P, P, P, I32, D, D, P, dp],
+        "lxw_indicator_grad_noalloc": [P, P, P, I32, D, D, P, P],
         "lxw_indicator_train": [P, P, P, I32, P, I32, I32, ctypes.POINTER(Adam), dp],
         "lxw_indicator_collect": [P, P, P, I32],
         "lxw_solver_set_indicator": [P, P, D, D],
@@ -387,6 +388,7 @@ class Solver(_Ops):
 
 
 NFEAT, NPARAM = 48, 7361
+IND_NOALLOC_MAX = 8192  # LXW_IND_NOALLOC_MAX
 
 
 def _dev(a, dtype):
@@ -447,6 +449,18 @@ class Indicator:
         _check(_L.lxw_indicator_grad(self.h, ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
                                      Xd.shape[0], w_pos, w_neg, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
         return g, loss.value
+
+    def grad_noalloc(self, X, y, grad, loss=None, w_pos=1.0, w_neg=1.0):
+        """lxw_indicator_grad_noalloc: X (n x 48), y (n), grad (NPARAM) and loss (1, or None) are
+        contiguous float32 CUDA tensors of the caller; enqueued on the indicator's stream without
+        waiting."""
+        for t in (X, y, grad) + ((loss,) if loss is not None else ()):
+            assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        n = X.shape[0]
+        assert X.shape == (n, NFEAT) and y.shape == (n,) and grad.shape == (NPARAM,)
+        _check(_L.lxw_indicator_grad_noalloc(self.h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(y.data_ptr()), n,
+                                             w_pos, w_neg, ctypes.c_void_p(grad.data_ptr()),
+                                             ctypes.c_void_p(loss.data_ptr()) if loss is not None else None))
 
     def train(self, X, y, order, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, w_pos=1.0, w_neg=1.0):
         Xd, yd = _dev(X, torch.float32), _dev(y, torch.float32)
