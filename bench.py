@@ -257,9 +257,18 @@ def batched_leg(L, steps, warmup):
     default_tune = B.get_tune()
     tune = B.autotune(3)
     ms_tuned = time_batch_graph(B, steps)
+    # A/B of the step's form at the tuned workgroup sizes: one launch per phase replayed from the
+    # graph, against the persistent kernel (all phases of all steps in one cooperative launch)
+    ab = {}
+    for pw in (0, 128, 256):
+        B.set_tune(dict(tune, persistent=pw))
+        ab["graph" if pw == 0 else f"persistent_{pw}"] = time_batch_graph(B, steps) / steps
+    log(f"[bench]   batched form A/B (ms/step): {ab}")
+    B.set_tune(dict(tune, persistent=0))
     B.set_graph(False)
     ms_eager = time_batch_graph(B, steps)
     B.set_graph(True)
+    B.set_tune(tune)
     B.set_timing(True)
     B.advance_steps(min(steps, 20))
     B.sync()
@@ -270,10 +279,11 @@ def batched_leg(L, steps, warmup):
         f"{ms_eager / steps:.3f} eager; {value:.4e} element-updates/s")
     return {"workload": "512 independent 2D Euler P2 triangle meshes, 2k-60k triangles each (log-uniform, seed 0), "
                         "jittered-lattice Delaunay on [-5,5]^2, isentropic vortex + random planar shock, "
-                        "FP32-mixed, per-mesh dt, one launch per kernel over all meshes, step replayed from a "
-                        "HIP graph, autotuned workgroup sizes",
+                        "FP32-mixed, per-mesh dt, the step's form (one launch per phase replayed from a HIP "
+                        "graph, or one persistent cooperative kernel) and workgroup sizes autotuned",
             "n_meshes": len(meshes), "n_elem": ntot, "steps": steps, "value": value, "unit": "element-updates/s",
             "ms_per_step": ms_tuned / steps, "tune": tune,
+            "persistent_ab_ms_per_step": ab,
             "default_tune": {"tune": default_tune, "ms_per_step": ms_default / steps},
             "eager_launches": {"ms_per_step": ms_eager / steps},
             "kernels": kt, "roofline": kelem_roofline(kt["k_elem"]["ms_avg"], ntot, traffic_ok=False)}
@@ -594,6 +604,49 @@ def equal_l1_leg(L, ind, taus, sizes=(48, 96, 192), T=1.0):
             f"{f['fp32_mixed']['l1_rho']:.4e}" + (f", learned {f['fp32_mixed_learned']['l1_rho']:.4e}"
                                                   if "fp32_mixed_learned" in f else ""))
         out["meshes"].append(row)
+    out["sedov_disk"] = equal_l1_sedov(L, ind, taus)
+    return out
+
+
+def equal_l1_sedov(L, ind, taus, T=0.1):
+    """Each form on the 2D Sedov blast (136k-triangle disk, to t = T), where the shock-capturing
+    limiter acts every step and the similarity solution is exact: L1 density error against it
+    (relative to the blast's density deviation) and the whole run's time per step."""
+    import torch
+    from paper_1601_08145_amd import inputs as I
+    from tests.exact_sedov import Sedov
+    xy, tri = I.sedov_disk()
+    Q0 = I.sedov_disk_state(xy, tri)
+    a = xy[tri]
+    w = np.array([[0.5, 0.5, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5],
+                  [2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
+    pts = np.einsum("pk,nkd->npd", w, a)
+    rho_e = Sedov(2, E=0.979264).state(np.hypot(pts[..., 0], pts[..., 1]), T)[0].mean(axis=1)
+    area = 0.5 * np.abs((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0]))
+    mesh = L.Mesh.tri(xy, tri)
+    out = {"workload": f"2D Sedov blast on the {len(tri)}-triangle disk to t = {T}, L1 of rho against the "
+                       "similarity solution over that of its deviation from the background", "forms": {}}
+    for name, prec, use_ind in (("fp64_plain", L.FP64, False), ("fp32_mixed", L.FP32_MIXED, False),
+                                ("fp32_mixed_learned", L.FP32_MIXED, True)):
+        if use_ind and ind is None:
+            continue
+        S = L.Solver(mesh, precision=prec)
+        S.set_state(Q0)
+        if use_ind:
+            S.set_indicator(ind, *taus)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.advance(T)
+        wall = time.perf_counter() - t0
+        Q, _ = S.get_state()
+        l1 = float(np.sum(np.abs(Q[:, 0, 0] - rho_e) * area) / np.sum(np.abs(rho_e - 1.0) * area))
+        f = {"l1_rho_vs_similarity": l1, "steps": int(st.steps), "ms_per_step": wall / st.steps * 1e3}
+        if use_ind:
+            cnt = S.indicator_decisions(False)[0].tolist()
+            f["skip_fraction"] = cnt[0] / max(sum(cnt), 1)
+        out["forms"][name] = f
+        log(f"[bench]   Sedov disk {name}: L1(rho) vs similarity {l1:.4f}, {st.steps} steps, "
+            f"{f['ms_per_step']:.4f} ms/step")
     return out
 
 

@@ -265,19 +265,30 @@ lxw_status lxw_kernel_times(lxw_solver* s, double* ms /*[LXW_K_COUNT]*/, int64_t
  * per workgroup.  LXW_K_PRE, LXW_K_ELEM, LXW_K_EDGE, LXW_K_FLIM and LXW_K_UPDATE accept 64, 128 or
  * 256 (defaults 256, 128, 256, 256, 256); the entries of LXW_K_DT, LXW_K_FINAL and LXW_K_IND are
  * ignored.
+ * persistent (batches of triangle meshes only): 0 (default) runs a step as one launch per phase,
+ * replayed from a HIP graph; 128 or 256 runs lxw_batch_advance_steps as one cooperative launch of a
+ * persistent kernel (up to 1024 steps per launch) whose workgroups of that many lanes stay resident
+ * and run every phase of every step over tiles of elements and edges, with grid-wide barriers where
+ * the per-phase launches have kernel boundaries.  It applies while per-kernel timing, stage
+ * read-out and the learned indicator are off (the per-phase launches run otherwise).
  * Launch shapes change no result bit. */
 typedef struct lxw_tune {
   int32_t block[LXW_K_COUNT];
+  int32_t persistent;
 } lxw_tune;
 
 lxw_status lxw_get_tune(const lxw_solver* s, lxw_tune* out);
-/* LXW_ERR_ARG for a size other than 64, 128, 256 in a tunable entry. */
+/* LXW_ERR_ARG for a size other than 64, 128, 256 in a tunable entry or a persistent value other
+ * than 0, 128, 256; LXW_ERR_UNSUPPORTED for a non-zero persistent on a solver that does not run a
+ * batch of triangle meshes. */
 lxw_status lxw_set_tune(lxw_solver* s, const lxw_tune* t);
 /* Times each allowed size of each tunable kernel on the solver's own mesh and current state (one
  * warm-up step, then trial_steps timed steps per candidate, kernels tuned one after another),
- * keeps the fastest per kernel, and restores the state, time and counters it found, so tuning does
- * not change the trajectory.  Synchronous; the chosen shapes also go to *out (nullable).  A device
- * error during the trials is returned after the state has been restored. */
+ * keeps the fastest per kernel; for a batch of triangle meshes it then times trial_steps whole
+ * steps of the per-phase launches (graph replay) against the persistent kernel at 128 and 256 lanes
+ * per workgroup and keeps the fastest.  It restores the state, time and counters it found, so tuning does not change the
+ * trajectory.  Synchronous; the chosen shapes also go to *out (nullable).  A device error during
+ * the trials is returned after the state has been restored. */
 lxw_status lxw_autotune(lxw_solver* s, int32_t trial_steps, lxw_tune* out);
 
 /* ---- Batched form -------------------------------------------------------------------------

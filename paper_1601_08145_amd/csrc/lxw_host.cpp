@@ -994,9 +994,26 @@ lxw_status set_end_time(lxw_solver* S, double T) {
   return LXW_OK;
 }
 
-// Enqueues n steps: replays of the captured step graph, or eager launches while timing, stage
-// read-out or graphs are off.
+// Steps of a batch by the persistent kernel, at most 1024 per cooperative launch.
+template <class E, class R>
+lxw_status persistent_steps_t(lxw_solver* S, const View<R>& v, int64_t n_steps) {
+  for (int64_t k = 0; k < n_steps; k += 1024)
+    HIPCHK((launch_persistent<E, R>(v, S->cfg.persistent, S->st, S->n_mesh, (int)std::min<int64_t>(1024, n_steps - k))));
+  return LXW_OK;
+}
+
+lxw_status persistent_steps(lxw_solver* S, int64_t n_steps) {
+  switch (S->M->kind) {
+    case LXW_LINE: return S->fp32 ? persistent_steps_t<ElLine, float>(S, S->vf, n_steps) : persistent_steps_t<ElLine, double>(S, S->vd, n_steps);
+    case LXW_QUAD: return S->fp32 ? persistent_steps_t<ElQuad, float>(S, S->vf, n_steps) : persistent_steps_t<ElQuad, double>(S, S->vd, n_steps);
+    default: return S->fp32 ? persistent_steps_t<ElTri, float>(S, S->vf, n_steps) : persistent_steps_t<ElTri, double>(S, S->vd, n_steps);
+  }
+}
+
+// Enqueues n steps: the persistent kernel (a batch with that launch shape), replays of the captured
+// step graph, or eager launches while timing, stage read-out or graphs are off.
 lxw_status replay_steps(lxw_solver* S, int64_t n_steps) {
+  if (S->batch && S->cfg.persistent && !S->timing && !S->debug && !S->ind) return persistent_steps(S, n_steps);
   if (S->timing || S->debug || !S->use_graph) {
     for (int64_t k = 0; k < n_steps; ++k) {
       lxw_status s = enqueue_step(S);
@@ -1566,6 +1583,7 @@ lxw_status lxw_kernel_times(lxw_solver* S, double* ms, int64_t* launches) {
 lxw_status lxw_get_tune(const lxw_solver* S, lxw_tune* out) {
   if (!S || !out) return fail(LXW_ERR_ARG, "null argument");
   for (int k = 0; k < LXW_K_COUNT; ++k) out->block[k] = S->cfg.bs[k];
+  out->persistent = S->cfg.persistent;
   return LXW_OK;
 }
 
@@ -1578,6 +1596,11 @@ lxw_status lxw_set_tune(lxw_solver* S, const lxw_tune* t) {
     if (b != 64 && b != 128 && b != 256) return fail(LXW_ERR_ARG, "workgroup sizes must be 64, 128 or 256");
     c.bs[k] = b;
   }
+  const int pw = t->persistent;
+  if (pw != 0 && pw != 128 && pw != 256) return fail(LXW_ERR_ARG, "persistent must be 0, 128 or 256");
+  if (pw && (!S->batch || S->M->kind != LXW_TRI))
+    return fail(LXW_ERR_UNSUPPORTED, "the persistent kernel runs batches of triangle meshes only");
+  c.persistent = pw;
   lxw_status s = sync_check(S);
   if (s) return s;
   S->cfg = c;
@@ -1638,6 +1661,39 @@ lxw_status lxw_autotune(lxw_solver* S, int32_t trial_steps, lxw_tune* out) {
     best.bs[k] = best_bs;
   }
   S->cfg = best;
+  if (!s && S->batch && S->M->kind == LXW_TRI && !S->ind) {
+    // whole steps: per-phase launches replayed from the graph against the persistent kernel
+    S->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) s = fail(LXW_ERR_DEVICE, "tuning events");
+    float best_ms = std::numeric_limits<float>::infinity();
+    int best_p = 0;
+    for (int pw : {0, 128, 256}) {
+      if (s) break;
+      drop_graph(S);
+      S->cfg = best;
+      S->cfg.persistent = pw;
+      s = replay_steps(S, 1);  // warm-up (captures the graph of the per-phase launches)
+      if (!s) s = sync_check(S);
+      if (s) {
+        if (pw == 0) break;
+        s = LXW_OK;  // this launch shape cannot run here (e.g. too few resident workgroups)
+        (void)hipGetLastError();
+        continue;
+      }
+      if (hipEventRecord(e0, S->st) != hipSuccess) { s = fail(LXW_ERR_DEVICE, "tuning events"); break; }
+      s = replay_steps(S, trial_steps);
+      if (!s && hipEventRecord(e1, S->st) != hipSuccess) s = fail(LXW_ERR_DEVICE, "tuning events");
+      if (!s) s = sync_check(S);
+      float ms = 0.0f;
+      if (!s && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = fail(LXW_ERR_DEVICE, "tuning events");
+      if (!s && ms < best_ms) { best_ms = ms; best_p = pw; }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    best.persistent = best_p;
+    S->cfg = best;
+  }
   S->timing = timing0;
   std::memcpy(S->kms, kms0, sizeof kms0);
   std::memcpy(S->kcount, kc0, sizeof kc0);
@@ -1651,7 +1707,10 @@ lxw_status lxw_autotune(lxw_solver* S, int32_t trial_steps, lxw_tune* out) {
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(LXW_ERR_DEVICE, "tuning restore failed");
   S->hscv = ssc;
   S->hsc = ssc[0];
-  if (out) for (int k = 0; k < LXW_K_COUNT; ++k) out->block[k] = S->cfg.bs[k];
+  if (out) {
+    for (int k = 0; k < LXW_K_COUNT; ++k) out->block[k] = S->cfg.bs[k];
+    out->persistent = S->cfg.persistent;
+  }
   return LXW_OK;
 }
 

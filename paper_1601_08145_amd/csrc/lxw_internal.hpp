@@ -158,6 +158,7 @@ enum KernelId { K_PRE = 0, K_DT = 1, K_ELEM = 2, K_EDGE = 3, K_FLIM = 4, K_UPDAT
 // tunable kernel accepts 64, 128 or 256.
 struct LaunchCfg {
   int bs[8] = {256, 0, 128, 256, 256, 256, 0, 0};
+  int persistent = 0;  // batches: 0 per-phase launches (graph replay), else k_persist with this workgroup size
 };
 inline bool tunable(int k) { return k == K_PRE || k == K_ELEM || k == K_EDGE || k == K_FLIM || k == K_UPDATE; }
 // Number of workgroups of an element or edge kernel: padded to a multiple of 8 (one contiguous
@@ -166,6 +167,10 @@ inline int egrid_blocks(int n, int bs) { return ((n + bs - 1) / bs + 7) / 8 * 8;
 
 template <class E, class R>
 hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_t st, int n_mesh, int mode);
+// n_steps whole steps of a batch (v.mesh_of set) in one cooperative launch of workgroups of bs
+// lanes (64, 128 or 256), as many as stay resident together; same results as the separate kernels.
+template <class E, class R>
+hipError_t launch_persistent(const View<R>& v, int bs, hipStream_t st, int n_mesh, int n_steps);
 
 // ---- learned troubled-cell indicator (lxw_indicator.hip) ------------------------------------
 // Network 48 -> 64 (ReLU) -> 64 (ReLU) -> 1 (sigmoid); flat FP32 parameters W1[48][64], b1[64],

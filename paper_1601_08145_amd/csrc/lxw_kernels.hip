@@ -23,6 +23,7 @@
 // read through the scalar cache (every lane of a wave reads the same entry).  State is stored as
 // cell averages Qbar[N][V] (float64, one record per element: also gathered by neighbour index) and
 // higher modes as structure-of-arrays Qh[V][ML-1][N].
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -340,17 +341,16 @@ __device__ __forceinline__ double exact_segment(const double* qb, const double* 
 // 1 read-out (pending shock-capturing limiter applied), 2 collection (its factor recorded), 3 step
 // with the exact pressure factor of the moment limiter, 4 step with the wave speed from the cell
 // averages only, 5 both.
+// Element i of k_pre (i may be past the last element: every lane of a wavefront takes part in the
+// wave-speed reduction).
 template <class E, class R, int mode>
-__global__ __launch_bounds__(256) void k_pre(View<R> v) {
+__device__ __forceinline__ void pre_item(View<R> v, const int i) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NP = E::NP, K = E::K;
   constexpr bool kStep = mode == 0 || mode >= 3;
   constexpr bool kExact = mode == 3 || mode == 5;  // exact pressure factor of the moment limiter
   constexpr bool kSavg = mode >= 4;                // wave speed from the cell averages only
-  // a single mesh at its end time: the step changes nothing (every lane leaves together)
-  if (kStep && !v.mesh_of && !(v.sc[0].t < v.sc[0].T)) return;
   const RefTab<E, double>& T = TabSel<E, double>::get();
   const int N = v.N;
-  const int i = xcd_item();
   const bool valid = i < N;
   const double gam = v.gamma, eps0 = v.eps0;
   double smax = 0.0;
@@ -585,6 +585,14 @@ __global__ __launch_bounds__(256) void k_pre(View<R> v) {
   }
 }
 
+template <class E, class R, int mode>
+__global__ __launch_bounds__(256) void k_pre(View<R> v) {
+  constexpr bool kStep = mode == 0 || mode >= 3;
+  // a single mesh at its end time: the step changes nothing (every lane leaves together)
+  if (kStep && !v.mesh_of && !(v.sc[0].t < v.sc[0].T)) return;
+  pre_item<E, R, mode>(v, xcd_item());
+}
+
 // ---------------------------------------------------------------------------------------------
 // k_dt: per mesh, dt from the CFL condition (reading of Sec. 4.1, "CFL 0.08"), clipped to T.
 // ---------------------------------------------------------------------------------------------
@@ -614,9 +622,7 @@ __global__ __launch_bounds__(1024) void k_dt_single(Scalars* sc, DevError* err, 
   S.dt = dt;
 }
 
-__global__ void k_dt(Scalars* sc, DevError* err, int n_mesh) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_mesh) return;
+__device__ __forceinline__ void dt_mesh(Scalars* sc, DevError* err, const int m) {
   Scalars& S = sc[m];
   S.idle = !(S.t < S.T);
   if (S.idle) return;
@@ -630,6 +636,11 @@ __global__ void k_dt(Scalars* sc, DevError* err, int n_mesh) {
   double dt = S.cfl / (s * S.geo);
   if (S.t + dt > S.T) dt = S.T - S.t;
   S.dt = dt;
+}
+
+__global__ void k_dt(Scalars* sc, DevError* err, int n_mesh) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < n_mesh) dt_mesh(sc, err, m);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -659,12 +670,11 @@ template <class E, class R>
 struct ElemOcc { static constexpr int waves = (E::kind == ElTri::kind && sizeof(R) == 4) ? 2 : 1; };
 
 template <class E, class R>
-__global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v) {
+__device__ __forceinline__ void elem_item(View<R> v, const int i) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NI = E::NI, K = E::K, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const RefTab<E, double>& TD = TabSel<E, double>::get();
   const int N = v.N, NE = v.E;
-  const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   // At the end time the step changes nothing: the stored modes are written back as they were.
@@ -958,7 +968,11 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
       }
     }
   }
+}
 
+template <class E, class R>
+__global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v) {
+  elem_item<E, R>(v, xcd_item());
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -979,8 +993,10 @@ __device__ __forceinline__ void lds_to_global(unsigned char* dst, const unsigned
   }
 }
 
+// Edge e of k_edge; every lane of the workgroup calls it with the edges e0 + threadIdx.x of one
+// contiguous tile (the records are staged through LDS and written together).
 template <class E, class R>
-__global__ __launch_bounds__(256) void k_edge(View<R> v) {
+__device__ __forceinline__ void edge_tile(View<R> v, const int e) {
   constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE;
   // per-edge records: F* at the edge points, and (f^LxW, f^LxF); each lane writes its edge's
   // records into LDS as it computes them
@@ -989,7 +1005,6 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   __shared__ __align__(16) unsigned char rec_fl[256 * FL];
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const int NE = v.E;
-  const int e = xcd_item();
   const bool valid = e < NE;
   const int e0 = e - (int)threadIdx.x;  // first edge of the workgroup (its edges are consecutive)
   const int nrec = max(0, min((int)blockDim.x, NE - e0));
@@ -1067,6 +1082,14 @@ __global__ __launch_bounds__(256) void k_edge(View<R> v) {
   __syncthreads();
   lds_to_global<FS % 16 == 0>(reinterpret_cast<unsigned char*>(v.fstar) + (size_t)max(e0, 0) * FS, rec_fs, nrec * FS);
   lds_to_global<FL % 16 == 0>(reinterpret_cast<unsigned char*>(v.fLxW) + (size_t)max(e0, 0) * FL, rec_fl, nrec * FL);
+  // the staging area is free again only when every lane has copied its part out (a workgroup of
+  // the persistent kernel goes on to its next tile)
+  __syncthreads();
+}
+
+template <class E, class R>
+__global__ __launch_bounds__(256) void k_edge(View<R> v) {
+  edge_tile<E, R>(v, xcd_item());
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1118,10 +1141,9 @@ __device__ double mu_solve(const double* qL, const double* qa, double gam, doubl
 // corner 000 is the pure LxF update; the pressure target is eps_p = min(eps0, p(q^LxF)).
 // ---------------------------------------------------------------------------------------------
 template <class E, class R>
-__global__ __launch_bounds__(256) void k_flim(View<R> v) {
+__device__ __forceinline__ void flim_item(View<R> v, const int i) {
   constexpr int V = E::V, DIM = E::DIM, K = E::K;
   const int N = v.N;
-  const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   const double dt = v.sc[mid].dt;
@@ -1171,6 +1193,7 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   double mm[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) mm[k] = 1.0;
+#pragma unroll
   for (int a = 1; a < (1 << K); ++a) {
     double qa[V];
 #pragma unroll
@@ -1193,6 +1216,11 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
   for (int k = 0; k < K; ++k) v.cedge[(size_t)eidx[k] * 2 + sd[k]] = Lam[k] * mm[k];
 }
 
+template <class E, class R>
+__global__ __launch_bounds__(256) void k_flim(View<R> v) {
+  flim_item<E, R>(v, xcd_item());
+}
+
 // ---------------------------------------------------------------------------------------------
 // k_update: Sec. 3.3 Step 6 with theta_k = Lambda_{e_ik} = min(1, both sides' candidates):
 //   Q^(1) -= dt/|T| sum_k eps_ik [theta_k f^LxW + (1 - theta_k) f^LxF]            (float64)
@@ -1201,11 +1229,10 @@ __global__ __launch_bounds__(256) void k_flim(View<R> v) {
 // new cell average.
 // ---------------------------------------------------------------------------------------------
 template <class E, class R>
-__global__ __launch_bounds__(256) void k_update(View<R> v) {
+__device__ __forceinline__ void update_item(View<R> v, const int i) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, K = E::K, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const int N = v.N;
-  const int i = xcd_item();
   if (i >= N) return;
   const int mid = mesh_id<R>(v.mesh_of, i);
   // at the end time the step changes nothing: the flag is read here and applied at the stores
@@ -1263,6 +1290,70 @@ __global__ __launch_bounds__(256) void k_update(View<R> v) {
     S.s_bits = 0ull;
     S.shock_pending = v.shock ? 1 : 0;
   }
+}
+
+template <class E, class R>
+__global__ __launch_bounds__(256) void k_update(View<R> v) {
+  update_item<E, R>(v, xcd_item());
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_persist: n_steps whole steps of a batch of meshes in one cooperative launch.  Every workgroup
+// stays resident and runs each phase of the step (the bodies of k_pre, k_dt, k_elem, k_edge,
+// k_flim, k_update) over tiles of elements or edges, with a grid-wide barrier where the separate
+// launches have a kernel boundary; the arithmetic is that of the separate kernels, so the results
+// are the same bit for bit.  The grid is a multiple of 8 workgroups: workgroup b runs on XCD b mod 8,
+// and the tiles of each XCD are one contiguous range of the space-filling-curve order.
+// ---------------------------------------------------------------------------------------------
+template <class E, class R, int pmode>
+__global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_persist(View<R> v, int n_mesh, int n_steps) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int bs = (int)blockDim.x, nb = (int)gridDim.x;
+  const int x = (int)blockIdx.x & 7, r = (int)blockIdx.x >> 3, per = nb >> 3;
+  auto tiles = [&](int n_items, auto&& body) {
+    const int nt = (n_items + bs - 1) / bs;
+    const int t0 = (int)((long long)nt * x / 8), t1 = (int)((long long)nt * (x + 1) / 8);
+    for (int t = t0 + r; t < t1; t += per) body(t * bs + (int)threadIdx.x);
+  };
+  for (int step = 0; step < n_steps; ++step) {
+    tiles(v.N, [&](int i) { pre_item<E, R, pmode>(v, i); });
+    grid.sync();
+    for (int m = (int)(blockIdx.x * blockDim.x + threadIdx.x); m < n_mesh; m += nb * bs) dt_mesh(v.sc, v.err, m);
+    grid.sync();
+    tiles(v.N, [&](int i) { elem_item<E, R>(v, i); });
+    grid.sync();
+    tiles(v.E, [&](int e) { edge_tile<E, R>(v, e); });
+    grid.sync();
+    tiles(v.N, [&](int i) { flim_item<E, R>(v, i); });
+    grid.sync();
+    tiles(v.N, [&](int i) { update_item<E, R>(v, i); });
+    grid.sync();
+  }
+}
+
+template <class E, class R>
+hipError_t launch_persistent(const View<R>& v, int bs, hipStream_t st, int n_mesh, int n_steps) {
+  if (bs != 128 && bs != 256) return hipErrorInvalidConfiguration;
+  if (!v.mesh_of || n_steps < 1 || E::kind != ElTri::kind) return hipErrorInvalidValue;
+  const void* fn = nullptr;
+  switch ((v.theta_exact ? 1 : 0) + (v.s_avg ? 2 : 0)) {
+    case 0: fn = reinterpret_cast<const void*>(&k_persist<E, R, 0>); break;
+    case 1: fn = reinterpret_cast<const void*>(&k_persist<E, R, 3>); break;
+    case 2: fn = reinterpret_cast<const void*>(&k_persist<E, R, 4>); break;
+    default: fn = reinterpret_cast<const void*>(&k_persist<E, R, 5>); break;
+  }
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bs, 0);
+  if (e != hipSuccess) return e;
+  // every workgroup must be resident for the grid barriers; a multiple of 8 for the XCD mapping
+  const int nb = per_cu * prop.multiProcessorCount / 8 * 8;
+  if (nb < 8) return hipErrorCooperativeLaunchTooLarge;
+  View<R> vv = v;
+  void* args[] = {&vv, &n_mesh, &n_steps};
+  return hipLaunchCooperativeKernel(fn, dim3((unsigned)nb), dim3((unsigned)bs), args, 0, st);
 }
 
 // Sets the end time of every mesh (a kernel, so that it is ordered on the stream and may be
@@ -1337,6 +1428,12 @@ hipError_t launch(KernelId k, const View<R>& v, const LaunchCfg& cfg, hipStream_
   return hipGetLastError();
 }
 
+template hipError_t launch_persistent<ElLine, double>(const View<double>&, int, hipStream_t, int, int);
+template hipError_t launch_persistent<ElLine, float>(const View<float>&, int, hipStream_t, int, int);
+template hipError_t launch_persistent<ElQuad, double>(const View<double>&, int, hipStream_t, int, int);
+template hipError_t launch_persistent<ElQuad, float>(const View<float>&, int, hipStream_t, int, int);
+template hipError_t launch_persistent<ElTri, double>(const View<double>&, int, hipStream_t, int, int);
+template hipError_t launch_persistent<ElTri, float>(const View<float>&, int, hipStream_t, int, int);
 template hipError_t launch<ElLine, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
 template hipError_t launch<ElLine, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
 template hipError_t launch<ElQuad, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);

@@ -54,7 +54,7 @@ class MeshInfo(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32 * 8)]
+    _fields_ = [("block", ctypes.c_int32 * 8), ("persistent", ctypes.c_int32)]
 
 
 class Adam(ctypes.Structure):
@@ -276,23 +276,33 @@ class _Ops:
     def set_graph(self, on=True):
         _check(_L.lxw_set_graph(self._sh(), int(on)))
 
+    @staticmethod
+    def _tune_dict(t):
+        d = {KERNEL_NAMES[k]: int(t.block[k]) for k in range(K_COUNT)}
+        d["persistent"] = int(t.persistent)
+        return d
+
     def get_tune(self):
         t = Tune()
         _check(_L.lxw_get_tune(self._sh(), ctypes.byref(t)))
-        return {KERNEL_NAMES[k]: int(t.block[k]) for k in range(K_COUNT)}
+        return self._tune_dict(t)
 
     def set_tune(self, blocks):
-        """blocks: {kernel name: workgroup size} for any of the tunable kernels."""
+        """blocks: {kernel name: workgroup size} for any of the tunable kernels, and "persistent"
+        (batches: 0, or the persistent kernel's workgroup size)."""
         t = Tune()
         _check(_L.lxw_get_tune(self._sh(), ctypes.byref(t)))
         for name, b in blocks.items():
-            t.block[KERNEL_NAMES.index(name)] = int(b)
+            if name == "persistent":
+                t.persistent = int(b)
+            else:
+                t.block[KERNEL_NAMES.index(name)] = int(b)
         _check(_L.lxw_set_tune(self._sh(), ctypes.byref(t)))
 
     def autotune(self, trial_steps=3):
         t = Tune()
         _check(_L.lxw_autotune(self._sh(), trial_steps, ctypes.byref(t)))
-        return {KERNEL_NAMES[k]: int(t.block[k]) for k in range(K_COUNT)}
+        return self._tune_dict(t)
 
     def set_indicator(self, ind, tau_lo=0.0, tau_hi=1.0):
         """Learned detection for the shock-capturing limiter (None: plain everywhere)."""
