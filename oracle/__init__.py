@@ -70,9 +70,12 @@ def lib():
             "ora_error_elem": (i, [P]),
             "ora_error_msg": (ctypes.c_char_p, [P]),
             "ora_stage": (i, [P, i, dp]),
-            "ora_ref_info": (None, [i, ip]),
-            "ora_ref_tables": (None, [i, dp, dp, dp, dp, dp]),
-            "ora_phi": (d, [i, i, dp, i, i]),
+            "ora_ref_info": (None, [i, i, ip]),
+            "ora_ref_tables": (None, [i, i, dp, dp, dp, dp, dp]),
+            "ora_phi": (d, [i, i, i, dp, i, i]),
+            "ora_mesh_set_degree": (i, [P, i]),
+            "ora_flux_3vp": (None, [i, d, dp, i, dp, dp, dp, dp]),
+            "ora_ft4": (None, [i, d, d, dp, dp, dp, dp, dp]),
             "ora_flux": (None, [i, d, dp, i, dp]),
             "ora_flux_jvp": (None, [i, d, dp, i, dp, dp]),
             "ora_flux_hvp": (None, [i, d, dp, i, dp, dp, dp]),
@@ -109,31 +112,37 @@ def i32(a):
 
 
 class RefElem:
-    """Reference element tables of kind LINE, QUAD or TRI."""
+    """Reference element tables of kind LINE, QUAD or TRI and polynomial degree 2 (or 3: LINE,
+    TRI)."""
 
-    def __init__(self, kind):
+    def __init__(self, kind, degree=2):
         L = lib()
         info = np.zeros(5, np.int32)
-        L.ora_ref_info(kind, _i(info))
+        L.ora_ref_info(kind, degree, _i(info))
         self.kind = kind
+        self.degree = degree
         self.dim, self.ML, self.K, self.NI, self.NQE = (int(x) for x in info)
         self.C = np.zeros((self.ML, self.ML))
         self.xi_int = np.zeros((self.NI, self.dim))
         self.w_int = np.zeros(self.NI)
         self.xi_edge = np.zeros((self.K, self.NQE, self.dim))
         self.om_edge = np.zeros(self.NQE)
-        L.ora_ref_tables(kind, _d(self.C), _d(self.xi_int), _d(self.w_int), _d(self.xi_edge), _d(self.om_edge))
+        L.ora_ref_tables(kind, degree, _d(self.C), _d(self.xi_int), _d(self.w_int), _d(self.xi_edge),
+                         _d(self.om_edge))
 
     def phi(self, l, xi, da=0, db=0):
         xi = f64(np.atleast_1d(xi))
-        return lib().ora_phi(self.kind, l, _d(xi), da, db)
+        return lib().ora_phi(self.kind, self.degree, l, _d(xi), da, db)
 
 
 class Mesh:
-    def __init__(self, handle):
+    def __init__(self, handle, degree=2):
         if not handle:
             raise ValueError("oracle mesh construction failed: " + lib().ora_last_error().decode())
         self.h = handle
+        if degree != 2 and lib().ora_mesh_set_degree(self.h, degree) != 0:
+            raise ValueError(f"no degree-{degree} elements of this kind")
+        self.degree = degree
         info = np.zeros(8, np.int32)
         lib().ora_mesh_info(self.h, _i(info))
         self.kind, self.dim, self.N, self.E, self.ML, self.K, self.NI, self.NQE = (int(x) for x in info)
@@ -150,8 +159,8 @@ class Mesh:
             self.h = None
 
     @staticmethod
-    def line(n, x0, x1, bc_left, bc_right):
-        return Mesh(lib().ora_mesh_1d(n, x0, x1, bc_left, bc_right))
+    def line(n, x0, x1, bc_left, bc_right, degree=2):
+        return Mesh(lib().ora_mesh_1d(n, x0, x1, bc_left, bc_right), degree)
 
     @staticmethod
     def cart(nx, ny, x0, x1, y0, y1, bc, keep=None, wall_bc=2):
@@ -168,14 +177,14 @@ class Mesh:
                                         int(wall_bc)))
 
     @staticmethod
-    def tri(xy, tri, bnd=None, period=None):
+    def tri(xy, tri, bnd=None, period=None, degree=2):
         xy = f64(xy)
         tri = i32(tri)
         b = i32(bnd) if bnd is not None else None
         p = f64(period) if period is not None else None
         h = lib().ora_mesh_tri(len(xy), _d(xy), len(tri), _i(tri), _i(b) if b is not None else None,
                                _d(p) if p is not None else None)
-        return Mesh(h)
+        return Mesh(h, degree)
 
     def quad_points(self):
         x = np.zeros((self.N, self.NI, self.dim))
@@ -259,7 +268,7 @@ class Solver:
             STAGE_QLIM: (m.N, m.V, m.ML), STAGE_THETA_MOM: (m.N,), STAGE_VOL: (m.N, m.V, m.ML),
             STAGE_FLXW: (m.N, m.K, m.V), STAGE_FLXF: (m.N, m.K, m.V), STAGE_LAM_IK: (m.N, m.K),
             STAGE_C_IK: (m.N, m.K), STAGE_LAM_E: (m.N, m.K), STAGE_QUPD: (m.N, m.V, m.ML),
-            STAGE_THETA_SC: (m.N,), STAGE_SDT: (2,), STAGE_QDERIV: (m.N, m.NI, 2, m.V),
+            STAGE_THETA_SC: (m.N,), STAGE_SDT: (2,), STAGE_QDERIV: (m.N, m.NI, 3, m.V),
         }
         out = np.zeros(shapes[stage])
         if lib().ora_stage(self.h, stage, _d(out)) != 0:
@@ -326,6 +335,21 @@ def ft(q, qt, qtt, dt, gamma=1.4):
     dim = len(q) - 2
     out = np.zeros((dim, len(q)))
     lib().ora_ft(dim, gamma, dt, _d(q), _d(qt), _d(qtt), _d(out))
+    return out
+
+
+def flux_3vp(q, x, y, z, d=0, gamma=1.4):
+    q, x, y, z = f64(q), f64(x), f64(y), f64(z)
+    out = np.zeros(len(q))
+    lib().ora_flux_3vp(len(q) - 2, gamma, _d(q), d, _d(x), _d(y), _d(z), _d(out))
+    return out
+
+
+def ft4(q, qt, qtt, qttt, dt, gamma=1.4):
+    q, qt, qtt, qttt = f64(q), f64(qt), f64(qtt), f64(qttt)
+    dim = len(q) - 2
+    out = np.zeros((dim, len(q)))
+    lib().ora_ft4(dim, gamma, dt, _d(q), _d(qt), _d(qtt), _d(qttt), _d(out))
     return out
 
 

@@ -66,6 +66,39 @@ static inline HD recip(HD x) {
 }
 static inline HD operator/(HD x, HD y) { return x * recip(y); }
 
+// Triple-dual numbers: coefficients c[S] of the products e_S of the infinitesimals in S (bit i of S
+// for e_{i+1}, e_i^2 = 0).  Evaluating F(q + e1 x + e2 y + e3 z) gives the third derivative
+// F^(3)(q)(x, y, z) exactly as the e1 e2 e3 coefficient (the third time derivative of the flux,
+// for the fourth-order time-averaged flux).
+struct TD {
+  double c[8];
+};
+static inline TD td(double v) { TD r{}; r.c[0] = v; return r; }
+static inline TD operator+(TD x, TD y) { for (int k = 0; k < 8; ++k) x.c[k] += y.c[k]; return x; }
+static inline TD operator-(TD x, TD y) { for (int k = 0; k < 8; ++k) x.c[k] -= y.c[k]; return x; }
+static inline TD operator*(TD x, TD y) {
+  TD r{};
+  for (int S = 0; S < 8; ++S)
+    for (int T = S;; T = (T - 1) & S) {  // every subset T of S
+      r.c[S] += x.c[T] * y.c[S ^ T];
+      if (T == 0) break;
+    }
+  return r;
+}
+static inline TD operator*(double s, TD x) { for (int k = 0; k < 8; ++k) x.c[k] *= s; return x; }
+static inline TD operator+(TD x, double s) { x.c[0] += s; return x; }
+static inline TD recip(TD x) {
+  // 1/(v + n) = (1/v) (1 - n/v + (n/v)^2 - (n/v)^3) with n nilpotent (n^4 = 0)
+  const double r = 1.0 / x.c[0];
+  TD n = x;
+  n.c[0] = 0.0;
+  n = r * n;
+  TD n2 = n * n, n3 = n2 * n;
+  TD out = td(1.0) - n + n2 - n3;
+  return r * out;
+}
+static inline TD operator/(TD x, TD y) { return x * recip(y); }
+
 // ------------------------------------------------------------------------------------------
 // Physics: Eq. (euler-eqns) with the equation of state Eq. (eos); the flux in direction d as
 // written in Sec. 1.5.  Conserved variables q = (rho, M, E) in 1D and (rho, Mx, My, E) in 2D.
@@ -125,6 +158,21 @@ static void flux_hvp(int dim, double gam, const double* q, int d, const double* 
   for (int i = 0; i < V; ++i) out[i] = Fh[i].ab;
 }
 
+// F^(3)_d(q)(x, y, z)  (third derivative of the flux applied to three vectors)
+static void flux_3vp(int dim, double gam, const double* q, int d, const double* x, const double* y,
+                     const double* z, double* out) {
+  TD qh[4] = {}, Fh[4] = {};
+  int V = dim + 2;
+  for (int i = 0; i < V; ++i) {
+    qh[i] = td(q[i]);
+    qh[i].c[1] = x[i];
+    qh[i].c[2] = y[i];
+    qh[i].c[4] = z[i];
+  }
+  euler_flux<TD>(dim, gam, qh, d, Fh);
+  for (int i = 0; i < V; ++i) out[i] = Fh[i].c[7];
+}
+
 // Pressure from conserved variables, Eq. (eos) / Eq. (ave_press).
 static double pressure(int dim, double gam, const double* q) {
   if (dim == 1) return (gam - 1.0) * (q[2] - 0.5 * q[1] * q[1] / q[0]);
@@ -142,7 +190,7 @@ static double pressure(int dim, double gam, const double* q) {
 enum Kind { LINE = 0, QUAD = 1, TRI = 2 };
 
 struct RefElem {
-  int kind = 0, dim = 0, ML = 0, K = 0, NI = 0, NQE = 0, NV = 0;
+  int kind = 0, deg = 2, dim = 0, ML = 0, K = 0, NI = 0, NQE = 0, NV = 0;
   double T0 = 0.0;                 // |T0|
   std::vector<int> ex, ey;         // monomial exponents
   std::vector<double> C;           // ML x ML: phi_l = sum_j C[l*ML+j] * mono_j
@@ -179,13 +227,86 @@ static double dpow(double x, int n, int k) {
   return c * ipow(x, n - k);
 }
 
-static RefElem make_ref(int kind) {
+// n-point Gauss rule on [-1, 1] for the weight (1 - x)^a (a = 0: Gauss-Legendre, a = 1:
+// Gauss-Jacobi with alpha = 1, beta = 0): the roots of the orthogonal polynomial of degree n,
+// found by Newton's method on the three-term recurrence from the Chebyshev points, and the weights
+// 2^(a+1) / ((1 - x^2) P_n'(x)^2).
+static void gauss_rule(int n, int a, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  auto poly = [&](double t, double& p, double& dp) {
+    // Jacobi P_k^(a,0): 2k(k+a)(2k+a-2) P_k = (2k+a-1)[(2k+a)(2k+a-2) t + a^2] P_{k-1}
+    //                                         - 2(k+a-1)(k-1)(2k+a) P_{k-2}
+    double p0 = 1.0, p1 = 0.5 * ((a + 2) * t + a);
+    if (n == 0) { p = p0; dp = 0.0; return; }
+    for (int k = 2; k <= n; ++k) {
+      const double c1 = 2.0 * k * (k + a) * (2.0 * k + a - 2.0);
+      const double c2 = (2.0 * k + a - 1.0) * ((2.0 * k + a) * (2.0 * k + a - 2.0) * t + a * a);
+      const double c3 = 2.0 * (k + a - 1.0) * (k - 1.0) * (2.0 * k + a);
+      const double p2 = (c2 * p1 - c3 * p0) / c1;
+      p0 = p1;
+      p1 = p2;
+    }
+    p = p1;
+    // (2n + a)(1 - t^2) P_n' = n [(a - (2n + a) t) P_n + 2 (n + a) P_{n-1}]   (Jacobi, beta = 0)
+    dp = n * ((a - (2.0 * n + a) * t) * p1 + 2.0 * (n + a) * p0) / ((2.0 * n + a) * (1.0 - t * t));
+  };
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      poly(t, p, dp);
+      const double dt = p / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    double p, dp;
+    poly(t, p, dp);
+    x[n - 1 - i] = t;
+    w[n - 1 - i] = std::pow(2.0, a + 1) / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+static RefElem make_ref(int kind, int deg = 2) {
   RefElem R;
   R.kind = kind;
+  R.deg = deg;
   const double g = std::sqrt(3.0 / 5.0);
   R.s_edge = {-g, 0.0, g};
   R.om_edge = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
-  if (kind == LINE) {
+  if (deg == 3) {
+    // P3: 4-point Gauss-Legendre on the edges and in 1D; on the triangle the collapsed product of
+    // 4-point Gauss-Legendre in s and 4-point Gauss-Jacobi (weight 1 - t) in t, at
+    // (xi, eta) = (s (1 - t), t): 16 points, exact to degree 7 (the products phi_l phi_m of
+    // degree 6 of the projection included).
+    std::vector<double> xl, wl, xj, wj;
+    gauss_rule(4, 0, xl, wl);
+    gauss_rule(4, 1, xj, wj);
+    R.s_edge = xl;
+    R.om_edge = wl;
+    if (kind == LINE) {
+      R.dim = 1; R.ML = 4; R.K = 2; R.NV = 2; R.NQE = 1; R.T0 = 2.0;
+      R.ex = {0, 1, 2, 3}; R.ey = {0, 0, 0, 0};
+      R.xv = {-1.0, 1.0};
+      for (int i = 0; i < 4; ++i) { R.xi_int.push_back(xl[i]); R.w_int.push_back(wl[i] / 2.0); }
+      R.s_edge = {0.0}; R.om_edge = {2.0};
+    } else if (kind == TRI) {
+      R.dim = 2; R.ML = 10; R.K = 3; R.NV = 3; R.NQE = 4; R.T0 = 0.5;
+      R.ex = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0}; R.ey = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
+      R.xv = {0, 0, 1, 0, 0, 1};
+      for (int j = 0; j < 4; ++j)
+        for (int i = 0; i < 4; ++i) {
+          const double sv = 0.5 * (xl[i] + 1.0), tv = 0.5 * (xj[j] + 1.0);
+          R.xi_int.push_back(sv * (1.0 - tv));
+          R.xi_int.push_back(tv);
+          // (1/|T0|) int = 2 int_0^1 int_0^1 f (1 - t) ds dt; ds = dx/2, (1 - t) dt = (1 - x) dx / 4
+          R.w_int.push_back(2.0 * (wl[i] / 2.0) * (wj[j] / 4.0));
+        }
+    } else {
+      return R;  // no degree-3 element of this kind (R.ML == 0)
+    }
+    R.NI = (int)R.w_int.size();
+  } else if (kind == LINE) {
     R.dim = 1; R.ML = 3; R.K = 2; R.NV = 2; R.NQE = 1; R.T0 = 2.0;
     R.ex = {0, 1, 2}; R.ey = {0, 0, 0};
     R.xv = {-1.0, 1.0};
@@ -503,7 +624,7 @@ struct Solver {
   double s = 0.0, dt = 0.0;
   std::vector<double> theta_mom, theta_sc, Qlim, Vol, Qupd;
   std::vector<double> fLxW_ik, fLxF_ik, Lam_ik, c_ik, Lam_e_ik;  // per (element, local edge)
-  std::vector<double> qderiv;  // q_t and q_tt at the interior points: N x NI x 2 x V
+  std::vector<double> qderiv;  // q_t, q_tt, q_ttt (zero below degree 3) at the interior points: N x NI x 3 x V
   // Cells the shock-capturing limiter may act on (empty: all).  A learned troubled-cell
   // indicator replaces only the detection of that limiter; this mask carries its decisions.
   std::vector<unsigned char> shock_mask;
@@ -550,6 +671,27 @@ static void hess_phi(const Mesh& M, int i, int l, const double* xi, double* H) {
         for (int b = 0; b < 2; ++b) s += Ji[a * 2 + d] * Ji[b * 2 + e] * r[a][b];
       H[d * 2 + e] = s;
     }
+}
+
+// Physical third derivatives of phi_l: T[(d dim + e) dim + f] = sum_abc Jinv[a][d] Jinv[b][e]
+// Jinv[c][f] d3 phi / dxi_a dxi_b dxi_c (affine elements).
+static void d3_phi(const Mesh& M, int i, int l, const double* xi, double* T) {
+  const RefElem& R = M.R;
+  const double* Ji = &M.Jinv[i * R.dim * R.dim];
+  if (R.dim == 1) { T[0] = Ji[0] * Ji[0] * Ji[0] * phi(R, l, xi, 3, 0); return; }
+  double r[2][2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int c = 0; c < 2; ++c) r[a][b][c] = phi(R, l, xi, (a == 0) + (b == 0) + (c == 0), (a == 1) + (b == 1) + (c == 1));
+  for (int d = 0; d < 2; ++d)
+    for (int e = 0; e < 2; ++e)
+      for (int f = 0; f < 2; ++f) {
+        double t = 0.0;
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) t += Ji[a * 2 + d] * Ji[b * 2 + e] * Ji[c * 2 + f] * r[a][b][c];
+        T[(d * 2 + e) * 2 + f] = t;
+      }
 }
 
 // q^h(xi) on element i (Sec. 1.2)
@@ -702,8 +844,29 @@ static void ft_from_derivs(int dim, double gam, double dt, const double* q, cons
   }
 }
 
-struct Trace {  // per element, local edge, edge point: q, q_t, q_tt and F_T (dim x V)
-  double q[4], qt[4], qtt[4], FT[8];
+// Degree 3: the time-averaged flux to fourth order (Sec. 2.2, the Taylor series one term further),
+//   F_T = F + dt/2 F_t + dt^2/6 F_tt + dt^3/24 F_ttt,
+//   F_ttt = F^(3)(q_t, q_t, q_t) + 3 H(q_t, q_tt) + A q_ttt.
+static void ft4_from_derivs(int dim, double gam, double dt, const double* q, const double* qt,
+                            const double* qtt, const double* qttt, double* FT /* dim x V */) {
+  int V = dim + 2;
+  for (int d = 0; d < dim; ++d) {
+    double F[4], Ft[4], H[4], Aqtt[4], T3[4], H2[4], Aqttt[4];
+    euler_flux<double>(dim, gam, q, d, F);
+    flux_jvp(dim, gam, q, d, qt, Ft);
+    flux_hvp(dim, gam, q, d, qt, qt, H);
+    flux_jvp(dim, gam, q, d, qtt, Aqtt);
+    flux_3vp(dim, gam, q, d, qt, qt, qt, T3);
+    flux_hvp(dim, gam, q, d, qt, qtt, H2);
+    flux_jvp(dim, gam, q, d, qttt, Aqttt);
+    for (int v = 0; v < V; ++v)
+      FT[d * V + v] = F[v] + 0.5 * dt * Ft[v] + (dt * dt / 6.0) * (H[v] + Aqtt[v]) +
+                      (dt * dt * dt / 24.0) * (T3[v] + 3.0 * H2[v] + Aqttt[v]);
+  }
+}
+
+struct Trace {  // per element, local edge, edge point: q and its time derivatives, F_T (dim x V)
+  double q[4], qt[4], qtt[4], qttt[4], FT[8];
 };
 
 // The shock-capturing limiter (Sec. 1.5 Step 5, Sec. 4.1).  The paper cites this limiter but does
@@ -883,11 +1046,11 @@ static int step(Solver& S, double T) {
   //   V_l = (1/|T|) int grad phi_l . F_T  ~  sum_m w_m grad phi_l(x_m) . F_T(x_m).
   std::vector<Trace> tr((size_t)N * K * NQE);
   S.Vol.assign((size_t)N * QS, 0.0);
-  S.qderiv.assign((size_t)N * NI * 2 * V, 0.0);
+  S.qderiv.assign((size_t)N * NI * 3 * V, 0.0);
 #pragma omp parallel for schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     const double* Qi = &S.Q[i * QS];
-    double Fh[2][4][9];
+    double Fh[2][4][10];
     for (int d = 0; d < dim; ++d)
       for (int v = 0; v < V; ++v)
         for (int l = 0; l < ML; ++l) Fh[d][v][l] = 0.0;
@@ -902,7 +1065,7 @@ static int step(Solver& S, double T) {
           for (int l = 0; l < ML; ++l) Fh[d][v][l] += R.w_int[m] * F[v] * phi(R, l, xi);
       }
     }
-    auto at_point = [&](const double* xi, double* q, double* qt, double* qtt, double* FT) {
+    auto at_point = [&](const double* xi, double* q, double* qt, double* qtt, double* qttt, double* FT) {
       double dq[2][4], D[4], dD[2][4];
       eval_q(M, Qi, xi, q);
       for (int v = 0; v < V; ++v) {
@@ -929,16 +1092,67 @@ static int step(Solver& S, double T) {
         flux_jvp(dim, gam, q, d, dD[d], a);
         for (int v = 0; v < V; ++v) qtt[v] += h[v] + a[v];
       }
-      ft_from_derivs(dim, gam, dt, q, qt, qtt, FT);
+      if (R.deg != 3) {
+        for (int v = 0; v < V; ++v) qttt[v] = 0.0;
+        ft_from_derivs(dim, gam, dt, q, qt, qtt, FT);
+        return;
+      }
+      // Degree 3 (the same chain rule one derivative further):
+      //   q_ttt = -sum_d d_d F_tt,d = -sum_d [F3_d(d_d q, q_t, q_t) + 2 H_d(d_d q_t, q_t)
+      //                                       + H_d(d_d q, q_tt) + A_d d_d q_tt],
+      //   d_e q_t = -d_e D,
+      //   d_e q_tt = sum_d [F3_d(d_e q, d_d q, D) + H_d(d_e d_d q, D) + H_d(d_d q, d_e D)
+      //                     + H_d(d_e q, d_d D) + A_d d_e d_d D],
+      // with the Hessian of q and that of D = div F^h (third derivatives of F^h).
+      double Hq[2][2][4], HD[2][2][4];
+      for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b)
+          for (int v = 0; v < V; ++v) { Hq[a][b][v] = 0.0; HD[a][b][v] = 0.0; }
+      for (int l = 0; l < ML; ++l) {
+        double H[4], T3[8];
+        hess_phi(M, i, l, xi, H);
+        d3_phi(M, i, l, xi, T3);
+        for (int v = 0; v < V; ++v)
+          for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) {
+              Hq[a][b][v] += Qi[v * ML + l] * H[a * dim + b];
+              for (int d = 0; d < dim; ++d) HD[a][b][v] += Fh[d][v][l] * T3[(d * dim + a) * dim + b];
+            }
+      }
+      double dqtt[2][4];
+      for (int e = 0; e < dim; ++e) {
+        for (int v = 0; v < V; ++v) dqtt[e][v] = 0.0;
+        for (int d = 0; d < dim; ++d) {
+          double t1[4], t2[4], t3[4], t4[4], t5[4];
+          flux_3vp(dim, gam, q, d, dq[e], dq[d], D, t1);
+          flux_hvp(dim, gam, q, d, Hq[e][d], D, t2);
+          flux_hvp(dim, gam, q, d, dq[d], dD[e], t3);
+          flux_hvp(dim, gam, q, d, dq[e], dD[d], t4);
+          flux_jvp(dim, gam, q, d, HD[e][d], t5);
+          for (int v = 0; v < V; ++v) dqtt[e][v] += t1[v] + t2[v] + t3[v] + t4[v] + t5[v];
+        }
+      }
+      for (int v = 0; v < V; ++v) qttt[v] = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        double dqt[4], t1[4], t2[4], t3[4], t4[4];
+        for (int v = 0; v < V; ++v) dqt[v] = -dD[d][v];
+        flux_3vp(dim, gam, q, d, dq[d], qt, qt, t1);
+        flux_hvp(dim, gam, q, d, dqt, qt, t2);
+        flux_hvp(dim, gam, q, d, dq[d], qtt, t3);
+        flux_jvp(dim, gam, q, d, dqtt[d], t4);
+        for (int v = 0; v < V; ++v) qttt[v] -= t1[v] + 2.0 * t2[v] + t3[v] + t4[v];
+      }
+      ft4_from_derivs(dim, gam, dt, q, qt, qtt, qttt, FT);
     };
     double* Vi = &S.Vol[i * QS];
     for (int m = 0; m < NI; ++m) {
       const double* xi = &R.xi_int[m * dim];
-      double q[4], qt[4], qtt[4], FT[8];
-      at_point(xi, q, qt, qtt, FT);
+      double q[4], qt[4], qtt[4], qttt[4], FT[8];
+      at_point(xi, q, qt, qtt, qttt, FT);
       for (int v = 0; v < V; ++v) {
-        S.qderiv[(((size_t)i * NI + m) * 2 + 0) * V + v] = qt[v];
-        S.qderiv[(((size_t)i * NI + m) * 2 + 1) * V + v] = qtt[v];
+        S.qderiv[(((size_t)i * NI + m) * 3 + 0) * V + v] = qt[v];
+        S.qderiv[(((size_t)i * NI + m) * 3 + 1) * V + v] = qtt[v];
+        S.qderiv[(((size_t)i * NI + m) * 3 + 2) * V + v] = qttt[v];
       }
       for (int l = 0; l < ML; ++l) {
         double g[2];
@@ -955,7 +1169,7 @@ static int step(Solver& S, double T) {
         double xi[2] = {0, 0};
         edge_point(R, k, j, xi);
         Trace& T_ = tr[((size_t)i * K + k) * NQE + j];
-        at_point(xi, T_.q, T_.qt, T_.qtt, T_.FT);
+        at_point(xi, T_.q, T_.qt, T_.qtt, T_.qttt, T_.FT);
       }
   }
 
@@ -984,15 +1198,21 @@ static int step(Solver& S, double T) {
         for (int v = 0; v < V; ++v) qp[v] = Tp.q[v];
         for (int x = 0; x < dim * V; ++x) FTp[x] = Tp.FT[x];
       } else if (bc == BC_REFLECTIVE) {
-        double qt[4], qtt[4];
+        double qt[4], qtt[4], qttt[4];
         bc_reflect(dim, Tm.q, nh, qp);
         bc_reflect(dim, Tm.qt, nh, qt);
         bc_reflect(dim, Tm.qtt, nh, qtt);
-        ft_from_derivs(dim, gam, dt, qp, qt, qtt, FTp);
+        if (R.deg == 3) {
+          bc_reflect(dim, Tm.qttt, nh, qttt);
+          ft4_from_derivs(dim, gam, dt, qp, qt, qtt, qttt, FTp);
+        } else {
+          ft_from_derivs(dim, gam, dt, qp, qt, qtt, FTp);
+        }
       } else if (bc == BC_INFLOW) {
         double z[4] = {0, 0, 0, 0};
         for (int v = 0; v < V; ++v) qp[v] = qbj[v];
-        ft_from_derivs(dim, gam, dt, qp, z, z, FTp);
+        if (R.deg == 3) ft4_from_derivs(dim, gam, dt, qp, z, z, z, FTp);
+        else ft_from_derivs(dim, gam, dt, qp, z, z, FTp);
       } else {
         for (int v = 0; v < V; ++v) qp[v] = Tm.q[v];
         for (int x = 0; x < dim * V; ++x) FTp[x] = Tm.FT[x];
@@ -1267,12 +1487,22 @@ int ora_stage(void* s, int stage, double* out) {
 
 // Reference element tables, for tests: basis monomial coefficients, interior points and weights,
 // edge points (reference coordinates), and basis values/derivatives at an arbitrary point.
-void ora_ref_info(int kind, int* out) {
-  RefElem R = make_ref(kind);
+// Polynomial degree of a mesh's elements (2 by default; 3 for lines and triangles).  Returns 0, or
+// -1 for a degree the element kind does not have here.
+int ora_mesh_set_degree(void* m, int deg) {
+  Mesh* M = (Mesh*)m;
+  if (deg != 2 && deg != 3) return -1;
+  RefElem R = make_ref(M->R.kind, deg);
+  if (R.ML == 0) return -1;
+  M->R = R;
+  return 0;
+}
+void ora_ref_info(int kind, int deg, int* out) {
+  RefElem R = make_ref(kind, deg);
   out[0] = R.dim; out[1] = R.ML; out[2] = R.K; out[3] = R.NI; out[4] = R.NQE;
 }
-void ora_ref_tables(int kind, double* C, double* xi_int, double* w_int, double* xi_edge, double* om_edge) {
-  RefElem R = make_ref(kind);
+void ora_ref_tables(int kind, int deg, double* C, double* xi_int, double* w_int, double* xi_edge, double* om_edge) {
+  RefElem R = make_ref(kind, deg);
   for (size_t x = 0; x < R.C.size(); ++x) C[x] = R.C[x];
   for (size_t x = 0; x < R.xi_int.size(); ++x) xi_int[x] = R.xi_int[x];
   for (int m = 0; m < R.NI; ++m) w_int[m] = R.w_int[m];
@@ -1285,9 +1515,18 @@ void ora_ref_tables(int kind, double* C, double* xi_int, double* w_int, double* 
     }
   for (int j = 0; j < R.NQE; ++j) om_edge[j] = R.om_edge[j];
 }
-double ora_phi(int kind, int l, const double* xi, int da, int db) {
-  static RefElem R[3] = {make_ref(0), make_ref(1), make_ref(2)};
-  return phi(R[kind], l, xi, da, db);
+double ora_phi(int kind, int deg, int l, const double* xi, int da, int db) {
+  static RefElem R[2][3] = {{make_ref(0), make_ref(1), make_ref(2)}, {make_ref(0, 3), make_ref(1, 3), make_ref(2, 3)}};
+  return phi(R[deg == 3 ? 1 : 0][kind], l, xi, da, db);
+}
+// Third derivative of the flux applied to three vectors, and F_T to fourth order, for tests.
+void ora_flux_3vp(int dim, double gam, const double* q, int d, const double* x, const double* y, const double* z,
+                  double* out) {
+  flux_3vp(dim, gam, q, d, x, y, z, out);
+}
+void ora_ft4(int dim, double gam, double dt, const double* q, const double* qt, const double* qtt, const double* qttt,
+             double* FT) {
+  ft4_from_derivs(dim, gam, dt, q, qt, qtt, qttt, FT);
 }
 
 // Flux, Jacobian-vector and Hessian-vector products, for tests.
