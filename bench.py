@@ -108,11 +108,11 @@ def _timed(S, steps):
     return e0.elapsed_time(e1)
 
 
-def time_gpu(L, mesh, Q0, precision, steps, warmup, kernel_events=True):
+def time_gpu(L, mesh, Q0, precision, steps, warmup, kernel_events=True, kw=None):
     """Two timed regions of `steps` steps each after `warmup` steps: (1) every kernel launched by
     the library with HIP events around each launch (per-kernel durations); (2) the step replayed
     from its HIP graph."""
-    S = L.Solver(mesh, precision=precision)
+    S = L.Solver(mesh, precision=precision, **(kw or {}))
     S.set_state(Q0)
     S.run_steps(warmup)
     S.sync()
@@ -550,6 +550,30 @@ def cartesian_blast_leg(L, n=512, steps=100, warmup=5):
     return out
 
 
+def p3_leg(L, mesh, xy, tri, steps, warmup):
+    """The degree-3 step (P3, F_T to dt^3) on the benchmark's triangle mesh and four-quadrant data
+    (averages, higher modes zero), CFL 0.05, both forms: ms per step from graph replay, per-kernel
+    times, element and degree-of-freedom updates per second, and FP32-mixed vs FP64 after the same
+    steps."""
+    from paper_1601_08145_amd import inputs as I
+    Q0 = I.averages_to_modal(I.cell_average_state(I.four_quadrant_fn(0), I.tri_sample_points(xy, tri, 2), 1.4), 10)
+    n = mesh.N
+    out = {"n_elem": n, "modes": 10, "cfl": 0.05, "steps": steps}
+    res = {}
+    for prec, name in ((L.FP32_MIXED, "FP32_MIXED"), (L.FP64, "FP64")):
+        r = time_gpu(L, mesh, Q0, prec, steps, warmup, kw={"degree": 3, "cfl": 0.05})
+        res[name] = r
+        ms = r["ms_graph"] / steps
+        out[name] = {"ms_per_step": ms, "element_updates_per_s": n / (ms * 1e-3), "dof_updates_per_s": 10 * n / (ms * 1e-3),
+                     "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in r["kernels"].items() if v[1]}}
+        log(f"[bench]   P3 triangles, {name}: {ms:.3f} ms/step ({out[name]['element_updates_per_s']:.3e} element-updates/s, "
+            f"{out[name]['dof_updates_per_s']:.3e} modes/s); kernels "
+            f"{ {k: round(v * 1e3, 1) for k, v in out[name]['kernels_ms'].items()} } us")
+    out["rel_l1_fp32_vs_fp64"] = rel_l1(res["FP32_MIXED"]["Q"], res["FP64"]["Q"])
+    log(f"[bench]   P3 FP32-mixed vs FP64 after {warmup + 2 * steps} steps: rel L1 {out['rel_l1_fp32_vs_fp64']:.2e}")
+    return out
+
+
 def sedov_disk_steps(L, steps, warmup, t_start=0.05):
     """The 2D Sedov blast (136k triangles, FP32-mixed), advanced to t_start, then `warmup` and
     `steps` steps replayed from the graph: the near-vacuum core keeps the flux and moment limiters
@@ -669,6 +693,8 @@ def main():
     ap.add_argument("--sedov-2d-end", type=float, default=0.1, help="end time of the 2D Sedov run (default 0.1)")
     ap.add_argument("--no-exact-theta", action="store_true", help="skip the exact moment-limiter factor leg")
     ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian Q2 blast leg")
+    ap.add_argument("--no-p3", action="store_true", help="skip the degree-3 leg")
+    ap.add_argument("--p3-only", action="store_true", help="run only the degree-3 leg (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -709,6 +735,9 @@ def main():
     xy, tri, Q0 = build_workload()
     mesh = L.Mesh.tri(xy, tri)
     N = mesh.N
+    if args.p3_only:
+        print(json.dumps({"p3": p3_leg(L, mesh, xy, tri, args.steps, args.warmup)}), flush=True)
+        return
 
     log(f"[bench] FP32-mixed: {args.warmup} warm-up + 2 x {args.steps} timed steps")
     mix = time_gpu(L, mesh, Q0, L.FP32_MIXED, args.steps, args.warmup, not args.no_kernel_events)
@@ -785,6 +814,9 @@ def main():
     if not args.no_diffraction:
         log("[bench] shock diffraction (whole runs)")
         out["diffraction"] = diffraction_leg(L)
+    if not args.no_p3:
+        log("[bench] degree 3 (P3 triangles)")
+        out["p3"] = p3_leg(L, mesh, xy, tri, args.steps, args.warmup)
     if not args.no_cartesian:
         log("[bench] Cartesian Q2 near-vacuum blast")
         out["cartesian_blast"] = cartesian_blast_leg(L)

@@ -26,7 +26,10 @@
  *    in 1D local edge 0 is the left end and 1 the right end.
  *  - Basis: Gram-Schmidt orthonormalisation, under (1/|T0|) int_{T0} f g, of the monomials
  *    1D {1, x, x^2}; quadrilateral {1, x, y, x^2, xy, y^2, x^2 y, x y^2, x^2 y^2} (tensor Legendre,
- *    9 modes); triangle {1, x, y, x^2, xy, y^2} (6 modes).
+ *    9 modes); triangle {1, x, y, x^2, xy, y^2} (6 modes).  At degree 3 (line and triangle, the
+ *    construction of Sec. 2.2 one order further): 1D {1, x, x^2, x^3} (4 modes), triangle
+ *    {1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3} (10 modes); n_modes in Q is then the
+ *    degree's count, not the mesh's (lxw_mesh_get_info reports degree 2).
  */
 #ifndef LXW_H
 #define LXW_H
@@ -42,7 +45,7 @@ typedef int32_t lxw_status;
 enum {
   LXW_OK = 0,
   LXW_ERR_ARG = -1,         /* invalid argument (null pointer, size, enum value) */
-  LXW_ERR_UNSUPPORTED = -2, /* valid but not implemented (e.g. degree != 2) */
+  LXW_ERR_UNSUPPORTED = -2, /* valid but not implemented (e.g. degree 4, or degree 3 on quadrilaterals) */
   LXW_ERR_MESH = -3,        /* non-positive area, clockwise triangle, bad connectivity */
   LXW_ERR_STATE = -4,       /* input state violates rho_bar >= eps0, p_bar > 0 (Sec. 1.5 Step 1,
                                Sec. 3.1 Step 0) or is not finite */
@@ -56,7 +59,8 @@ enum {
 
 /* Boundary conditions (Sec. 2.4).  Periodic pairs opposite sides.  Transparent: ghost state
  * equals the interior trace.  Reflective: normal momentum negated, tangential kept, and the same
- * for q_t and q_tt.  Inflow: a fixed Dirichlet state (lxw_params.inflow) with q_t = q_tt = 0. */
+ * for q_t and q_tt (and q_ttt at degree 3).  Inflow: a fixed Dirichlet state (lxw_params.inflow)
+ * with q_t = q_tt = 0 (and q_ttt = 0). */
 enum { LXW_BC_PERIODIC = 0, LXW_BC_TRANSPARENT = 1, LXW_BC_REFLECTIVE = 2, LXW_BC_INFLOW = 3 };
 
 /* Mesh kinds. */
@@ -87,7 +91,10 @@ typedef struct lxw_indicator lxw_indicator;
 
 typedef struct lxw_params {
   double gamma;      /* ratio of specific heats, Eq. (eos); > 1 */
-  int32_t degree;    /* polynomial degree M_D; only 2 is supported (LXW_ERR_UNSUPPORTED else) */
+  int32_t degree;    /* polynomial degree M_D: 2, or 3 on line and triangle meshes for single-mesh
+                        solvers without the learned indicator (LXW_ERR_UNSUPPORTED else).  Degree 3
+                        adds q_ttt to the time-averaged flux (Sec. 2.2: F_T to dt^3); it is stable
+                        at smaller Courant numbers than degree 2 (0.05 where 0.1 is not) */
   double cfl;        /* CFL number nu: dt = nu / (s * max_i |dT_i| / (2 |T_i|)), s the global
                         maximum wave speed; the paper uses 0.08 (Sec. 4.1); must be in (0, 1] */
   double eps0;       /* density cutoff eps0 of Sec. 3.1 Step 0 (1e-12 in the paper); > 0 */
@@ -173,12 +180,18 @@ lxw_status lxw_mesh_get_info(const lxw_mesh* m, lxw_mesh_info* out);
  * 7-point degree-5 rule; 3-point and 3x3 Gauss-Legendre in 1D and on quadrilaterals). */
 lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w, double* phi);
 
+/* The same at polynomial degree `degree` (2, or 3 for LXW_LINE and LXW_TRI; LXW_ERR_UNSUPPORTED
+ * else).  Degree 3: the 4-point Gauss-Legendre rule in 1D and a 16-point collapsed Gauss rule on
+ * the triangle (both exact to degree 7), phi[n_pts][4] or [n_pts][10]; the projection is exact for
+ * f of degree <= 4. */
+lxw_status lxw_refelem_info_deg(int32_t kind, int32_t degree, int32_t* n_pts, double* xi, double* w, double* phi);
+
 /* ---- Solver ------------------------------------------------------------------------------ */
 
 /* Creates a solver on device 0 for mesh m (which must outlive it).  stream: a hipStream_t (null
  * for the default stream); every kernel of the solver runs on it.  Allocates all device memory
  * the step needs.  Device arrays use 32-bit indices: n_var * n_modes * n_elem and
- * 2 * q * n_var * n_edges (q = 3 edge points in 2D, 1 in 1D) must not exceed 2^31 - 1 (about 89
+ * 2 * q * n_var * n_edges (q = degree + 1 edge points in 2D, 1 in 1D) must not exceed 2^31 - 1 (about 89
  * million P2 triangles or 59 million Q2 quadrilaterals per solver).  Errors: LXW_ERR_ARG / LXW_ERR_UNSUPPORTED for bad parameters or a
  * mesh above that size, LXW_ERR_OOM, LXW_ERR_DEVICE. */
 lxw_status lxw_solver_create(const lxw_mesh* m, const lxw_params* p, void* stream, lxw_solver** out);

@@ -43,9 +43,8 @@ lxw_status fail(lxw_status code, const std::string& msg) {
 // 3x3 tensor product on the square, and the symmetric 7-point degree-5 rule on the triangle
 // (centroid plus two three-point orbits).  Basis: on the line and the square the orthonormal
 // Legendre polynomials sqrt(2n+1) P_n and their products; on the triangle the monomials
-// 1, x, y, x^2, xy, y^2 orthonormalised through the Cholesky factor of their Gram matrix
-// (computed with the 7-point rule, exact for these degree-4 products), which is Gram-Schmidt in
-// that order.
+// 1, x, y, x^2, xy, y^2 (and at degree 3 x^3, x^2 y, x y^2, y^3) orthonormalised through the
+// Cholesky factor of their Gram matrix, which is Gram-Schmidt in that order.
 // ---------------------------------------------------------------------------------------------
 struct Rule {
   std::vector<double> x, w;  // points (n x dim), weights summing to 1
@@ -81,20 +80,112 @@ Rule rule_tri() {
   return r;
 }
 
-// Legendre, orthonormal on [-1,1] under (1/2) int: value and derivatives of order 0..2.
+// Degree 3: four-point Gauss-Legendre, nodes +-sqrt(3/7 -+ (2/7) sqrt(6/5)) with weights
+// (18 +- sqrt 30)/36, on the edges and in 1D; on the triangle the collapsed product rule
+// (xi, eta) = ((1 + s)/2 (1 - t), t), t = (1 + x)/2, of the four Gauss-Legendre nodes s and the
+// four Gauss-Jacobi nodes x of the weight 1 - x (the Jacobian 1 - t of the collapse), 16 points
+// exact to degree 7.  The Gauss-Jacobi nodes and weights are the eigenvalues and squared first
+// eigenvector components (times int (1 - x) dx = 2) of the symmetric Jacobi matrix of the
+// three-term recurrence (Golub-Welsch), found by cyclic Jacobi rotations.
+double GL4_S[4], GL4_W[4];
+struct GL4Init {
+  GL4Init() {
+    const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    const double wa = (18.0 + std::sqrt(30.0)) / 36.0, wb = (18.0 - std::sqrt(30.0)) / 36.0;
+    const double s[4] = {-b, -a, a, b}, w[4] = {wb, wa, wa, wb};
+    for (int i = 0; i < 4; ++i) { GL4_S[i] = s[i]; GL4_W[i] = w[i]; }
+  }
+} gl4_init;
+
+void gauss_jacobi4(double* x, double* w) {
+  const double al = 1.0, be = 0.0;
+  double A[4][4] = {}, Z[4][4] = {};
+  for (int n = 0; n < 4; ++n) {
+    const double s = 2.0 * n + al + be;
+    A[n][n] = (be * be - al * al) / (s * (s + 2.0));
+    Z[n][n] = 1.0;
+    if (n + 1 < 4) {
+      const double m = n + 1.0, t = 2.0 * m + al + be;
+      const double off = std::sqrt(4.0 * m * (m + al) * (m + be) * (m + al + be) / (t * t * (t + 1.0) * (t - 1.0)));
+      A[n][n + 1] = A[n + 1][n] = off;
+    }
+  }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double offn = 0.0;
+    for (int p = 0; p < 4; ++p)
+      for (int q = p + 1; q < 4; ++q) offn += A[p][q] * A[p][q];
+    if (offn < 1e-40) break;
+    for (int p = 0; p < 4; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        if (A[p][q] == 0.0) continue;
+        const double th = 0.5 * (A[q][q] - A[p][p]) / A[p][q];
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 4; ++k) {  // A <- A G (columns p, q)
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 4; ++k) {  // A <- G^T A (rows p, q)
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 4; ++k) {  // eigenvectors
+          const double zkp = Z[k][p], zkq = Z[k][q];
+          Z[k][p] = c * zkp - sn * zkq;
+          Z[k][q] = sn * zkp + c * zkq;
+        }
+      }
+  }
+  int idx[4] = {0, 1, 2, 3};
+  std::sort(idx, idx + 4, [&](int i, int j) { return A[i][i] < A[j][j]; });
+  for (int k = 0; k < 4; ++k) {
+    x[k] = A[idx[k]][idx[k]];
+    w[k] = 2.0 * Z[0][idx[k]] * Z[0][idx[k]];
+  }
+}
+
+Rule rule_line4() {
+  Rule r;
+  for (int i = 0; i < 4; ++i) { r.x.push_back(GL4_S[i]); r.w.push_back(GL4_W[i] / 2.0); }
+  return r;
+}
+Rule rule_tri16() {
+  double xj[4], wj[4];
+  gauss_jacobi4(xj, wj);
+  Rule r;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const double t = 0.5 * (1.0 + xj[j]);
+      r.x.push_back(0.5 * (1.0 + GL4_S[i]) * (1.0 - t));
+      r.x.push_back(t);
+      r.w.push_back(0.25 * GL4_W[i] * wj[j]);  // (1/8) int (1 - x) ds dx over the area 1/2
+    }
+  return r;
+}
+
+// Legendre, orthonormal on [-1,1] under (1/2) int: sqrt(2n+1) P_n, n <= 3, and its derivatives.
 double leg(int n, double x, int der) {
-  const double s3 = std::sqrt(3.0), s5 = std::sqrt(5.0);
+  const double s3 = std::sqrt(3.0), s5 = std::sqrt(5.0), s7 = std::sqrt(7.0);
   if (n == 0) return der == 0 ? 1.0 : 0.0;
   if (n == 1) return der == 0 ? s3 * x : (der == 1 ? s3 : 0.0);
-  if (der == 0) return 0.5 * s5 * (3.0 * x * x - 1.0);
-  if (der == 1) return 3.0 * s5 * x;
-  return 3.0 * s5;
+  if (n == 2) {
+    if (der == 0) return 0.5 * s5 * (3.0 * x * x - 1.0);
+    if (der == 1) return 3.0 * s5 * x;
+    return der == 2 ? 3.0 * s5 : 0.0;
+  }
+  if (der == 0) return 0.5 * s7 * (5.0 * x * x * x - 3.0 * x);
+  if (der == 1) return 0.5 * s7 * (15.0 * x * x - 3.0);
+  if (der == 2) return 15.0 * s7 * x;
+  return der == 3 ? 15.0 * s7 : 0.0;
 }
 
 const int QUAD_I[9] = {0, 1, 0, 2, 1, 0, 2, 1, 2};
 const int QUAD_J[9] = {0, 0, 1, 0, 1, 2, 1, 2, 2};
-const int TRI_EX[6] = {0, 1, 0, 2, 1, 0};
-const int TRI_EY[6] = {0, 0, 1, 0, 1, 2};
+const int TRI_EX[10] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0};
+const int TRI_EY[10] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
 
 double dmono(double x, int n, int k) {
   if (k > n) return 0.0;
@@ -105,29 +196,32 @@ double dmono(double x, int n, int k) {
   return r;
 }
 
+// The first ML of the monomials above (6 for P2, 10 for P3) orthonormalised on the triangle
+// through the Cholesky factor of their Gram matrix, whose entries are the exact moments
+// (1/|T0|) int x^a y^b = 2 a! b! / (a + b + 2)!.
+template <int ML>
 struct TriBasis {
-  double C[6][6];  // phi_l = sum_j C[l][j] x^ex_j y^ey_j
+  double C[ML][ML];  // phi_l = sum_j C[l][j] x^ex_j y^ey_j
   TriBasis() {
-    Rule r = rule_tri();
-    double G[6][6] = {};
-    for (size_t q = 0; q < r.w.size(); ++q) {
-      double m[6];
-      for (int a = 0; a < 6; ++a) m[a] = dmono(r.x[2 * q], TRI_EX[a], 0) * dmono(r.x[2 * q + 1], TRI_EY[a], 0);
-      for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) G[a][b] += r.w[q] * m[a] * m[b];
-    }
-    double L[6][6] = {};
-    for (int i = 0; i < 6; ++i)
+    auto fact = [](int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; };
+    double G[ML][ML];
+    for (int a = 0; a < ML; ++a)
+      for (int b = 0; b < ML; ++b) {
+        const int px = TRI_EX[a] + TRI_EX[b], py = TRI_EY[a] + TRI_EY[b];
+        G[a][b] = 2.0 * fact(px) * fact(py) / fact(px + py + 2);
+      }
+    double L[ML][ML] = {};
+    for (int i = 0; i < ML; ++i)
       for (int j = 0; j <= i; ++j) {
         double s = G[i][j];
         for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
         L[i][j] = (i == j) ? std::sqrt(s) : s / L[j][j];
       }
     // C = L^{-1} (lower triangular)
-    for (int i = 0; i < 6; ++i)
-      for (int j = 0; j < 6; ++j) C[i][j] = 0.0;
-    for (int col = 0; col < 6; ++col)
-      for (int i = col; i < 6; ++i) {
+    for (int i = 0; i < ML; ++i)
+      for (int j = 0; j < ML; ++j) C[i][j] = 0.0;
+    for (int col = 0; col < ML; ++col)
+      for (int i = col; i < ML; ++i) {
         double s = (i == col) ? 1.0 : 0.0;
         for (int k = col; k < i; ++k) s -= L[i][k] * C[k][col];
         C[i][col] = s / L[i][i];
@@ -135,13 +229,18 @@ struct TriBasis {
   }
 };
 
-// basis value / derivative: dx, dy derivative orders
-double basis(int kind, int l, const double* xi, int dx, int dy) {
+// basis value / derivative at polynomial degree deg (2, or 3 on the line and the triangle): dx, dy
+// derivative orders
+double basis(int kind, int deg, int l, const double* xi, int dx, int dy) {
   if (kind == LXW_LINE) return dy ? 0.0 : leg(l, xi[0], dx);
   if (kind == LXW_QUAD) return leg(QUAD_I[l], xi[0], dx) * leg(QUAD_J[l], xi[1], dy);
-  static const TriBasis tb;
+  static const TriBasis<6> tb2;
+  static const TriBasis<10> tb3;
   double s = 0.0;
-  for (int j = 0; j < 6; ++j) s += tb.C[l][j] * dmono(xi[0], TRI_EX[j], dx) * dmono(xi[1], TRI_EY[j], dy);
+  if (deg == 3)
+    for (int j = 0; j < 10; ++j) s += tb3.C[l][j] * dmono(xi[0], TRI_EX[j], dx) * dmono(xi[1], TRI_EY[j], dy);
+  else
+    for (int j = 0; j < 6; ++j) s += tb2.C[l][j] * dmono(xi[0], TRI_EX[j], dx) * dmono(xi[1], TRI_EY[j], dy);
   return s;
 }
 
@@ -156,18 +255,28 @@ void ref_vertex(int kind, int a, double* xi) {
   else { xi[0] = tri[2 * a]; xi[1] = tri[2 * a + 1]; }
 }
 
+template <class E>
+Rule rule_of() {
+  if constexpr (E::DEG == 3) return E::kind == LXW_LINE ? rule_line4() : rule_tri16();
+  else return E::kind == LXW_LINE ? rule_line() : (E::kind == LXW_QUAD ? rule_quad() : rule_tri());
+}
+// Gauss-Legendre node j of the edges and its weight on [-1, 1]
+template <class E>
+double edge_s(int j) { return E::DEG == 3 ? GL4_S[j] : GL_S[j]; }
+template <class E>
+double edge_w(int j) { return E::DIM == 1 ? 2.0 : (E::DEG == 3 ? GL4_W[j] : GL_W[j]); }
+
 // limiter / update points: interior rule, then edge k Gauss point j (counter-clockwise)
 template <class E>
 std::vector<double> all_points() {
-  Rule r = E::kind == LXW_LINE ? rule_line() : (E::kind == LXW_QUAD ? rule_quad() : rule_tri());
-  std::vector<double> pts = r.x;
+  std::vector<double> pts = rule_of<E>().x;
   for (int k = 0; k < E::K; ++k)
     for (int j = 0; j < E::NQE; ++j) {
       double a[2] = {0, 0}, b[2] = {0, 0};
       ref_vertex(E::kind, k, a);
       ref_vertex(E::kind, (k + 1) % nverts(E::kind), b);
       if (E::DIM == 1) { pts.push_back(a[0]); continue; }
-      const double t = 0.5 * (1.0 + GL_S[j]);
+      const double t = 0.5 * (1.0 + edge_s<E>(j));
       pts.push_back(a[0] + t * (b[0] - a[0]));
       pts.push_back(a[1] + t * (b[1] - a[1]));
     }
@@ -177,18 +286,19 @@ std::vector<double> all_points() {
 template <class E, class R>
 void fill_tab(RefTab<E, R>& T) {
   std::memset(&T, 0, sizeof(T));
-  Rule r = E::kind == LXW_LINE ? rule_line() : (E::kind == LXW_QUAD ? rule_quad() : rule_tri());
+  Rule r = rule_of<E>();
   std::vector<double> pts = all_points<E>();
+  auto B = [](int l, const double* xi, int dx, int dy) { return basis(E::kind, E::DEG, l, xi, dx, dy); };
   for (int p = 0; p < E::NP; ++p) {
     double xi[2] = {pts[p * E::DIM], E::DIM == 2 ? pts[p * E::DIM + 1] : 0.0};
     for (int l = 0; l < E::ML; ++l) {
-      T.phi[p][l] = R(basis(E::kind, l, xi, 0, 0));
-      T.dphi[p][0][l] = R(basis(E::kind, l, xi, 1, 0));
-      T.d2phi[p][0][l] = R(basis(E::kind, l, xi, 2, 0));
+      T.phi[p][l] = R(B(l, xi, 0, 0));
+      T.dphi[p][0][l] = R(B(l, xi, 1, 0));
+      T.d2phi[p][0][l] = R(B(l, xi, 2, 0));
       if constexpr (E::DIM == 2) {
-        T.dphi[p][1][l] = R(basis(E::kind, l, xi, 0, 1));
-        T.d2phi[p][1][l] = R(basis(E::kind, l, xi, 1, 1));
-        T.d2phi[p][2][l] = R(basis(E::kind, l, xi, 0, 2));
+        T.dphi[p][1][l] = R(B(l, xi, 0, 1));
+        T.d2phi[p][1][l] = R(B(l, xi, 1, 1));
+        T.d2phi[p][2][l] = R(B(l, xi, 0, 2));
       }
     }
   }
@@ -197,31 +307,31 @@ void fill_tab(RefTab<E, R>& T) {
   {
     const double o[2] = {0.0, 0.0};
     for (int l = 0; l < E::ML; ++l) {
-      T.dphi0[0][l] = R(basis(E::kind, l, o, 1, 0));
-      T.d2c[0][l] = R(basis(E::kind, l, o, 2, 0));
+      T.dphi0[0][l] = R(B(l, o, 1, 0));
+      T.d2c[0][l] = R(B(l, o, 2, 0));
       if constexpr (E::DIM == 2) {
-        T.dphi0[1][l] = R(basis(E::kind, l, o, 0, 1));
-        T.d2c[1][l] = R(basis(E::kind, l, o, 1, 1));
-        T.d2c[2][l] = R(basis(E::kind, l, o, 0, 2));
+        T.dphi0[1][l] = R(B(l, o, 0, 1));
+        T.d2c[1][l] = R(B(l, o, 1, 1));
+        T.d2c[2][l] = R(B(l, o, 0, 2));
       }
+      if constexpr (E::DEG == 3)  // third derivatives, j of them in eta
+        for (int j = 0; j < E::ND3; ++j) T.d3c[j][l] = R(B(l, o, 3 - j, j));
     }
   }
   for (int m = 0; m < E::NI; ++m)
     for (int l = 0; l < E::ML; ++l) {
       double xi[2] = {pts[m * E::DIM], E::DIM == 2 ? pts[m * E::DIM + 1] : 0.0};
-      T.wphi[m][l] = R(r.w[m] * basis(E::kind, l, xi, 0, 0));
-      T.wdphi[m][0][l] = R(r.w[m] * basis(E::kind, l, xi, 1, 0));
-      if constexpr (E::DIM == 2) T.wdphi[m][1][l] = R(r.w[m] * basis(E::kind, l, xi, 0, 1));
+      T.wphi[m][l] = R(r.w[m] * B(l, xi, 0, 0));
+      T.wdphi[m][0][l] = R(r.w[m] * B(l, xi, 1, 0));
+      if constexpr (E::DIM == 2) T.wdphi[m][1][l] = R(r.w[m] * B(l, xi, 0, 1));
     }
   // in 1D a face is a point with the single weight 2, so that (1/2) sum omega = 1
-  const double om1d[1] = {2.0};
-  for (int j = 0; j < E::NQE; ++j) T.om[j] = R(E::DIM == 1 ? om1d[0] : GL_W[j]);
+  for (int j = 0; j < E::NQE; ++j) T.om[j] = R(edge_w<E>(j));
   for (int k = 0; k < E::K; ++k)
     for (int j = 0; j < E::NQE; ++j) {
-      const double om = E::DIM == 1 ? om1d[0] : GL_W[j];
       const int p = E::NI + k * E::NQE + j;
       double xi[2] = {pts[p * E::DIM], E::DIM == 2 ? pts[p * E::DIM + 1] : 0.0};
-      for (int l = 0; l < E::ML; ++l) T.ephi[k][j][l] = R(0.5 * om * basis(E::kind, l, xi, 0, 0));
+      for (int l = 0; l < E::ML; ++l) T.ephi[k][j][l] = R(0.5 * edge_w<E>(j) * B(l, xi, 0, 0));
     }
 }
 
@@ -235,6 +345,8 @@ lxw_status ensure_init() {
   fill_tab(t->line_d); fill_tab(t->line_f);
   fill_tab(t->quad_d); fill_tab(t->quad_f);
   fill_tab(t->tri_d); fill_tab(t->tri_f);
+  fill_tab(t->line3_d); fill_tab(t->line3_f);
+  fill_tab(t->tri3_d); fill_tab(t->tri3_f);
   hipError_t e = upload_tables(*t);
   if (e != hipSuccess) {
     g_init_state = -1;
@@ -261,6 +373,7 @@ lxw_status ensure_init() {
 // ---------------------------------------------------------------------------------------------
 struct lxw_mesh {
   int kind = 0, dim = 0, N = 0, E = 0, K = 0, V = 0, ML = 0;
+  int deg = 2;                      // polynomial degree (3 only in a degree-3 solver's own copy)
   std::vector<int> perm, iperm;     // internal -> caller, caller -> internal
   std::vector<double> vx;           // internal order: N x nv x dim
   std::vector<double> area, perim, Jinv, nout, hsz;  // N; N; N*dim*dim; N*K*dim; N
@@ -273,6 +386,13 @@ struct lxw_mesh {
 };
 
 namespace {
+
+// Gauss points per face: one in 1D, degree + 1 on the sides of 2D elements.
+int nqe_of(const lxw_mesh& M) { return M.kind == LXW_LINE ? 1 : M.deg + 1; }
+
+// Element configuration of a mesh: its kind, or 3 + kind at degree 3 (line and triangle).
+enum { EK_LINE = LXW_LINE, EK_QUAD = LXW_QUAD, EK_TRI = LXW_TRI, EK_LINE3 = 3 + LXW_LINE, EK_TRI3 = 3 + LXW_TRI };
+int ekind(const lxw_mesh& M) { return M.deg == 3 ? 3 + M.kind : M.kind; }
 
 int bc_to_slot(int bc) {
   switch (bc) {
@@ -439,6 +559,7 @@ struct DevBuf {
 
 struct lxw_solver {
   const lxw_mesh* M = nullptr;
+  std::unique_ptr<lxw_mesh> own_mesh;  // degree 3: M is this copy of the caller's mesh
   lxw_params P{};
   hipStream_t st = nullptr;
   bool fp32 = false;
@@ -546,7 +667,7 @@ template <class R>
 lxw_status setup_view(lxw_solver* S, View<R>& v) {
   const lxw_mesh& M = *S->M;
   const int N = M.N, E = M.E, K = M.K, dim = M.dim, V = M.V, ML = M.ML;
-  const int NQE = M.kind == LXW_LINE ? 1 : 3;
+  const int NQE = nqe_of(M);
   std::memset(&v, 0, sizeof(v));
   v.N = N;
   v.E = E;
@@ -697,17 +818,21 @@ lxw_status enqueue_shock_t(lxw_solver* S, const View<R>& v) {
 }
 
 lxw_status enqueue_step(lxw_solver* S) {
-  switch (S->M->kind) {
-    case LXW_LINE: return S->fp32 ? enqueue_step_t<ElLine, float>(S, S->vf) : enqueue_step_t<ElLine, double>(S, S->vd);
-    case LXW_QUAD: return S->fp32 ? enqueue_step_t<ElQuad, float>(S, S->vf) : enqueue_step_t<ElQuad, double>(S, S->vd);
+  switch (ekind(*S->M)) {
+    case EK_LINE: return S->fp32 ? enqueue_step_t<ElLine, float>(S, S->vf) : enqueue_step_t<ElLine, double>(S, S->vd);
+    case EK_QUAD: return S->fp32 ? enqueue_step_t<ElQuad, float>(S, S->vf) : enqueue_step_t<ElQuad, double>(S, S->vd);
+    case EK_LINE3: return S->fp32 ? enqueue_step_t<ElLine3, float>(S, S->vf) : enqueue_step_t<ElLine3, double>(S, S->vd);
+    case EK_TRI3: return S->fp32 ? enqueue_step_t<ElTri3, float>(S, S->vf) : enqueue_step_t<ElTri3, double>(S, S->vd);
     default: return S->fp32 ? enqueue_step_t<ElTri, float>(S, S->vf) : enqueue_step_t<ElTri, double>(S, S->vd);
   }
 }
 
 lxw_status enqueue_shock(lxw_solver* S) {
-  switch (S->M->kind) {
-    case LXW_LINE: return S->fp32 ? enqueue_shock_t<ElLine, float>(S, S->vf) : enqueue_shock_t<ElLine, double>(S, S->vd);
-    case LXW_QUAD: return S->fp32 ? enqueue_shock_t<ElQuad, float>(S, S->vf) : enqueue_shock_t<ElQuad, double>(S, S->vd);
+  switch (ekind(*S->M)) {
+    case EK_LINE: return S->fp32 ? enqueue_shock_t<ElLine, float>(S, S->vf) : enqueue_shock_t<ElLine, double>(S, S->vd);
+    case EK_QUAD: return S->fp32 ? enqueue_shock_t<ElQuad, float>(S, S->vf) : enqueue_shock_t<ElQuad, double>(S, S->vd);
+    case EK_LINE3: return S->fp32 ? enqueue_shock_t<ElLine3, float>(S, S->vf) : enqueue_shock_t<ElLine3, double>(S, S->vd);
+    case EK_TRI3: return S->fp32 ? enqueue_shock_t<ElTri3, float>(S, S->vf) : enqueue_shock_t<ElTri3, double>(S, S->vd);
     default: return S->fp32 ? enqueue_shock_t<ElTri, float>(S, S->vf) : enqueue_shock_t<ElTri, double>(S, S->vd);
   }
 }
@@ -870,7 +995,7 @@ void drop_graph(lxw_solver* S) {
 }
 
 lxw_status check_params(const lxw_params* p) {
-  if (p->degree != 2) return fail(LXW_ERR_UNSUPPORTED, "only polynomial degree 2 is implemented");
+  if (p->degree != 2 && p->degree != 3) return fail(LXW_ERR_UNSUPPORTED, "polynomial degree 2 or 3");
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl <= 1.0) || !(p->eps0 > 0.0) || !(p->alpha0 >= 0.0))
     return fail(LXW_ERR_ARG, "need gamma > 1, 0 < cfl <= 1, eps0 > 0, alpha0 >= 0");
   if (p->precision != LXW_FP64 && p->precision != LXW_FP32_MIXED) return fail(LXW_ERR_ARG, "bad precision");
@@ -949,15 +1074,27 @@ lxw_status create_solver(const lxw_mesh* m, const lxw_params* p, void* stream, B
   lxw_status s = check_params(p);
   if (s) return s;
   if ((s = ensure_init())) return s;
+  std::unique_ptr<lxw_mesh> own;
+  if (p->degree == 3) {
+    if (bl) return fail(LXW_ERR_UNSUPPORTED, "degree 3 is for single-mesh solvers");
+    if (m->kind == LXW_QUAD) return fail(LXW_ERR_UNSUPPORTED, "degree 3 is for line and triangle meshes");
+    // the solver's own copy of the mesh at degree 3 (more modes; the geometry is the same)
+    own.reset(new (std::nothrow) lxw_mesh(*m));
+    if (!own) return fail(LXW_ERR_OOM, "host allocation");
+    own->deg = 3;
+    own->ML = m->kind == LXW_LINE ? ElLine3::ML : ElTri3::ML;
+    m = own.get();
+  }
   {
     // device arrays are indexed with 32-bit integers: the largest per-element array has V*ML
     // columns of N entries, the largest per-edge array 3*V columns of E entries
-    const int64_t nqe = m->kind == LXW_LINE ? 1 : 3;
+    const int64_t nqe = nqe_of(*m);
     if ((int64_t)m->V * m->ML * m->N > INT32_MAX || 2 * nqe * m->V * (int64_t)m->E > INT32_MAX)
       return fail(LXW_ERR_ARG, "mesh too large for one solver (32-bit device indices)");
   }
   std::unique_ptr<lxw_solver> S(new (std::nothrow) lxw_solver);
   if (!S) return fail(LXW_ERR_OOM, "host allocation");
+  S->own_mesh = std::move(own);
   S->M = m;
   S->P = *p;
   S->st = (hipStream_t)stream;
@@ -1003,6 +1140,7 @@ lxw_status persistent_steps_t(lxw_solver* S, const View<R>& v, int64_t n_steps) 
 }
 
 lxw_status persistent_steps(lxw_solver* S, int64_t n_steps) {
+  if (S->M->deg != 2) return fail(LXW_ERR_UNSUPPORTED, "the persistent kernel is for degree-2 batches");
   switch (S->M->kind) {
     case LXW_LINE: return S->fp32 ? persistent_steps_t<ElLine, float>(S, S->vf, n_steps) : persistent_steps_t<ElLine, double>(S, S->vd, n_steps);
     case LXW_QUAD: return S->fp32 ? persistent_steps_t<ElQuad, float>(S, S->vf, n_steps) : persistent_steps_t<ElQuad, double>(S, S->vd, n_steps);
@@ -1327,10 +1465,13 @@ lxw_status lxw_mesh_get_info(const lxw_mesh* m, lxw_mesh_info* out) {
   return LXW_OK;
 }
 
-lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w, double* phi) {
+lxw_status lxw_refelem_info_deg(int32_t kind, int32_t degree, int32_t* n_pts, double* xi, double* w, double* phi) {
   if (kind < 0 || kind > 2 || !n_pts) return fail(LXW_ERR_ARG, "bad kind or null n_pts");
-  Rule r = kind == LXW_LINE ? rule_line() : (kind == LXW_QUAD ? rule_quad() : rule_tri());
-  const int dim = kind == LXW_LINE ? 1 : 2, ML = kind == LXW_LINE ? 3 : (kind == LXW_QUAD ? 9 : 6);
+  if (degree != 2 && (degree != 3 || kind == LXW_QUAD)) return fail(LXW_ERR_UNSUPPORTED, "degree 2, or 3 on lines and triangles");
+  Rule r = degree == 3 ? (kind == LXW_LINE ? rule_line4() : rule_tri16())
+                       : (kind == LXW_LINE ? rule_line() : (kind == LXW_QUAD ? rule_quad() : rule_tri()));
+  const int dim = kind == LXW_LINE ? 1 : 2;
+  const int ML = degree == 3 ? (kind == LXW_LINE ? 4 : 10) : (kind == LXW_LINE ? 3 : (kind == LXW_QUAD ? 9 : 6));
   const int n = (int)r.w.size();
   *n_pts = n;
   if (xi) for (int x = 0; x < n * dim; ++x) xi[x] = r.x[x];
@@ -1338,9 +1479,13 @@ lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w,
   if (phi)
     for (int m = 0; m < n; ++m) {
       double p[2] = {r.x[m * dim], dim == 2 ? r.x[m * dim + 1] : 0.0};
-      for (int l = 0; l < ML; ++l) phi[m * ML + l] = basis(kind, l, p, 0, 0);
+      for (int l = 0; l < ML; ++l) phi[m * ML + l] = basis(kind, degree, l, p, 0, 0);
     }
   return LXW_OK;
+}
+
+lxw_status lxw_refelem_info(int32_t kind, int32_t* n_pts, double* xi, double* w, double* phi) {
+  return lxw_refelem_info_deg(kind, 2, n_pts, xi, w, phi);
 }
 
 lxw_status lxw_solver_create(const lxw_mesh* m, const lxw_params* p, void* stream, lxw_solver** out) {
@@ -1944,7 +2089,8 @@ lxw_status lxw_indicator_train(lxw_indicator* I, const float* X, const float* y,
 
 lxw_status lxw_indicator_collect(lxw_solver* S, float* X, double* theta_sc, int32_t flags) {
   if (check_solver(S) || !X || !theta_sc) return fail(LXW_ERR_ARG, "null argument");
-  if (S->M->kind != LXW_TRI || S->batch) return fail(LXW_ERR_UNSUPPORTED, "the indicator is for single triangle meshes");
+  if (S->M->kind != LXW_TRI || S->M->deg != 2 || S->batch)
+    return fail(LXW_ERR_UNSUPPORTED, "the indicator is for single degree-2 triangle meshes");
   lxw_status s = sync_check(S);
   if (s) return s;
   if (!S->hsc.shock_pending || !S->P.shock)
@@ -1986,7 +2132,8 @@ lxw_status lxw_indicator_collect(lxw_solver* S, float* X, double* theta_sc, int3
 
 lxw_status lxw_solver_set_indicator(lxw_solver* S, const lxw_indicator* ind, double tau_lo, double tau_hi) {
   if (check_solver(S)) return LXW_ERR_ARG;
-  if (ind && S->M->kind != LXW_TRI) return fail(LXW_ERR_UNSUPPORTED, "the indicator is for triangle meshes");
+  if (ind && (S->M->kind != LXW_TRI || S->M->deg != 2))
+    return fail(LXW_ERR_UNSUPPORTED, "the indicator is for degree-2 triangle meshes");
   if (ind && !(tau_lo >= 0.0 && tau_lo <= tau_hi && tau_hi <= 1.0))
     return fail(LXW_ERR_ARG, "need 0 <= tau_lo <= tau_hi <= 1");
   lxw_status s = sync_check(S);

@@ -8,21 +8,30 @@
 
 namespace lxw {
 
-// ---- Element configurations (Sec. 1.2): P2 on the line, tensor Q2 on quads, P2 on triangles.
-// NI interior quadrature points, K faces with NQE Gauss points each; NP = NI + K*NQE limiter
-// points (Sec. 3.1 uses exactly the points of the update); NC = 2^K - 1 pressure corners
-// (Sec. 3.3 Step 5a).
+// ---- Element configurations (Sec. 1.2): P2 on the line, tensor Q2 on quads, P2 on triangles,
+// and the degree-3 forms P3 on the line and on triangles (the construction of Sec. 2.2 carried one
+// order further).  NI interior quadrature points, K faces with NQE Gauss points each; NP = NI +
+// K*NQE limiter points (Sec. 3.1 uses exactly the points of the update); NC = 2^K - 1 pressure
+// corners (Sec. 3.3 Step 5a); ND2 / ND3 independent second / third reference derivatives.
 struct ElLine {
-  static constexpr int kind = 0, DIM = 1, V = 3, ML = 3, K = 2, NI = 3, NQE = 1;
-  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 1;
+  static constexpr int kind = 0, DEG = 2, DIM = 1, V = 3, ML = 3, K = 2, NI = 3, NQE = 1;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 1, ND3 = 1;
 };
 struct ElQuad {
-  static constexpr int kind = 1, DIM = 2, V = 4, ML = 9, K = 4, NI = 9, NQE = 3;
-  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3;
+  static constexpr int kind = 1, DEG = 2, DIM = 2, V = 4, ML = 9, K = 4, NI = 9, NQE = 3;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3, ND3 = 1;
 };
 struct ElTri {
-  static constexpr int kind = 2, DIM = 2, V = 4, ML = 6, K = 3, NI = 7, NQE = 3;
-  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3;
+  static constexpr int kind = 2, DEG = 2, DIM = 2, V = 4, ML = 6, K = 3, NI = 7, NQE = 3;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3, ND3 = 1;
+};
+struct ElLine3 {
+  static constexpr int kind = 0, DEG = 3, DIM = 1, V = 3, ML = 4, K = 2, NI = 4, NQE = 1;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 1, ND3 = 1;
+};
+struct ElTri3 {
+  static constexpr int kind = 2, DEG = 3, DIM = 2, V = 4, ML = 10, K = 3, NI = 16, NQE = 4;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3, ND3 = 4;
 };
 
 // Reference tables of one element kind in one precision, kept in __constant__ memory so that
@@ -41,6 +50,8 @@ struct RefTab {
   R dphi0[E::DIM][E::ML];          // reference gradient at the reference origin
   R d2c[E::ND2][E::ML];            // reference second derivatives at the origin (constant for
                                    // complete P2 on the line and the triangle)
+  R d3c[E::ND3][E::ML];            // reference third derivatives (xxx[, xxy, xyy, yyy]): constant
+                                   // for complete P3, unused at degree 2
 };
 
 // Per-mesh device scalars (one record per mesh; the batched form holds many).
@@ -142,7 +153,13 @@ struct HostTabs {
   RefTab<ElQuad, float> quad_f;
   RefTab<ElTri, double> tri_d;
   RefTab<ElTri, float> tri_f;
+  RefTab<ElLine3, double> line3_d;
+  RefTab<ElLine3, float> line3_f;
+  RefTab<ElTri3, double> tri3_d;
+  RefTab<ElTri3, float> tri3_f;
 };
+// The device copies of these tables share the 64 KiB of constant memory.
+static_assert(sizeof(HostTabs) <= 65536, "reference tables exceed the constant memory");
 
 // ---- host-side launchers implemented in lxw_kernels.hip -----------------------------------
 hipError_t upload_tables(const HostTabs& t);

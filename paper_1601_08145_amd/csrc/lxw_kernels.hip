@@ -38,6 +38,10 @@ __constant__ RefTab<ElQuad, double> c_quad_d;
 __constant__ RefTab<ElQuad, float> c_quad_f;
 __constant__ RefTab<ElTri, double> c_tri_d;
 __constant__ RefTab<ElTri, float> c_tri_f;
+__constant__ RefTab<ElLine3, double> c_line3_d;
+__constant__ RefTab<ElLine3, float> c_line3_f;
+__constant__ RefTab<ElTri3, double> c_tri3_d;
+__constant__ RefTab<ElTri3, float> c_tri3_f;
 
 template <class E, class R>
 struct TabSel;
@@ -47,6 +51,10 @@ template <> struct TabSel<ElQuad, double> { static __device__ __forceinline__ co
 template <> struct TabSel<ElQuad, float> { static __device__ __forceinline__ const RefTab<ElQuad, float>& get() { return c_quad_f; } };
 template <> struct TabSel<ElTri, double> { static __device__ __forceinline__ const RefTab<ElTri, double>& get() { return c_tri_d; } };
 template <> struct TabSel<ElTri, float> { static __device__ __forceinline__ const RefTab<ElTri, float>& get() { return c_tri_f; } };
+template <> struct TabSel<ElLine3, double> { static __device__ __forceinline__ const RefTab<ElLine3, double>& get() { return c_line3_d; } };
+template <> struct TabSel<ElLine3, float> { static __device__ __forceinline__ const RefTab<ElLine3, float>& get() { return c_line3_f; } };
+template <> struct TabSel<ElTri3, double> { static __device__ __forceinline__ const RefTab<ElTri3, double>& get() { return c_tri3_d; } };
+template <> struct TabSel<ElTri3, float> { static __device__ __forceinline__ const RefTab<ElTri3, float>& get() { return c_tri3_f; } };
 
 hipError_t upload_tables(const HostTabs& t) {
   hipError_t e = hipSuccess;
@@ -56,6 +64,10 @@ hipError_t upload_tables(const HostTabs& t) {
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_quad_f), &t.quad_f, sizeof(t.quad_f));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri_d), &t.tri_d, sizeof(t.tri_d));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri_f), &t.tri_f, sizeof(t.tri_f));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_line3_d), &t.line3_d, sizeof(t.line3_d));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_line3_f), &t.line3_f, sizeof(t.line3_f));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri3_d), &t.tri3_d, sizeof(t.tri3_d));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri3_f), &t.tri3_f, sizeof(t.tri3_f));
   return e;
 }
 
@@ -172,6 +184,64 @@ __device__ __forceinline__ void ft_from(const R* q, const R* qt, const R* qtt, R
     dflux<DIM, R>(s, d, qtt, vtt, A2);
 #pragma unroll
     for (int c = 0; c < V; ++c) FT[d][c] = F[c] + c1 * A1[c] + c2 * (H[c] + A2[c]);
+  }
+}
+
+// Degree 3: the third variation F^(3)_d(a, b, c), through the third variations of u and p (the
+// first and second are those above):
+//   d3u_k[a,b,c] = -(d2u_k[a,b] c_rho + d2u_k[a,c] b_rho + d2u_k[b,c] a_rho)/rho,
+//   d3p[a,b,c]   = (gamma-1)(a_rho du[b].du[c] + b_rho du[a].du[c] + c_rho du[a].du[b]);
+// M_k u_d picks up a_Mk d2u_d[b,c] (and its two permutations) + M_k d3u_d, and u_d (E + p) the full
+// product rule with first, second and third variations a_E + dp, d2p and d3p of E + p.
+template <int DIM, class R>
+__device__ __forceinline__ void d3flux(const St<DIM, R>& s, int d, const R* a, const Var<DIM, R>& va, const R* b,
+                                       const Var<DIM, R>& vb, const R* c, const Var<DIM, R>& vc, R gm1, R* F) {
+  constexpr int V = DIM + 2;
+  R ab = R(0), ac = R(0), bc = R(0);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    ab += va.du[k] * vb.du[k];
+    ac += va.du[k] * vc.du[k];
+    bc += vb.du[k] * vc.du[k];
+  }
+  const R pab = -gm1 * s.rho * ab, pac = -gm1 * s.rho * ac, pbc = -gm1 * s.rho * bc;
+  const R p3 = gm1 * (a[0] * bc + b[0] * ac + c[0] * ab);
+  const R uab = -(va.du[d] * b[0] + vb.du[d] * a[0]) * s.r;
+  const R uac = -(va.du[d] * c[0] + vc.du[d] * a[0]) * s.r;
+  const R ubc = -(vb.du[d] * c[0] + vc.du[d] * b[0]) * s.r;
+  const R u3 = -(uab * c[0] + uac * b[0] + ubc * a[0]) * s.r;
+  F[0] = R(0);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) F[1 + k] = a[1 + k] * ubc + b[1 + k] * uac + c[1 + k] * uab + s.m[k] * u3 + (k == d ? p3 : R(0));
+  F[V - 1] = u3 * s.Ep + uab * (c[V - 1] + vc.dp) + uac * (b[V - 1] + vb.dp) + ubc * (a[V - 1] + va.dp) +
+             va.du[d] * pbc + vb.du[d] * pac + vc.du[d] * pab + s.u[d] * p3;
+}
+
+// Degree 3: F_T one Taylor term further, + dt^3/24 (F^(3)(q_t, q_t, q_t) + 3 H(q_t, q_tt) + A q_ttt).
+template <int DIM, class R>
+__device__ __forceinline__ void ft4_from(const R* q, const R* qt, const R* qtt, const R* qttt, R gm1, R dt,
+                                         R FT[DIM][DIM + 2]) {
+  constexpr int V = DIM + 2;
+  St<DIM, R> s = base_state<DIM, R>(q, gm1);
+  Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
+  Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
+  Var<DIM, R> vttt = var1<DIM, R>(s, qttt, gm1);
+  const R d2p = d2p_of<DIM, R>(s, vt, vt, gm1);
+  const R d2p12 = d2p_of<DIM, R>(s, vt, vtt, gm1);
+  const R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0), c3 = dt * dt * dt * R(1.0 / 24.0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    R F[V], A1[V], H[V], A2[V], T3[V], H12[V], A3[V];
+    flux<DIM, R>(s, d, F);
+    dflux<DIM, R>(s, d, qt, vt, A1);
+    d2flux<DIM, R>(s, d, qt, vt, qt, vt, d2p, H);
+    dflux<DIM, R>(s, d, qtt, vtt, A2);
+    d3flux<DIM, R>(s, d, qt, vt, qt, vt, qt, vt, gm1, T3);
+    d2flux<DIM, R>(s, d, qt, vt, qtt, vtt, d2p12, H12);
+    dflux<DIM, R>(s, d, qttt, vttt, A3);
+#pragma unroll
+    for (int c = 0; c < V; ++c)
+      FT[d][c] = F[c] + c1 * A1[c] + c2 * (H[c] + A2[c]) + c3 * (T3[c] + R(3) * H12[c] + A3[c]);
   }
 }
 
@@ -667,10 +737,10 @@ __device__ __forceinline__ void store_rec(R* p, const R (&x)[V]) {
 }
 
 template <class E, class R>
-struct ElemOcc { static constexpr int waves = (E::kind == ElTri::kind && sizeof(R) == 4) ? 2 : 1; };
+struct ElemOcc { static constexpr int waves = (E::kind == ElTri::kind && E::DEG == 2 && sizeof(R) == 4) ? 2 : 1; };
 
 template <class E, class R>
-__device__ __forceinline__ void elem_item(View<R> v, const int i) {
+__device__ __forceinline__ void elem_item2(View<R> v, const int i) {
   constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NI = E::NI, K = E::K, NQE = E::NQE;
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const RefTab<E, double>& TD = TabSel<E, double>::get();
@@ -968,6 +1038,313 @@ __device__ __forceinline__ void elem_item(View<R> v, const int i) {
       }
     }
   }
+}
+
+// k_elem at degree 3 (P3 on the line and on triangles, affine elements).  The same steps as above
+// with the Taylor series of Sec. 2.2 carried one term further: F_T needs q_ttt = -div F_tt, which
+// takes the gradient of q_tt, hence the Hessians of q and of D = div F^h (constant for cubic F^h).
+// With D_e = d/dx_e D and q_e = d/dx_e q:
+//   q_t = -D,  q_tt = sum_d [H_d(q_d, D) + A_d D_d],
+//   d/dx_e q_tt = sum_d [F3_d(q_e, q_d, D) + H_d(q_ed, D) + H_d(q_d, D_e) + H_d(q_e, D_d) + A_d D_ed],
+//   q_ttt = -sum_d [F3_d(q_d, q_t, q_t) - 2 H_d(D_d, q_t) + H_d(q_d, q_tt) + A_d d/dx_d q_tt].
+// Gradients and Hessians are contracted per point from the reference tables (quadratic and linear
+// in the reference coordinates), the Hessian of D once per element.
+template <class E, class R>
+__device__ __forceinline__ void elem_item3(View<R> v, const int i) {
+  constexpr int V = E::V, ML = E::ML, DIM = E::DIM, NI = E::NI, K = E::K, NQE = E::NQE;
+  const RefTab<E, R>& T = TabSel<E, R>::get();
+  const RefTab<E, double>& TD = TabSel<E, double>::get();
+  const int N = v.N, NE = v.E;
+  if (i >= N) return;
+  const int mid = mesh_id<R>(v.mesh_of, i);
+  const bool idle = v.sc[mid].idle;
+  const R dt = R(v.sc[mid].dt);
+  const R gm1 = R(v.gamma - 1.0);
+
+  double qb[V];
+  R Qr[V][ML - 1];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    qb[c] = v.Qbar[(size_t)i * V + c];
+#pragma unroll
+    for (int l = 1; l < ML; ++l) Qr[c][l - 1] = v.Qh[(c * (ML - 1) + l - 1) * N + i];
+  }
+  const double th = v.theta[i];
+  const R thR = R(th);
+  R Ji[DIM][DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Ji[a][d] = v.Jinv[(a * DIM + d) * N + i];
+
+  auto state_at = [&](int p, R* q) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 1; l < ML; ++l) acc += double(Qr[c][l - 1]) * TD.phi[p][l];
+      q[c] = R(qb[c] + th * acc);
+    }
+  };
+  // physical second derivatives from the reference ones (xx[, xy, yy] at index a + b)
+  auto map2 = [&](const R* hr, R out[DIM][DIM]) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) {
+        R t = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) t += Ji[a][d] * Ji[b][e] * hr[a + b];
+        out[d][e] = t;
+      }
+  };
+
+  // Sec. 2.3 Step 1: Fc^h_a = sum_m w_m Fc_a(q(x_m)) phi_l(x_m)
+  R Fh[DIM][V][ML];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int c = 0; c < V; ++c)
+#pragma unroll
+      for (int l = 0; l < ML; ++l) Fh[a][c][l] = R(0);
+  for (int m = 0; m < NI; ++m) {
+    R q[V];
+    state_at(m, q);
+    St<DIM, R> s = base_state<DIM, R>(q, gm1);
+    R F[DIM][V];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) flux<DIM, R>(s, d, F[d]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R fc = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) fc += Ji[a][d] * F[d][c];
+#pragma unroll
+        for (int l = 0; l < ML; ++l) Fh[a][c][l] += T.wphi[m][l] * fc;
+      }
+  }
+
+  // Hessian of D (constant): d/dxi_b d/dxi_b' sum_a d/dxi_a Fc_a, third reference derivative
+  // index = number of eta derivatives
+  R HD[DIM][DIM][V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    R hr[2 * DIM - 1];
+#pragma unroll
+    for (int j = 0; j < 2 * DIM - 1; ++j) {
+      R t = R(0);
+#pragma unroll
+      for (int l = 0; l < ML; ++l)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) t += Fh[a][c][l] * T.d3c[a + j][l];
+      hr[j] = t;
+    }
+    R h[DIM][DIM];
+    map2(hr, h);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) HD[d][e][c] = h[d][e];
+  }
+
+  auto point = [&](int p, R* q, R* qt, R* qtt, R* qttt, R FT[DIM][V]) {
+    R gq[DIM][V], Hq[DIM][DIM][V], D[V], gD[DIM][V];
+    state_at(p, q);
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      R g[DIM], hq[2 * DIM - 1], gd[DIM];
+      R dd = R(0);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) { g[a] = R(0); gd[a] = R(0); }
+#pragma unroll
+      for (int j = 0; j < 2 * DIM - 1; ++j) hq[j] = R(0);
+#pragma unroll
+      for (int l = 0; l < ML; ++l) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          if (l > 0) g[a] += Qr[c][l - 1] * T.dphi[p][a][l];
+          dd += Fh[a][c][l] * T.dphi[p][a][l];
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) gd[b] += Fh[a][c][l] * T.d2phi[p][a + b][l];
+        }
+        if (l > 0) {
+#pragma unroll
+          for (int j = 0; j < 2 * DIM - 1; ++j) hq[j] += Qr[c][l - 1] * T.d2phi[p][j][l];
+        }
+      }
+      D[c] = dd;
+#pragma unroll
+      for (int j = 0; j < 2 * DIM - 1; ++j) hq[j] *= thR;
+      R h[DIM][DIM];
+      map2(hq, h);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        R sg = R(0), sd = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) { sg += Ji[a][d] * g[a]; sd += Ji[a][d] * gd[a]; }
+        gq[d][c] = thR * sg;
+        gD[d][c] = sd;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) Hq[d][e][c] = h[d][e];
+      }
+    }
+    St<DIM, R> s = base_state<DIM, R>(q, gm1);
+    Var<DIM, R> vD = var1<DIM, R>(s, D, gm1);
+    Var<DIM, R> vq[DIM], vg[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      vq[d] = var1<DIM, R>(s, gq[d], gm1);
+      vg[d] = var1<DIM, R>(s, gD[d], gm1);
+    }
+#pragma unroll
+    for (int c = 0; c < V; ++c) { qt[c] = -D[c]; qtt[c] = R(0); qttt[c] = R(0); }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      R H[V], A[V];
+      d2flux<DIM, R>(s, d, gq[d], vq[d], D, vD, d2p_of<DIM, R>(s, vq[d], vD, gm1), H);
+      dflux<DIM, R>(s, d, gD[d], vg[d], A);
+#pragma unroll
+      for (int c = 0; c < V; ++c) qtt[c] += H[c] + A[c];
+    }
+    Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
+    Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      // d/dx_d q_tt
+      R dq2[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) dq2[c] = R(0);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        R t1[V], t2[V], t3[V], t4[V], t5[V];
+        Var<DIM, R> vH = var1<DIM, R>(s, Hq[d][k], gm1);
+        Var<DIM, R> vHD = var1<DIM, R>(s, HD[d][k], gm1);
+        d3flux<DIM, R>(s, k, gq[d], vq[d], gq[k], vq[k], D, vD, gm1, t1);
+        d2flux<DIM, R>(s, k, Hq[d][k], vH, D, vD, d2p_of<DIM, R>(s, vH, vD, gm1), t2);
+        d2flux<DIM, R>(s, k, gq[k], vq[k], gD[d], vg[d], d2p_of<DIM, R>(s, vq[k], vg[d], gm1), t3);
+        d2flux<DIM, R>(s, k, gq[d], vq[d], gD[k], vg[k], d2p_of<DIM, R>(s, vq[d], vg[k], gm1), t4);
+        dflux<DIM, R>(s, k, HD[d][k], vHD, t5);
+#pragma unroll
+        for (int c = 0; c < V; ++c) dq2[c] += t1[c] + t2[c] + t3[c] + t4[c] + t5[c];
+      }
+      R t1[V], t2[V], t3[V], t4[V];
+      Var<DIM, R> v2 = var1<DIM, R>(s, dq2, gm1);
+      d3flux<DIM, R>(s, d, gq[d], vq[d], qt, vt, qt, vt, gm1, t1);
+      d2flux<DIM, R>(s, d, gD[d], vg[d], qt, vt, d2p_of<DIM, R>(s, vg[d], vt, gm1), t2);
+      d2flux<DIM, R>(s, d, gq[d], vq[d], qtt, vtt, d2p_of<DIM, R>(s, vq[d], vtt, gm1), t3);
+      dflux<DIM, R>(s, d, dq2, v2, t4);
+#pragma unroll
+      for (int c = 0; c < V; ++c) qttt[c] -= t1[c] - R(2) * t2[c] + t3[c] + t4[c];
+    }
+    ft4_from<DIM, R>(q, qt, qtt, qttt, gm1, dt, FT);
+  };
+
+  R vol[V][ML - 1];
+#pragma unroll
+  for (int c = 0; c < V; ++c)
+#pragma unroll
+    for (int l = 0; l < ML - 1; ++l) vol[c][l] = R(0);
+  for (int m = 0; m < NI; ++m) {
+    R q[V], qt[V], qtt[V], qttt[V], FT[DIM][V];
+    point(m, q, qt, qtt, qttt, FT);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        R fc = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) fc += Ji[a][d] * FT[d][c];
+#pragma unroll
+        for (int l = 1; l < ML; ++l) vol[c][l - 1] += T.wdphi[m][a][l] * fc;
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < V; ++c)
+#pragma unroll
+    for (int l = 1; l < ML; ++l)
+      v.Qh[(c * (ML - 1) + l - 1) * N + i] = idle ? Qr[c][l - 1] : thR * Qr[c][l - 1] + dt * vol[c][l - 1];
+  if (v.dbg_vol) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      v.dbg_vol[(c * ML) * N + i] = 0.0;
+#pragma unroll
+      for (int l = 1; l < ML; ++l) v.dbg_vol[(c * ML + l) * N + i] = double(vol[c][l - 1]);
+    }
+  }
+
+  // edge points: traces q and n_out . F_T (and the ghost side on boundary edges)
+  for (int k = 0; k < K; ++k) {
+    const int slot = v.eslot[k * N + i];
+    const int e = slot >> 3, side = (slot >> 2) & 1, bc = slot & 3;
+    R n[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) n[d] = v.nout[(k * DIM + d) * N + i];
+    for (int jl = 0; jl < NQE; ++jl) {
+      const int p = NI + k * NQE + jl;
+      const int jj = side ? (NQE - 1 - jl) : jl;
+      R q[V], qt[V], qtt[V], qttt[V], FT[DIM][V];
+      point(p, q, qt, qtt, qttt, FT);
+      R fn[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        fn[c] = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) fn[c] += n[d] * FT[d][c];
+      }
+      store_rec<R, V>(v.tq + (((size_t)side * NE + e) * NQE + jj) * V, q);
+      store_rec<R, V>(v.tf + (((size_t)side * NE + e) * NQE + jj) * V, fn);
+      if (bc != SB_INTERIOR) {
+        R qg[V], FTg[DIM][V];
+        if (bc == SB_TRANSPARENT) {
+#pragma unroll
+          for (int c = 0; c < V; ++c) qg[c] = q[c];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d)
+#pragma unroll
+            for (int c = 0; c < V; ++c) FTg[d][c] = FT[d][c];
+        } else if (bc == SB_REFLECTIVE) {
+          R nh[DIM], len2 = R(0);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) len2 += n[d] * n[d];
+          const R il = R(1) / sqrt(len2);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) nh[d] = n[d] * il;
+          R qtg[V], qttg[V], q3g[V];
+          reflect<DIM, R>(q, nh, qg);
+          reflect<DIM, R>(qt, nh, qtg);
+          reflect<DIM, R>(qtt, nh, qttg);
+          reflect<DIM, R>(qttt, nh, q3g);
+          ft4_from<DIM, R>(qg, qtg, qttg, q3g, gm1, dt, FTg);
+        } else {
+          R z[V];
+#pragma unroll
+          for (int c = 0; c < V; ++c) z[c] = R(0);
+          inflow_state<DIM, R>(v.inflow, qg);
+          ft4_from<DIM, R>(qg, z, z, z, gm1, dt, FTg);
+        }
+        R fg[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          R f = R(0);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) f += n[d] * FTg[d][c];
+          fg[c] = -f;
+        }
+        store_rec<R, V>(v.tq + (((size_t)NE + e) * NQE + jj) * V, qg);
+        store_rec<R, V>(v.tf + (((size_t)NE + e) * NQE + jj) * V, fg);
+      }
+    }
+  }
+}
+
+template <class E, class R>
+__device__ __forceinline__ void elem_item(View<R> v, const int i) {
+  if constexpr (E::DEG == 3) elem_item3<E, R>(v, i);
+  else elem_item2<E, R>(v, i);
 }
 
 template <class E, class R>
@@ -1440,5 +1817,9 @@ template hipError_t launch<ElQuad, double>(KernelId, const View<double>&, const 
 template hipError_t launch<ElQuad, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
 template hipError_t launch<ElTri, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
 template hipError_t launch<ElTri, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElLine3, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElLine3, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElTri3, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElTri3, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
 
 }  // namespace lxw

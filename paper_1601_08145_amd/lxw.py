@@ -84,6 +84,7 @@ def _load():
         "lxw_mesh_destroy": [P],
         "lxw_mesh_get_info": [P, ctypes.POINTER(MeshInfo)],
         "lxw_refelem_info": [I32, ip, dp, dp, dp],
+        "lxw_refelem_info_deg": [I32, I32, ip, dp, dp, dp],
         "lxw_solver_create": [P, ctypes.POINTER(Params), P, ctypes.POINTER(P)],
         "lxw_solver_destroy": [P],
         "lxw_set_state": [P, P, D, I32],
@@ -165,16 +166,20 @@ def default_params(**kw):
     return p
 
 
-def refelem_info(kind):
-    """Interior quadrature points xi[n][dim], weights w[n] (sum 1) and basis values phi[n][n_modes]."""
+def n_modes(kind, degree=2):
+    return {(LINE, 2): 3, (QUAD, 2): 9, (TRI, 2): 6, (LINE, 3): 4, (TRI, 3): 10}[(kind, degree)]
+
+
+def refelem_info(kind, degree=2):
+    """Interior quadrature points xi[n][dim], weights w[n] (sum 1) and basis values phi[n][n_modes]
+    at polynomial degree 2 (or 3 on lines and triangles)."""
     n = ctypes.c_int32(0)
-    _check(_L.lxw_refelem_info(kind, ctypes.byref(n), None, None, None))
+    _check(_L.lxw_refelem_info_deg(kind, degree, ctypes.byref(n), None, None, None))
     dim = 1 if kind == LINE else 2
-    ml = {LINE: 3, QUAD: 9, TRI: 6}[kind]
     xi = np.zeros((n.value, dim))
     w = np.zeros(n.value)
-    phi = np.zeros((n.value, ml))
-    _check(_L.lxw_refelem_info(kind, ctypes.byref(n), _dp(xi), _dp(w), _dp(phi)))
+    phi = np.zeros((n.value, n_modes(kind, degree)))
+    _check(_L.lxw_refelem_info_deg(kind, degree, ctypes.byref(n), _dp(xi), _dp(w), _dp(phi)))
     return xi, w, phi
 
 
@@ -236,9 +241,9 @@ class Mesh:
                                       _dp(p) if p is not None else None, ctypes.byref(h)))
         return Mesh(h, TRI, xy[tri])
 
-    def quad_points(self):
+    def quad_points(self, degree=2):
         """Physical coordinates of the interior quadrature points of every element (N x n x dim)."""
-        xi, w, phi = refelem_info(self.kind)
+        xi, w, phi = refelem_info(self.kind, degree)
         v = self.verts
         if self.kind == LINE:
             return v[:, 0, None, :] + 0.5 * (xi[None, :, :] + 1.0) * (v[:, 1, None, :] - v[:, 0, None, :])
@@ -248,10 +253,10 @@ class Mesh:
         return v[:, 0, None, :] + 0.5 * (xi[None, :, 0, None] + 1) * (v[:, 1, None, :] - v[:, 0, None, :]) \
             + 0.5 * (xi[None, :, 1, None] + 1) * (v[:, 3, None, :] - v[:, 0, None, :])
 
-    def project(self, vals):
-        """L2 projection of point values at quad_points() (N x n x V) onto the documented basis,
+    def project(self, vals, degree=2):
+        """L2 projection of point values at quad_points(degree) (N x n x V) onto the documented basis,
         with the library's quadrature tables: Q_l = sum_m w_m f(x_m) phi_l(x_m)."""
-        xi, w, phi = refelem_info(self.kind)
+        xi, w, phi = refelem_info(self.kind, degree)
         return np.einsum("m,nmv,ml->nvl", w, np.asarray(vals, dtype=np.float64), phi)
 
 
@@ -344,8 +349,12 @@ class Solver(_Ops):
         return self.mesh.N
 
     @property
+    def ML(self):
+        return n_modes(self.mesh.kind, self.params.degree)
+
+    @property
     def shape(self):
-        return (self.mesh.N, self.mesh.V, self.mesh.ML)
+        return (self.mesh.N, self.mesh.V, self.ML)
 
     def set_state(self, Q, t0=0.0, checked=True):
         extra = 0 if checked else STATE_UNCHECKED

@@ -429,7 +429,7 @@ def test_error_paths(L):
         S.set_state(bad)
     assert "element 5" in e.value.msg
     with pytest.raises(L.LxwError) as e:
-        L.Solver(lm, degree=3)
+        L.Solver(lm, degree=4)
     assert e.value.name == "LXW_ERR_UNSUPPORTED"
     with pytest.raises(L.LxwError) as e:
         L.Solver(lm, cfl=1.5)

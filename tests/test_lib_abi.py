@@ -51,6 +51,27 @@ def test_refelem_tables_match_the_oracle(L, kind):
     assert a == b
 
 
+@pytest.mark.parametrize("kind", [0, 2])
+def test_degree3_refelem_tables_match_the_oracle(L, kind):
+    """Degree 3: the library's rules (closed-form four-point Gauss; on the triangle Gauss-Jacobi
+    nodes from the eigenvalues of the recurrence's Jacobi matrix) and its P3 basis (closed-form
+    Legendre; Cholesky of the exact triangle moments) equal the oracle's (Newton on the recurrence,
+    Gram-Schmidt) point for point; quadrilaterals have no degree-3 form."""
+    xi, w, phi = L.refelem_info(kind, 3)
+    R = O.RefElem(kind, 3)
+    assert phi.shape == (R.NI, R.ML) and w.sum() == pytest.approx(1.0, abs=1e-15)
+    for m in range(len(w)):
+        for l in range(R.ML):
+            assert phi[m, l] == pytest.approx(R.phi(l, xi[m]), abs=1e-12)
+    a = sorted(zip(map(tuple, np.round(xi, 12)), np.round(w, 14)))
+    b = sorted(zip(map(tuple, np.round(R.xi_int, 12)), np.round(R.w_int, 14)))
+    assert a == b
+    with pytest.raises(L.LxwError):
+        L.refelem_info(1, 3)
+    with pytest.raises(L.LxwError):
+        L.refelem_info(kind, 4)
+
+
 def test_masked_cartesian_mesh_counts(L):
     """The library's masked Cartesian mesh (the block step's solid removed) has the oracle's cell
     and edge counts, and rejects a mask that keeps nothing."""
