@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lxw_oracle.cpp")
 LIB = os.path.join(HERE, "liblxw_oracle.so")
 
-LINE, QUAD, TRI = 0, 1, 2
+LINE, QUAD, TRI, TET = 0, 1, 2, 3
 BC_PERIODIC, BC_TRANSPARENT, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
 
 STAGE_QLIM, STAGE_THETA_MOM, STAGE_VOL, STAGE_FLXW, STAGE_FLXF = 0, 1, 2, 3, 4
@@ -54,6 +54,9 @@ def lib():
             "ora_set_num_threads": (None, [i]),
             "ora_mesh_cart": (P, [i, i, d, d, d, d, ip, u8p, i]),
             "ora_mesh_tri": (P, [i, dp, i, ip, ip, dp]),
+            "ora_mesh_tet": (P, [i, dp, i, ip, ip, dp]),
+            "ora_mesh_edges": (None, [P, ip, ip, ip, ip, dp]),
+            "ora_mesh_point_order": (None, [P, ip]),
             "ora_last_error": (ctypes.c_char_p, []),
             "ora_mesh_free": (None, [P]),
             "ora_mesh_info": (None, [P, ip]),
@@ -72,7 +75,7 @@ def lib():
             "ora_stage": (i, [P, i, dp]),
             "ora_ref_info": (None, [i, i, ip]),
             "ora_ref_tables": (None, [i, i, dp, dp, dp, dp, dp]),
-            "ora_phi": (d, [i, i, i, dp, i, i]),
+            "ora_phi": (d, [i, i, i, dp, i, i, i]),
             "ora_mesh_set_degree": (i, [P, i]),
             "ora_flux_3vp": (None, [i, d, dp, i, dp, dp, dp, dp]),
             "ora_ft4": (None, [i, d, d, dp, dp, dp, dp, dp]),
@@ -112,8 +115,8 @@ def i32(a):
 
 
 class RefElem:
-    """Reference element tables of kind LINE, QUAD or TRI and polynomial degree 2 (or 3: LINE,
-    TRI)."""
+    """Reference element tables of kind LINE, QUAD, TRI or TET and polynomial degree 2 (or 3:
+    LINE, TRI)."""
 
     def __init__(self, kind, degree=2):
         L = lib()
@@ -130,9 +133,9 @@ class RefElem:
         L.ora_ref_tables(kind, degree, _d(self.C), _d(self.xi_int), _d(self.w_int), _d(self.xi_edge),
                          _d(self.om_edge))
 
-    def phi(self, l, xi, da=0, db=0):
+    def phi(self, l, xi, da=0, db=0, dc=0):
         xi = f64(np.atleast_1d(xi))
-        return lib().ora_phi(self.kind, self.degree, l, _d(xi), da, db)
+        return lib().ora_phi(self.kind, self.degree, l, _d(xi), da, db, dc)
 
 
 class Mesh:
@@ -185,6 +188,31 @@ class Mesh:
         h = lib().ora_mesh_tri(len(xy), _d(xy), len(tri), _i(tri), _i(b) if b is not None else None,
                                _d(p) if p is not None else None)
         return Mesh(h, degree)
+
+    @staticmethod
+    def tet(xyz, tet, bnd=None, period=None):
+        """Tetrahedral P2 mesh: nodes xyz (n x 3), tetrahedra (n_tet x 4, positively oriented),
+        boundary codes per (tetrahedron, face k opposite vertex k), period (3 lengths)."""
+        xyz = f64(xyz)
+        tet = i32(tet)
+        b = i32(bnd) if bnd is not None else None
+        p = f64(period) if period is not None else None
+        h = lib().ora_mesh_tet(len(xyz), _d(xyz), len(tet), _i(tet), _i(b) if b is not None else None,
+                               _d(p) if p is not None else None)
+        return Mesh(h)
+
+    def edges(self):
+        """(e_i, e_ki, e_j, e_kj, n_e[E][3]) of the edges (faces in 3D)."""
+        ei, ki, ej, kj = (np.zeros(self.E, np.int32) for _ in range(4))
+        n = np.zeros((self.E, 3))
+        lib().ora_mesh_edges(self.h, _i(ei), _i(ki), _i(ej), _i(kj), _d(n))
+        return ei, ki, ej, kj, n
+
+    def point_order(self):
+        """fmap[N][K][NQE]: local edge point jl of (i, k) is point fmap of the edge in i_e's order."""
+        f = np.zeros((self.N, self.K, self.NQE), np.int32)
+        lib().ora_mesh_point_order(self.h, _i(f))
+        return f
 
     def quad_points(self):
         x = np.zeros((self.N, self.NI, self.dim))

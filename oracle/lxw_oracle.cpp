@@ -101,7 +101,8 @@ static inline TD operator/(TD x, TD y) { return x * recip(y); }
 
 // ------------------------------------------------------------------------------------------
 // Physics: Eq. (euler-eqns) with the equation of state Eq. (eos); the flux in direction d as
-// written in Sec. 1.5.  Conserved variables q = (rho, M, E) in 1D and (rho, Mx, My, E) in 2D.
+// written in Sec. 1.5.  Conserved variables q = (rho, M, E) in 1D, (rho, Mx, My, E) in 2D and
+// (rho, Mx, My, Mz, E) in 3D.
 // ------------------------------------------------------------------------------------------
 template <class T>
 static void euler_flux(int dim, double gam, const T* q, int d, T* F) {
@@ -112,7 +113,7 @@ static void euler_flux(int dim, double gam, const T* q, int d, T* F) {
     F[0] = m;
     F[1] = m * u + p;
     F[2] = u * (E + p);
-  } else {
+  } else if (dim == 2) {
     T rho = q[0], mx = q[1], my = q[2], E = q[3];
     T u = mx / rho, v = my / rho;
     T p = (gam - 1.0) * (E - 0.5 * (mx * u + my * v));
@@ -127,12 +128,21 @@ static void euler_flux(int dim, double gam, const T* q, int d, T* F) {
       F[2] = my * v + p;
       F[3] = v * (E + p);
     }
+  } else {
+    T rho = q[0], E = q[4];
+    T m[3] = {q[1], q[2], q[3]};
+    T u[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
+    T p = (gam - 1.0) * (E - 0.5 * (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]));
+    F[0] = m[d];
+    for (int k = 0; k < 3; ++k) F[1 + k] = m[k] * u[d];
+    F[1 + d] = F[1 + d] + p;
+    F[4] = u[d] * (E + p);
   }
 }
 
 template <>
 void euler_flux<double>(int dim, double gam, const double* q, int d, double* F) {
-  HD qh[4] = {}, Fh[4] = {};
+  HD qh[5] = {}, Fh[5] = {};
   int V = dim + 2;
   for (int i = 0; i < V; ++i) qh[i] = hd(q[i]);
   euler_flux<HD>(dim, gam, qh, d, Fh);
@@ -141,7 +151,7 @@ void euler_flux<double>(int dim, double gam, const double* q, int d, double* F) 
 
 // A_d(q) x  (flux Jacobian times a vector), Eq. (fluxderivs-a)
 static void flux_jvp(int dim, double gam, const double* q, int d, const double* x, double* out) {
-  HD qh[4] = {}, Fh[4] = {};
+  HD qh[5] = {}, Fh[5] = {};
   int V = dim + 2;
   for (int i = 0; i < V; ++i) qh[i] = {q[i], x[i], 0.0, 0.0};
   euler_flux<HD>(dim, gam, qh, d, Fh);
@@ -151,7 +161,7 @@ static void flux_jvp(int dim, double gam, const double* q, int d, const double* 
 // H_d(q)(x, y)  (flux Hessian applied to two vectors), Eq. (fluxderivs-b)
 static void flux_hvp(int dim, double gam, const double* q, int d, const double* x, const double* y,
                      double* out) {
-  HD qh[4] = {}, Fh[4] = {};
+  HD qh[5] = {}, Fh[5] = {};
   int V = dim + 2;
   for (int i = 0; i < V; ++i) qh[i] = {q[i], x[i], y[i], 0.0};
   euler_flux<HD>(dim, gam, qh, d, Fh);
@@ -161,7 +171,7 @@ static void flux_hvp(int dim, double gam, const double* q, int d, const double* 
 // F^(3)_d(q)(x, y, z)  (third derivative of the flux applied to three vectors)
 static void flux_3vp(int dim, double gam, const double* q, int d, const double* x, const double* y,
                      const double* z, double* out) {
-  TD qh[4] = {}, Fh[4] = {};
+  TD qh[5] = {}, Fh[5] = {};
   int V = dim + 2;
   for (int i = 0; i < V; ++i) {
     qh[i] = td(q[i]);
@@ -176,7 +186,8 @@ static void flux_3vp(int dim, double gam, const double* q, int d, const double* 
 // Pressure from conserved variables, Eq. (eos) / Eq. (ave_press).
 static double pressure(int dim, double gam, const double* q) {
   if (dim == 1) return (gam - 1.0) * (q[2] - 0.5 * q[1] * q[1] / q[0]);
-  return (gam - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+  if (dim == 2) return (gam - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+  return (gam - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -185,18 +196,21 @@ static double pressure(int dim, double gam, const double* q) {
 // integrals; phi_1 == 1 so that Q^(1) is the cell average (Sec. 1.2).  Line: Legendre P0..P2 on
 // [-1,1].  Quad: the same procedure on [-1,1]^2 with the graded list below, which yields the
 // tensor-product Legendre basis (Q2, 9 modes).  Triangle: reference triangle (0,0),(1,0),(0,1),
-// P2 (6 modes).
+// P2 (6 modes).  Tetrahedron (Sec. 3.3 remark: the construction carries over face by face):
+// reference tetrahedron (0,0,0),(1,0,0),(0,1,0),(0,0,1), P2 (10 modes).
 // ------------------------------------------------------------------------------------------
-enum Kind { LINE = 0, QUAD = 1, TRI = 2 };
+enum Kind { LINE = 0, QUAD = 1, TRI = 2, TET = 3 };
 
 struct RefElem {
   int kind = 0, deg = 2, dim = 0, ML = 0, K = 0, NI = 0, NQE = 0, NV = 0;
   double T0 = 0.0;                 // |T0|
-  std::vector<int> ex, ey;         // monomial exponents
+  std::vector<int> ex, ey, ez;     // monomial exponents
   std::vector<double> C;           // ML x ML: phi_l = sum_j C[l*ML+j] * mono_j
   std::vector<double> xi_int;      // NI x dim interior quadrature points
   std::vector<double> w_int;       // NI weights, normalised to sum 1
   std::vector<double> s_edge, om_edge;  // NQE Gauss-Legendre nodes on [-1,1], weights sum 2
+                                   // (tetrahedron: om_edge the face rule's weights, sum 2)
+  std::vector<double> fb;          // tetrahedron: NQE x 3 barycentric coordinates of the face points
   std::vector<double> xv;          // NV x dim reference vertices (CCW)
 };
 
@@ -206,13 +220,18 @@ static double fact(int n) {
   return r;
 }
 
-// (1/|T0|) int_{T0} xi^a eta^b
-static double mono_moment(int kind, int a, int b) {
+// (1/|T0|) int_{T0} xi^a eta^b zeta^c
+static double mono_moment(int kind, int a, int b, int c = 0) {
   auto line = [](int n) { return (n % 2) ? 0.0 : 1.0 / (n + 1); };  // (1/2) int_{-1}^1 x^n
   if (kind == LINE) return line(a);
   if (kind == QUAD) return line(a) * line(b);
+  if (kind == TET) return 6.0 * fact(a) * fact(b) * fact(c) / fact(a + b + c + 3);  // |T0| = 1/6
   return 2.0 * fact(a) * fact(b) / fact(a + b + 2);  // |T0| = 1/2
 }
+
+// Faces of the reference tetrahedron: face k is opposite vertex k, its vertices ordered so that
+// (b - a) x (c - a) points outward.
+static const int TET_FACE[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
 
 static double ipow(double x, int n) {
   double r = 1.0;
@@ -321,6 +340,43 @@ static RefElem make_ref(int kind, int deg = 2) {
         R.xi_int.push_back(R.s_edge[i]); R.xi_int.push_back(R.s_edge[j]);
         R.w_int.push_back(R.om_edge[i] * R.om_edge[j] / 4.0);
       }
+  } else if (kind == TET) {
+    R.dim = 3; R.ML = 10; R.K = 4; R.NV = 4; R.T0 = 1.0 / 6.0;
+    R.ex = {0, 1, 0, 0, 2, 1, 1, 0, 0, 0};
+    R.ey = {0, 0, 1, 0, 0, 1, 0, 2, 1, 0};
+    R.ez = {0, 0, 0, 1, 0, 0, 1, 0, 1, 2};
+    R.xv = {0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1};
+    // Interior: the collapsed (Duffy) product rule (xi, eta, zeta) = (u (1 - v)(1 - w), v (1 - w), w)
+    // with u, v, w = (1 + t)/2 at the 3-point Gauss rules for the weights 1, (1 - t) and (1 - t)^2
+    // (the Jacobian (1 - v)(1 - w)^2 of the collapse): 27 points, exact to degree 5.
+    std::vector<double> x0, w0, x1, w1, x2, w2;
+    gauss_rule(3, 0, x0, w0);
+    gauss_rule(3, 1, x1, w1);
+    gauss_rule(3, 2, x2, w2);
+    for (int k = 0; k < 3; ++k)
+      for (int j = 0; j < 3; ++j)
+        for (int i = 0; i < 3; ++i) {
+          const double u = 0.5 * (1.0 + x0[i]), v = 0.5 * (1.0 + x1[j]), w = 0.5 * (1.0 + x2[k]);
+          R.xi_int.push_back(u * (1.0 - v) * (1.0 - w));
+          R.xi_int.push_back(v * (1.0 - w));
+          R.xi_int.push_back(w);
+          // (1/|T0|) int = 6 int u,v,w f (1 - v)(1 - w)^2 = (6/64) int f (1 - t1)(1 - t2)^2 dt0 dt1 dt2
+          R.w_int.push_back(6.0 / 64.0 * w0[i] * w1[j] * w2[k]);
+        }
+    // Faces: the same 7-point degree-5 rule as the triangle interior, in barycentric coordinates
+    // (fully symmetric, so both sides of a face see the same point set); weights scaled to sum 2.
+    const double r15 = std::sqrt(15.0);
+    const double a1 = (6.0 - r15) / 21.0, b1 = (9.0 + 2.0 * r15) / 21.0, v1 = (155.0 - r15) / 1200.0;
+    const double a2 = (6.0 + r15) / 21.0, b2 = (9.0 - 2.0 * r15) / 21.0, v2 = (155.0 + r15) / 1200.0;
+    R.om_edge.clear();
+    auto addf = [&](double l0, double l1, double l2, double w) {
+      R.fb.push_back(l0); R.fb.push_back(l1); R.fb.push_back(l2); R.om_edge.push_back(2.0 * w);
+    };
+    addf(1.0 / 3, 1.0 / 3, 1.0 / 3, 9.0 / 40.0);
+    addf(b1, a1, a1, v1); addf(a1, b1, a1, v1); addf(a1, a1, b1, v1);
+    addf(b2, a2, a2, v2); addf(a2, b2, a2, v2); addf(a2, a2, b2, v2);
+    R.NQE = 7;
+    R.s_edge.assign(7, 0.0);
   } else {
     R.dim = 2; R.ML = 6; R.K = 3; R.NV = 3; R.NQE = 3; R.T0 = 0.5;
     R.ex = {0, 1, 0, 2, 1, 0}; R.ey = {0, 0, 1, 0, 1, 2};
@@ -338,11 +394,13 @@ static RefElem make_ref(int kind, int deg = 2) {
     add(a2, a2, b2, w2); add(a2, b2, a2, w2); add(b2, a2, a2, w2);
   }
   R.NI = (int)R.w_int.size();
+  if (R.ez.empty()) R.ez.assign(R.ML, 0);
   // Gram-Schmidt in the monomial coordinates with the exact Gram matrix G.
   int ML = R.ML;
   std::vector<double> G(ML * ML);
   for (int a = 0; a < ML; ++a)
-    for (int b = 0; b < ML; ++b) G[a * ML + b] = mono_moment(kind, R.ex[a] + R.ex[b], R.ey[a] + R.ey[b]);
+    for (int b = 0; b < ML; ++b)
+      G[a * ML + b] = mono_moment(kind, R.ex[a] + R.ex[b], R.ey[a] + R.ey[b], R.ez[a] + R.ez[b]);
   auto ip = [&](const double* u, const double* v) {
     double s = 0.0;
     for (int a = 0; a < ML; ++a)
@@ -363,14 +421,17 @@ static RefElem make_ref(int kind, int deg = 2) {
   return R;
 }
 
-// phi_l and its reference derivatives at xi.  da, db count derivatives in xi and eta.
-static double phi(const RefElem& R, int l, const double* xi, int da = 0, int db = 0) {
+// phi_l and its reference derivatives at xi.  da, db, dc count derivatives in xi, eta, zeta.
+static double phi(const RefElem& R, int l, const double* xi, int da = 0, int db = 0, int dc = 0) {
   double s = 0.0;
-  double x = xi[0], y = (R.dim == 2) ? xi[1] : 0.0;
+  double x = xi[0], y = (R.dim >= 2) ? xi[1] : 0.0, z = (R.dim == 3) ? xi[2] : 0.0;
   for (int j = 0; j < R.ML; ++j) {
     double c = R.C[l * R.ML + j];
     if (c == 0.0) continue;
-    s += c * dpow(x, R.ex[j], da) * dpow(y, R.ey[j], db);
+    double t = c * dpow(x, R.ex[j], da) * dpow(y, R.ey[j], db);
+    if (R.dim == 3) t *= dpow(z, R.ez[j], dc);
+    else if (dc) t = 0.0;
+    s += t;
   }
   return s;
 }
@@ -379,6 +440,13 @@ static double phi(const RefElem& R, int l, const double* xi, int da = 0, int db 
 // k+1 (counter-clockwise); in 1D local edge k is vertex k.
 static void edge_point(const RefElem& R, int k, int j, double* xi) {
   if (R.dim == 1) { xi[0] = R.xv[k]; return; }
+  if (R.dim == 3) {  // face k: barycentric combination of its three vertices
+    for (int a = 0; a < 3; ++a) {
+      xi[a] = 0.0;
+      for (int m = 0; m < 3; ++m) xi[a] += R.fb[j * 3 + m] * R.xv[TET_FACE[k][m] * 3 + a];
+    }
+    return;
+  }
   int a = k, b = (k + 1) % R.NV;
   double t = 0.5 * (1.0 + R.s_edge[j]);
   xi[0] = R.xv[2 * a] + t * (R.xv[2 * b] - R.xv[2 * a]);
@@ -402,8 +470,14 @@ struct Mesh {
   std::vector<int> ebc;            // N x K boundary type of local edge (BC_INTERIOR inside)
   std::vector<int> eid, eps;       // N x K
   std::vector<int> e_i, e_ki, e_j, e_kj, e_bc;
-  std::vector<double> e_n, e_len;  // E x dim
+  std::vector<double> e_n, e_len;  // E x 3 (unused components zero); |n_e| = edge length / face area
+  // Point order on an edge or face: local point jl of (element i, local edge k) is point
+  // fmap[(i K + k) NQE + jl] in the order of i_e; finv is the inverse.
+  std::vector<int> fmap, finv;
 };
+
+static void map_point(const Mesh& M, int i, const double* xi, double* x);
+static void build_point_order(Mesh& M);
 
 static void finish_mesh(Mesh& M) {
   const RefElem& R = M.R;
@@ -418,6 +492,31 @@ static void finish_mesh(Mesh& M) {
       M.Jinv[i] = 1.0 / J;
       M.area[i] = v[1] - v[0];
       M.perim[i] = 2.0;
+    } else if (R.kind == TET) {
+      // J[a][b] = d x_a / d xi_b = (v_{b+1} - v_0)_a; Jinv by the adjugate
+      double J[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) J[a][b] = v[3 * (b + 1) + a] - v[a];
+      double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      double* Ji = &M.Jinv[i * 9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          // inverse[a][b] = cofactor[b][a] / det
+          int r0 = (b + 1) % 3, r1 = (b + 2) % 3, c0 = (a + 1) % 3, c1 = (a + 2) % 3;
+          Ji[a * 3 + b] = (J[r0][c0] * J[r1][c1] - J[r0][c1] * J[r1][c0]) / det;
+        }
+      M.area[i] = det * R.T0;
+      double P = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        const double* A = &v[3 * TET_FACE[k][0]];
+        const double* B = &v[3 * TET_FACE[k][1]];
+        const double* C = &v[3 * TET_FACE[k][2]];
+        double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]}, w[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        P += 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      }
+      M.perim[i] = P;
     } else {
       double J[2][2];
       if (R.kind == TRI) {
@@ -457,15 +556,63 @@ static void finish_mesh(Mesh& M) {
       if (j >= 0) { M.eid[j * K + kj] = e; M.eps[j * K + kj] = -1; }
       const double* v = &M.vx[i * R.NV * dim];
       if (dim == 1) {
-        M.e_n.push_back(k == 0 ? -1.0 : 1.0); M.e_n.push_back(0.0);
+        M.e_n.push_back(k == 0 ? -1.0 : 1.0); M.e_n.push_back(0.0); M.e_n.push_back(0.0);
         M.e_len.push_back(1.0);
-      } else {
+      } else if (dim == 2) {
         int b = (k + 1) % R.NV;
         double dx = v[2 * b] - v[2 * k], dy = v[2 * b + 1] - v[2 * k + 1];
-        M.e_n.push_back(dy); M.e_n.push_back(-dx);
+        M.e_n.push_back(dy); M.e_n.push_back(-dx); M.e_n.push_back(0.0);
         M.e_len.push_back(std::hypot(dx, dy));
+      } else {  // face k: n = (1/2)(B - A) x (C - A), outward, |n| = face area
+        const double* A = &v[3 * TET_FACE[k][0]];
+        const double* B = &v[3 * TET_FACE[k][1]];
+        const double* C = &v[3 * TET_FACE[k][2]];
+        double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]}, w[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        double n[3] = {0.5 * (u[1] * w[2] - u[2] * w[1]), 0.5 * (u[2] * w[0] - u[0] * w[2]), 0.5 * (u[0] * w[1] - u[1] * w[0])};
+        for (int a = 0; a < 3; ++a) M.e_n.push_back(n[a]);
+        M.e_len.push_back(std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
       }
     }
+  build_point_order(M);
+}
+
+// Point order across each edge: in 1D and 2D the second element visits the edge's points in
+// reverse.  On tetrahedron faces the points of the j_e side are located among those of the
+// i_e side by their physical coordinates (shifted by the difference of the face centroids,
+// which is the period on periodic faces).
+static void build_point_order(Mesh& M) {
+  const RefElem& R = M.R;
+  const int N = M.N, K = R.K, dim = R.dim, NQ = R.NQE;
+  M.fmap.assign((size_t)N * K * NQ, 0);
+  M.finv.assign((size_t)N * K * NQ, 0);
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < K; ++k)
+      for (int jl = 0; jl < NQ; ++jl) {
+        int jj = (M.eps[i * K + k] > 0 || dim < 3) ? ((M.eps[i * K + k] > 0) ? jl : NQ - 1 - jl) : -1;
+        if (jj < 0) {
+          const int e = M.eid[i * K + k], ie = M.e_i[e], ke = M.e_ki[e];
+          double xj[3], ci[3] = {0, 0, 0}, cj[3] = {0, 0, 0}, xi_[3];
+          for (int q = 0; q < NQ; ++q) {
+            double a[3], b[3];
+            edge_point(R, ke, q, xi_); map_point(M, ie, xi_, a);
+            edge_point(R, k, q, xi_); map_point(M, i, xi_, b);
+            for (int c = 0; c < 3; ++c) { ci[c] += a[c] / NQ; cj[c] += b[c] / NQ; }
+          }
+          edge_point(R, k, jl, xi_);
+          map_point(M, i, xi_, xj);
+          double best = 1e300;
+          for (int q = 0; q < NQ; ++q) {
+            double a[3];
+            edge_point(R, ke, q, xi_);
+            map_point(M, ie, xi_, a);
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) d2 += (xj[c] - (cj[c] - ci[c]) - a[c]) * (xj[c] - (cj[c] - ci[c]) - a[c]);
+            if (d2 < best) { best = d2; jj = q; }
+          }
+        }
+        M.fmap[((size_t)i * K + k) * NQ + jl] = jj;
+        M.finv[((size_t)i * K + k) * NQ + jj] = jl;
+      }
 }
 
 static Mesh* mesh_1d(int n, double x0, double x1, int bcl, int bcr) {
@@ -601,6 +748,84 @@ static Mesh* mesh_tri(int nn, const double* xy, int nt, const int* tri, const in
   return M;
 }
 
+// Tetrahedral mesh: nodes xyz (nn x 3), tetrahedra tet (nt x 4, positively oriented), boundary
+// codes per (tetrahedron, face k opposite vertex k) (null: transparent), period (3 lengths, 0 for
+// a non-periodic axis) for periodic faces, which are paired by their centroids.  Inflow sides are
+// not supported on tetrahedra.
+static Mesh* mesh_tet(int nn, const double* xyz, int nt, const int* tet, const int* bnd, const double* period,
+                      std::string* err) {
+  Mesh* M = new Mesh;
+  M->R = make_ref(TET);
+  M->N = nt;
+  for (int t = 0; t < nt; ++t)
+    for (int a = 0; a < 4; ++a) {
+      int v = tet[4 * t + a];
+      if (v < 0 || v >= nn) { *err = "node index out of range"; delete M; return nullptr; }
+      for (int c = 0; c < 3; ++c) M->vx.push_back(xyz[3 * v + c]);
+    }
+  M->nbr.assign(4 * nt, -1); M->nbr_k.assign(4 * nt, -1); M->ebc.assign(4 * nt, BC_INTERIOR);
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> open;
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < 4; ++k) {
+      int f[3];
+      for (int m = 0; m < 3; ++m) f[m] = tet[4 * t + TET_FACE[k][m]];
+      std::sort(f, f + 3);
+      auto key = std::make_tuple(f[0], f[1], f[2]);
+      auto it = open.find(key);
+      if (it == open.end()) open[key] = {t, k};
+      else {
+        int t2 = it->second.first, k2 = it->second.second;
+        M->nbr[4 * t + k] = t2; M->nbr_k[4 * t + k] = k2;
+        M->nbr[4 * t2 + k2] = t; M->nbr_k[4 * t2 + k2] = k;
+        open.erase(it);
+      }
+    }
+  std::vector<std::pair<int, int>> per;
+  for (auto& kv : open) {
+    int t = kv.second.first, k = kv.second.second;
+    int code = bnd ? bnd[4 * t + k] : BC_TRANSPARENT;
+    if (code == BC_INFLOW) { *err = "inflow boundaries are not supported on tetrahedra"; delete M; return nullptr; }
+    if (code == BC_PERIODIC) per.push_back({t, k});
+    else M->ebc[4 * t + k] = code;
+  }
+  if (!per.empty()) {
+    if (!period) { *err = "periodic faces without a period"; delete M; return nullptr; }
+    auto cen = [&](int t, int k, double* c) {
+      const double* v = &M->vx[12 * t];
+      for (int a = 0; a < 3; ++a)
+        c[a] = (v[3 * TET_FACE[k][0] + a] + v[3 * TET_FACE[k][1] + a] + v[3 * TET_FACE[k][2] + a]) / 3.0;
+    };
+    const double tol = 1e-9 * (std::fabs(period[0]) + std::fabs(period[1]) + std::fabs(period[2]));
+    std::vector<int> used(per.size(), 0);
+    for (size_t p = 0; p < per.size(); ++p) {
+      if (used[p]) continue;
+      double cp[3]; cen(per[p].first, per[p].second, cp);
+      bool found = false;
+      for (size_t q = p + 1; q < per.size() && !found; ++q) {
+        if (used[q]) continue;
+        double cq[3]; cen(per[q].first, per[q].second, cq);
+        int shifted = 0, same = 0;
+        for (int a = 0; a < 3; ++a) {
+          const double d = std::fabs(cq[a] - cp[a]);
+          if (d < tol) ++same;
+          else if (period[a] > 0 && std::fabs(d - period[a]) < tol) ++shifted;
+        }
+        if (shifted == 1 && same == 2) {
+          int t = per[p].first, k = per[p].second, t2 = per[q].first, k2 = per[q].second;
+          M->nbr[4 * t + k] = t2; M->nbr_k[4 * t + k] = k2;
+          M->nbr[4 * t2 + k2] = t; M->nbr_k[4 * t2 + k2] = k;
+          used[p] = used[q] = 1; found = true;
+        }
+      }
+      if (!found) { *err = "unpaired periodic face"; delete M; return nullptr; }
+    }
+  }
+  finish_mesh(*M);
+  for (int t = 0; t < nt; ++t)
+    if (!(M->area[t] > 0.0)) { *err = "tetrahedron not positively oriented or degenerate"; delete M; return nullptr; }
+  return M;
+}
+
 // ------------------------------------------------------------------------------------------
 // Solver state and the step.
 // ------------------------------------------------------------------------------------------
@@ -639,6 +864,11 @@ static void map_point(const Mesh& M, int i, const double* xi, double* x) {
   const RefElem& R = M.R;
   const double* v = &M.vx[i * R.NV * R.dim];
   if (R.kind == LINE) { x[0] = v[0] + 0.5 * (xi[0] + 1.0) * (v[1] - v[0]); return; }
+  if (R.kind == TET) {
+    for (int a = 0; a < 3; ++a)
+      x[a] = v[a] + xi[0] * (v[3 + a] - v[a]) + xi[1] * (v[6 + a] - v[a]) + xi[2] * (v[9 + a] - v[a]);
+    return;
+  }
   if (R.kind == TRI) {
     x[0] = v[0] + xi[0] * (v[2] - v[0]) + xi[1] * (v[4] - v[0]);
     x[1] = v[1] + xi[0] * (v[3] - v[1]) + xi[1] * (v[5] - v[1]);
@@ -653,6 +883,11 @@ static void grad_phi(const Mesh& M, int i, int l, const double* xi, double* g) {
   const RefElem& R = M.R;
   const double* Ji = &M.Jinv[i * R.dim * R.dim];
   if (R.dim == 1) { g[0] = Ji[0] * phi(R, l, xi, 1, 0); return; }
+  if (R.dim == 3) {
+    const double r[3] = {phi(R, l, xi, 1, 0, 0), phi(R, l, xi, 0, 1, 0), phi(R, l, xi, 0, 0, 1)};
+    for (int d = 0; d < 3; ++d) g[d] = Ji[0 * 3 + d] * r[0] + Ji[1 * 3 + d] * r[1] + Ji[2 * 3 + d] * r[2];
+    return;
+  }
   double d0 = phi(R, l, xi, 1, 0), d1 = phi(R, l, xi, 0, 1);
   g[0] = Ji[0] * d0 + Ji[2] * d1;
   g[1] = Ji[1] * d0 + Ji[3] * d1;
@@ -663,6 +898,20 @@ static void hess_phi(const Mesh& M, int i, int l, const double* xi, double* H) {
   const RefElem& R = M.R;
   const double* Ji = &M.Jinv[i * R.dim * R.dim];
   if (R.dim == 1) { H[0] = Ji[0] * Ji[0] * phi(R, l, xi, 2, 0); return; }
+  if (R.dim == 3) {
+    double r[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        r[a][b] = phi(R, l, xi, (a == 0) + (b == 0), (a == 1) + (b == 1), (a == 2) + (b == 2));
+    for (int d = 0; d < 3; ++d)
+      for (int e = 0; e < 3; ++e) {
+        double t = 0.0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) t += Ji[a * 3 + d] * Ji[b * 3 + e] * r[a][b];
+        H[d * 3 + e] = t;
+      }
+    return;
+  }
   double r[2][2] = {{phi(R, l, xi, 2, 0), phi(R, l, xi, 1, 1)}, {phi(R, l, xi, 1, 1), phi(R, l, xi, 0, 2)}};
   for (int d = 0; d < 2; ++d)
     for (int e = 0; e < 2; ++e) {
@@ -708,12 +957,16 @@ static void eval_q(const Mesh& M, const double* Qi, const double* xi, double* q)
 // The limiter points: interior quadrature points and edge quadrature points (Sec. 3.1).
 static std::vector<std::vector<double>> limiter_points(const RefElem& R) {
   std::vector<std::vector<double>> pts;
-  for (int m = 0; m < R.NI; ++m) pts.push_back({R.xi_int[m * R.dim], R.dim == 2 ? R.xi_int[m * R.dim + 1] : 0.0});
+  for (int m = 0; m < R.NI; ++m) {
+    std::vector<double> x(3, 0.0);
+    for (int a = 0; a < R.dim; ++a) x[a] = R.xi_int[m * R.dim + a];
+    pts.push_back(x);
+  }
   for (int k = 0; k < R.K; ++k)
     for (int j = 0; j < R.NQE; ++j) {
-      double xi[2] = {0, 0};
+      double xi[3] = {0, 0, 0};
       edge_point(R, k, j, xi);
-      pts.push_back({xi[0], xi[1]});
+      pts.push_back({xi[0], xi[1], xi[2]});
     }
   return pts;
 }
@@ -740,7 +993,7 @@ static std::vector<std::vector<double>> limiter_points(const RefElem& R) {
 static double exact_segment_root(int dim, double gam, const double* qbar, const double* qt, double eps_p,
                                  double s_c) {
   const int V = dim + 2;
-  double D[4];
+  double D[5];
   for (int v = 0; v < V; ++v) D[v] = qt[v] - qbar[v];
   const double gm1 = gam - 1.0;
   double dMdM = 0.0, dMM = 0.0, MM = 0.0;
@@ -758,7 +1011,7 @@ static double exact_segment_root(int dim, double gam, const double* qbar, const 
     sr = den > 0.0 ? 2.0 * C / den : 1.0;
   }
   sr = std::min(sr, 1.0) * (1.0 - 1e-10);
-  double q[4];
+  double q[5];
   for (int v = 0; v < V; ++v) q[v] = qbar[v] + sr * D[v];
   if (!(q[0] > 0.0) || !(pressure(dim, gam, q) >= eps_p)) return s_c;
   return std::max(s_c, sr);
@@ -767,7 +1020,7 @@ static double exact_segment_root(int dim, double gam, const double* qbar, const 
 static double moment_limit(const Mesh& M, const Params& P, double* Qi) {
   const RefElem& R = M.R;
   int V = NVAR(M), ML = R.ML, dim = R.dim;
-  double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+  double qbar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML + 0];
   double rbar = qbar[0];
   double pbar = pressure(dim, P.gamma, qbar);
@@ -778,7 +1031,7 @@ static double moment_limit(const Mesh& M, const Params& P, double* Qi) {
     auto pts = limiter_points(R);
     std::vector<std::vector<double>> dev;  // q~_m
     for (auto& x : pts) {
-      double q[4];
+      double q[5];
       eval_q(M, Qi, x.data(), q);
       std::vector<double> d(V);
       for (int v = 0; v < V; ++v) d[v] = q[v] - qbar[v];
@@ -792,7 +1045,7 @@ static double moment_limit(const Mesh& M, const Params& P, double* Qi) {
     double eps_p = std::min(P.eps0, pbar);
     theta = th_rho;
     for (auto& d : dev) {
-      double qt[4];
+      double qt[5];
       for (int v = 0; v < V; ++v) qt[v] = qbar[v] + th_rho * d[v];
       double pt = pressure(dim, P.gamma, qt);
       double thm = th_rho;
@@ -824,9 +1077,9 @@ static void bc_reflect(int dim, const double* q, const double* nhat, double* out
   int V = dim + 2;
   for (int v = 0; v < V; ++v) out[v] = q[v];
   if (dim == 1) { out[1] = -q[1]; return; }
-  double mn = q[1] * nhat[0] + q[2] * nhat[1];
-  out[1] = q[1] - 2.0 * mn * nhat[0];
-  out[2] = q[2] - 2.0 * mn * nhat[1];
+  double mn = 0.0;
+  for (int d = 0; d < dim; ++d) mn += q[1 + d] * nhat[d];
+  for (int d = 0; d < dim; ++d) out[1 + d] = q[1 + d] - 2.0 * mn * nhat[d];
 }
 
 // F_T of Eq. (taylor3-flux) from q, q_t, q_tt at a point (chain rule for F_t and F_tt).
@@ -834,7 +1087,7 @@ static void ft_from_derivs(int dim, double gam, double dt, const double* q, cons
                            const double* qtt, double* FT /* dim x V */) {
   int V = dim + 2;
   for (int d = 0; d < dim; ++d) {
-    double F[4], Ft[4], H[4], Aqtt[4];
+    double F[5], Ft[5], H[5], Aqtt[5];
     euler_flux<double>(dim, gam, q, d, F);
     flux_jvp(dim, gam, q, d, qt, Ft);
     flux_hvp(dim, gam, q, d, qt, qt, H);
@@ -851,7 +1104,7 @@ static void ft4_from_derivs(int dim, double gam, double dt, const double* q, con
                             const double* qtt, const double* qttt, double* FT /* dim x V */) {
   int V = dim + 2;
   for (int d = 0; d < dim; ++d) {
-    double F[4], Ft[4], H[4], Aqtt[4], T3[4], H2[4], Aqttt[4];
+    double F[5], Ft[5], H[5], Aqtt[5], T3[5], H2[5], Aqttt[5];
     euler_flux<double>(dim, gam, q, d, F);
     flux_jvp(dim, gam, q, d, qt, Ft);
     flux_hvp(dim, gam, q, d, qt, qt, H);
@@ -866,13 +1119,14 @@ static void ft4_from_derivs(int dim, double gam, double dt, const double* q, con
 }
 
 struct Trace {  // per element, local edge, edge point: q and its time derivatives, F_T (dim x V)
-  double q[4], qt[4], qtt[4], qttt[4], FT[8];
+  double q[5], qt[5], qtt[5], qttt[5], FT[15];
 };
 
 // The shock-capturing limiter (Sec. 1.5 Step 5, Sec. 4.1).  The paper cites this limiter but does
 // not define it; the reading implemented here works on the primitive variables w in
-// {rho, u, (v), p}, with relaxation delta = alpha0 h^1.5 (alpha0 = 500; h = Delta x in 1D,
-// sqrt|T| on quads, sqrt(2|T|) on triangles).  Bounds: M_w = max(w_bar_i + delta, max over edge
+// {rho, u, (v, w), p}, with relaxation delta = alpha0 h^1.5 (alpha0 = 500; h = Delta x in 1D,
+// sqrt|T| on quads, sqrt(2|T|) on triangles, cbrt(6|T|) on tetrahedra: the lattice spacing of
+// the split square and cube).  Bounds: M_w = max(w_bar_i + delta, max over edge
 // neighbours of w_bar_j), m_w = min(w_bar_i - delta, min_j w_bar_j); neighbour averages across
 // boundary edges are the boundary operator applied to the own average.  theta^w shrinks the
 // deviation from w_bar_i at the limiter points so that the extremes meet the bounds; velocity and
@@ -888,36 +1142,38 @@ static double shock_limit(const Solver& S, const std::vector<double>& Qold, int 
     for (int d = 0; d < dim; ++d) w[1 + d] = q[1 + d] / q[0];
     w[dim + 1] = pressure(dim, gam, q);
   };
-  double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+  double qbar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML];
   if (!(qbar[0] >= S.P.eps0) || !(pressure(dim, gam, qbar) > 0.0)) return 1.0;
-  double wbar[4];
+  double wbar[5];
   prim(qbar, wbar);
-  double h = (R.kind == LINE) ? M.area[i] : (R.kind == QUAD ? std::sqrt(M.area[i]) : std::sqrt(2.0 * M.area[i]));
+  double h = (R.kind == LINE) ? M.area[i]
+             : (R.kind == QUAD ? std::sqrt(M.area[i])
+                               : (R.kind == TET ? std::cbrt(6.0 * M.area[i]) : std::sqrt(2.0 * M.area[i])));
   double delta = S.P.alpha0 * std::pow(h, 1.5);
-  double Mx[4], Mn[4];
+  double Mx[5], Mn[5];
   for (int w = 0; w < V; ++w) { Mx[w] = wbar[w] + delta; Mn[w] = wbar[w] - delta; }
   for (int k = 0; k < K; ++k) {
-    double qn[4];
+    double qn[5];
     int j = M.nbr[i * K + k];
     if (j >= 0) {
       for (int v = 0; v < V; ++v) qn[v] = Qold[(size_t)j * V * ML + v * ML];
     } else {
       int bc = M.ebc[i * K + k];
       int e = M.eid[i * K + k];
-      double nh[2] = {M.e_n[2 * e] / M.e_len[e], M.e_n[2 * e + 1] / M.e_len[e]};
+      double nh[3] = {M.e_n[3 * e] / M.e_len[e], M.e_n[3 * e + 1] / M.e_len[e], M.e_n[3 * e + 2] / M.e_len[e]};
       if (bc == BC_REFLECTIVE) bc_reflect(dim, qbar, nh, qn);
       else if (bc == BC_INFLOW) for (int v = 0; v < V; ++v) qn[v] = (dim == 1 && v == 2) ? S.P.inflow[3] : S.P.inflow[v];
       else for (int v = 0; v < V; ++v) qn[v] = qbar[v];
     }
-    double wn[4];
+    double wn[5];
     prim(qn, wn);
     for (int w = 0; w < V; ++w) { Mx[w] = std::max(Mx[w], wn[w]); Mn[w] = std::min(Mn[w], wn[w]); }
   }
-  double wmax[4], wmin[4];
+  double wmax[5], wmin[5];
   for (int w = 0; w < V; ++w) { wmax[w] = wbar[w]; wmin[w] = wbar[w]; }
   for (auto& x : limiter_points(R)) {
-    double q[4], wv[4];
+    double q[5], wv[5];
     eval_q(M, Qi, x.data(), q);
     wmax[0] = std::max(wmax[0], q[0]); wmin[0] = std::min(wmin[0], q[0]);
     if (q[0] > 0.0) {
@@ -944,12 +1200,12 @@ static double shock_limit(const Solver& S, const std::vector<double>& Qold, int 
 static double mu_solve(int dim, double gam, double eps_p, const double* qL, const double* qa) {
   int V = dim + 2;
   auto ok = [&](double mu) {
-    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int v = 0; v < V; ++v) q[v] = qL[v] + mu * (qa[v] - qL[v]);
     return q[0] > 0.0 && pressure(dim, gam, q) >= eps_p;
   };
   if (ok(1.0)) return 1.0;
-  double d[4];
+  double d[5];
   for (int v = 0; v < V; ++v) d[v] = qa[v] - qL[v];
   double mL2 = 0.0, mLd = 0.0, dd2 = 0.0;
   for (int k = 1; k <= dim; ++k) { mL2 += qL[k] * qL[k]; mLd += qL[k] * d[k]; dd2 += d[k] * d[k]; }
@@ -989,8 +1245,9 @@ static int step(Solver& S, double T) {
   const double gam = S.P.gamma;
   const size_t QS = (size_t)V * ML;
   S.err_elem = -1; S.err.clear();
-  // threads only where the loops are long enough to pay for them (results do not depend on it)
-  const bool par = N >= 4096;
+  // threads only where the loops are long enough to pay for them (results do not depend on it);
+  // a tetrahedron's step costs about 30 times a triangle's
+  const bool par = N >= (dim == 3 ? 64 : 4096);
   (void)par;
   for (double x : S.Q)
     if (!std::isfinite(x)) return set_err(S, ERR_NONFINITE, -1, "non-finite state");
@@ -1001,7 +1258,7 @@ static int step(Solver& S, double T) {
 #pragma omp parallel for schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     double* Qi = &S.Q[i * QS];
-    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    double qbar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML];
     if (!(qbar[0] > 0.0) || !(pressure(dim, gam, qbar) > 0.0)) {
 #pragma omp critical
@@ -1021,11 +1278,11 @@ static int step(Solver& S, double T) {
 #pragma omp parallel for reduction(max : s, geo) schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     const double* Qi = &S.Q[i * QS];
-    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    double qbar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int v = 0; v < V; ++v) qbar[v] = Qi[v * ML];
     double si = wave_speed(dim, gam, qbar);
     if (!S.P.s_avg) for (auto& x : pts) {
-      double q[4];
+      double q[5];
       eval_q(M, Qi, x.data(), q);
       si = std::max(si, wave_speed(dim, gam, q));
     }
@@ -1050,30 +1307,30 @@ static int step(Solver& S, double T) {
 #pragma omp parallel for schedule(static) if (par)
   for (int i = 0; i < N; ++i) {
     const double* Qi = &S.Q[i * QS];
-    double Fh[2][4][10];
+    double Fh[3][5][10];
     for (int d = 0; d < dim; ++d)
       for (int v = 0; v < V; ++v)
         for (int l = 0; l < ML; ++l) Fh[d][v][l] = 0.0;
     for (int m = 0; m < NI; ++m) {
       const double* xi = &R.xi_int[m * dim];
-      double q[4];
+      double q[5];
       eval_q(M, Qi, xi, q);
       for (int d = 0; d < dim; ++d) {
-        double F[4];
+        double F[5];
         euler_flux<double>(dim, gam, q, d, F);
         for (int v = 0; v < V; ++v)
           for (int l = 0; l < ML; ++l) Fh[d][v][l] += R.w_int[m] * F[v] * phi(R, l, xi);
       }
     }
     auto at_point = [&](const double* xi, double* q, double* qt, double* qtt, double* qttt, double* FT) {
-      double dq[2][4], D[4], dD[2][4];
+      double dq[3][5], D[5], dD[3][5];
       eval_q(M, Qi, xi, q);
       for (int v = 0; v < V; ++v) {
         for (int a = 0; a < dim; ++a) { dq[a][v] = 0.0; dD[a][v] = 0.0; }
         D[v] = 0.0;
       }
       for (int l = 0; l < ML; ++l) {
-        double g[2], H[4];
+        double g[3], H[9];
         grad_phi(M, i, l, xi, g);
         hess_phi(M, i, l, xi, H);
         for (int v = 0; v < V; ++v) {
@@ -1087,7 +1344,7 @@ static int step(Solver& S, double T) {
       for (int v = 0; v < V; ++v) qt[v] = -D[v];
       for (int v = 0; v < V; ++v) qtt[v] = 0.0;
       for (int d = 0; d < dim; ++d) {
-        double h[4], a[4];
+        double h[5], a[5];
         flux_hvp(dim, gam, q, d, dq[d], D, h);
         flux_jvp(dim, gam, q, d, dD[d], a);
         for (int v = 0; v < V; ++v) qtt[v] += h[v] + a[v];
@@ -1147,7 +1404,7 @@ static int step(Solver& S, double T) {
     double* Vi = &S.Vol[i * QS];
     for (int m = 0; m < NI; ++m) {
       const double* xi = &R.xi_int[m * dim];
-      double q[4], qt[4], qtt[4], qttt[4], FT[8];
+      double q[5], qt[5], qtt[5], qttt[5], FT[15];
       at_point(xi, q, qt, qtt, qttt, FT);
       for (int v = 0; v < V; ++v) {
         S.qderiv[(((size_t)i * NI + m) * 3 + 0) * V + v] = qt[v];
@@ -1155,7 +1412,7 @@ static int step(Solver& S, double T) {
         S.qderiv[(((size_t)i * NI + m) * 3 + 2) * V + v] = qttt[v];
       }
       for (int l = 0; l < ML; ++l) {
-        double g[2];
+        double g[3];
         grad_phi(M, i, l, xi, g);
         for (int v = 0; v < V; ++v) {
           double dot = 0.0;
@@ -1166,7 +1423,7 @@ static int step(Solver& S, double T) {
     }
     for (int k = 0; k < K; ++k)
       for (int j = 0; j < NQE; ++j) {
-        double xi[2] = {0, 0};
+        double xi[3] = {0, 0, 0};
         edge_point(R, k, j, xi);
         Trace& T_ = tr[((size_t)i * K + k) * NQE + j];
         at_point(xi, T_.q, T_.qt, T_.qtt, T_.qttt, T_.FT);
@@ -1180,11 +1437,11 @@ static int step(Solver& S, double T) {
 #pragma omp parallel for schedule(static) if (par)
   for (int e = 0; e < E; ++e) {
     int i = M.e_i[e], ki = M.e_ki[e], j = M.e_j[e], kj = M.e_kj[e];
-    const double* n = &M.e_n[2 * e];
+    const double* n = &M.e_n[3 * e];
     double len = M.e_len[e];
-    double nh[2] = {n[0] / len, n[1] / len};
+    double nh[3] = {n[0] / len, n[1] / len, n[2] / len};
     int bc = M.e_bc[e];
-    double qbi[4], qbj[4];
+    double qbi[5], qbj[5];
     for (int v = 0; v < V; ++v) qbi[v] = S.Q[i * QS + v * ML];
     if (j >= 0) for (int v = 0; v < V; ++v) qbj[v] = S.Q[j * QS + v * ML];
     else if (bc == BC_REFLECTIVE) bc_reflect(dim, qbi, nh, qbj);
@@ -1192,13 +1449,13 @@ static int step(Solver& S, double T) {
     else for (int v = 0; v < V; ++v) qbj[v] = qbi[v];
     for (int jj = 0; jj < NQE; ++jj) {
       const Trace& Tm = tr[((size_t)i * K + ki) * NQE + jj];
-      double qp[4], FTp[8];
+      double qp[5], FTp[15];
       if (j >= 0) {
-        const Trace& Tp = tr[((size_t)j * K + kj) * NQE + (NQE - 1 - jj)];
+        const Trace& Tp = tr[((size_t)j * K + kj) * NQE + M.finv[((size_t)j * K + kj) * NQE + jj]];
         for (int v = 0; v < V; ++v) qp[v] = Tp.q[v];
         for (int x = 0; x < dim * V; ++x) FTp[x] = Tp.FT[x];
       } else if (bc == BC_REFLECTIVE) {
-        double qt[4], qtt[4], qttt[4];
+        double qt[5], qtt[5], qttt[5];
         bc_reflect(dim, Tm.q, nh, qp);
         bc_reflect(dim, Tm.qt, nh, qt);
         bc_reflect(dim, Tm.qtt, nh, qtt);
@@ -1209,7 +1466,7 @@ static int step(Solver& S, double T) {
           ft_from_derivs(dim, gam, dt, qp, qt, qtt, FTp);
         }
       } else if (bc == BC_INFLOW) {
-        double z[4] = {0, 0, 0, 0};
+        double z[5] = {0, 0, 0, 0, 0};
         for (int v = 0; v < V; ++v) qp[v] = qbj[v];
         if (R.deg == 3) ft4_from_derivs(dim, gam, dt, qp, z, z, z, FTp);
         else ft_from_derivs(dim, gam, dt, qp, z, z, FTp);
@@ -1229,7 +1486,7 @@ static int step(Solver& S, double T) {
       for (int jj = 0; jj < NQE; ++jj) acc += R.om_edge[jj] * Fstar[((size_t)e * NQE + jj) * V + v];
       fLxW[e * V + v] = 0.5 * acc;
     }
-    double Fi[4], Fj[4];
+    double Fi[5], Fj[5];
     for (int v = 0; v < V; ++v) fLxF[e * V + v] = 0.0;
     for (int d = 0; d < dim; ++d) {
       euler_flux<double>(dim, gam, qbi, d, Fi);
@@ -1256,11 +1513,11 @@ static int step(Solver& S, double T) {
   S.c_ik.assign((size_t)N * K, 1.0);
   int cfl_bad = -1;
   for (int i = 0; i < N; ++i) {
-    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    double qbar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int v = 0; v < V; ++v) qbar[v] = S.Q[i * QS + v * ML];
     double area = M.area[i];
     double Gam = area * qbar[0] / dt;
-    double df[4], fW[4][4], fF[4][4];
+    double df[4], fW[4][5], fF[4][5];
     for (int k = 0; k < K; ++k) {
       int e = M.eid[i * K + k];
       double ep = M.eps[i * K + k];
@@ -1278,7 +1535,7 @@ static int step(Solver& S, double T) {
       if (df[k] < 0.0) Lam[k] = std::max(0.0, std::min(1.0, Gam / std::fabs(Sneg)));
       S.Lam_ik[i * K + k] = Lam[k];
     }
-    double qL[4];
+    double qL[5];
     for (int v = 0; v < V; ++v) {
       double acc = 0.0;
       for (int k = 0; k < K; ++k) acc += fF[k][v];
@@ -1289,7 +1546,7 @@ static int step(Solver& S, double T) {
     double eps_p = std::min(S.P.eps0, pL);
     double mmin[4] = {1.0, 1.0, 1.0, 1.0};
     for (int a = 1; a < (1 << K); ++a) {
-      double qa[4];
+      double qa[5];
       for (int v = 0; v < V; ++v) {
         double acc = 0.0;
         for (int k = 0; k < K; ++k) {
@@ -1339,8 +1596,8 @@ static int step(Solver& S, double T) {
       }
       for (int jl = 0; jl < NQE; ++jl) {
         // local point jl of element i corresponds to edge point jj in i_e's ordering
-        int jj = (ep > 0) ? jl : (NQE - 1 - jl);
-        double xi[2] = {0, 0};
+        int jj = M.fmap[((size_t)i * K + k) * NQE + jl];
+        double xi[3] = {0, 0, 0};
         edge_point(R, k, jl, xi);
         for (int l = 1; l < ML; ++l) {
           double ph = phi(R, l, xi);
@@ -1368,7 +1625,7 @@ static int step(Solver& S, double T) {
 
   // ---- Positivity of the new cell averages (guaranteed by Sec. 3.2-3.3) ---------------------
   for (int i = 0; i < N; ++i) {
-    double qbar[4] = {0.0, 0.0, 0.0, 0.0};
+    double qbar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int v = 0; v < V; ++v) qbar[v] = S.Q[i * QS + v * ML];
     for (int v = 0; v < V; ++v)
       if (!std::isfinite(qbar[v])) return set_err(S, ERR_NONFINITE, i, "non-finite cell average");
@@ -1408,6 +1665,10 @@ void* ora_mesh_tri(int nn, const double* xy, int nt, const int* tri, const int* 
   g_err.clear();
   return mesh_tri(nn, xy, nt, tri, bnd, period, &g_err);
 }
+void* ora_mesh_tet(int nn, const double* xyz, int nt, const int* tet, const int* bnd, const double* period) {
+  g_err.clear();
+  return mesh_tet(nn, xyz, nt, tet, bnd, period, &g_err);
+}
 const char* ora_last_error() { return g_err.c_str(); }
 void ora_mesh_free(void* m) { delete (Mesh*)m; }
 
@@ -1421,6 +1682,20 @@ void ora_mesh_geom(void* m, double* area, double* perim, int* nbr, int* nbr_k) {
   Mesh* M = (Mesh*)m;
   for (int i = 0; i < M->N; ++i) { area[i] = M->area[i]; perim[i] = M->perim[i]; }
   for (int x = 0; x < M->N * M->R.K; ++x) { nbr[x] = M->nbr[x]; nbr_k[x] = M->nbr_k[x]; }
+}
+
+// Edges (faces in 3D): i_e, its local index, j_e (-1 on the boundary), its local index, and n_e
+// (E x 3, |n_e| the edge length or face area); the point order of every (element, local edge).
+void ora_mesh_edges(void* m, int* ei, int* ki, int* ej, int* kj, double* n) {
+  Mesh* M = (Mesh*)m;
+  for (int e = 0; e < M->E; ++e) {
+    ei[e] = M->e_i[e]; ki[e] = M->e_ki[e]; ej[e] = M->e_j[e]; kj[e] = M->e_kj[e];
+    for (int a = 0; a < 3; ++a) n[3 * e + a] = M->e_n[3 * e + a];
+  }
+}
+void ora_mesh_point_order(void* m, int* fmap) {
+  Mesh* M = (Mesh*)m;
+  for (size_t x = 0; x < M->fmap.size(); ++x) fmap[x] = M->fmap[x];
 }
 
 void* ora_solver_new(void* m, double gamma, double cfl, double eps0, double alpha0, int shock, const double* inflow) {
@@ -1495,6 +1770,7 @@ int ora_mesh_set_degree(void* m, int deg) {
   RefElem R = make_ref(M->R.kind, deg);
   if (R.ML == 0) return -1;
   M->R = R;
+  build_point_order(*M);
   return 0;
 }
 void ora_ref_info(int kind, int deg, int* out) {
@@ -1509,15 +1785,16 @@ void ora_ref_tables(int kind, int deg, double* C, double* xi_int, double* w_int,
   int c = 0;
   for (int k = 0; k < R.K; ++k)
     for (int j = 0; j < R.NQE; ++j) {
-      double xi[2] = {0, 0};
+      double xi[3] = {0, 0, 0};
       edge_point(R, k, j, xi);
       for (int d = 0; d < R.dim; ++d) xi_edge[c++] = xi[d];
     }
   for (int j = 0; j < R.NQE; ++j) om_edge[j] = R.om_edge[j];
 }
-double ora_phi(int kind, int deg, int l, const double* xi, int da, int db) {
-  static RefElem R[2][3] = {{make_ref(0), make_ref(1), make_ref(2)}, {make_ref(0, 3), make_ref(1, 3), make_ref(2, 3)}};
-  return phi(R[deg == 3 ? 1 : 0][kind], l, xi, da, db);
+double ora_phi(int kind, int deg, int l, const double* xi, int da, int db, int dc) {
+  static RefElem R[2][4] = {{make_ref(0), make_ref(1), make_ref(2), make_ref(3)},
+                            {make_ref(0, 3), make_ref(1, 3), make_ref(2, 3), make_ref(3, 3)}};
+  return phi(R[deg == 3 ? 1 : 0][kind], l, xi, da, db, dc);
 }
 // Third derivative of the flux applied to three vectors, and F_T to fourth order, for tests.
 void ora_flux_3vp(int dim, double gam, const double* q, int d, const double* x, const double* y, const double* z,

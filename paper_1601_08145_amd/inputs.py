@@ -79,6 +79,62 @@ def boundary_tags(xy, tri, box, codes):
     return tags
 
 
+def lattice_tets(n, seed, jitter=0.12, box=(0.0, 1.0, 0.0, 1.0, 0.0, 1.0), periodic=False):
+    """Tetrahedral mesh of an n x n x n lattice of points on `box`: each lattice cube split into
+    the six tetrahedra along its main diagonal (the Kuhn subdivision, conforming across cubes),
+    interior points jittered by U[-jitter*h, jitter*h]^3, points on a side jittered only within
+    it.  With periodic=True the points on the high sides copy the jitter of their low-side
+    partners, so that boundary faces pair up under translation by one period.
+
+    Returns (xyz[n^3][3], tet[6 (n-1)^3][4]) with positively oriented tetrahedra."""
+    x0, x1, y0, y1, z0, z1 = box
+    h = np.array([(x1 - x0), (y1 - y0), (z1 - z0)]) / (n - 1)
+    g = rng(seed)
+    idx = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1)  # [i][j][k][3]
+    d = g.uniform(-jitter, jitter, size=idx.shape) * h
+    for a in range(3):
+        on = (idx[..., a] == 0) | (idx[..., a] == n - 1)
+        d[..., a][on] = 0.0
+    if periodic:
+        d[n - 1, :, :] = d[0, :, :]
+        d[:, n - 1, :] = d[:, 0, :]
+        d[:, :, n - 1] = d[:, :, 0]
+    xyz = (np.array([x0, y0, z0]) + idx * h + d).reshape(-1, 3)
+    node = lambda i, j, k: (i * n + j) * n + k
+    c = np.stack(np.meshgrid(np.arange(n - 1), np.arange(n - 1), np.arange(n - 1), indexing="ij"), -1).reshape(-1, 3)
+    tets = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        v = [c.copy()]
+        for a in perm:
+            nxt = v[-1].copy()
+            nxt[:, a] += 1
+            v.append(nxt)
+        tets.append(np.stack([node(w[:, 0], w[:, 1], w[:, 2]) for w in v], 1))
+    tet = np.concatenate(tets, 0).astype(np.int32)
+    a = xyz[tet]
+    vol = np.einsum("ij,ij->i", a[:, 1] - a[:, 0], np.cross(a[:, 2] - a[:, 0], a[:, 3] - a[:, 0]))
+    flip = vol < 0
+    tet[flip] = tet[flip][:, [0, 2, 1, 3]]
+    return np.ascontiguousarray(xyz), np.ascontiguousarray(tet)
+
+
+TET_FACES = ((1, 2, 3), (0, 3, 2), (0, 1, 3), (0, 2, 1))  # face k opposite vertex k, outward
+
+
+def boundary_tags_tet(xyz, tet, box, codes):
+    """Per tetrahedron face (n_tet x 4; face k opposite vertex k) the boundary code of the side of
+    `box` the face lies on (codes = {x-low, x-high, y-low, y-high, z-low, z-high}), -1 elsewhere."""
+    tol = 1e-9 * max(box[1] - box[0], box[3] - box[2], box[5] - box[4])
+    tags = np.full(tet.shape, -1, np.int32)
+    for k, f in enumerate(TET_FACES):
+        p = xyz[tet[:, list(f)]]  # [n][3][3]
+        for side in range(6):
+            a, val = side // 2, box[side]
+            on = np.all(np.abs(p[:, :, a] - val) < tol, axis=1)
+            tags[on, k] = codes[side]
+    return tags
+
+
 def ramp_channel(n_target, seed, angle_deg=30.0, length=4.0, height=1.5, ramp_x=0.5, ramp_len=1.0, jitter=0.25):
     """Channel [0, length] x [floor, height] whose floor rises at `angle_deg` from x = ramp_x over a
     horizontal run ramp_len and is flat after it (a double-Mach-reflection shaped domain), meshed
@@ -631,6 +687,28 @@ def random_modal_state(N, dim, n_modes, seed, amp=0.3, gamma=1.4, p_range=(0.3, 
         a[g.uniform(0, 1, N) < rough_frac] = rough_amp
     Q[:, :, 1:] = g.uniform(-1.0, 1.0, (N, V, n_modes - 1)) * (a[:, None] * scale)[:, :, None] / np.sqrt(n_modes)
     return Q
+
+
+def bowl_prim_tet(xyz, tet, pts, seed, rho_range=(1e-6, 1.0), p_range=(1e-8, 1.0), depth=0.02, curv=6.0, spread=3.0):
+    """The same adversarial fields on tetrahedra: in every tetrahedron a bowl-shaped density and
+    pressure (low at the centroid) of random log-uniform scale, and a random velocity plus an
+    outward spread from the centroid (h = the cube root of 6 |T|).  pts[N][P][3] are sample points
+    of each tetrahedron; returns prim[N][P][5]."""
+    g = rng(seed)
+    N = len(tet)
+    v = xyz[tet]
+    c = v.mean(axis=1)
+    vol = np.abs(np.einsum("ij,ij->i", v[:, 1] - v[:, 0], np.cross(v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]))) / 6.0
+    h = np.cbrt(6.0 * vol)
+    rs = np.exp(g.uniform(math.log(rho_range[0]), math.log(rho_range[1]), N))
+    ps = np.exp(g.uniform(math.log(p_range[0]), math.log(p_range[1]), N))
+    vel = g.uniform(-2.0, 2.0, (N, 3))
+    d = (pts - c[:, None, :]) / h[:, None, None]
+    r2 = np.sum(d * d, axis=-1)
+    rho = rs[:, None] * (depth + curv * r2)
+    p = ps[:, None] * (depth + curv * r2)
+    u = [vel[:, None, a] + spread * d[..., a] for a in range(3)]
+    return np.stack([rho, u[0], u[1], u[2], p], axis=-1)
 
 
 def bowl_prim(xy, tri, pts, seed, rho_range=(1e-6, 1.0), p_range=(1e-8, 1.0), depth=0.02, curv=6.0, spread=3.0):

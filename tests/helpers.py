@@ -104,6 +104,19 @@ def error_rule(kind, n=6):
     return np.stack([U.ravel(), ((1 - U) * V).ravel()], 1), 2.0 * W.ravel()
 
 
+def error_rule_tet(n=5):
+    """An independent collapsed Gauss rule on the reference tetrahedron (0,0,0),(1,0,0),(0,1,0),
+    (0,0,1) (points, weights summing to 1), exact to degree 2n - 1."""
+    from scipy.special import roots_jacobi
+    x0, w0 = roots_jacobi(n, 0, 0)
+    x1, w1 = roots_jacobi(n, 1, 0)
+    x2, w2 = roots_jacobi(n, 2, 0)
+    U, Vv, W = np.meshgrid(0.5 * (1 + x0), 0.5 * (1 + x1), 0.5 * (1 + x2), indexing="ij")
+    wt = (6 / 64) * w0[:, None, None] * w1[None, :, None] * w2[None, None, :]
+    pts = np.stack([U * (1 - Vv) * (1 - W), Vv * (1 - W), W], -1).reshape(-1, 3)
+    return pts, wt.ravel()
+
+
 def l2_error(solver, ref, exact_fn, var=0):
     """L2 error of variable `var` of q^h against exact_fn (x -> conserved), measured with an
     independent higher-order rule (the method's own rule can coincide with interpolation

@@ -262,13 +262,19 @@ def test_shock_limiter_exact_where_variable_is_linear(which):
     assert n_lim >= M.N // 3, n_lim
 
 
-@pytest.mark.parametrize("kind", ["tri", "cart", "line"])
+@pytest.mark.parametrize("kind", ["tri", "cart", "line", "tet"])
 def test_shock_limiter_relaxation_uses_cell_size(kind):
     """delta = alpha0 h^1.5 with h the lattice spacing of a split-square triangle lattice
-    (h = sqrt(2|T|)), the side of a square cell (sqrt|T|) and dx in 1D: a cell whose neighbours all
-    share its average is bound by the relaxation alone, theta = delta / max_m |rho_m - rho_bar|."""
+    (h = sqrt(2|T|)), the side of a square cell (sqrt|T|), dx in 1D and the lattice spacing of a
+    cube split into six tetrahedra (h = cbrt(6|T|)): a cell whose neighbours all share its average
+    is bound by the relaxation alone, theta = delta / max_m |rho_m - rho_bar|."""
     n = 6
-    if kind == "tri":
+    if kind == "tet":
+        n = 3
+        xyz, tet = I.lattice_tets(n + 1, 0, jitter=0.0)
+        M = O.Mesh.tet(xyz, tet)
+        kcode, hlat = O.TET, 1.0 / n
+    elif kind == "tri":
         xy, tri = I.lattice_delaunay(n + 1, 0, jitter=0.0)
         M = O.Mesh.tri(xy, tri)
         kcode, hlat = O.TRI, 1.0 / n
