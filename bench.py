@@ -574,6 +574,39 @@ def p3_leg(L, mesh, xy, tri, steps, warmup):
     return out
 
 
+def tet_leg(L, steps, warmup, n=56):
+    """The step on tetrahedra (3D P2): a periodic jittered (n-1)^3-cube lattice split into six
+    tetrahedra per cube (998,250 at n = 56), the plane density wave along (1, 1, 1) with a uniform
+    flow, both forms: ms per step from graph replay, per-kernel times, element-updates per second,
+    FP32-mixed vs FP64 after the same steps."""
+    from paper_1601_08145_amd import inputs as I
+    xyz, tet = I.lattice_tets(n, 3, periodic=True)
+    tags = I.boundary_tags_tet(xyz, tet, (0, 1, 0, 1, 0, 1), [0] * 6)
+    mesh = L.Mesh.tet(xyz, tet, tags, (1.0, 1.0, 1.0))
+    xq = mesh.quad_points()
+    kv, u0 = np.array([1.0, 1.0, 1.0]), np.array([0.6, -0.3, 0.4])
+    rho = 1 + 0.3 * np.sin(2 * np.pi * (xq @ kv))
+    one = np.ones_like(rho)
+    prim = np.stack([rho, u0[0] * one, u0[1] * one, u0[2] * one, one], -1)
+    cons = np.concatenate([prim[..., :1], prim[..., :1] * prim[..., 1:4],
+                           prim[..., 4:] / 0.4 + 0.5 * prim[..., :1] * np.sum(prim[..., 1:4] ** 2, -1, keepdims=True)], -1)
+    Q0 = mesh.project(cons)
+    N = mesh.N
+    out = {"n_elem": N, "modes": 10, "workload": "plane density wave, periodic jittered tetrahedra", "steps": steps}
+    res = {}
+    for prec, name in ((L.FP32_MIXED, "FP32_MIXED"), (L.FP64, "FP64")):
+        r = time_gpu(L, mesh, Q0, prec, steps, warmup)
+        res[name] = r
+        ms = r["ms_graph"] / steps
+        out[name] = {"ms_per_step": ms, "element_updates_per_s": N / (ms * 1e-3),
+                     "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in r["kernels"].items() if v[1]}}
+        log(f"[bench]   tetrahedra {N}, {name}: {ms:.3f} ms/step ({out[name]['element_updates_per_s']:.3e} element-updates/s); "
+            f"kernels { {k: round(v * 1e3, 1) for k, v in out[name]['kernels_ms'].items()} } us")
+    out["rel_l1_fp32_vs_fp64"] = rel_l1(res["FP32_MIXED"]["Q"], res["FP64"]["Q"])
+    log(f"[bench]   tetrahedra FP32-mixed vs FP64 after {warmup + 2 * steps} steps: rel L1 {out['rel_l1_fp32_vs_fp64']:.2e}")
+    return out
+
+
 def sedov_disk_steps(L, steps, warmup, t_start=0.05):
     """The 2D Sedov blast (136k triangles, FP32-mixed), advanced to t_start, then `warmup` and
     `steps` steps replayed from the graph: the near-vacuum core keeps the flux and moment limiters
@@ -694,6 +727,8 @@ def main():
     ap.add_argument("--no-exact-theta", action="store_true", help="skip the exact moment-limiter factor leg")
     ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian Q2 blast leg")
     ap.add_argument("--no-p3", action="store_true", help="skip the degree-3 leg")
+    ap.add_argument("--no-tet", action="store_true", help="skip the tetrahedra (3D) leg")
+    ap.add_argument("--tet-only", action="store_true", help="run only the tetrahedra leg (for profiling)")
     ap.add_argument("--p3-only", action="store_true", help="run only the degree-3 leg (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy a float32 buffer of BYTES bytes 3 times (reference for HBM counters)")
@@ -727,6 +762,9 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched": batched_leg(L, args.steps, args.warmup)}), flush=True)
+        return
+    if args.tet_only:
+        print(json.dumps({"tet": tet_leg(L, args.steps, args.warmup)}), flush=True)
         return
     if args.sedov_disk_only:
         print(json.dumps({"sedov_disk": sedov_disk_steps(L, args.steps, args.warmup)}), flush=True)
@@ -817,6 +855,9 @@ def main():
     if not args.no_p3:
         log("[bench] degree 3 (P3 triangles)")
         out["p3"] = p3_leg(L, mesh, xy, tri, args.steps, args.warmup)
+    if not args.no_tet:
+        log("[bench] tetrahedra (3D)")
+        out["tet"] = tet_leg(L, args.steps, args.warmup)
     if not args.no_cartesian:
         log("[bench] Cartesian Q2 near-vacuum blast")
         out["cartesian_blast"] = cartesian_blast_leg(L)

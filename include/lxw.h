@@ -23,10 +23,13 @@
  *    lxw_refelem_info): phi_1 == 1, so Q[i][v][0] is the cell average of variable v.
  *  - Reference elements: 1D [-1,1]; quadrilateral [-1,1]^2 with vertices (-1,-1), (1,-1), (1,1),
  *    (-1,1); triangle (0,0), (1,0), (0,1).  Local edge k joins vertices k and k+1 (mod count);
- *    in 1D local edge 0 is the left end and 1 the right end.
+ *    in 1D local edge 0 is the left end and 1 the right end.  Tetrahedron (0,0,0), (1,0,0),
+ *    (0,1,0), (0,0,1) (3D, the construction of Sec. 3.3 carried face by face, as the paper
+ *    remarks): local face k is opposite vertex k.  n_var = 5 in 3D (rho, Mx, My, Mz, E).
  *  - Basis: Gram-Schmidt orthonormalisation, under (1/|T0|) int_{T0} f g, of the monomials
  *    1D {1, x, x^2}; quadrilateral {1, x, y, x^2, xy, y^2, x^2 y, x y^2, x^2 y^2} (tensor Legendre,
- *    9 modes); triangle {1, x, y, x^2, xy, y^2} (6 modes).  At degree 3 (line and triangle, the
+ *    9 modes); triangle {1, x, y, x^2, xy, y^2} (6 modes); tetrahedron {1, x, y, z, x^2, xy, xz,
+ *    y^2, yz, z^2} (10 modes).  At degree 3 (line and triangle, the
  *    construction of Sec. 2.2 one order further): 1D {1, x, x^2, x^3} (4 modes), triangle
  *    {1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3} (10 modes); n_modes in Q is then the
  *    degree's count, not the mesh's (lxw_mesh_get_info reports degree 2).
@@ -64,7 +67,7 @@ enum {
 enum { LXW_BC_PERIODIC = 0, LXW_BC_TRANSPARENT = 1, LXW_BC_REFLECTIVE = 2, LXW_BC_INFLOW = 3 };
 
 /* Mesh kinds. */
-enum { LXW_LINE = 0, LXW_QUAD = 1, LXW_TRI = 2 };
+enum { LXW_LINE = 0, LXW_QUAD = 1, LXW_TRI = 2, LXW_TET = 3 };
 
 /* Arithmetic of the step. */
 enum {
@@ -158,16 +161,29 @@ lxw_status lxw_mesh_create_cart_masked(int32_t nx, int32_t ny, double x0, double
 lxw_status lxw_mesh_create_tri(int32_t n_nodes, const double* xy, int32_t n_tri, const int32_t* tri,
                                const int32_t* bnd_tag, const double* period, lxw_mesh** out);
 
+/* Tetrahedral mesh (3D P2; Sec. 3.3's closing remark): n_nodes nodes xyz[n][3], n_tet positively
+ * oriented tetrahedra tet[n_tet][4] (det [v1-v0, v2-v0, v3-v0] > 0), optional boundary codes
+ * bnd_tag[n_tet][4] for the boundary faces (face k opposite vertex k; periodic, transparent or
+ * reflective; null: transparent), period[3] (lengths; 0 for an axis that is not periodic) when a
+ * code is periodic: periodic faces are paired by their centroids modulo the period.  Quadrature:
+ * 27-point collapsed Gauss rule inside (degree 5), the 7-point triangle rule on each face.  Errors:
+ * LXW_ERR_UNSUPPORTED for inflow sides; LXW_ERR_MESH for a degenerate or negatively oriented
+ * tetrahedron, a face shared by more than two tetrahedra or an unpaired periodic face;
+ * LXW_ERR_ARG for null arrays or out-of-range indices.  Tetrahedral meshes take single-mesh
+ * solvers of degree 2 without the learned indicator. */
+lxw_status lxw_mesh_create_tet(int32_t n_nodes, const double* xyz, int32_t n_tet, const int32_t* tet,
+                               const int32_t* bnd_tag, const double* period, lxw_mesh** out);
+
 lxw_status lxw_mesh_destroy(lxw_mesh* m);
 
 typedef struct lxw_mesh_info {
-  int32_t kind;      /* LXW_LINE, LXW_QUAD, LXW_TRI */
-  int32_t dim;       /* 1 or 2 */
+  int32_t kind;      /* LXW_LINE, LXW_QUAD, LXW_TRI, LXW_TET */
+  int32_t dim;       /* 1, 2 or 3 */
   int32_t n_elem;
   int32_t n_edge;
-  int32_t n_var;     /* 3 or 4 */
-  int32_t n_modes;   /* 3, 9 or 6 */
-  int32_t n_faces;   /* edges per element K: 2, 4 or 3 */
+  int32_t n_var;     /* 3, 4 or 5 */
+  int32_t n_modes;   /* 3, 9, 6 or 10 */
+  int32_t n_faces;   /* edges (faces) per element K: 2, 4, 3 or 4 */
   double min_area, max_area;
 } lxw_mesh_info;
 

@@ -98,14 +98,15 @@ struct GL4Init {
   }
 } gl4_init;
 
-void gauss_jacobi4(double* x, double* w) {
-  const double al = 1.0, be = 0.0;
+// n-point Gauss rule (n <= 4) for the weight (1 - x)^al on [-1, 1].
+void gauss_jacobi(int npt, double al, double* x, double* w) {
+  const double be = 0.0;
   double A[4][4] = {}, Z[4][4] = {};
-  for (int n = 0; n < 4; ++n) {
+  for (int n = 0; n < npt; ++n) {
     const double s = 2.0 * n + al + be;
-    A[n][n] = (be * be - al * al) / (s * (s + 2.0));
+    A[n][n] = (s == 0.0) ? 0.0 : (be * be - al * al) / (s * (s + 2.0));
     Z[n][n] = 1.0;
-    if (n + 1 < 4) {
+    if (n + 1 < npt) {
       const double m = n + 1.0, t = 2.0 * m + al + be;
       const double off = std::sqrt(4.0 * m * (m + al) * (m + be) * (m + al + be) / (t * t * (t + 1.0) * (t - 1.0)));
       A[n][n + 1] = A[n + 1][n] = off;
@@ -113,26 +114,26 @@ void gauss_jacobi4(double* x, double* w) {
   }
   for (int sweep = 0; sweep < 50; ++sweep) {
     double offn = 0.0;
-    for (int p = 0; p < 4; ++p)
-      for (int q = p + 1; q < 4; ++q) offn += A[p][q] * A[p][q];
+    for (int p = 0; p < npt; ++p)
+      for (int q = p + 1; q < npt; ++q) offn += A[p][q] * A[p][q];
     if (offn < 1e-40) break;
-    for (int p = 0; p < 4; ++p)
-      for (int q = p + 1; q < 4; ++q) {
+    for (int p = 0; p < npt; ++p)
+      for (int q = p + 1; q < npt; ++q) {
         if (A[p][q] == 0.0) continue;
         const double th = 0.5 * (A[q][q] - A[p][p]) / A[p][q];
         const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
         const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-        for (int k = 0; k < 4; ++k) {  // A <- A G (columns p, q)
+        for (int k = 0; k < npt; ++k) {  // A <- A G (columns p, q)
           const double akp = A[k][p], akq = A[k][q];
           A[k][p] = c * akp - sn * akq;
           A[k][q] = sn * akp + c * akq;
         }
-        for (int k = 0; k < 4; ++k) {  // A <- G^T A (rows p, q)
+        for (int k = 0; k < npt; ++k) {  // A <- G^T A (rows p, q)
           const double apk = A[p][k], aqk = A[q][k];
           A[p][k] = c * apk - sn * aqk;
           A[q][k] = sn * apk + c * aqk;
         }
-        for (int k = 0; k < 4; ++k) {  // eigenvectors
+        for (int k = 0; k < npt; ++k) {  // eigenvectors
           const double zkp = Z[k][p], zkq = Z[k][q];
           Z[k][p] = c * zkp - sn * zkq;
           Z[k][q] = sn * zkp + c * zkq;
@@ -140,10 +141,11 @@ void gauss_jacobi4(double* x, double* w) {
       }
   }
   int idx[4] = {0, 1, 2, 3};
-  std::sort(idx, idx + 4, [&](int i, int j) { return A[i][i] < A[j][j]; });
-  for (int k = 0; k < 4; ++k) {
+  std::sort(idx, idx + npt, [&](int i, int j) { return A[i][i] < A[j][j]; });
+  const double mu0 = std::pow(2.0, al + 1.0) / (al + 1.0);  // int_{-1}^{1} (1 - x)^al dx
+  for (int k = 0; k < npt; ++k) {
     x[k] = A[idx[k]][idx[k]];
-    w[k] = 2.0 * Z[0][idx[k]] * Z[0][idx[k]];
+    w[k] = mu0 * Z[0][idx[k]] * Z[0][idx[k]];
   }
 }
 
@@ -154,7 +156,7 @@ Rule rule_line4() {
 }
 Rule rule_tri16() {
   double xj[4], wj[4];
-  gauss_jacobi4(xj, wj);
+  gauss_jacobi(4, 1.0, xj, wj);
   Rule r;
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) {
@@ -165,6 +167,32 @@ Rule rule_tri16() {
     }
   return r;
 }
+
+// Tetrahedron (0,0,0),(1,0,0),(0,1,0),(0,0,1): the collapsed product rule
+// (xi, eta, zeta) = (u (1 - v)(1 - w), v (1 - w), w), u, v, w = (1 + t)/2 at the 3-point Gauss rules
+// for the weights 1, (1 - t) and (1 - t)^2, 27 points exact to degree 5; faces: the 7-point
+// triangle rule on each face (barycentric coordinates on the face's vertices).
+Rule rule_tet27() {
+  double x0[4], w0[4], x1[4], w1[4], x2[4], w2[4];
+  gauss_jacobi(3, 0.0, x0, w0);
+  gauss_jacobi(3, 1.0, x1, w1);
+  gauss_jacobi(3, 2.0, x2, w2);
+  Rule r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        const double u = 0.5 * (1.0 + x0[i]), v = 0.5 * (1.0 + x1[j]), w = 0.5 * (1.0 + x2[k]);
+        r.x.push_back(u * (1.0 - v) * (1.0 - w));
+        r.x.push_back(v * (1.0 - w));
+        r.x.push_back(w);
+        r.w.push_back(6.0 / 64.0 * w0[i] * w1[j] * w2[k]);  // (1/|T0|) int over 1/64 of the t-cube
+      }
+  return r;
+}
+// face k of the tetrahedron is opposite vertex k; vertex order with (b - a) x (c - a) outward
+const int TET_FACE[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+// the six orderings of a face's three vertices (index 0 the identity)
+const int PERM3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
 // Legendre, orthonormal on [-1,1] under (1/2) int: sqrt(2n+1) P_n, n <= 3, and its derivatives.
 double leg(int n, double x, int der) {
@@ -229,9 +257,49 @@ struct TriBasis {
   }
 };
 
-// basis value / derivative at polynomial degree deg (2, or 3 on the line and the triangle): dx, dy
-// derivative orders
-double basis(int kind, int deg, int l, const double* xi, int dx, int dy) {
+// Tetrahedron: 1, x, y, z, x^2, xy, xz, y^2, yz, z^2 orthonormalised through the Cholesky factor
+// of their Gram matrix of exact moments (1/|T0|) int x^a y^b z^c = 6 a! b! c! / (a + b + c + 3)!.
+const int TET_E[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                          {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
+struct TetBasis {
+  double C[10][10];
+  TetBasis() {
+    auto fact = [](int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; };
+    double G[10][10];
+    for (int a = 0; a < 10; ++a)
+      for (int b = 0; b < 10; ++b) {
+        const int px = TET_E[a][0] + TET_E[b][0], py = TET_E[a][1] + TET_E[b][1], pz = TET_E[a][2] + TET_E[b][2];
+        G[a][b] = 6.0 * fact(px) * fact(py) * fact(pz) / fact(px + py + pz + 3);
+      }
+    double L[10][10] = {};
+    for (int i = 0; i < 10; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double s = G[i][j];
+        for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+        L[i][j] = (i == j) ? std::sqrt(s) : s / L[j][j];
+      }
+    for (int i = 0; i < 10; ++i)
+      for (int j = 0; j < 10; ++j) C[i][j] = 0.0;
+    for (int col = 0; col < 10; ++col)
+      for (int i = col; i < 10; ++i) {
+        double s = (i == col) ? 1.0 : 0.0;
+        for (int k = col; k < i; ++k) s -= L[i][k] * C[k][col];
+        C[i][col] = s / L[i][i];
+      }
+  }
+};
+
+// basis value / derivative at polynomial degree deg (2, or 3 on the line and the triangle): dx, dy,
+// dz derivative orders
+double basis(int kind, int deg, int l, const double* xi, int dx, int dy, int dz = 0) {
+  if (kind == LXW_TET) {
+    static const TetBasis tb;
+    double s = 0.0;
+    for (int j = 0; j < 10; ++j)
+      s += tb.C[l][j] * dmono(xi[0], TET_E[j][0], dx) * dmono(xi[1], TET_E[j][1], dy) * dmono(xi[2], TET_E[j][2], dz);
+    return s;
+  }
+  if (dz) return 0.0;
   if (kind == LXW_LINE) return dy ? 0.0 : leg(l, xi[0], dx);
   if (kind == LXW_QUAD) return leg(QUAD_I[l], xi[0], dx) * leg(QUAD_J[l], xi[1], dy);
   static const TriBasis<6> tb2;
@@ -244,12 +312,14 @@ double basis(int kind, int deg, int l, const double* xi, int dx, int dy) {
   return s;
 }
 
-int nverts(int kind) { return kind == LXW_LINE ? 2 : (kind == LXW_QUAD ? 4 : 3); }
+int nverts(int kind) { return kind == LXW_LINE ? 2 : (kind == LXW_QUAD || kind == LXW_TET ? 4 : 3); }
 
 void ref_vertex(int kind, int a, double* xi) {
   static const double line[2] = {-1, 1};
   static const double quad[8] = {-1, -1, 1, -1, 1, 1, -1, 1};
   static const double tri[6] = {0, 0, 1, 0, 0, 1};
+  static const double tet[12] = {0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1};
+  if (kind == LXW_TET) { for (int d = 0; d < 3; ++d) xi[d] = tet[3 * a + d]; return; }
   if (kind == LXW_LINE) xi[0] = line[a];
   else if (kind == LXW_QUAD) { xi[0] = quad[2 * a]; xi[1] = quad[2 * a + 1]; }
   else { xi[0] = tri[2 * a]; xi[1] = tri[2 * a + 1]; }
@@ -258,13 +328,17 @@ void ref_vertex(int kind, int a, double* xi) {
 template <class E>
 Rule rule_of() {
   if constexpr (E::DEG == 3) return E::kind == LXW_LINE ? rule_line4() : rule_tri16();
+  else if constexpr (E::kind == LXW_TET) return rule_tet27();
   else return E::kind == LXW_LINE ? rule_line() : (E::kind == LXW_QUAD ? rule_quad() : rule_tri());
 }
 // Gauss-Legendre node j of the edges and its weight on [-1, 1]
 template <class E>
 double edge_s(int j) { return E::DEG == 3 ? GL4_S[j] : GL_S[j]; }
 template <class E>
-double edge_w(int j) { return E::DIM == 1 ? 2.0 : (E::DEG == 3 ? GL4_W[j] : GL_W[j]); }
+double edge_w(int j) {
+  if constexpr (E::DIM == 3) return 2.0 * rule_tri().w[j];  // face rule, weights summing to 2
+  else return E::DIM == 1 ? 2.0 : (E::DEG == 3 ? GL4_W[j] : GL_W[j]);
+}
 
 // limiter / update points: interior rule, then edge k Gauss point j (counter-clockwise)
 template <class E>
@@ -272,7 +346,19 @@ std::vector<double> all_points() {
   std::vector<double> pts = rule_of<E>().x;
   for (int k = 0; k < E::K; ++k)
     for (int j = 0; j < E::NQE; ++j) {
-      double a[2] = {0, 0}, b[2] = {0, 0};
+      double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+      if constexpr (E::DIM == 3) {  // face k: the triangle rule's point j on the face's vertices
+        const Rule f = rule_tri();
+        const double lam[3] = {1.0 - f.x[2 * j] - f.x[2 * j + 1], f.x[2 * j], f.x[2 * j + 1]};
+        double x[3] = {0, 0, 0};
+        for (int m = 0; m < 3; ++m) {
+          double vm[3];
+          ref_vertex(E::kind, TET_FACE[k][m], vm);
+          for (int d = 0; d < 3; ++d) x[d] += lam[m] * vm[d];
+        }
+        for (int d = 0; d < 3; ++d) pts.push_back(x[d]);
+        continue;
+      }
       ref_vertex(E::kind, k, a);
       ref_vertex(E::kind, (k + 1) % nverts(E::kind), b);
       if (E::DIM == 1) { pts.push_back(a[0]); continue; }
@@ -288,9 +374,19 @@ void fill_tab(RefTab<E, R>& T) {
   std::memset(&T, 0, sizeof(T));
   Rule r = rule_of<E>();
   std::vector<double> pts = all_points<E>();
-  auto B = [](int l, const double* xi, int dx, int dy) { return basis(E::kind, E::DEG, l, xi, dx, dy); };
+  auto B = [](int l, const double* xi, int dx, int dy, int dz = 0) { return basis(E::kind, E::DEG, l, xi, dx, dy, dz); };
+  // (dx, dy, dz) of the second derivatives in table order (3D: xx, xy, xz, yy, yz, zz)
+  static const int D2[6][3] = {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
   for (int p = 0; p < E::NP; ++p) {
-    double xi[2] = {pts[p * E::DIM], E::DIM == 2 ? pts[p * E::DIM + 1] : 0.0};
+    double xi[3] = {pts[p * E::DIM], E::DIM >= 2 ? pts[p * E::DIM + 1] : 0.0, E::DIM == 3 ? pts[p * E::DIM + 2] : 0.0};
+    if constexpr (E::DIM == 3) {
+      for (int l = 0; l < E::ML; ++l) {
+        T.phi[p][l] = R(B(l, xi, 0, 0, 0));
+        for (int a = 0; a < 3; ++a) T.dphi[p][a][l] = R(B(l, xi, a == 0, a == 1, a == 2));
+        for (int k = 0; k < 6; ++k) T.d2phi[p][k][l] = R(B(l, xi, D2[k][0], D2[k][1], D2[k][2]));
+      }
+      continue;
+    }
     for (int l = 0; l < E::ML; ++l) {
       T.phi[p][l] = R(B(l, xi, 0, 0));
       T.dphi[p][0][l] = R(B(l, xi, 1, 0));
@@ -304,7 +400,13 @@ void fill_tab(RefTab<E, R>& T) {
   }
   for (int p = 0; p < E::NP; ++p)
     for (int d = 0; d < E::DIM; ++d) T.xr[p][d] = R(pts[p * E::DIM + d]);
-  {
+  if constexpr (E::DIM == 3) {
+    const double o[3] = {0.0, 0.0, 0.0};
+    for (int l = 0; l < E::ML; ++l) {
+      for (int a = 0; a < 3; ++a) T.dphi0[a][l] = R(B(l, o, a == 0, a == 1, a == 2));
+      for (int k = 0; k < 6; ++k) T.d2c[k][l] = R(B(l, o, D2[k][0], D2[k][1], D2[k][2]));
+    }
+  } else {
     const double o[2] = {0.0, 0.0};
     for (int l = 0; l < E::ML; ++l) {
       T.dphi0[0][l] = R(B(l, o, 1, 0));
@@ -320,19 +422,41 @@ void fill_tab(RefTab<E, R>& T) {
   }
   for (int m = 0; m < E::NI; ++m)
     for (int l = 0; l < E::ML; ++l) {
-      double xi[2] = {pts[m * E::DIM], E::DIM == 2 ? pts[m * E::DIM + 1] : 0.0};
+      double xi[3] = {pts[m * E::DIM], E::DIM >= 2 ? pts[m * E::DIM + 1] : 0.0, E::DIM == 3 ? pts[m * E::DIM + 2] : 0.0};
       T.wphi[m][l] = R(r.w[m] * B(l, xi, 0, 0));
-      T.wdphi[m][0][l] = R(r.w[m] * B(l, xi, 1, 0));
-      if constexpr (E::DIM == 2) T.wdphi[m][1][l] = R(r.w[m] * B(l, xi, 0, 1));
+      for (int a = 0; a < E::DIM; ++a) T.wdphi[m][a][l] = R(r.w[m] * B(l, xi, a == 0, a == 1, a == 2));
     }
   // in 1D a face is a point with the single weight 2, so that (1/2) sum omega = 1
   for (int j = 0; j < E::NQE; ++j) T.om[j] = R(edge_w<E>(j));
   for (int k = 0; k < E::K; ++k)
     for (int j = 0; j < E::NQE; ++j) {
       const int p = E::NI + k * E::NQE + j;
-      double xi[2] = {pts[p * E::DIM], E::DIM == 2 ? pts[p * E::DIM + 1] : 0.0};
+      double xi[3] = {pts[p * E::DIM], E::DIM >= 2 ? pts[p * E::DIM + 1] : 0.0, E::DIM == 3 ? pts[p * E::DIM + 2] : 0.0};
       for (int l = 0; l < E::ML; ++l) T.ephi[k][j][l] = R(0.5 * edge_w<E>(j) * B(l, xi, 0, 0));
     }
+  // tetrahedron faces: point jl of a face whose vertex m is the first element's face vertex
+  // PERM3[p][m] has barycentric coordinates lam'_{PERM3[p][m]} = lam_m in the first element's order
+  for (int p = 0; p < 6; ++p)
+    for (int j = 0; j < E::NQE; ++j) T.pperm[p][j] = j;
+  if constexpr (E::DIM == 3) {
+    const Rule f = rule_tri();
+    auto bary = [&](int j, double* lam) { lam[0] = 1.0 - f.x[2 * j] - f.x[2 * j + 1]; lam[1] = f.x[2 * j]; lam[2] = f.x[2 * j + 1]; };
+    for (int p = 0; p < 6; ++p)
+      for (int jl = 0; jl < E::NQE; ++jl) {
+        double mu[3], lam[3];
+        bary(jl, mu);
+        for (int m = 0; m < 3; ++m) lam[PERM3[p][m]] = mu[m];
+        int best = -1;
+        double bd = 1e300;
+        for (int jj = 0; jj < E::NQE; ++jj) {
+          double c[3];
+          bary(jj, c);
+          const double d = std::fabs(c[0] - lam[0]) + std::fabs(c[1] - lam[1]) + std::fabs(c[2] - lam[2]);
+          if (d < bd) { bd = d; best = jj; }
+        }
+        T.pperm[p][jl] = best;
+      }
+  }
 }
 
 std::mutex g_init_mu;
@@ -347,6 +471,7 @@ lxw_status ensure_init() {
   fill_tab(t->tri_d); fill_tab(t->tri_f);
   fill_tab(t->line3_d); fill_tab(t->line3_f);
   fill_tab(t->tri3_d); fill_tab(t->tri3_f);
+  fill_tab(t->tet_d); fill_tab(t->tet_f);
   hipError_t e = upload_tables(*t);
   if (e != hipSuccess) {
     g_init_state = -1;
@@ -379,6 +504,8 @@ struct lxw_mesh {
   std::vector<double> area, perim, Jinv, nout, hsz;  // N; N; N*dim*dim; N*K*dim; N
   std::vector<int> nbr, nbr_k, bcode;                // N*K (internal indices); bcode LXW_BC_* or -1
   std::vector<int> eslot;                            // N*K
+  std::vector<unsigned char> fperm;                  // tetrahedra, N*K: order of the face's vertices
+                                                     //   relative to the face's first element
   std::vector<int> e_i, e_j, e_bc;
   std::vector<int> e_ki, e_kj;                       // local edge index in i_e and j_e (-1)
   std::vector<double> e_n;                           // E*dim
@@ -388,11 +515,12 @@ struct lxw_mesh {
 namespace {
 
 // Gauss points per face: one in 1D, degree + 1 on the sides of 2D elements.
-int nqe_of(const lxw_mesh& M) { return M.kind == LXW_LINE ? 1 : M.deg + 1; }
+int nqe_of(const lxw_mesh& M) { return M.kind == LXW_LINE ? 1 : (M.kind == LXW_TET ? 7 : M.deg + 1); }
 
-// Element configuration of a mesh: its kind, or 3 + kind at degree 3 (line and triangle).
-enum { EK_LINE = LXW_LINE, EK_QUAD = LXW_QUAD, EK_TRI = LXW_TRI, EK_LINE3 = 3 + LXW_LINE, EK_TRI3 = 3 + LXW_TRI };
-int ekind(const lxw_mesh& M) { return M.deg == 3 ? 3 + M.kind : M.kind; }
+// Element configuration of a mesh: its kind, or 4 + kind at degree 3 (line and triangle).
+enum { EK_LINE = LXW_LINE, EK_QUAD = LXW_QUAD, EK_TRI = LXW_TRI, EK_TET = LXW_TET, EK_LINE3 = 4 + LXW_LINE,
+       EK_TRI3 = 4 + LXW_TRI };
+int ekind(const lxw_mesh& M) { return M.deg == 3 ? 4 + M.kind : M.kind; }
 
 int bc_to_slot(int bc) {
   switch (bc) {
@@ -425,13 +553,45 @@ uint64_t hilbert2(uint32_t x, uint32_t y) {
 
 // Finish a mesh given, in caller order: vertex coordinates cvx (N x nv x dim), neighbours cnb /
 // cnk (N x K, -1 on the boundary) and boundary codes cbc (N x K).
+// Index of (x, y, z) along the Morton (Z-order) curve over a 2^21 grid per axis: elements close in
+// the order are close in space (3D locality of the element numbering).
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  uint64_t d = 0;
+  for (int b = 20; b >= 0; --b)
+    d = (d << 3) | ((uint64_t)((x >> b) & 1u) << 2) | ((uint64_t)((y >> b) & 1u) << 1) | (uint64_t)((z >> b) & 1u);
+  return d;
+}
+
 lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::vector<int>& cnb,
-                       const std::vector<int>& cnk, const std::vector<int>& cbc, double alpha_unused) {
+                       const std::vector<int>& cnk, const std::vector<int>& cbc, double alpha_unused,
+                       const std::vector<unsigned char>* csig = nullptr) {
   (void)alpha_unused;
   const int N = M->N, K = M->K, dim = M->dim, nv = nverts(M->kind);
   // renumbering
   M->perm.resize(N);
   for (int i = 0; i < N; ++i) M->perm[i] = i;
+  if (dim == 3 && N > 1) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    std::vector<double> cen(3 * (size_t)N);
+    for (int i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) {
+        double c = 0.0;
+        for (int a = 0; a < nv; ++a) c += cvx[((size_t)i * nv + a) * 3 + d];
+        cen[3 * (size_t)i + d] = c / nv;
+        lo[d] = std::min(lo[d], cen[3 * (size_t)i + d]);
+        hi[d] = std::max(hi[d], cen[3 * (size_t)i + d]);
+      }
+    std::vector<uint64_t> code(N);
+    for (int i = 0; i < N; ++i) {
+      uint32_t q[3];
+      for (int d = 0; d < 3; ++d) {
+        double f = (hi[d] > lo[d]) ? (cen[3 * (size_t)i + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+        q[d] = (uint32_t)std::min(2097151.0, std::max(0.0, f * 2097151.0));
+      }
+      code[i] = morton3(q[0], q[1], q[2]);
+    }
+    std::stable_sort(M->perm.begin(), M->perm.end(), [&](int a, int b) { return code[a] < code[b]; });
+  }
   if (dim == 2 && N > 1) {
     double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
     std::vector<double> cen(2 * N);
@@ -460,6 +620,8 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
   M->nbr.assign((size_t)N * K, -1);
   M->nbr_k.assign((size_t)N * K, -1);
   M->bcode.assign((size_t)N * K, -1);
+  std::vector<unsigned char> sig;  // internal order, per (element, face): permutation to the partner
+  if (csig) sig.assign((size_t)N * K, 0);
   for (int i = 0; i < N; ++i) {
     const int c = M->perm[i];
     for (int x = 0; x < nv * dim; ++x) M->vx[(size_t)i * nv * dim + x] = cvx[(size_t)c * nv * dim + x];
@@ -468,6 +630,7 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
       M->nbr[(size_t)i * K + k] = j >= 0 ? M->iperm[j] : -1;
       M->nbr_k[(size_t)i * K + k] = cnk[(size_t)c * K + k];
       M->bcode[(size_t)i * K + k] = j >= 0 ? -1 : cbc[(size_t)c * K + k];
+      if (csig) sig[(size_t)i * K + k] = (*csig)[(size_t)c * K + k];
     }
   }
   // geometry
@@ -488,6 +651,39 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
       M->nout[(size_t)i * K + 0] = -1.0;
       M->nout[(size_t)i * K + 1] = 1.0;
       M->hsz[i] = h;
+    } else if (M->kind == LXW_TET) {
+      // J[a][b] = d x_a / d xi_b = (v_{b+1} - v_0)_a; Jinv = adj(J) / det
+      double J[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) J[a][b] = v[3 * (b + 1) + a] - v[a];
+      double cof[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const int a1 = (a + 1) % 3, a2 = (a + 2) % 3, b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+          cof[a][b] = J[a1][b1] * J[a2][b2] - J[a1][b2] * J[a2][b1];
+        }
+      const double det = J[0][0] * cof[0][0] + J[0][1] * cof[0][1] + J[0][2] * cof[0][2];
+      if (!(det > 0.0)) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "element %d is negatively oriented or degenerate", M->perm[i]);
+        return fail(LXW_ERR_MESH, buf);
+      }
+      double* Ji = &M->Jinv[(size_t)i * 9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Ji[a * 3 + b] = cof[b][a] / det;
+      M->area[i] = det / 6.0;
+      double P = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double* A = &v[3 * TET_FACE[k][0]];
+        const double* B = &v[3 * TET_FACE[k][1]];
+        const double* C = &v[3 * TET_FACE[k][2]];
+        const double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]}, w[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        const double n[3] = {0.5 * (u[1] * w[2] - u[2] * w[1]), 0.5 * (u[2] * w[0] - u[0] * w[2]), 0.5 * (u[0] * w[1] - u[1] * w[0])};
+        for (int d = 0; d < 3; ++d) M->nout[((size_t)i * K + k) * 3 + d] = n[d];
+        P += std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      }
+      M->perim[i] = P;
+      M->hsz[i] = std::cbrt(6.0 * M->area[i]);  // the lattice spacing of a cube split into six
     } else {
       double J[2][2];
       if (M->kind == LXW_TRI) {
@@ -544,6 +740,13 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
       }
     }
   M->E = E;
+  // tetrahedra: the first element of a face reads its points in its own order (permutation 0),
+  // the second one through the permutation of its face's vertices onto the first one's
+  if (csig) {
+    M->fperm.assign((size_t)N * K, 0);
+    for (int e = 0; e < E; ++e)
+      if (M->e_j[e] >= 0) M->fperm[(size_t)M->e_j[e] * K + M->e_kj[e]] = sig[(size_t)M->e_j[e] * K + M->e_kj[e]];
+  }
   return LXW_OK;
 }
 
@@ -693,6 +896,12 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   if ((st = upload(S, &v.nout, noR))) return st;
   if ((st = upload(S, &v.eslot, es))) return st;
   if ((st = upload(S, &v.nbr, nb))) return st;
+  if (!M.fperm.empty()) {
+    std::vector<unsigned char> fp((size_t)K * N);
+    for (int i = 0; i < N; ++i)
+      for (int k = 0; k < K; ++k) fp[(size_t)k * N + i] = M.fperm[(size_t)i * K + k];
+    if ((st = upload(S, &v.fperm, fp))) return st;
+  }
   if ((st = upload(S, &v.delta, delta))) return st;
   if ((st = upload(S, &v.e_i, M.e_i))) return st;
   if ((st = upload(S, &v.e_j, M.e_j))) return st;
@@ -823,6 +1032,7 @@ lxw_status enqueue_step(lxw_solver* S) {
     case EK_QUAD: return S->fp32 ? enqueue_step_t<ElQuad, float>(S, S->vf) : enqueue_step_t<ElQuad, double>(S, S->vd);
     case EK_LINE3: return S->fp32 ? enqueue_step_t<ElLine3, float>(S, S->vf) : enqueue_step_t<ElLine3, double>(S, S->vd);
     case EK_TRI3: return S->fp32 ? enqueue_step_t<ElTri3, float>(S, S->vf) : enqueue_step_t<ElTri3, double>(S, S->vd);
+    case EK_TET: return S->fp32 ? enqueue_step_t<ElTet, float>(S, S->vf) : enqueue_step_t<ElTet, double>(S, S->vd);
     default: return S->fp32 ? enqueue_step_t<ElTri, float>(S, S->vf) : enqueue_step_t<ElTri, double>(S, S->vd);
   }
 }
@@ -833,6 +1043,7 @@ lxw_status enqueue_shock(lxw_solver* S) {
     case EK_QUAD: return S->fp32 ? enqueue_shock_t<ElQuad, float>(S, S->vf) : enqueue_shock_t<ElQuad, double>(S, S->vd);
     case EK_LINE3: return S->fp32 ? enqueue_shock_t<ElLine3, float>(S, S->vf) : enqueue_shock_t<ElLine3, double>(S, S->vd);
     case EK_TRI3: return S->fp32 ? enqueue_shock_t<ElTri3, float>(S, S->vf) : enqueue_shock_t<ElTri3, double>(S, S->vd);
+    case EK_TET: return S->fp32 ? enqueue_shock_t<ElTet, float>(S, S->vf) : enqueue_shock_t<ElTet, double>(S, S->vd);
     default: return S->fp32 ? enqueue_shock_t<ElTri, float>(S, S->vf) : enqueue_shock_t<ElTri, double>(S, S->vd);
   }
 }
@@ -1077,7 +1288,7 @@ lxw_status create_solver(const lxw_mesh* m, const lxw_params* p, void* stream, B
   std::unique_ptr<lxw_mesh> own;
   if (p->degree == 3) {
     if (bl) return fail(LXW_ERR_UNSUPPORTED, "degree 3 is for single-mesh solvers");
-    if (m->kind == LXW_QUAD) return fail(LXW_ERR_UNSUPPORTED, "degree 3 is for line and triangle meshes");
+    if (m->kind == LXW_QUAD || m->kind == LXW_TET) return fail(LXW_ERR_UNSUPPORTED, "degree 3 is for line and triangle meshes");
     // the solver's own copy of the mesh at degree 3 (more modes; the geometry is the same)
     own.reset(new (std::nothrow) lxw_mesh(*m));
     if (!own) return fail(LXW_ERR_OOM, "host allocation");
@@ -1451,6 +1662,127 @@ lxw_status lxw_mesh_create_tri(int32_t n_nodes, const double* xy, int32_t n_tri,
   return LXW_OK;
 }
 
+lxw_status lxw_mesh_create_tet(int32_t n_nodes, const double* xyz, int32_t n_tet, const int32_t* tet,
+                               const int32_t* bnd_tag, const double* period, lxw_mesh** out) {
+  if (!out || !xyz || !tet) return fail(LXW_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (n_nodes < 4 || n_tet < 1) return fail(LXW_ERR_ARG, "need at least one tetrahedron");
+  std::unique_ptr<lxw_mesh> M(new (std::nothrow) lxw_mesh);
+  if (!M) return fail(LXW_ERR_OOM, "host allocation");
+  const int N = n_tet;
+  M->kind = LXW_TET; M->dim = 3; M->N = N; M->K = 4; M->V = 5; M->ML = 10;
+  std::vector<double> cvx((size_t)N * 12);
+  for (int t = 0; t < N; ++t)
+    for (int a = 0; a < 4; ++a) {
+      const int v = tet[4 * t + a];
+      if (v < 0 || v >= n_nodes) return fail(LXW_ERR_ARG, "node index out of range in tetrahedron " + std::to_string(t));
+      for (int d = 0; d < 3; ++d) cvx[(size_t)t * 12 + 3 * a + d] = xyz[3 * (size_t)v + d];
+    }
+  std::vector<int> nb((size_t)N * 4, -1), nk((size_t)N * 4, -1), bcv((size_t)N * 4, -1);
+  std::vector<unsigned char> sig((size_t)N * 4, 0);
+  auto face_nodes = [&](int t, int k, int* f) { for (int m = 0; m < 3; ++m) f[m] = tet[4 * t + TET_FACE[k][m]]; };
+  // sigma[m] = the partner's face vertex equal to this face's vertex m
+  auto perm_index = [](const int* sigma) {
+    for (int p = 0; p < 6; ++p)
+      if (PERM3[p][0] == sigma[0] && PERM3[p][1] == sigma[1] && PERM3[p][2] == sigma[2]) return p;
+    return -1;
+  };
+  auto link = [&](int t, int k, int t2, int k2, const int* sig_t) {
+    nb[(size_t)t * 4 + k] = t2; nk[(size_t)t * 4 + k] = k2;
+    nb[(size_t)t2 * 4 + k2] = t; nk[(size_t)t2 * 4 + k2] = k;
+    int inv[3];
+    for (int m = 0; m < 3; ++m) inv[sig_t[m]] = m;
+    sig[(size_t)t * 4 + k] = (unsigned char)perm_index(sig_t);
+    sig[(size_t)t2 * 4 + k2] = (unsigned char)perm_index(inv);
+  };
+  // interior faces: the sorted node triple
+  std::vector<std::tuple<int, int, int, int>> faces;  // (a, b, c, t*4 + k), a < b < c
+  faces.reserve((size_t)N * 4);
+  for (int t = 0; t < N; ++t)
+    for (int k = 0; k < 4; ++k) {
+      int f[3];
+      face_nodes(t, k, f);
+      std::sort(f, f + 3);
+      faces.emplace_back(f[0], f[1], f[2], t * 4 + k);
+    }
+  std::sort(faces.begin(), faces.end());
+  std::vector<int> open;
+  for (size_t x = 0; x < faces.size();) {
+    size_t y = x + 1;
+    while (y < faces.size() && std::get<0>(faces[y]) == std::get<0>(faces[x]) && std::get<1>(faces[y]) == std::get<1>(faces[x]) &&
+           std::get<2>(faces[y]) == std::get<2>(faces[x]))
+      ++y;
+    if (y - x > 2) return fail(LXW_ERR_MESH, "a face is shared by more than two tetrahedra");
+    if (y - x == 2) {
+      const int a = std::get<3>(faces[x]), b = std::get<3>(faces[x + 1]);
+      int fa[3], fb[3], sg[3];
+      face_nodes(a / 4, a % 4, fa);
+      face_nodes(b / 4, b % 4, fb);
+      for (int m = 0; m < 3; ++m) sg[m] = (int)(std::find(fb, fb + 3, fa[m]) - fb);
+      link(a / 4, a % 4, b / 4, b % 4, sg);
+    } else {
+      open.push_back(std::get<3>(faces[x]));
+    }
+    x = y;
+  }
+  // boundary faces; periodic faces paired by their centroid modulo the period
+  std::map<std::tuple<int64_t, int64_t, int64_t>, int> pmap;
+  for (int tk : open) {
+    const int t = tk / 4, k = tk % 4;
+    const int code = bnd_tag ? bnd_tag[4 * t + k] : LXW_BC_TRANSPARENT;
+    if (code < 0 || code > 3) return fail(LXW_ERR_ARG, "bad boundary code on tetrahedron " + std::to_string(t));
+    if (code == LXW_BC_INFLOW) return fail(LXW_ERR_UNSUPPORTED, "inflow sides are not supported on tetrahedra");
+    if (code != LXW_BC_PERIODIC) { bcv[(size_t)t * 4 + k] = code; continue; }
+    if (!period) return fail(LXW_ERR_ARG, "periodic faces need a period");
+    const double* v = &cvx[(size_t)t * 12];
+    double c[3];
+    for (int d = 0; d < 3; ++d) c[d] = (v[3 * TET_FACE[k][0] + d] + v[3 * TET_FACE[k][1] + d] + v[3 * TET_FACE[k][2] + d]) / 3.0;
+    int64_t q[3];
+    for (int d = 0; d < 3; ++d) {
+      const double L = period[d];
+      const int64_t Q = 1ll << 24;
+      if (L > 0) {
+        int64_t x = (int64_t)std::llround(c[d] / L * (double)Q);
+        q[d] = ((x % Q) + Q) % Q;
+      } else {
+        q[d] = (int64_t)std::llround(c[d] * 1e9);
+      }
+    }
+    auto key = std::make_tuple(q[0], q[1], q[2]);
+    auto it = pmap.find(key);
+    if (it == pmap.end()) {
+      pmap.emplace(key, tk);
+    } else {
+      const int t2 = it->second / 4, k2 = it->second % 4;
+      // vertices matched by position after removing the shift between the two faces
+      const double* v2 = &cvx[(size_t)t2 * 12];
+      double c2[3];
+      for (int d = 0; d < 3; ++d) c2[d] = (v2[3 * TET_FACE[k2][0] + d] + v2[3 * TET_FACE[k2][1] + d] + v2[3 * TET_FACE[k2][2] + d]) / 3.0;
+      int sg[3];
+      for (int m = 0; m < 3; ++m) {
+        double best = 1e300;
+        sg[m] = -1;
+        for (int m2 = 0; m2 < 3; ++m2) {
+          double d2 = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            const double dd = (v[3 * TET_FACE[k][m] + d] - c[d]) - (v2[3 * TET_FACE[k2][m2] + d] - c2[d]);
+            d2 += dd * dd;
+          }
+          if (d2 < best) { best = d2; sg[m] = m2; }
+        }
+      }
+      if (perm_index(sg) < 0) return fail(LXW_ERR_MESH, "periodic faces whose vertices do not match");
+      link(t, k, t2, k2, sg);
+      pmap.erase(it);
+    }
+  }
+  if (!pmap.empty()) return fail(LXW_ERR_MESH, "unpaired periodic face");
+  lxw_status s = finish_mesh(M.get(), cvx, nb, nk, bcv, 0.0, &sig);
+  if (s) return s;
+  *out = M.release();
+  return LXW_OK;
+}
+
 lxw_status lxw_mesh_destroy(lxw_mesh* m) {
   delete m;
   return LXW_OK;
@@ -1466,19 +1798,22 @@ lxw_status lxw_mesh_get_info(const lxw_mesh* m, lxw_mesh_info* out) {
 }
 
 lxw_status lxw_refelem_info_deg(int32_t kind, int32_t degree, int32_t* n_pts, double* xi, double* w, double* phi) {
-  if (kind < 0 || kind > 2 || !n_pts) return fail(LXW_ERR_ARG, "bad kind or null n_pts");
-  if (degree != 2 && (degree != 3 || kind == LXW_QUAD)) return fail(LXW_ERR_UNSUPPORTED, "degree 2, or 3 on lines and triangles");
+  if (kind < 0 || kind > 3 || !n_pts) return fail(LXW_ERR_ARG, "bad kind or null n_pts");
+  if (degree != 2 && (degree != 3 || kind == LXW_QUAD || kind == LXW_TET))
+    return fail(LXW_ERR_UNSUPPORTED, "degree 2, or 3 on lines and triangles");
   Rule r = degree == 3 ? (kind == LXW_LINE ? rule_line4() : rule_tri16())
-                       : (kind == LXW_LINE ? rule_line() : (kind == LXW_QUAD ? rule_quad() : rule_tri()));
-  const int dim = kind == LXW_LINE ? 1 : 2;
-  const int ML = degree == 3 ? (kind == LXW_LINE ? 4 : 10) : (kind == LXW_LINE ? 3 : (kind == LXW_QUAD ? 9 : 6));
+                       : (kind == LXW_LINE ? rule_line()
+                                           : (kind == LXW_QUAD ? rule_quad() : (kind == LXW_TET ? rule_tet27() : rule_tri())));
+  const int dim = kind == LXW_LINE ? 1 : (kind == LXW_TET ? 3 : 2);
+  const int ML = degree == 3 ? (kind == LXW_LINE ? 4 : 10)
+                             : (kind == LXW_LINE ? 3 : (kind == LXW_QUAD ? 9 : (kind == LXW_TET ? 10 : 6)));
   const int n = (int)r.w.size();
   *n_pts = n;
   if (xi) for (int x = 0; x < n * dim; ++x) xi[x] = r.x[x];
   if (w) for (int m = 0; m < n; ++m) w[m] = r.w[m];
   if (phi)
     for (int m = 0; m < n; ++m) {
-      double p[2] = {r.x[m * dim], dim == 2 ? r.x[m * dim + 1] : 0.0};
+      double p[3] = {r.x[m * dim], dim >= 2 ? r.x[m * dim + 1] : 0.0, dim == 3 ? r.x[m * dim + 2] : 0.0};
       for (int l = 0; l < ML; ++l) phi[m * ML + l] = basis(kind, degree, l, p, 0, 0);
     }
   return LXW_OK;
@@ -1868,6 +2203,7 @@ lxw_status lxw_batch_create(int32_t n, const lxw_mesh* const* meshes, const lxw_
   for (int b = 0; b < n; ++b) {
     if (!meshes[b]) return fail(LXW_ERR_ARG, "null mesh " + std::to_string(b));
     if (meshes[b]->kind != meshes[0]->kind) return fail(LXW_ERR_ARG, "all meshes of a batch must be of one kind");
+    if (meshes[b]->kind == LXW_TET) return fail(LXW_ERR_UNSUPPORTED, "batches are for 1D and 2D meshes");
   }
   lxw_status s = check_params(p);
   if (s) return s;

@@ -33,6 +33,12 @@ struct ElTri3 {
   static constexpr int kind = 2, DEG = 3, DIM = 2, V = 4, ML = 10, K = 3, NI = 16, NQE = 4;
   static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 3, ND3 = 4;
 };
+// P2 on tetrahedra (3D; the paper's closing remark of Sec. 3.3): 27 interior points, four faces of
+// 7 points, 15 pressure corners, second derivatives xx, xy, xz, yy, yz, zz.
+struct ElTet {
+  static constexpr int kind = 3, DEG = 2, DIM = 3, V = 5, ML = 10, K = 4, NI = 27, NQE = 7;
+  static constexpr int NP = NI + K * NQE, NC = (1 << K) - 1, ND2 = 6, ND3 = 1;
+};
 
 // Reference tables of one element kind in one precision, kept in __constant__ memory so that
 // every lane of a wave (one element per lane) reads the same entry through the scalar cache.
@@ -52,6 +58,9 @@ struct RefTab {
                                    // complete P2 on the line and the triangle)
   R d3c[E::ND3][E::ML];            // reference third derivatives (xxx[, xxy, xyy, yyy]): constant
                                    // for complete P3, unused at degree 2
+  int pperm[6][E::NQE];            // tetrahedron faces: point jl of a face whose vertices are those
+                                   // of the first element's face permuted by permutation p is that
+                                   // face's point pperm[p][jl] (p = 0 the identity); unused in 1D/2D
 };
 
 // Per-mesh device scalars (one record per mesh; the batched form holds many).
@@ -85,6 +94,8 @@ struct View {
   const R* Jinv;          // [DIM*DIM][N], Jinv[a][d] = d xi_a / d x_d
   const R* nout;          // [K][DIM][N] outward normal of local edge k, length = edge length
   const int* eslot;       // [K][N] edge*8 + side*4 + boundary code
+  const unsigned char* fperm;  // tetrahedra: [K][N] permutation of the face's vertices relative to
+                               //   the face's first element (RefTab::pperm); null in 1D/2D
   const int* nbr;         // [K][N] neighbour element or -1
   const double* delta;    // [N] shock-limiter relaxation alpha0 h^1.5
   const int* mesh_of;     // [N] mesh index (batched form) or null
@@ -157,9 +168,12 @@ struct HostTabs {
   RefTab<ElLine3, float> line3_f;
   RefTab<ElTri3, double> tri3_d;
   RefTab<ElTri3, float> tri3_f;
+  RefTab<ElTet, double> tet_d;
+  RefTab<ElTet, float> tet_f;
 };
-// The device copies of these tables share the 64 KiB of constant memory.
-static_assert(sizeof(HostTabs) <= 65536, "reference tables exceed the constant memory");
+// Constant memory on gfx950 is ordinary device memory read through the scalar cache (there is no
+// 64 KiB constant bank); the tables are kept well within a few hundred KiB.
+static_assert(sizeof(HostTabs) <= 256 * 1024, "reference tables larger than intended");
 
 // ---- host-side launchers implemented in lxw_kernels.hip -----------------------------------
 hipError_t upload_tables(const HostTabs& t);

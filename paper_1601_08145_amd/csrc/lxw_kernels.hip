@@ -42,6 +42,8 @@ __constant__ RefTab<ElLine3, double> c_line3_d;
 __constant__ RefTab<ElLine3, float> c_line3_f;
 __constant__ RefTab<ElTri3, double> c_tri3_d;
 __constant__ RefTab<ElTri3, float> c_tri3_f;
+__constant__ RefTab<ElTet, double> c_tet_d;
+__constant__ RefTab<ElTet, float> c_tet_f;
 
 template <class E, class R>
 struct TabSel;
@@ -55,6 +57,8 @@ template <> struct TabSel<ElLine3, double> { static __device__ __forceinline__ c
 template <> struct TabSel<ElLine3, float> { static __device__ __forceinline__ const RefTab<ElLine3, float>& get() { return c_line3_f; } };
 template <> struct TabSel<ElTri3, double> { static __device__ __forceinline__ const RefTab<ElTri3, double>& get() { return c_tri3_d; } };
 template <> struct TabSel<ElTri3, float> { static __device__ __forceinline__ const RefTab<ElTri3, float>& get() { return c_tri3_f; } };
+template <> struct TabSel<ElTet, double> { static __device__ __forceinline__ const RefTab<ElTet, double>& get() { return c_tet_d; } };
+template <> struct TabSel<ElTet, float> { static __device__ __forceinline__ const RefTab<ElTet, float>& get() { return c_tet_f; } };
 
 hipError_t upload_tables(const HostTabs& t) {
   hipError_t e = hipSuccess;
@@ -68,6 +72,8 @@ hipError_t upload_tables(const HostTabs& t) {
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_line3_f), &t.line3_f, sizeof(t.line3_f));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri3_d), &t.tri3_d, sizeof(t.tri3_d));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tri3_f), &t.tri3_f, sizeof(t.tri3_f));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tet_d), &t.tet_d, sizeof(t.tet_d));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_tet_f), &t.tet_f, sizeof(t.tet_f));
   return e;
 }
 
@@ -270,17 +276,22 @@ __device__ __forceinline__ void reflect(const T* q, const T* nh, T* out) {
   for (int c = 0; c < V; ++c) out[c] = q[c];
   if constexpr (DIM == 1) {
     out[1] = -q[1];
-  } else {
+  } else if constexpr (DIM == 2) {
     T mn = q[1] * nh[0] + q[DIM] * nh[DIM - 1];
     out[1] = q[1] - T(2) * mn * nh[0];
     out[DIM] = q[DIM] - T(2) * mn * nh[DIM - 1];
+  } else {
+    T mn = q[1] * nh[0] + q[2] * nh[1] + q[3] * nh[2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[1 + d] = q[1 + d] - T(2) * mn * nh[d];
   }
 }
 
 template <int DIM, class T>
 __device__ __forceinline__ void inflow_state(const double* inflow, T* out) {
   if constexpr (DIM == 1) { out[0] = T(inflow[0]); out[1] = T(inflow[1]); out[2] = T(inflow[3]); }
-  else { out[0] = T(inflow[0]); out[1] = T(inflow[1]); out[DIM] = T(inflow[2]); out[DIM + 1] = T(inflow[3]); }
+  else if constexpr (DIM == 2) { out[0] = T(inflow[0]); out[1] = T(inflow[1]); out[DIM] = T(inflow[2]); out[DIM + 1] = T(inflow[3]); }
+  else { out[0] = T(inflow[0]); out[1] = T(inflow[1]); out[2] = T(inflow[2]); out[3] = T(0); out[4] = T(inflow[3]); }  // not used: no inflow sides on tetrahedra
 }
 
 template <class R>
@@ -736,6 +747,14 @@ __device__ __forceinline__ void store_rec(R* p, const R (&x)[V]) {
   }
 }
 
+// Index of the second reference derivative d/dxi_a d/dxi_b in the tables (2D: xx, xy, yy; 3D:
+// xx, xy, xz, yy, yz, zz).
+template <int DIM>
+__device__ __forceinline__ constexpr int sidx(int a, int b) {
+  if (a > b) { const int t = a; a = b; b = t; }
+  return DIM == 3 ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : a + b;
+}
+
 template <class E, class R>
 struct ElemOcc { static constexpr int waves = (E::kind == ElTri::kind && E::DEG == 2 && sizeof(R) == 4) ? 2 : 1; };
 
@@ -848,9 +867,14 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
         for (int a = 0; a < DIM; ++a) dd += Fh[a][c][l] * T.dphi0[a][l];
         if constexpr (DIM == 1) {
           h[0] += Fh[0][c][l] * T.d2c[0][l];
-        } else {
+        } else if constexpr (DIM == 2) {
           h[0] += Fh[0][c][l] * T.d2c[0][l] + Fh[1][c][l] * T.d2c[1][l];
           h[1] += Fh[0][c][l] * T.d2c[1][l] + Fh[1][c][l] * T.d2c[2][l];
+        } else {
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            h[b] += Fh[0][c][l] * T.d2c[sidx<3>(0, b)][l] + Fh[1][c][l] * T.d2c[sidx<3>(1, b)][l] +
+                    Fh[2][c][l] * T.d2c[sidx<3>(2, b)][l];
         }
       }
       D0[c] = dd;
@@ -880,10 +904,15 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
         if constexpr (DIM == 1) {
           g[0] = g0[c][0] + Hq[c][0] * x[0];
           D[c] = D0[c] + gDr[c][0] * x[0];
-        } else {
+        } else if constexpr (DIM == 2) {
           g[0] = g0[c][0] + Hq[c][0] * x[0] + Hq[c][1] * x[1];
           g[1] = g0[c][1] + Hq[c][1] * x[0] + Hq[c][2] * x[1];
           D[c] = D0[c] + gDr[c][0] * x[0] + gDr[c][1] * x[1];
+        } else {
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            g[a] = g0[c][a] + Hq[c][sidx<3>(a, 0)] * x[0] + Hq[c][sidx<3>(a, 1)] * x[1] + Hq[c][sidx<3>(a, 2)] * x[2];
+          D[c] = D0[c] + gDr[c][0] * x[0] + gDr[c][1] * x[1] + gDr[c][2] * x[2];
         }
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -980,12 +1009,14 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
   for (int k = 0; k < K; ++k) {
     const int slot = v.eslot[k * N + i];
     const int e = slot >> 3, side = (slot >> 2) & 1, bc = slot & 3;
+    const int perm = (DIM == 3) ? v.fperm[k * N + i] : 0;
     R n[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) n[d] = v.nout[(k * DIM + d) * N + i];
     for (int jl = 0; jl < NQE; ++jl) {
       const int p = NI + k * NQE + jl;
-      const int jj = side ? (NQE - 1 - jl) : jl;  // point order of i_e along the edge
+      // point order of i_e along the edge (reversed on the other side), or on the face
+      const int jj = (DIM == 3) ? T.pperm[perm][jl] : (side ? (NQE - 1 - jl) : jl);
       R q[V], qt[V], qtt[V], FT[DIM][V];
       point(p, q, qt, qtt, FT);
       R fn[V];
@@ -1635,9 +1666,10 @@ __device__ __forceinline__ void update_item(View<R> v, const int i) {
     for (int c = 0; c < V; ++c)
       qb[c] -= r * ep * (th * v.fLxW[(size_t)e * (2 * V) + c] + (1.0 - th) * v.fLxW[(size_t)e * (2 * V) + V + c]);
     const R re = R(r * ep);
+    const int perm = (DIM == 3) ? at(v.fperm + (size_t)k * N, i) : 0;
 #pragma unroll
     for (int jl = 0; jl < NQE; ++jl) {
-      const int jj = side ? (NQE - 1 - jl) : jl;
+      const int jj = (DIM == 3) ? T.pperm[perm][jl] : (side ? (NQE - 1 - jl) : jl);
 #pragma unroll
       for (int c = 0; c < V; ++c) {
         const R fs = re * v.fstar[(size_t)e * (NQE * V) + jj * V + c];
@@ -1821,5 +1853,7 @@ template hipError_t launch<ElLine3, double>(KernelId, const View<double>&, const
 template hipError_t launch<ElLine3, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
 template hipError_t launch<ElTri3, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
 template hipError_t launch<ElTri3, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElTet, double>(KernelId, const View<double>&, const LaunchCfg&, hipStream_t, int, int);
+template hipError_t launch<ElTet, float>(KernelId, const View<float>&, const LaunchCfg&, hipStream_t, int, int);
 
 }  // namespace lxw

@@ -22,7 +22,7 @@ ERRORS = {-1: "LXW_ERR_ARG", -2: "LXW_ERR_UNSUPPORTED", -3: "LXW_ERR_MESH", -4: 
           -9: "LXW_ERR_OOM"}
 BC_PERIODIC, BC_TRANSPARENT, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
 SPEED_POINTS, SPEED_AVERAGES = 0, 1
-LINE, QUAD, TRI = 0, 1, 2
+LINE, QUAD, TRI, TET = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
 SHOCK_OFF, SHOCK_PLAIN = 0, 1
 HOST_PTR, DEVICE_PTR, STATE_UNCHECKED = 0, 1, 2
@@ -81,6 +81,7 @@ def _load():
         "lxw_mesh_create_cart_masked": [I32, I32, D, D, D, D, ip, ctypes.POINTER(ctypes.c_uint8), I32,
                                         ctypes.POINTER(P)],
         "lxw_mesh_create_tri": [I32, dp, I32, ip, ip, dp, ctypes.POINTER(P)],
+        "lxw_mesh_create_tet": [I32, dp, I32, ip, ip, dp, ctypes.POINTER(P)],
         "lxw_mesh_destroy": [P],
         "lxw_mesh_get_info": [P, ctypes.POINTER(MeshInfo)],
         "lxw_refelem_info": [I32, ip, dp, dp, dp],
@@ -167,7 +168,7 @@ def default_params(**kw):
 
 
 def n_modes(kind, degree=2):
-    return {(LINE, 2): 3, (QUAD, 2): 9, (TRI, 2): 6, (LINE, 3): 4, (TRI, 3): 10}[(kind, degree)]
+    return {(LINE, 2): 3, (QUAD, 2): 9, (TRI, 2): 6, (TET, 2): 10, (LINE, 3): 4, (TRI, 3): 10}[(kind, degree)]
 
 
 def refelem_info(kind, degree=2):
@@ -175,7 +176,7 @@ def refelem_info(kind, degree=2):
     at polynomial degree 2 (or 3 on lines and triangles)."""
     n = ctypes.c_int32(0)
     _check(_L.lxw_refelem_info_deg(kind, degree, ctypes.byref(n), None, None, None))
-    dim = 1 if kind == LINE else 2
+    dim = 1 if kind == LINE else (3 if kind == TET else 2)
     xi = np.zeros((n.value, dim))
     w = np.zeros(n.value)
     phi = np.zeros((n.value, n_modes(kind, degree)))
@@ -241,12 +242,27 @@ class Mesh:
                                       _dp(p) if p is not None else None, ctypes.byref(h)))
         return Mesh(h, TRI, xy[tri])
 
+    @staticmethod
+    def tet(xyz, tet, bnd=None, period=None):
+        """Tetrahedral P2 mesh: nodes xyz (n x 3), positively oriented tetrahedra (n_tet x 4),
+        boundary codes per (tetrahedron, face k opposite vertex k), period (3 lengths)."""
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tet = np.ascontiguousarray(tet, dtype=np.int32)
+        b = np.ascontiguousarray(bnd, dtype=np.int32) if bnd is not None else None
+        p = np.ascontiguousarray(period, dtype=np.float64) if period is not None else None
+        h = ctypes.c_void_p()
+        _check(_L.lxw_mesh_create_tet(len(xyz), _dp(xyz), len(tet), _ip(tet), _ip(b) if b is not None else None,
+                                      _dp(p) if p is not None else None, ctypes.byref(h)))
+        return Mesh(h, TET, xyz[tet])
+
     def quad_points(self, degree=2):
         """Physical coordinates of the interior quadrature points of every element (N x n x dim)."""
         xi, w, phi = refelem_info(self.kind, degree)
         v = self.verts
         if self.kind == LINE:
             return v[:, 0, None, :] + 0.5 * (xi[None, :, :] + 1.0) * (v[:, 1, None, :] - v[:, 0, None, :])
+        if self.kind == TET:
+            return v[:, 0, None, :] + sum(xi[None, :, a, None] * (v[:, a + 1, None, :] - v[:, 0, None, :]) for a in range(3))
         if self.kind == TRI:
             return v[:, 0, None, :] + xi[None, :, 0, None] * (v[:, 1, None, :] - v[:, 0, None, :]) \
                 + xi[None, :, 1, None] * (v[:, 2, None, :] - v[:, 0, None, :])

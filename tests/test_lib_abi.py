@@ -72,6 +72,36 @@ def test_degree3_refelem_tables_match_the_oracle(L, kind):
         L.refelem_info(kind, 4)
 
 
+def test_tet_tables_and_mesh_match_the_oracle(L):
+    """Tetrahedra: the library's rule (Golub-Welsch Gauss-Jacobi nodes) and basis (Cholesky of the
+    exact moments) equal the oracle's point for point; both mesh builders find the same elements,
+    faces and volumes on a periodic jittered lattice; inflow sides are refused."""
+    xi, w, phi = L.refelem_info(L.TET)
+    R = O.RefElem(O.TET)
+    assert phi.shape == (27, 10)
+    for m in range(27):
+        for l in range(10):
+            assert phi[m, l] == pytest.approx(R.phi(l, xi[m]), abs=1e-12)
+    a = sorted(zip(map(tuple, np.round(xi, 12)), np.round(w, 14)))
+    b = sorted(zip(map(tuple, np.round(R.xi_int, 12)), np.round(R.w_int, 14)))
+    assert a == b
+    xyz, tet = I.lattice_tets(5, 3, periodic=True)
+    tags = I.boundary_tags_tet(xyz, tet, (0, 1, 0, 1, 0, 1), [0] * 6)
+    m = L.Mesh.tet(xyz, tet, tags, (1.0, 1.0, 1.0))
+    om = O.Mesh.tet(xyz, tet, tags, (1.0, 1.0, 1.0))
+    assert (m.N, m.E, m.dim, m.V, m.ML, m.K) == (om.N, om.E, 3, 5, 10, 4)
+    assert m.info.min_area == pytest.approx(om.area.min(), rel=1e-14)
+    assert m.info.max_area == pytest.approx(om.area.max(), rel=1e-14)
+    with pytest.raises(L.LxwError) as e:
+        L.Mesh.tet(xyz, tet, np.where(tags >= 0, 3, -1), (1.0, 1.0, 1.0))
+    assert e.value.name == "LXW_ERR_UNSUPPORTED"
+    bad = tet.copy()
+    bad[0, [1, 2]] = bad[0, [2, 1]]
+    with pytest.raises(L.LxwError) as e:
+        L.Mesh.tet(xyz, bad, tags, (1.0, 1.0, 1.0))
+    assert e.value.name == "LXW_ERR_MESH"
+
+
 def test_masked_cartesian_mesh_counts(L):
     """The library's masked Cartesian mesh (the block step's solid removed) has the oracle's cell
     and edge counts, and rejects a mask that keeps nothing."""
