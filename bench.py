@@ -720,6 +720,7 @@ def main():
     ap.add_argument("--sedov-disk-only", action="store_true",
                     help="only steps of the 2D Sedov blast mid-run (near-vacuum limiting; for profiling)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-indicator leg")
+    ap.add_argument("--learned-only", action="store_true", help="run only the learned-indicator leg (for profiling)")
     ap.add_argument("--no-equal-l1", action="store_true", help="skip the equal-L1 comparison on the vortex")
     ap.add_argument("--no-diffraction", action="store_true", help="skip the shock-diffraction runs")
     ap.add_argument("--no-sedov", action="store_true", help="skip the Sedov blast runs")
@@ -775,6 +776,9 @@ def main():
     N = mesh.N
     if args.p3_only:
         print(json.dumps({"p3": p3_leg(L, mesh, xy, tri, args.steps, args.warmup)}), flush=True)
+        return
+    if args.learned_only:
+        print(json.dumps({"learned": learned_leg(L, args.steps, args.warmup, mesh, Q0)[0]}), flush=True)
         return
 
     log(f"[bench] FP32-mixed: {args.warmup} warm-up + 2 x {args.steps} timed steps")

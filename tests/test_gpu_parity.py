@@ -391,7 +391,8 @@ def test_device_pointer_state(L):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_smallest_meshes(L, prec):
     """Degenerate sizes: one triangle (every edge a boundary edge), two 1D cells, 2 x 2 Cartesian
-    cells with walls; each workgroup is almost all tail.  Five steps against the oracle."""
+    cells with walls, one walled tetrahedron, and at degree 3 one triangle and two 1D cells; each
+    workgroup is almost all tail.  Five steps against the oracle."""
     print(f"[gpu] smallest meshes, precision {prec}", flush=True)
     xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
     tri = np.array([[0, 1, 2]], dtype=np.int32)
@@ -399,10 +400,20 @@ def test_smallest_meshes(L, prec):
              (L.Mesh.line(2, 0, 1, 1, 2), O.Mesh.line(2, 0, 1, 1, 2), I.random_modal_state(2, 1, 3, seed=32, amp=0.2)),
              (L.Mesh.cart(2, 2, 0, 1, 0, 1, [2, 2, 2, 2]), O.Mesh.cart(2, 2, 0, 1, 0, 1, [2, 2, 2, 2]),
               I.random_modal_state(4, 2, 9, seed=33, amp=0.2))]
-    for lm, om, Q0 in cases:
-        S = L.Solver(lm, precision=prec)
+    # one tetrahedron with walls on every face (all four faces boundary faces)
+    xyz = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    tet = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    walls = np.full((1, 4), 2, np.int32)
+    cases.append((L.Mesh.tet(xyz, tet, walls), O.Mesh.tet(xyz, tet, walls), I.random_modal_state(1, 3, 10, seed=34, amp=0.2)))
+    kw = [{}] * len(cases)
+    # degree 3: one triangle and two 1D cells
+    cases += [(L.Mesh.tri(xy, tri), O.Mesh.tri(xy, tri, degree=3), I.random_modal_state(1, 2, 10, seed=35, amp=0.2)),
+              (L.Mesh.line(2, 0, 1, 1, 2), O.Mesh.line(2, 0, 1, 1, 2, degree=3), I.random_modal_state(2, 1, 4, seed=36, amp=0.2))]
+    kw += [{"degree": 3, "cfl": 0.05}] * 2
+    for (lm, om, Q0), k in zip(cases, kw):
+        S = L.Solver(lm, precision=prec, **k)
         S.set_state(Q0)
-        Ob = O.Solver(om)
+        Ob = O.Solver(om, cfl=k.get("cfl", 0.08))
         Ob.set_state(Q0)
         for _ in range(5):
             S.step()
