@@ -193,6 +193,49 @@ __device__ __forceinline__ void ft_from(const R* q, const R* qt, const R* qtt, R
   }
 }
 
+// n . F_T for an edge normal n (length included), from the flux along n, F_n = sum_d n_d F_d, and
+// its variations (the directional formulas above summed over d with weights n_d: only u.n, M.n and
+// p n enter), so an edge point forms one normal flux instead of DIM fluxes and a dot product.
+template <int DIM, class R>
+__device__ __forceinline__ R dot_n(const R* x, const R* n) {
+  R t = R(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) t += x[d] * n[d];
+  return t;
+}
+template <int DIM, class R>
+__device__ __forceinline__ void ftn_from(const R* q, const R* qt, const R* qtt, const R* n, R gm1, R dt, R* FTn) {
+  constexpr int V = DIM + 2;
+  St<DIM, R> s = base_state<DIM, R>(q, gm1);
+  Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
+  Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
+  const R d2p = d2p_of<DIM, R>(s, vt, vt, gm1);
+  const R un = dot_n<DIM, R>(s.u, n), mn = dot_n<DIM, R>(s.m, n);
+  const R dun = dot_n<DIM, R>(vt.du, n), ddun = dot_n<DIM, R>(vtt.du, n);
+  const R d2un = -R(2) * dun * qt[0] * s.r;  // (d2u[qt, qt]) . n
+  R an = R(0), bn = R(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) { an += qt[1 + d] * n[d]; bn += qtt[1 + d] * n[d]; }
+  const R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0);
+  // F_n, A_n q_t, H_n(q_t, q_t), A_n q_tt
+  FTn[0] = mn + c1 * an + c2 * bn;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const R F = s.m[k] * un + s.p * n[k];
+    const R A1 = qt[1 + k] * un + s.m[k] * dun + vt.dp * n[k];
+    const R H = R(2) * qt[1 + k] * dun + s.m[k] * d2un + d2p * n[k];
+    const R A2 = qtt[1 + k] * un + s.m[k] * ddun + vtt.dp * n[k];
+    FTn[1 + k] = F + c1 * A1 + c2 * (H + A2);
+  }
+  {
+    const R F = un * s.Ep;
+    const R A1 = dun * s.Ep + un * (qt[V - 1] + vt.dp);
+    const R H = d2un * s.Ep + R(2) * dun * (qt[V - 1] + vt.dp) + un * d2p;
+    const R A2 = ddun * s.Ep + un * (qtt[V - 1] + vtt.dp);
+    FTn[V - 1] = F + c1 * A1 + c2 * (H + A2);
+  }
+}
+
 // Degree 3: the third variation F^(3)_d(a, b, c), through the third variations of u and p (the
 // first and second are those above):
 //   d3u_k[a,b,c] = -(d2u_k[a,b] c_rho + d2u_k[a,c] b_rho + d2u_k[b,c] a_rho)/rho,
@@ -891,7 +934,7 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
   }
 
   // Sec. 2.3 Step 2 at point p: q, grad q, D = div F^h, grad D, then q_t, q_tt and F_T.
-  auto point = [&](int p, R* q, R* qt, R* qtt, R FT[DIM][V]) {
+  auto derivs = [&](int p, R* q, R* qt, R* qtt) {
     R gq[DIM][V], D[V], gD[DIM][V];
     state_at(p, q);
     if constexpr (AFF) {
@@ -970,6 +1013,9 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
 #pragma unroll
       for (int c = 0; c < V; ++c) qtt[c] += H[c] + A[c];
     }
+  };
+  auto point = [&](int p, R* q, R* qt, R* qtt, R FT[DIM][V]) {
+    derivs(p, q, qt, qtt);
     ft_from<DIM, R>(q, qt, qtt, gm1, dt, FT);
   };
 
@@ -1017,26 +1063,29 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
       const int p = NI + k * NQE + jl;
       // point order of i_e along the edge (reversed on the other side), or on the face
       const int jj = (DIM == 3) ? T.pperm[perm][jl] : (side ? (NQE - 1 - jl) : jl);
-      R q[V], qt[V], qtt[V], FT[DIM][V];
-      point(p, q, qt, qtt, FT);
-      R fn[V];
+      // the normal flux directly (3D: 5% faster), or both directions and a dot product (1D/2D:
+      // measured faster there, the two directions' independent chains hide latency at two waves)
+      R q[V], qt[V], qtt[V], fn[V];
+      if constexpr (DIM == 3) {
+        derivs(p, q, qt, qtt);
+        ftn_from<DIM, R>(q, qt, qtt, n, gm1, dt, fn);
+      } else {
+        R FT[DIM][V];
+        point(p, q, qt, qtt, FT);
 #pragma unroll
-      for (int c = 0; c < V; ++c) {
-        fn[c] = R(0);
+        for (int c = 0; c < V; ++c) {
+          fn[c] = R(0);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) fn[c] += n[d] * FT[d][c];
+          for (int d = 0; d < DIM; ++d) fn[c] += n[d] * FT[d][c];
+        }
       }
       store_rec<R, V>(v.tq + (((size_t)side * NE + e) * NQE + jj) * V, q);
       store_rec<R, V>(v.tf + (((size_t)side * NE + e) * NQE + jj) * V, fn);
       if (bc != SB_INTERIOR) {
-        R qg[V], FTg[DIM][V];
+        R qg[V], fgn[V];
         if (bc == SB_TRANSPARENT) {
 #pragma unroll
-          for (int c = 0; c < V; ++c) qg[c] = q[c];
-#pragma unroll
-          for (int d = 0; d < DIM; ++d)
-#pragma unroll
-            for (int c = 0; c < V; ++c) FTg[d][c] = FT[d][c];
+          for (int c = 0; c < V; ++c) { qg[c] = q[c]; fgn[c] = fn[c]; }
         } else if (bc == SB_REFLECTIVE) {
           R nh[DIM], len2 = R(0);
 #pragma unroll
@@ -1048,22 +1097,17 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
           reflect<DIM, R>(q, nh, qg);
           reflect<DIM, R>(qt, nh, qtg);
           reflect<DIM, R>(qtt, nh, qttg);
-          ft_from<DIM, R>(qg, qtg, qttg, gm1, dt, FTg);
+          ftn_from<DIM, R>(qg, qtg, qttg, n, gm1, dt, fgn);
         } else {
           R z[V];
 #pragma unroll
           for (int c = 0; c < V; ++c) z[c] = R(0);
           inflow_state<DIM, R>(v.inflow, qg);
-          ft_from<DIM, R>(qg, z, z, gm1, dt, FTg);
+          ftn_from<DIM, R>(qg, z, z, n, gm1, dt, fgn);
         }
         R fg[V];
 #pragma unroll
-        for (int c = 0; c < V; ++c) {
-          R fn = R(0);
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) fn += n[d] * FTg[d][c];
-          fg[c] = -fn;
-        }
+        for (int c = 0; c < V; ++c) fg[c] = -fgn[c];
         store_rec<R, V>(v.tq + (((size_t)NE + e) * NQE + jj) * V, qg);
         store_rec<R, V>(v.tf + (((size_t)NE + e) * NQE + jj) * V, fg);
       }
