@@ -63,9 +63,9 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "a280ba401ec96fc61586b8fdf76b6fc1ffa833de21ae2276184783d33f38eb5f",
-           "bytes_per_launch": {"k_pre": 136551188, "k_elem": 685821133, "k_edge": 525907968,
-                                "k_flim": 173588890, "k_update": 459481088}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "ae42d716e1d982dc349c4d51fd78a865976d861bbfe422972c96e05c94763de1",
+           "bytes_per_launch": {"k_pre": 136560548, "k_elem": 680733696, "k_edge": 525987840,
+                                "k_flim": 173578035, "k_update": 459344896}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
