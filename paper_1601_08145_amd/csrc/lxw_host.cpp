@@ -737,6 +737,10 @@ lxw_status finish_mesh(lxw_mesh* M, const std::vector<double>& cvx, const std::v
       if (j >= 0) {
         if (M->eslot[(size_t)j * K + kj] >= 0) return fail(LXW_ERR_MESH, "an edge is shared by more than two elements");
         M->eslot[(size_t)j * K + kj] = e * 8 + 1 * 4 + SB_INTERIOR;
+        // the second element takes the edge's normal negated (its own cross product or vertex
+        // differences can differ by rounding, on periodic sides and on faces): both sides of an
+        // edge then form the same |n_e| for the Lax-Friedrichs part of F*
+        for (int d = 0; d < dim; ++d) M->nout[((size_t)j * K + kj) * dim + d] = -M->nout[((size_t)i * K + k) * dim + d];
       }
     }
   M->E = E;
@@ -917,8 +921,7 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   if ((st = S->alloc(&v.Qh, (size_t)V * (ML - 1) * N))) return st;
   if ((st = S->alloc(&v.theta, (size_t)N))) return st;
   if ((st = S->alloc(&v.spart, (size_t)egrid_blocks(N, 64)))) return st;  // smallest tunable workgroup
-  if ((st = S->alloc(&v.tq, (size_t)2 * NQE * V * E))) return st;
-  if ((st = S->alloc(&v.tf, (size_t)2 * NQE * V * E))) return st;
+  if ((st = S->alloc(&v.tr, (size_t)2 * NQE * V * E))) return st;
   if ((st = S->alloc(&v.fstar, (size_t)NQE * V * E))) return st;
   if ((st = S->alloc(&v.fLxW, (size_t)2 * V * E))) return st;  // records [E][2][V]
   v.fLxF = v.fLxW + V;

@@ -112,11 +112,11 @@ struct View {
   R* Qh;                  // [V][ML-1][N] modes 2..ML
   // work
   double* theta;          // [N] limiter factor of the step (shock x moment), applied by k_elem
-  R* tq;                  // [2][E][NQE][V] traces q (side 0 = i_e, side 1 = j_e or the ghost state),
-                          //   points in i_e's order along the edge: one record per edge side,
-                          //   written by the element with vector stores, read by k_edge with
-                          //   coalesced vector loads
-  R* tf;                  // [2][E][NQE][V] traces n_out . F_T of that side
+  R* tr;                  // [2][E][NQE][V] one trace per edge side (side 0 = i_e, side 1 = j_e or
+                          //   the ghost state), n_out . F_T / 2 + (s |n_e| / 2) q of that side,
+                          //   so that F*_T . n_e = side 0 - side 1; points in i_e's order along
+                          //   the edge: one record per edge side, written by the element with
+                          //   vector stores, read by k_edge with coalesced vector loads
   // Per-edge records (array of structures): the element kernels gather them by edge index, and
   // one record spans one or two cache lines instead of one line per component.
   R* fstar;               // [E][NQE][V] F*_T . n_e at the edge points

@@ -10,7 +10,8 @@
 //            mesh it first reduces the workgroup partials);
 //   k_elem   per element: Galerkin projection of F (Sec. 2.3 Step 1), the time-averaged flux F_T
 //            of Eq. (taylor3-flux) at every interior and edge point (Sec. 2.2, 2.3 Step 2), the
-//            volume term (Sec. 2.3 Step 3) added to the higher modes, and the edge traces;
+//            volume term (Sec. 2.3 Step 3) added to the higher modes, and the edge traces (each
+//            side's half of Eq. (LLF), which is linear in the two sides' values);
 //   k_edge   per edge: Lax-Friedrichs flux of F_T at the edge points (Eq. (LLF)), the
 //            edge-averaged high-order flux f^LxW and the low-order flux f^LxF (Sec. 3.3 Step 3);
 //   k_flim   per element, float64: the flux limiter of Sec. 3.3 Steps 4-5 (Gamma, Lambda_ik, the
@@ -172,25 +173,33 @@ __device__ __forceinline__ R d2p_of(const St<DIM, R>& s, const Var<DIM, R>& va, 
 }
 
 // F_T = F + dt/2 A q_t + dt^2/6 (H(q_t, q_t) + A q_tt) for every direction d (Eq. (taylor3-flux)
-// with the chain rule of Sec. 2.2; also the ghost-state flux of Sec. 2.4).
+// with the chain rule of Sec. 2.2; also the ghost-state flux of Sec. 2.4).  A is linear, so its two
+// products are formed as one, A (dt/2 q_t + dt^2/6 q_tt).  The caller passes the state s of q and
+// the variation vt of q_t (the element kernel has them from the time derivatives).
 template <int DIM, class R>
-__device__ __forceinline__ void ft_from(const R* q, const R* qt, const R* qtt, R gm1, R dt, R FT[DIM][DIM + 2]) {
+__device__ __forceinline__ void ft_core(const St<DIM, R>& s, const R* qt, const Var<DIM, R>& vt, const R* qtt, R gm1,
+                                        R dt, R FT[DIM][DIM + 2]) {
   constexpr int V = DIM + 2;
-  St<DIM, R> s = base_state<DIM, R>(q, gm1);
-  Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
-  Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
-  R d2p = d2p_of<DIM, R>(s, vt, vt, gm1);
-  R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0);
+  const R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0);
+  R qc[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) qc[c] = c1 * qt[c] + c2 * qtt[c];
+  const Var<DIM, R> vc = var1<DIM, R>(s, qc, gm1);
+  const R d2p = d2p_of<DIM, R>(s, vt, vt, gm1);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    R F[V], A1[V], H[V], A2[V];
+    R F[V], A[V], H[V];
     flux<DIM, R>(s, d, F);
-    dflux<DIM, R>(s, d, qt, vt, A1);
+    dflux<DIM, R>(s, d, qc, vc, A);
     d2flux<DIM, R>(s, d, qt, vt, qt, vt, d2p, H);
-    dflux<DIM, R>(s, d, qtt, vtt, A2);
 #pragma unroll
-    for (int c = 0; c < V; ++c) FT[d][c] = F[c] + c1 * A1[c] + c2 * (H[c] + A2[c]);
+    for (int c = 0; c < V; ++c) FT[d][c] = F[c] + A[c] + c2 * H[c];
   }
+}
+template <int DIM, class R>
+__device__ __forceinline__ void ft_from(const R* q, const R* qt, const R* qtt, R gm1, R dt, R FT[DIM][DIM + 2]) {
+  const St<DIM, R> s = base_state<DIM, R>(q, gm1);
+  ft_core<DIM, R>(s, qt, var1<DIM, R>(s, qt, gm1), qtt, gm1, dt, FT);
 }
 
 // n . F_T for an edge normal n (length included), from the flux along n, F_n = sum_d n_d F_d, and
@@ -204,36 +213,41 @@ __device__ __forceinline__ R dot_n(const R* x, const R* n) {
   return t;
 }
 template <int DIM, class R>
-__device__ __forceinline__ void ftn_from(const R* q, const R* qt, const R* qtt, const R* n, R gm1, R dt, R* FTn) {
+__device__ __forceinline__ void ftn_core(const St<DIM, R>& s, const R* qt, const Var<DIM, R>& vt, const R* qtt,
+                                         const R* n, R gm1, R dt, R* FTn) {
   constexpr int V = DIM + 2;
-  St<DIM, R> s = base_state<DIM, R>(q, gm1);
-  Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
-  Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
+  const R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0);
+  R qc[V];  // one Jacobian product A_n (dt/2 q_t + dt^2/6 q_tt), as in ft_core
+#pragma unroll
+  for (int c = 0; c < V; ++c) qc[c] = c1 * qt[c] + c2 * qtt[c];
+  const Var<DIM, R> vc = var1<DIM, R>(s, qc, gm1);
   const R d2p = d2p_of<DIM, R>(s, vt, vt, gm1);
   const R un = dot_n<DIM, R>(s.u, n), mn = dot_n<DIM, R>(s.m, n);
-  const R dun = dot_n<DIM, R>(vt.du, n), ddun = dot_n<DIM, R>(vtt.du, n);
+  const R dun = dot_n<DIM, R>(vt.du, n), dcn = dot_n<DIM, R>(vc.du, n);
   const R d2un = -R(2) * dun * qt[0] * s.r;  // (d2u[qt, qt]) . n
-  R an = R(0), bn = R(0);
+  R an = R(0);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) { an += qt[1 + d] * n[d]; bn += qtt[1 + d] * n[d]; }
-  const R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0);
-  // F_n, A_n q_t, H_n(q_t, q_t), A_n q_tt
-  FTn[0] = mn + c1 * an + c2 * bn;
+  for (int d = 0; d < DIM; ++d) an += qc[1 + d] * n[d];
+  // F_n + A_n qc + dt^2/6 H_n(q_t, q_t)
+  FTn[0] = mn + an;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const R F = s.m[k] * un + s.p * n[k];
-    const R A1 = qt[1 + k] * un + s.m[k] * dun + vt.dp * n[k];
+    const R A = qc[1 + k] * un + s.m[k] * dcn + vc.dp * n[k];
     const R H = R(2) * qt[1 + k] * dun + s.m[k] * d2un + d2p * n[k];
-    const R A2 = qtt[1 + k] * un + s.m[k] * ddun + vtt.dp * n[k];
-    FTn[1 + k] = F + c1 * A1 + c2 * (H + A2);
+    FTn[1 + k] = F + A + c2 * H;
   }
   {
     const R F = un * s.Ep;
-    const R A1 = dun * s.Ep + un * (qt[V - 1] + vt.dp);
+    const R A = dcn * s.Ep + un * (qc[V - 1] + vc.dp);
     const R H = d2un * s.Ep + R(2) * dun * (qt[V - 1] + vt.dp) + un * d2p;
-    const R A2 = ddun * s.Ep + un * (qtt[V - 1] + vtt.dp);
-    FTn[V - 1] = F + c1 * A1 + c2 * (H + A2);
+    FTn[V - 1] = F + A + c2 * H;
   }
+}
+template <int DIM, class R>
+__device__ __forceinline__ void ftn_from(const R* q, const R* qt, const R* qtt, const R* n, R gm1, R dt, R* FTn) {
+  const St<DIM, R> s = base_state<DIM, R>(q, gm1);
+  ftn_core<DIM, R>(s, qt, var1<DIM, R>(s, qt, gm1), qtt, n, gm1, dt, FTn);
 }
 
 // Degree 3: the third variation F^(3)_d(a, b, c), through the third variations of u and p (the
@@ -267,31 +281,40 @@ __device__ __forceinline__ void d3flux(const St<DIM, R>& s, int d, const R* a, c
 }
 
 // Degree 3: F_T one Taylor term further, + dt^3/24 (F^(3)(q_t, q_t, q_t) + 3 H(q_t, q_tt) + A q_ttt).
+// A is linear and H bilinear, so the terms are gathered as
+//   F + A (c1 q_t + c2 q_tt + c3 q_ttt) + H(q_t, c2 q_t + 3 c3 q_tt) + c3 F^(3)(q_t, q_t, q_t)
+// with c1 = dt/2, c2 = dt^2/6, c3 = dt^3/24: one Jacobian and one Hessian product per direction.
+template <int DIM, class R>
+__device__ __forceinline__ void ft4_core(const St<DIM, R>& s, const R* qt, const Var<DIM, R>& vt, const R* qtt,
+                                         const R* qttt, R gm1, R dt, R FT[DIM][DIM + 2]) {
+  constexpr int V = DIM + 2;
+  const R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0), c3 = dt * dt * dt * R(1.0 / 24.0);
+  const R c33 = R(3) * c3;
+  R qc[V], qh[V];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    qc[c] = c1 * qt[c] + c2 * qtt[c] + c3 * qttt[c];
+    qh[c] = c2 * qt[c] + c33 * qtt[c];
+  }
+  const Var<DIM, R> vc = var1<DIM, R>(s, qc, gm1);
+  const Var<DIM, R> vh = var1<DIM, R>(s, qh, gm1);
+  const R d2p = d2p_of<DIM, R>(s, vt, vh, gm1);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    R F[V], A[V], H[V], T3[V];
+    flux<DIM, R>(s, d, F);
+    dflux<DIM, R>(s, d, qc, vc, A);
+    d2flux<DIM, R>(s, d, qt, vt, qh, vh, d2p, H);
+    d3flux<DIM, R>(s, d, qt, vt, qt, vt, qt, vt, gm1, T3);
+#pragma unroll
+    for (int c = 0; c < V; ++c) FT[d][c] = F[c] + A[c] + H[c] + c3 * T3[c];
+  }
+}
 template <int DIM, class R>
 __device__ __forceinline__ void ft4_from(const R* q, const R* qt, const R* qtt, const R* qttt, R gm1, R dt,
                                          R FT[DIM][DIM + 2]) {
-  constexpr int V = DIM + 2;
-  St<DIM, R> s = base_state<DIM, R>(q, gm1);
-  Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
-  Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
-  Var<DIM, R> vttt = var1<DIM, R>(s, qttt, gm1);
-  const R d2p = d2p_of<DIM, R>(s, vt, vt, gm1);
-  const R d2p12 = d2p_of<DIM, R>(s, vt, vtt, gm1);
-  const R c1 = R(0.5) * dt, c2 = dt * dt * R(1.0 / 6.0), c3 = dt * dt * dt * R(1.0 / 24.0);
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    R F[V], A1[V], H[V], A2[V], T3[V], H12[V], A3[V];
-    flux<DIM, R>(s, d, F);
-    dflux<DIM, R>(s, d, qt, vt, A1);
-    d2flux<DIM, R>(s, d, qt, vt, qt, vt, d2p, H);
-    dflux<DIM, R>(s, d, qtt, vtt, A2);
-    d3flux<DIM, R>(s, d, qt, vt, qt, vt, qt, vt, gm1, T3);
-    d2flux<DIM, R>(s, d, qt, vt, qtt, vtt, d2p12, H12);
-    dflux<DIM, R>(s, d, qttt, vttt, A3);
-#pragma unroll
-    for (int c = 0; c < V; ++c)
-      FT[d][c] = F[c] + c1 * A1[c] + c2 * (H[c] + A2[c]) + c3 * (T3[c] + R(3) * H12[c] + A3[c]);
-  }
+  const St<DIM, R> s = base_state<DIM, R>(q, gm1);
+  ft4_core<DIM, R>(s, qt, var1<DIM, R>(s, qt, gm1), qtt, qttt, gm1, dt, FT);
 }
 
 // Pressure and wave speed (double, for the limiters and s).
@@ -933,8 +956,9 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
     }
   }
 
-  // Sec. 2.3 Step 2 at point p: q, grad q, D = div F^h, grad D, then q_t, q_tt and F_T.
-  auto derivs = [&](int p, R* q, R* qt, R* qtt) {
+  // Sec. 2.3 Step 2 at point p: q, grad q, D = div F^h, grad D, then q_t, q_tt and F_T; also the
+  // state s of q and the variation vt of q_t, which F_T needs.
+  auto derivs = [&](int p, R* q, R* qt, R* qtt, St<DIM, R>& s, Var<DIM, R>& vt) {
     R gq[DIM][V], D[V], gD[DIM][V];
     state_at(p, q);
     if constexpr (AFF) {
@@ -998,8 +1022,11 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
         }
       }
     }
-    St<DIM, R> s = base_state<DIM, R>(q, gm1);
-    Var<DIM, R> vD = var1<DIM, R>(s, D, gm1);
+    s = base_state<DIM, R>(q, gm1);
+    const Var<DIM, R> vD = var1<DIM, R>(s, D, gm1);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) vt.du[d] = -vD.du[d];  // var1 is linear: q_t = -D
+    vt.dp = -vD.dp;
 #pragma unroll
     for (int c = 0; c < V; ++c) { qt[c] = -D[c]; qtt[c] = R(0); }
 #pragma unroll
@@ -1014,9 +1041,15 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
       for (int c = 0; c < V; ++c) qtt[c] += H[c] + A[c];
     }
   };
+  // In 3D the state and q_t's variation are formed again from q and q_t instead of being held across
+  // the call: at one wave per SIMD the float64 tetrahedron kernel then spills less (820 instead of
+  // 924 bytes per lane).
   auto point = [&](int p, R* q, R* qt, R* qtt, R FT[DIM][V]) {
-    derivs(p, q, qt, qtt);
-    ft_from<DIM, R>(q, qt, qtt, gm1, dt, FT);
+    St<DIM, R> s;
+    Var<DIM, R> vt;
+    derivs(p, q, qt, qtt, s, vt);
+    if constexpr (DIM == 3) ft_from<DIM, R>(q, qt, qtt, gm1, dt, FT);
+    else ft_core<DIM, R>(s, qt, vt, qtt, gm1, dt, FT);
   };
 
   // interior points: volume term V_l = sum_m w_m grad phi_l . F_T
@@ -1051,14 +1084,17 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
     }
   }
 
-  // edge points: traces q and n_out . F_T (and the ghost side on boundary edges)
+  // edge points: the trace n_out . F_T / 2 + hs q (and the ghost side's on boundary edges)
+  const double hs0 = 0.5 * v.sc[mid].s;
   for (int k = 0; k < K; ++k) {
     const int slot = v.eslot[k * N + i];
     const int e = slot >> 3, side = (slot >> 2) & 1, bc = slot & 3;
     const int perm = (DIM == 3) ? v.fperm[k * N + i] : 0;
-    R n[DIM];
+    R n[DIM], len2 = R(0);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) n[d] = v.nout[(k * DIM + d) * N + i];
+    for (int d = 0; d < DIM; ++d) { n[d] = v.nout[(k * DIM + d) * N + i]; len2 += n[d] * n[d]; }
+    // s |n_e| / 2: both elements of an edge hold the same normal up to sign, so they form it alike
+    const R hs = R(hs0 * double(sqrt(len2)));
     for (int jl = 0; jl < NQE; ++jl) {
       const int p = NI + k * NQE + jl;
       // point order of i_e along the edge (reversed on the other side), or on the face
@@ -1067,7 +1103,9 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
       // measured faster there, the two directions' independent chains hide latency at two waves)
       R q[V], qt[V], qtt[V], fn[V];
       if constexpr (DIM == 3) {
-        derivs(p, q, qt, qtt);
+        St<DIM, R> s;
+        Var<DIM, R> vt;
+        derivs(p, q, qt, qtt, s, vt);
         ftn_from<DIM, R>(q, qt, qtt, n, gm1, dt, fn);
       } else {
         R FT[DIM][V];
@@ -1079,17 +1117,17 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
           for (int d = 0; d < DIM; ++d) fn[c] += n[d] * FT[d][c];
         }
       }
-      store_rec<R, V>(v.tq + (((size_t)side * NE + e) * NQE + jj) * V, q);
-      store_rec<R, V>(v.tf + (((size_t)side * NE + e) * NQE + jj) * V, fn);
+      R b[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) b[c] = R(0.5) * fn[c] + hs * q[c];
+      store_rec<R, V>(v.tr + (((size_t)side * NE + e) * NQE + jj) * V, b);
       if (bc != SB_INTERIOR) {
         R qg[V], fgn[V];
         if (bc == SB_TRANSPARENT) {
 #pragma unroll
           for (int c = 0; c < V; ++c) { qg[c] = q[c]; fgn[c] = fn[c]; }
         } else if (bc == SB_REFLECTIVE) {
-          R nh[DIM], len2 = R(0);
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) len2 += n[d] * n[d];
+          R nh[DIM];
           const R il = R(1) / sqrt(len2);
 #pragma unroll
           for (int d = 0; d < DIM; ++d) nh[d] = n[d] * il;
@@ -1105,11 +1143,11 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
           inflow_state<DIM, R>(v.inflow, qg);
           ftn_from<DIM, R>(qg, z, z, n, gm1, dt, fgn);
         }
-        R fg[V];
+        // the ghost is side 1: its outward normal is -n
+        R bg[V];
 #pragma unroll
-        for (int c = 0; c < V; ++c) fg[c] = -fgn[c];
-        store_rec<R, V>(v.tq + (((size_t)NE + e) * NQE + jj) * V, qg);
-        store_rec<R, V>(v.tf + (((size_t)NE + e) * NQE + jj) * V, fg);
+        for (int c = 0; c < V; ++c) bg[c] = hs * qg[c] - R(0.5) * fgn[c];
+        store_rec<R, V>(v.tr + (((size_t)NE + e) * NQE + jj) * V, bg);
       }
     }
   }
@@ -1285,7 +1323,10 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
 #pragma unroll
       for (int c = 0; c < V; ++c) qtt[c] += H[c] + A[c];
     }
-    Var<DIM, R> vt = var1<DIM, R>(s, qt, gm1);
+    Var<DIM, R> vt;  // the variation of q_t = -D (var1 is linear)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) vt.du[d] = -vD.du[d];
+    vt.dp = -vD.dp;
     Var<DIM, R> vtt = var1<DIM, R>(s, qtt, gm1);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -1315,7 +1356,7 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
 #pragma unroll
       for (int c = 0; c < V; ++c) qttt[c] -= t1[c] - R(2) * t2[c] + t3[c] + t4[c];
     }
-    ft4_from<DIM, R>(q, qt, qtt, qttt, gm1, dt, FT);
+    ft4_core<DIM, R>(s, qt, vt, qtt, qttt, gm1, dt, FT);
   };
 
   R vol[V][ML - 1];
@@ -1351,13 +1392,15 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
     }
   }
 
-  // edge points: traces q and n_out . F_T (and the ghost side on boundary edges)
+  // edge points: the trace n_out . F_T / 2 + hs q (and the ghost side's on boundary edges)
+  const double hs0 = 0.5 * v.sc[mid].s;
   for (int k = 0; k < K; ++k) {
     const int slot = v.eslot[k * N + i];
     const int e = slot >> 3, side = (slot >> 2) & 1, bc = slot & 3;
-    R n[DIM];
+    R n[DIM], len2 = R(0);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) n[d] = v.nout[(k * DIM + d) * N + i];
+    for (int d = 0; d < DIM; ++d) { n[d] = v.nout[(k * DIM + d) * N + i]; len2 += n[d] * n[d]; }
+    const R hs = R(hs0 * double(sqrt(len2)));
     for (int jl = 0; jl < NQE; ++jl) {
       const int p = NI + k * NQE + jl;
       const int jj = side ? (NQE - 1 - jl) : jl;
@@ -1370,8 +1413,10 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) fn[c] += n[d] * FT[d][c];
       }
-      store_rec<R, V>(v.tq + (((size_t)side * NE + e) * NQE + jj) * V, q);
-      store_rec<R, V>(v.tf + (((size_t)side * NE + e) * NQE + jj) * V, fn);
+      R b[V];
+#pragma unroll
+      for (int c = 0; c < V; ++c) b[c] = R(0.5) * fn[c] + hs * q[c];
+      store_rec<R, V>(v.tr + (((size_t)side * NE + e) * NQE + jj) * V, b);
       if (bc != SB_INTERIOR) {
         R qg[V], FTg[DIM][V];
         if (bc == SB_TRANSPARENT) {
@@ -1382,9 +1427,7 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
 #pragma unroll
             for (int c = 0; c < V; ++c) FTg[d][c] = FT[d][c];
         } else if (bc == SB_REFLECTIVE) {
-          R nh[DIM], len2 = R(0);
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) len2 += n[d] * n[d];
+          R nh[DIM];
           const R il = R(1) / sqrt(len2);
 #pragma unroll
           for (int d = 0; d < DIM; ++d) nh[d] = n[d] * il;
@@ -1401,16 +1444,15 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
           inflow_state<DIM, R>(v.inflow, qg);
           ft4_from<DIM, R>(qg, z, z, z, gm1, dt, FTg);
         }
-        R fg[V];
+        R bg[V];  // the ghost is side 1: its outward normal is -n
 #pragma unroll
         for (int c = 0; c < V; ++c) {
           R f = R(0);
 #pragma unroll
           for (int d = 0; d < DIM; ++d) f += n[d] * FTg[d][c];
-          fg[c] = -f;
+          bg[c] = hs * qg[c] - R(0.5) * f;
         }
-        store_rec<R, V>(v.tq + (((size_t)NE + e) * NQE + jj) * V, qg);
-        store_rec<R, V>(v.tf + (((size_t)NE + e) * NQE + jj) * V, fg);
+        store_rec<R, V>(v.tr + (((size_t)NE + e) * NQE + jj) * V, bg);
       }
     }
   }
@@ -1429,7 +1471,9 @@ __global__ __launch_bounds__(256, (ElemOcc<E, R>::waves)) void k_elem(View<R> v)
 
 // ---------------------------------------------------------------------------------------------
 // k_edge: F*_T . n_e = (1/2)(n_e.F_T(q+) + n_e.F_T(q-)) - (s |n_e| / 2)(q+ - q-) at each edge point
-// (Eq. (LLF) with the scaled normal), f^LxW_e = (1/2) sum_j omega_j F*_j (float64 sum), and
+// (Eq. (LLF) with the scaled normal; the flux is linear in the two sides' values, so each element
+// wrote its half n_out.F_T/2 + (s |n_e|/2) q and F* is side 0 minus side 1),
+// f^LxW_e = (1/2) sum_j omega_j F*_j (float64 sum), and
 // f^LxF_e = (1/2) n_e.(F(q_bar_j) + F(q_bar_i)) - (s |n_e| / 2)(q_bar_j - q_bar_i) in float64.
 // ---------------------------------------------------------------------------------------------
 // Copies nbytes (a multiple of 4) from LDS to global memory with the whole workgroup, 16 bytes per
@@ -1470,7 +1514,6 @@ __device__ __forceinline__ void edge_tile(View<R> v, const int e) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) { n[d] = at(v.e_n + (size_t)d * NE, e); len2 += n[d] * n[d]; }
     const double len = sqrt(len2);
-    const R hs = R(0.5 * s * len);
     const int ie = at(v.e_i, e), je = at(v.e_j, e);
     double W[V];
 #pragma unroll
@@ -1479,11 +1522,8 @@ __device__ __forceinline__ void edge_tile(View<R> v, const int e) {
     for (int jj = 0; jj < NQE; ++jj) {
 #pragma unroll
       for (int c = 0; c < V; ++c) {
-        const R qm = v.tq[((size_t)e * NQE + jj) * V + c];
-        const R fm = v.tf[((size_t)e * NQE + jj) * V + c];
-        const R qp = v.tq[(((size_t)NE + e) * NQE + jj) * V + c];
-        const R fp = -v.tf[(((size_t)NE + e) * NQE + jj) * V + c];
-        const R fs = R(0.5) * (fp + fm) - hs * (qp - qm);
+        // (n.F_T(q-) + n.F_T(q+))/2 - hs (q+ - q-), from the two sides' traces
+        const R fs = v.tr[((size_t)e * NQE + jj) * V + c] - v.tr[(((size_t)NE + e) * NQE + jj) * V + c];
         fsr[jj * V + c] = fs;
         W[c] += 0.5 * double(T.om[jj]) * double(fs);
       }
