@@ -923,8 +923,8 @@ lxw_status setup_view(lxw_solver* S, View<R>& v) {
   if ((st = S->alloc(&v.spart, (size_t)egrid_blocks(N, 64)))) return st;  // smallest tunable workgroup
   if ((st = S->alloc(&v.tr, (size_t)2 * NQE * V * E))) return st;
   if ((st = S->alloc(&v.fstar, (size_t)NQE * V * E))) return st;
-  if ((st = S->alloc(&v.fLxW, (size_t)2 * V * E))) return st;  // records [E][2][V]
-  v.fLxF = v.fLxW + V;
+  if ((st = S->alloc(&v.fLxW, (size_t)V * E))) return st;
+  if ((st = S->alloc(&v.fLxF, (size_t)V * E))) return st;
   if ((st = S->alloc(&v.cedge, (size_t)2 * E))) return st;
   {
     std::vector<double> ones((size_t)2 * E, 1.0);
@@ -2009,14 +2009,14 @@ lxw_status lxw_debug_stage(lxw_solver* S, int32_t stage, double* out) {
     }
     case LXW_STAGE_FLXW:
     case LXW_STAGE_FLXF: {
-      if ((s = dget(S->fp32 ? S->vf.fLxW : S->vd.fLxW, (size_t)2 * V * E, h))) return s;
-      const size_t off = stage == LXW_STAGE_FLXW ? 0 : (size_t)V;
+      const bool w = stage == LXW_STAGE_FLXW;
+      if ((s = dget(S->fp32 ? (w ? S->vf.fLxW : S->vf.fLxF) : (w ? S->vd.fLxW : S->vd.fLxF), (size_t)V * E, h))) return s;
       for (int i = 0; i < N; ++i)
         for (int k = 0; k < K; ++k) {
           const int slot = M.eslot[(size_t)i * K + k];
           const int e = slot >> 3;
           const double ep = ((slot >> 2) & 1) ? -1.0 : 1.0;
-          for (int v = 0; v < V; ++v) out[((size_t)M.perm[i] * K + k) * V + v] = ep * h[(size_t)e * 2 * V + off + v];
+          for (int v = 0; v < V; ++v) out[((size_t)M.perm[i] * K + k) * V + v] = ep * h[(size_t)e * V + v];
         }
       return LXW_OK;
     }

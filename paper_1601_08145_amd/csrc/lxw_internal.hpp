@@ -120,8 +120,9 @@ struct View {
   // Per-edge records (array of structures): the element kernels gather them by edge index, and
   // one record spans one or two cache lines instead of one line per component.
   R* fstar;               // [E][NQE][V] F*_T . n_e at the edge points
-  double* fLxW;           // [E][2][V]: f^LxW of edge e at fLxW[e * 2V + c]
-  double* fLxF;           // = fLxW + V: f^LxF of edge e at fLxF[e * 2V + c] (same records)
+  double* fLxW;           // [E][V] f^LxW of edge e (read by the flux limiter; k_update forms it
+                          //   again from the F* record, bit for bit)
+  double* fLxF;           // [E][V] f^LxF of edge e
   double* cedge;          // [E][2] damping candidate of each side (1 on a ghost side)
   const unsigned char* ind_flag;  // [N] learned indicator decision (0: the shock-capturing limiter
                                  //   is skipped) or null (plain detection everywhere)

@@ -97,11 +97,16 @@ struct St {
   R rho, r, u[DIM], m[DIM], E, p, Ep, u2;
 };
 
+// 1/rho: in the float32 bulk the hardware reciprocal (within 1 ulp; rho is positive and far above
+// the denormal range wherever it is used), in float64 the correctly rounded quotient.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <int DIM, class R>
 __device__ __forceinline__ St<DIM, R> base_state(const R* q, R gm1) {
   St<DIM, R> s;
   s.rho = q[0];
-  s.r = R(1) / q[0];
+  s.r = recip(q[0]);
   R mu = R(0), u2 = R(0);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -1489,23 +1494,40 @@ __device__ __forceinline__ void lds_to_global(unsigned char* dst, const unsigned
   }
 }
 
+// f^LxW_e = (1/2) sum_j omega_j F*_j in float64, summed in the edge's point order with explicit
+// fused multiply-adds: k_edge stores it for the flux limiter and k_update forms it again from the
+// F* record, and the two agree bit for bit.
+template <class E, class R>
+__device__ __forceinline__ void lxw_average(const RefTab<E, R>& T, const R (&fs)[E::NQE][E::V], double (&W)[E::V]) {
+#pragma unroll
+  for (int c = 0; c < E::V; ++c) W[c] = 0.0;
+#pragma unroll
+  for (int jj = 0; jj < E::NQE; ++jj) {
+    const double w = 0.5 * double(T.om[jj]);
+#pragma unroll
+    for (int c = 0; c < E::V; ++c) W[c] = __fma_rn(w, double(fs[jj][c]), W[c]);
+  }
+}
+
 // Edge e of k_edge; every lane of the workgroup calls it with the edges e0 + threadIdx.x of one
 // contiguous tile (the records are staged through LDS and written together).
 template <class E, class R>
 __device__ __forceinline__ void edge_tile(View<R> v, const int e) {
   constexpr int V = E::V, DIM = E::DIM, NQE = E::NQE;
-  // per-edge records: F* at the edge points, and (f^LxW, f^LxF); each lane writes its edge's
-  // records into LDS as it computes them
-  constexpr int FS = NQE * V * (int)sizeof(R), FL = 2 * V * (int)sizeof(double);
+  // per-edge records: F* at the edge points, f^LxW and f^LxF; each lane writes its edge's records
+  // into LDS as it computes them
+  constexpr int FS = NQE * V * (int)sizeof(R), FL = V * (int)sizeof(double);
   __shared__ __align__(16) unsigned char rec_fs[256 * FS];
-  __shared__ __align__(16) unsigned char rec_fl[256 * FL];
+  __shared__ __align__(16) unsigned char rec_fw[256 * FL];
+  __shared__ __align__(16) unsigned char rec_ff[256 * FL];
   const RefTab<E, R>& T = TabSel<E, R>::get();
   const int NE = v.E;
   const bool valid = e < NE;
   const int e0 = e - (int)threadIdx.x;  // first edge of the workgroup (its edges are consecutive)
   const int nrec = max(0, min((int)blockDim.x, NE - e0));
   R* fsr = reinterpret_cast<R*>(rec_fs + threadIdx.x * FS);
-  double* flr = reinterpret_cast<double*>(rec_fl + threadIdx.x * FL);
+  double* fwr = reinterpret_cast<double*>(rec_fw + threadIdx.x * FL);
+  double* ffr = reinterpret_cast<double*>(rec_ff + threadIdx.x * FL);
   if (valid) {
     const int mid = v.e_mesh ? at(v.e_mesh, e) : 0;
     const double s = v.sc[mid].s;
@@ -1515,21 +1537,20 @@ __device__ __forceinline__ void edge_tile(View<R> v, const int e) {
     for (int d = 0; d < DIM; ++d) { n[d] = at(v.e_n + (size_t)d * NE, e); len2 += n[d] * n[d]; }
     const double len = sqrt(len2);
     const int ie = at(v.e_i, e), je = at(v.e_j, e);
-    double W[V];
-#pragma unroll
-    for (int c = 0; c < V; ++c) W[c] = 0.0;
+    R fs[NQE][V];
 #pragma unroll
     for (int jj = 0; jj < NQE; ++jj) {
 #pragma unroll
       for (int c = 0; c < V; ++c) {
         // (n.F_T(q-) + n.F_T(q+))/2 - hs (q+ - q-), from the two sides' traces
-        const R fs = v.tr[((size_t)e * NQE + jj) * V + c] - v.tr[(((size_t)NE + e) * NQE + jj) * V + c];
-        fsr[jj * V + c] = fs;
-        W[c] += 0.5 * double(T.om[jj]) * double(fs);
+        fs[jj][c] = v.tr[((size_t)e * NQE + jj) * V + c] - v.tr[(((size_t)NE + e) * NQE + jj) * V + c];
+        fsr[jj * V + c] = fs[jj][c];
       }
     }
+    double W[V];
+    lxw_average<E, R>(T, fs, W);
 #pragma unroll
-    for (int c = 0; c < V; ++c) flr[c] = W[c];
+    for (int c = 0; c < V; ++c) fwr[c] = W[c];
 
     const int i = ie, j = je;
     double qi[V], qj[V];
@@ -1566,14 +1587,15 @@ __device__ __forceinline__ void edge_tile(View<R> v, const int e) {
       for (int c = 0; c < V; ++c) Lf[c] += 0.5 * n[d] * (Fj[c] + Fi[c]);
     }
 #pragma unroll
-    for (int c = 0; c < V; ++c) flr[V + c] = Lf[c] - 0.5 * s * len * (qj[c] - qi[c]);
+    for (int c = 0; c < V; ++c) ffr[c] = Lf[c] - 0.5 * s * len * (qj[c] - qi[c]);
   }
   // The records of the workgroup's edges are one contiguous range: staged in LDS, they are written
   // with coalesced stores (written straight from the lanes, every store instruction would touch a
   // cache line per lane).
   __syncthreads();
   lds_to_global<FS % 16 == 0>(reinterpret_cast<unsigned char*>(v.fstar) + (size_t)max(e0, 0) * FS, rec_fs, nrec * FS);
-  lds_to_global<FL % 16 == 0>(reinterpret_cast<unsigned char*>(v.fLxW) + (size_t)max(e0, 0) * FL, rec_fl, nrec * FL);
+  lds_to_global<FL % 16 == 0>(reinterpret_cast<unsigned char*>(v.fLxW) + (size_t)max(e0, 0) * FL, rec_fw, nrec * FL);
+  lds_to_global<FL % 16 == 0>(reinterpret_cast<unsigned char*>(v.fLxF) + (size_t)max(e0, 0) * FL, rec_ff, nrec * FL);
   // the staging area is free again only when every lane has copied its part out (a workgroup of
   // the persistent kernel goes on to its next tile)
   __syncthreads();
@@ -1657,8 +1679,8 @@ __device__ __forceinline__ void flim_item(View<R> v, const int i) {
     const double ep = sd[k] ? -1.0 : 1.0;
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      fW[k][c] = ep * v.fLxW[(size_t)eidx[k] * (2 * V) + c];
-      fF[k][c] = ep * v.fLxW[(size_t)eidx[k] * (2 * V) + V + c];
+      fW[k][c] = ep * v.fLxW[(size_t)eidx[k] * V + c];
+      fF[k][c] = ep * v.fLxF[(size_t)eidx[k] * V + c];
     }
     Gam -= fF[k][0];
     df[k] = fF[k][0] - fW[k][0];
@@ -1746,9 +1768,23 @@ __device__ __forceinline__ void update_item(View<R> v, const int i) {
     const double ep = side ? -1.0 : 1.0;
     const double th = fmin(1.0, fmin(v.cedge[(size_t)e * 2], v.cedge[(size_t)e * 2 + 1]));
     if (v.dbg_lame) v.dbg_lame[k * N + i] = th;
+    // 1D and 2D: the edge's F* record in registers, and f^LxW formed from it as k_edge formed the
+    // one the limiter used (one record read instead of two); 3D: f^LxW as stored (a face record of
+    // 7 points per face, four faces in flight, would not fit the registers)
+    R fsr[NQE][V];
+    double W[V];
+    if constexpr (DIM == 3) {
 #pragma unroll
-    for (int c = 0; c < V; ++c)
-      qb[c] -= r * ep * (th * v.fLxW[(size_t)e * (2 * V) + c] + (1.0 - th) * v.fLxW[(size_t)e * (2 * V) + V + c]);
+      for (int c = 0; c < V; ++c) W[c] = v.fLxW[(size_t)e * V + c];
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < NQE; ++jj)
+#pragma unroll
+        for (int c = 0; c < V; ++c) fsr[jj][c] = v.fstar[(size_t)e * (NQE * V) + jj * V + c];
+      lxw_average<E, R>(T, fsr, W);
+    }
+#pragma unroll
+    for (int c = 0; c < V; ++c) qb[c] -= r * ep * (th * W[c] + (1.0 - th) * v.fLxF[(size_t)e * V + c]);
     const R re = R(r * ep);
     const int perm = (DIM == 3) ? at(v.fperm + (size_t)k * N, i) : 0;
 #pragma unroll
@@ -1756,7 +1792,7 @@ __device__ __forceinline__ void update_item(View<R> v, const int i) {
       const int jj = (DIM == 3) ? T.pperm[perm][jl] : (side ? (NQE - 1 - jl) : jl);
 #pragma unroll
       for (int c = 0; c < V; ++c) {
-        const R fs = re * v.fstar[(size_t)e * (NQE * V) + jj * V + c];
+        const R fs = re * ((DIM == 3) ? v.fstar[(size_t)e * (NQE * V) + jj * V + c] : fsr[jj][c]);
 #pragma unroll
         for (int l = 1; l < ML; ++l) Qh[c][l - 1] -= T.ephi[k][jl][l] * fs;
       }
