@@ -51,21 +51,22 @@ STEP_BYTES_PER_ELEM = 228
 # Arithmetic of k_elem per triangle (P2, FP32-mixed): projection of F at 7 points, q, grad q,
 # div F^h, grad div F^h and F_T at 16 points, volume term, traces.  Counted from the kernel's
 # executed VALU instructions per wavefront (64 triangles): fp32 FMA x 2 + fp32 add + fp32 mul +
-# fp64 FMA x 2 + fp64 add + fp64 mul, divided by 64 (profiles/k_elem_tri_c3_counters.md).
-KELEM_FLOPS_PER_ELEM = 10.9e3
+# fp64 FMA x 2 + fp64 add + fp64 mul, divided by 64 (profiles/lxw_kernels_tri_c3_counters.md).
+KELEM_FLOPS_PER_ELEM = 10.07e3
 # Bytes k_elem must move per triangle (FP32-mixed): cell averages in (4 x f64), higher modes in
 # (20 x f32), limiter factor (f64), geometry (Jinv 4 x f32, outward normals 6 x f32, edge slots
-# 3 x i32), higher modes out (20 x f32), traces out (3 edges x 3 points x (q, n.F_T) x 4 x f32).
+# 3 x i32), higher modes out (20 x f32), traces out (3 edges x 3 points x 4 x f32: one record per
+# edge side and point, n_out.F_T/2 + (s|n|/2) q).
 def kelem_bytes_per_elem(rsize):
-    return 4 * 8 + 20 * rsize + 8 + 10 * rsize + 12 + 20 * rsize + 72 * rsize
+    return 4 * 8 + 20 * rsize + 8 + 10 * rsize + 12 + 20 * rsize + 36 * rsize
 
 
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "ae42d716e1d982dc349c4d51fd78a865976d861bbfe422972c96e05c94763de1",
-           "bytes_per_launch": {"k_pre": 136560548, "k_elem": 680733696, "k_edge": 525987840,
-                                "k_flim": 173578035, "k_update": 459344896}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "86ee63dc1202e022615f7e48dce5e96fce5aad76ac3a3312f23915a8be53e782",
+           "bytes_per_launch": {"k_pre": 136614359, "k_elem": 409235456, "k_edge": 381128704,
+                                "k_flim": 174039142, "k_update": 399587328}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
