@@ -174,6 +174,17 @@ __device__ __forceinline__ void d2flux(const St<DIM, R>& s, int d, const R* a, c
   F[DIM + 1] = d2u * s.Ep + va.du[d] * (b[DIM + 1] + vb.dp) + vb.du[d] * (a[DIM + 1] + va.dp) + s.u[d] * d2p;
 }
 
+// H_d(a, a), the same terms with the two symmetric ones gathered
+template <int DIM, class R>
+__device__ __forceinline__ void d2flux_sym(const St<DIM, R>& s, int d, const R* a, const Var<DIM, R>& va, R d2p, R* F) {
+  const R du2 = R(2) * va.du[d];
+  const R d2u = -du2 * a[0] * s.r;
+  F[0] = R(0);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) F[1 + k] = a[1 + k] * du2 + s.m[k] * d2u + (k == d ? d2p : R(0));
+  F[DIM + 1] = d2u * s.Ep + du2 * (a[DIM + 1] + va.dp) + s.u[d] * d2p;
+}
+
 template <int DIM, class R>
 __device__ __forceinline__ R d2p_of(const St<DIM, R>& s, const Var<DIM, R>& va, const Var<DIM, R>& vb, R gm1) {
   R t = R(0);
@@ -201,7 +212,7 @@ __device__ __forceinline__ void ft_core(const St<DIM, R>& s, const R* qt, const 
     R F[V], A[V], H[V];
     flux<DIM, R>(s, d, F);
     dflux<DIM, R>(s, d, qc, vc, A);
-    d2flux<DIM, R>(s, d, qt, vt, qt, vt, d2p, H);
+    d2flux_sym<DIM, R>(s, d, qt, vt, d2p, H);
 #pragma unroll
     for (int c = 0; c < V; ++c) FT[d][c] = F[c] + A[c] + c2 * H[c];
   }
