@@ -1272,23 +1272,56 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
       }
   }
 
-  // Hessian of D (constant): d/dxi_b d/dxi_b' sum_a d/dxi_a Fc_a, third reference derivative
-  // index = number of eta derivatives
+  // The point derivatives come from Taylor coefficients at the reference origin, formed once per
+  // element (reference derivative indices count the eta derivatives: second xx, xy, yy; third xxx,
+  // xxy, xyy, yyy): q is cubic, so its reference gradient is g0 + H0 x + T3[x, x]/2 and its
+  // reference Hessian H0 + T3 x; D = div F^h is quadratic, D0 + gD0 . x + x^T HDr x / 2, with
+  // reference gradient gD0 + HDr x and constant Hessian HDr (the physical HD).  The limiter
+  // factor theta is folded into q's coefficients.  F^h is not needed after this.
+  constexpr int N2 = 2 * DIM - 1;
+  R qg0[V][DIM], qH0[V][N2], qT3[V][E::ND3], D0[V], gD0[V][DIM], HDr[V][N2];
   R HD[DIM][DIM][V];
 #pragma unroll
   for (int c = 0; c < V; ++c) {
-    R hr[2 * DIM - 1];
 #pragma unroll
-    for (int j = 0; j < 2 * DIM - 1; ++j) {
-      R t = R(0);
+    for (int a = 0; a < DIM; ++a) {
+      R t = R(0), u = R(0);
+#pragma unroll
+      for (int l = 1; l < ML; ++l) t += Qr[c][l - 1] * T.dphi0[a][l];
+      qg0[c][a] = thR * t;
 #pragma unroll
       for (int l = 0; l < ML; ++l)
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) t += Fh[a][c][l] * T.d3c[a + j][l];
-      hr[j] = t;
+        for (int b = 0; b < DIM; ++b) u += Fh[b][c][l] * T.d2c[a + b][l];
+      gD0[c][a] = u;
     }
+#pragma unroll
+    for (int j = 0; j < N2; ++j) {
+      R t = R(0), u = R(0);
+#pragma unroll
+      for (int l = 1; l < ML; ++l) t += Qr[c][l - 1] * T.d2c[j][l];
+      qH0[c][j] = thR * t;
+#pragma unroll
+      for (int l = 0; l < ML; ++l)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) u += Fh[a][c][l] * T.d3c[a + j][l];
+      HDr[c][j] = u;
+    }
+#pragma unroll
+    for (int j = 0; j < E::ND3; ++j) {
+      R t = R(0);
+#pragma unroll
+      for (int l = 1; l < ML; ++l) t += Qr[c][l - 1] * T.d3c[j][l];
+      qT3[c][j] = thR * t;
+    }
+    R t = R(0);
+#pragma unroll
+    for (int l = 0; l < ML; ++l)
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) t += Fh[a][c][l] * T.dphi0[a][l];
+    D0[c] = t;
     R h[DIM][DIM];
-    map2(hr, h);
+    map2(HDr[c], h);
 #pragma unroll
     for (int d = 0; d < DIM; ++d)
 #pragma unroll
@@ -1298,31 +1331,43 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
   auto point = [&](int p, R* q, R* qt, R* qtt, R* qttt, R FT[DIM][V]) {
     R gq[DIM][V], Hq[DIM][DIM][V], D[V], gD[DIM][V];
     state_at(p, q);
+    // the point's reference coordinates x and the quadratic monomials m2[j] (j eta factors), with
+    // the factor 1/2 of the Taylor series and the two orderings of a mixed product
+    R x[DIM], m2[N2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) x[a] = T.xr[p][a];
+    if constexpr (DIM == 1) {
+      m2[0] = R(0.5) * x[0] * x[0];
+    } else {
+      m2[0] = R(0.5) * x[0] * x[0];
+      m2[1] = x[0] * x[1];
+      m2[2] = R(0.5) * x[1] * x[1];
+    }
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-      R g[DIM], hq[2 * DIM - 1], gd[DIM];
-      R dd = R(0);
+      R g[DIM], hq[N2], gd[DIM];
+      R dd = D0[c];
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) { g[a] = R(0); gd[a] = R(0); }
+      for (int j = 0; j < N2; ++j) dd += HDr[c][j] * m2[j];
 #pragma unroll
-      for (int j = 0; j < 2 * DIM - 1; ++j) hq[j] = R(0);
+      for (int a = 0; a < DIM; ++a) {
+        R t = qg0[c][a], u = gD0[c][a];
 #pragma unroll
-      for (int l = 0; l < ML; ++l) {
+        for (int b = 0; b < DIM; ++b) { t += qH0[c][a + b] * x[b]; u += HDr[c][a + b] * x[b]; }
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          if (l > 0) g[a] += Qr[c][l - 1] * T.dphi[p][a][l];
-          dd += Fh[a][c][l] * T.dphi[p][a][l];
+        for (int j = 0; j < N2; ++j) t += qT3[c][a + j] * m2[j];
+        g[a] = t;
+        gd[a] = u;
+        dd += gD0[c][a] * x[a];
+      }
 #pragma unroll
-          for (int b = 0; b < DIM; ++b) gd[b] += Fh[a][c][l] * T.d2phi[p][a + b][l];
-        }
-        if (l > 0) {
+      for (int j = 0; j < N2; ++j) {
+        R t = qH0[c][j];
 #pragma unroll
-          for (int j = 0; j < 2 * DIM - 1; ++j) hq[j] += Qr[c][l - 1] * T.d2phi[p][j][l];
-        }
+        for (int e = 0; e < DIM; ++e) t += qT3[c][j + e] * x[e];
+        hq[j] = t;
       }
       D[c] = dd;
-#pragma unroll
-      for (int j = 0; j < 2 * DIM - 1; ++j) hq[j] *= thR;
       R h[DIM][DIM];
       map2(hq, h);
 #pragma unroll
@@ -1330,7 +1375,7 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
         R sg = R(0), sd = R(0);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) { sg += Ji[a][d] * g[a]; sd += Ji[a][d] * gd[a]; }
-        gq[d][c] = thR * sg;
+        gq[d][c] = sg;
         gD[d][c] = sd;
 #pragma unroll
         for (int e = 0; e < DIM; ++e) Hq[d][e][c] = h[d][e];
