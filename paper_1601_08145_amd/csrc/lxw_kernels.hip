@@ -581,7 +581,10 @@ __device__ __forceinline__ void pre_item(View<R> v, const int i) {
       double wmax[V], wmin[V];
       prim_avg(wmax);
       prim_avg(wmin);
-#pragma unroll
+      // a loop at run time (the table rows are scalar loads): unrolled, the point states of all
+      // points were scheduled together and the kernel needed 160 registers (three waves per SIMD
+      // instead of four on triangles; 1.5x the time on tetrahedra)
+#pragma unroll 1
       for (int p = 0; p < NP; ++p) {
         double q[V];
 #pragma unroll
