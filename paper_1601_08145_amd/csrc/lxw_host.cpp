@@ -426,6 +426,23 @@ void fill_tab(RefTab<E, R>& T) {
       T.wphi[m][l] = R(r.w[m] * B(l, xi, 0, 0));
       for (int a = 0; a < E::DIM; ++a) T.wdphi[m][a][l] = R(r.w[m] * B(l, xi, a == 0, a == 1, a == 2));
     }
+  // the projection composed with div F^h and its gradient at the reference origin, in float64
+  // before rounding: kd0[m][a] = sum_l w_m phi_l(x_m) d_a phi_l(0), kd1[m][a][b] likewise with d_a d_b
+  for (int m = 0; m < E::NI; ++m) {
+    double xi[3] = {pts[m * E::DIM], E::DIM >= 2 ? pts[m * E::DIM + 1] : 0.0, E::DIM == 3 ? pts[m * E::DIM + 2] : 0.0};
+    const double o[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < E::DIM; ++a) {
+      double s0 = 0.0;
+      for (int l = 0; l < E::ML; ++l) s0 += r.w[m] * B(l, xi, 0, 0) * B(l, o, a == 0, a == 1, a == 2);
+      T.kd0[m][a] = R(s0);
+      for (int b2 = 0; b2 < E::DIM; ++b2) {
+        double s1 = 0.0;
+        for (int l = 0; l < E::ML; ++l)
+          s1 += r.w[m] * B(l, xi, 0, 0) * B(l, o, (a == 0) + (b2 == 0), (a == 1) + (b2 == 1), (a == 2) + (b2 == 2));
+        T.kd1[m][a][b2] = R(s1);
+      }
+    }
+  }
   // in 1D a face is a point with the single weight 2, so that (1/2) sum omega = 1
   for (int j = 0; j < E::NQE; ++j) T.om[j] = R(edge_w<E>(j));
   for (int k = 0; k < E::K; ++k)

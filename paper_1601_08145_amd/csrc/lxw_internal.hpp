@@ -50,6 +50,10 @@ struct RefTab {
   R d2phi[E::NP][E::ND2][E::ML];   // reference second derivatives (xx[, xy, yy])
   R wphi[E::NI][E::ML];            // w_m phi_l(x_m): projection onto the basis
   R wdphi[E::NI][E::DIM][E::ML];   // w_m grad phi_l(x_m): volume term
+  R kd0[E::NI][E::DIM];            // sum_l w_m phi_l(x_m) d phi_l/d xi_a (origin): the projection of
+                                   // Step 1 composed with div at the reference origin
+  R kd1[E::NI][E::DIM][E::DIM];    // sum_l w_m phi_l(x_m) d2 phi_l/d xi_a d xi_b (origin): the same
+                                   // with the gradient of div (complete P2, affine elements)
   R ephi[E::K][E::NQE][E::ML];     // (1/2) omega_j phi_l(x_kj): edge term of the update
   R om[E::NQE];                    // Gauss-Legendre weights on [-1, 1]
   R xr[E::NP][E::DIM];             // reference coordinates of the points

@@ -901,14 +901,33 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
     }
   };
 
+  // Complete P2 on an affine element (line, triangle, tetrahedron): grad q and div F^h are linear
+  // and their derivatives constant, so they are formed once per element from their values at the
+  // reference origin and the constant reference Hessians, and each point costs a few multiply-adds.
+  // In 2D and 3D F^h itself is never needed: Step 1's projection composed with div (and its
+  // gradient) at the origin is a fixed table (kd0, kd1), and D0 = div F^h(0) and gDr = grad div F^h
+  // accumulate directly from the quadrature values.  (1D, three modes, forms F^h as before; on the
+  // tensor Q2 quadrilateral they are not linear, and those points contract F^h and the modes
+  // directly.)
+  constexpr bool AFF = E::kind != ElQuad::kind;
+  constexpr bool KD = AFF && DIM >= 2;
   // Sec. 2.3 Step 1: Fc^h_a = sum_m w_m Fc_a(q(x_m)) phi_l(x_m)
   R Fh[DIM][V][ML];
+  R D0[V], gDr[V][DIM];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a)
+  for (int c = 0; c < V; ++c) {
+    D0[c] = R(0);
 #pragma unroll
-    for (int c = 0; c < V; ++c)
+    for (int b = 0; b < DIM; ++b) gDr[c][b] = R(0);
+  }
+  if constexpr (!KD) {
 #pragma unroll
-      for (int l = 0; l < ML; ++l) Fh[a][c][l] = R(0);
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int c = 0; c < V; ++c)
+#pragma unroll
+        for (int l = 0; l < ML; ++l) Fh[a][c][l] = R(0);
+  }
   for (int m = 0; m < NI; ++m) {
     R q[V];
     state_at(m, q);
@@ -923,8 +942,14 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
         R fc = R(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) fc += Ji[a][d] * F[d][c];
+        if constexpr (KD) {
+          D0[c] += T.kd0[m][a] * fc;
 #pragma unroll
-        for (int l = 0; l < ML; ++l) Fh[a][c][l] += T.wphi[m][l] * fc;
+          for (int b = 0; b < DIM; ++b) gDr[c][b] += T.kd1[m][a][b] * fc;
+        } else {
+#pragma unroll
+          for (int l = 0; l < ML; ++l) Fh[a][c][l] += T.wphi[m][l] * fc;
+        }
       }
   }
 
@@ -934,15 +959,20 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
 #pragma unroll
     for (int l = 0; l < ML - 1; ++l) vol[c][l] = R(0);
 
-  // Complete P2 on an affine element (line, triangle): grad q and div F^h are linear and their
-  // derivatives constant, so they are formed once per element from their values at the reference
-  // origin and the constant reference Hessians, and each point costs a few multiply-adds.  (On the
-  // tensor Q2 quadrilateral they are not linear; those points contract the modes directly.)
-  constexpr bool AFF = E::kind != ElQuad::kind;
-  R g0[V][DIM], Hq[V][E::ND2], D0[V], gDr[V][DIM], gDx[DIM][V];
+  R g0[V][DIM], Hq[V][E::ND2], gDx[DIM][V];
   if constexpr (AFF) {
 #pragma unroll
     for (int c = 0; c < V; ++c) {
+      if constexpr (!KD) {  // 1D: div F^h and its derivative at the origin from F^h
+        R dd = R(0), h = R(0);
+#pragma unroll
+        for (int l = 0; l < ML; ++l) {
+          dd += Fh[0][c][l] * T.dphi0[0][l];
+          h += Fh[0][c][l] * T.d2c[0][l];
+        }
+        D0[c] = dd;
+        gDr[c][0] = h;
+      }
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
         R acc = R(0);
@@ -957,34 +987,11 @@ __device__ __forceinline__ void elem_item2(View<R> v, const int i) {
         for (int l = 1; l < ML; ++l) acc += Qr[c][l - 1] * T.d2c[k][l];
         Hq[c][k] = thR * acc;
       }
-      R dd = R(0);
-      R h[DIM];
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) h[a] = R(0);
-#pragma unroll
-      for (int l = 0; l < ML; ++l) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) dd += Fh[a][c][l] * T.dphi0[a][l];
-        if constexpr (DIM == 1) {
-          h[0] += Fh[0][c][l] * T.d2c[0][l];
-        } else if constexpr (DIM == 2) {
-          h[0] += Fh[0][c][l] * T.d2c[0][l] + Fh[1][c][l] * T.d2c[1][l];
-          h[1] += Fh[0][c][l] * T.d2c[1][l] + Fh[1][c][l] * T.d2c[2][l];
-        } else {
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-            h[b] += Fh[0][c][l] * T.d2c[sidx<3>(0, b)][l] + Fh[1][c][l] * T.d2c[sidx<3>(1, b)][l] +
-                    Fh[2][c][l] * T.d2c[sidx<3>(2, b)][l];
-        }
-      }
-      D0[c] = dd;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) gDr[c][a] = h[a];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         R sh = R(0);
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) sh += Ji[a][d] * h[a];
+        for (int a = 0; a < DIM; ++a) sh += Ji[a][d] * gDr[c][a];
         gDx[d][c] = sh;
       }
     }
