@@ -441,6 +441,12 @@ void fill_tab(RefTab<E, R>& T) {
           s1 += r.w[m] * B(l, xi, 0, 0) * B(l, o, (a == 0) + (b2 == 0), (a == 1) + (b2 == 1), (a == 2) + (b2 == 2));
         T.kd1[m][a][b2] = R(s1);
       }
+      if constexpr (E::DEG == 3)
+        for (int j = 0; j < 2 * E::DIM - 1; ++j) {
+          double s2 = 0.0;  // third derivative with a + j of its three in eta (1D: xxx)
+          for (int l = 0; l < E::ML; ++l) s2 += r.w[m] * B(l, xi, 0, 0) * B(l, o, 3 - (a + j), a + j);
+          T.kd2[m][a][j] = R(s2);
+        }
     }
   }
   // in 1D a face is a point with the single weight 2, so that (1/2) sum omega = 1

@@ -54,6 +54,8 @@ struct RefTab {
                                    // Step 1 composed with div at the reference origin
   R kd1[E::NI][E::DIM][E::DIM];    // sum_l w_m phi_l(x_m) d2 phi_l/d xi_a d xi_b (origin): the same
                                    // with the gradient of div (complete P2, affine elements)
+  R kd2[E::DEG == 3 ? E::NI : 1][E::DIM][2 * E::DIM - 1];  // degree 3: the same with the (constant)
+                                   // second derivatives of div, index j = eta derivatives of the pair
   R ephi[E::K][E::NQE][E::ML];     // (1/2) omega_j phi_l(x_kj): edge term of the update
   R om[E::NQE];                    // Gauss-Legendre weights on [-1, 1]
   R xr[E::NP][E::DIM];             // reference coordinates of the points

@@ -1255,14 +1255,30 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
       }
   };
 
-  // Sec. 2.3 Step 1: Fc^h_a = sum_m w_m Fc_a(q(x_m)) phi_l(x_m)
+  // Sec. 2.3 Step 1: Fc^h_a = sum_m w_m Fc_a(q(x_m)) phi_l(x_m).  Only D = div F^h is needed, and
+  // it is quadratic: on triangles its value, gradient and Hessian at the reference origin accumulate
+  // straight from the quadrature values through the tables kd0, kd1, kd2 (the projection composed
+  // with div and its derivatives); in 1D F^h is formed.
+  constexpr int N2 = 2 * DIM - 1;
+  constexpr bool KD = DIM >= 2;
   R Fh[DIM][V][ML];
+  R D0[V], gD0[V][DIM], HDr[V][N2];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a)
+  for (int c = 0; c < V; ++c) {
+    D0[c] = R(0);
 #pragma unroll
-    for (int c = 0; c < V; ++c)
+    for (int a = 0; a < DIM; ++a) gD0[c][a] = R(0);
 #pragma unroll
-      for (int l = 0; l < ML; ++l) Fh[a][c][l] = R(0);
+    for (int j = 0; j < N2; ++j) HDr[c][j] = R(0);
+  }
+  if constexpr (!KD) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int c = 0; c < V; ++c)
+#pragma unroll
+        for (int l = 0; l < ML; ++l) Fh[a][c][l] = R(0);
+  }
   for (int m = 0; m < NI; ++m) {
     R q[V];
     state_at(m, q);
@@ -1277,8 +1293,16 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
         R fc = R(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) fc += Ji[a][d] * F[d][c];
+        if constexpr (KD) {
+          D0[c] += T.kd0[m][a] * fc;
 #pragma unroll
-        for (int l = 0; l < ML; ++l) Fh[a][c][l] += T.wphi[m][l] * fc;
+          for (int b = 0; b < DIM; ++b) gD0[c][b] += T.kd1[m][a][b] * fc;
+#pragma unroll
+          for (int j = 0; j < N2; ++j) HDr[c][j] += T.kd2[m][a][j] * fc;
+        } else {
+#pragma unroll
+          for (int l = 0; l < ML; ++l) Fh[a][c][l] += T.wphi[m][l] * fc;
+        }
       }
   }
 
@@ -1287,9 +1311,8 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
   // xxy, xyy, yyy): q is cubic, so its reference gradient is g0 + H0 x + T3[x, x]/2 and its
   // reference Hessian H0 + T3 x; D = div F^h is quadratic, D0 + gD0 . x + x^T HDr x / 2, with
   // reference gradient gD0 + HDr x and constant Hessian HDr (the physical HD).  The limiter
-  // factor theta is folded into q's coefficients.  F^h is not needed after this.
-  constexpr int N2 = 2 * DIM - 1;
-  R qg0[V][DIM], qH0[V][N2], qT3[V][E::ND3], D0[V], gD0[V][DIM], HDr[V][N2];
+  // factor theta is folded into q's coefficients.
+  R qg0[V][DIM], qH0[V][N2], qT3[V][E::ND3];
   R HD[DIM][DIM][V];
 #pragma unroll
   for (int c = 0; c < V; ++c) {
@@ -1299,11 +1322,13 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
 #pragma unroll
       for (int l = 1; l < ML; ++l) t += Qr[c][l - 1] * T.dphi0[a][l];
       qg0[c][a] = thR * t;
+      if constexpr (!KD) {
 #pragma unroll
-      for (int l = 0; l < ML; ++l)
+        for (int l = 0; l < ML; ++l)
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) u += Fh[b][c][l] * T.d2c[a + b][l];
-      gD0[c][a] = u;
+          for (int b = 0; b < DIM; ++b) u += Fh[b][c][l] * T.d2c[a + b][l];
+        gD0[c][a] = u;
+      }
     }
 #pragma unroll
     for (int j = 0; j < N2; ++j) {
@@ -1311,11 +1336,13 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
 #pragma unroll
       for (int l = 1; l < ML; ++l) t += Qr[c][l - 1] * T.d2c[j][l];
       qH0[c][j] = thR * t;
+      if constexpr (!KD) {
 #pragma unroll
-      for (int l = 0; l < ML; ++l)
+        for (int l = 0; l < ML; ++l)
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) u += Fh[a][c][l] * T.d3c[a + j][l];
-      HDr[c][j] = u;
+          for (int a = 0; a < DIM; ++a) u += Fh[a][c][l] * T.d3c[a + j][l];
+        HDr[c][j] = u;
+      }
     }
 #pragma unroll
     for (int j = 0; j < E::ND3; ++j) {
@@ -1324,12 +1351,14 @@ __device__ __forceinline__ void elem_item3(View<R> v, const int i) {
       for (int l = 1; l < ML; ++l) t += Qr[c][l - 1] * T.d3c[j][l];
       qT3[c][j] = thR * t;
     }
-    R t = R(0);
+    if constexpr (!KD) {
+      R t = R(0);
 #pragma unroll
-    for (int l = 0; l < ML; ++l)
+      for (int l = 0; l < ML; ++l)
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) t += Fh[a][c][l] * T.dphi0[a][l];
-    D0[c] = t;
+        for (int a = 0; a < DIM; ++a) t += Fh[a][c][l] * T.dphi0[a][l];
+      D0[c] = t;
+    }
     R h[DIM][DIM];
     map2(HDr[c], h);
 #pragma unroll
