@@ -52,7 +52,7 @@ STEP_BYTES_PER_ELEM = 228
 # div F^h, grad div F^h and F_T at 16 points, volume term, traces.  Counted from the kernel's
 # executed VALU instructions per wavefront (64 triangles): fp32 FMA x 2 + fp32 add + fp32 mul +
 # fp64 FMA x 2 + fp64 add + fp64 mul, divided by 64 (profiles/lxw_kernels_tri_c3_counters.md).
-KELEM_FLOPS_PER_ELEM = 10.04e3
+KELEM_FLOPS_PER_ELEM = 9.41e3
 # Bytes k_elem must move per triangle (FP32-mixed): cell averages in (4 x f64), higher modes in
 # (20 x f32), limiter factor (f64), geometry (Jinv 4 x f32, outward normals 6 x f32, edge slots
 # 3 x i32), higher modes out (20 x f32), traces out (3 edges x 3 points x 4 x f32: one record per
@@ -64,9 +64,9 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "72e2df630d75e5c2f52d013e5b03f8ac419570ea5244f4bfe8716e4e45f7423a",
-           "bytes_per_launch": {"k_pre": 139070925, "k_elem": 408239514, "k_edge": 381169664,
-                                "k_flim": 174051738, "k_update": 399890432}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "e92fed35705d2a751e153de70f5d22a144e4467abf547dea3584bbb18def691c",
+           "bytes_per_launch": {"k_pre": 138928589, "k_elem": 409497600, "k_edge": 381149184,
+                                "k_flim": 174045901, "k_update": 399915008}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
