@@ -53,6 +53,11 @@ STEP_BYTES_PER_ELEM = 228
 # executed VALU instructions per wavefront (64 triangles): fp32 FMA x 2 + fp32 add + fp32 mul +
 # fp64 FMA x 2 + fp64 add + fp64 mul, divided by 64 (profiles/lxw_kernels_tri_c3_counters.md).
 KELEM_FLOPS_PER_ELEM = 9.41e3
+# The bound k_elem actually meets: VALU instruction issue.  Executed VALU instructions per wavefront
+# of 64 triangles (SQ_INSTS_VALU / SQ_WAVES, same counter file); a wave64 VALU instruction occupies a
+# 16-lane SIMD for 4 cycles, and the chip has 256 CUs x 4 SIMDs at 2.4 GHz.
+KELEM_VALU_INSTS_PER_WAVE = 5872
+VALU_SIMDS, CLOCK_GHZ = 1024, 2.4
 # Bytes k_elem must move per triangle (FP32-mixed): cell averages in (4 x f64), higher modes in
 # (20 x f32), limiter factor (f64), geometry (Jinv 4 x f32, outward normals 6 x f32, edge slots
 # 3 x i32), higher modes out (20 x f32), traces out (3 edges x 3 points x 4 x f32: one record per
@@ -199,6 +204,7 @@ def kelem_roofline(kavg_ms, n_elem, traffic_ok, ms_per_step=None):
     peak; with ms_per_step, the whole step's algorithmic bytes against the HBM peak and the counted
     traffic of the step's kernels against those bytes."""
     achieved = KELEM_FLOPS_PER_ELEM * n_elem / (kavg_ms * 1e-3) / 1e12
+    issue_ms = KELEM_VALU_INSTS_PER_WAVE * (-(-n_elem // 64)) * 4 / VALU_SIMDS / (CLOCK_GHZ * 1e9) * 1e3
     bytes_ = kelem_bytes_per_elem(4) * n_elem
     traffic = None
     if traffic_ok and traffic_valid():
@@ -208,6 +214,10 @@ def kelem_roofline(kavg_ms, n_elem, traffic_ok, ms_per_step=None):
            "kernel_ms": kavg_ms, "flops_per_elem": KELEM_FLOPS_PER_ELEM, "units_per_launch": n_elem,
            "frac_of_nonpacked_fp32_peak": achieved / PEAK_VECTOR_NONPACKED_TFLOPS,
            "nonpacked_fp32_peak": PEAK_VECTOR_NONPACKED_TFLOPS,
+           "issue_view": {"valu_insts_per_wave": KELEM_VALU_INSTS_PER_WAVE, "waves": -(-n_elem // 64),
+                          "issue_ms": issue_ms, "frac": issue_ms / kavg_ms,
+                          "note": "VALU issue time of the counted instructions (4 cycles per wave64 "
+                                  "instruction, 1024 SIMDs at 2.4 GHz) over the kernel time"},
            "hbm_view": {"achieved_GBs": bytes_ / (kavg_ms * 1e-3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
                         "frac": bytes_ / (kavg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                         "bytes_per_elem": kelem_bytes_per_elem(4)}}
