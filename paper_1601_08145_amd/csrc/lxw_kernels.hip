@@ -98,9 +98,10 @@ struct St {
 };
 
 // 1/rho: in the float32 bulk the hardware reciprocal refined by one Newton-Raphson step,
-// r + r (1 - x r) (the estimate is within 1 ulp; the step brings it to the correctly rounded
-// quotient but for rare ties, in 3 instructions instead of the division's 10; rho is positive and
-// far above the denormal range wherever it is used), in float64 the correctly rounded quotient.
+// r + r (1 - x r) with the residual formed exactly by a fused multiply-add (the estimate is within
+// 1 ulp; the refined value is within an ulp and almost always the correctly rounded quotient, in 3
+// instructions instead of the division's 10; rho is positive and far above the denormal range
+// wherever it is used), in float64 the correctly rounded quotient.
 __device__ __forceinline__ float recip(float x) {
   const float r = __builtin_amdgcn_rcpf(x);
   return __fmaf_rn(r, __fmaf_rn(-x, r, 1.0f), r);
