@@ -302,6 +302,24 @@ __device__ __forceinline__ void d3flux(const St<DIM, R>& s, int d, const R* a, c
              va.du[d] * pbc + vb.du[d] * pac + vc.du[d] * pab + s.u[d] * p3;
 }
 
+// F^(3)_d(a, a, a): the terms of d3flux with the three directions equal, gathered (the three
+// pairwise products are one, and each permuted sum becomes three times one term).
+template <int DIM, class R>
+__device__ __forceinline__ void d3flux_sym(const St<DIM, R>& s, int d, const R* a, const Var<DIM, R>& va, R gm1, R* F) {
+  constexpr int V = DIM + 2;
+  R aa = R(0);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) aa += va.du[k] * va.du[k];
+  const R paa = -gm1 * s.rho * aa;
+  const R p3 = R(3) * gm1 * a[0] * aa;
+  const R uaa = -R(2) * va.du[d] * a[0] * s.r;
+  const R u3 = -R(3) * uaa * a[0] * s.r;
+  F[0] = R(0);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) F[1 + k] = R(3) * a[1 + k] * uaa + s.m[k] * u3 + (k == d ? p3 : R(0));
+  F[V - 1] = u3 * s.Ep + R(3) * (uaa * (a[V - 1] + va.dp) + va.du[d] * paa) + s.u[d] * p3;
+}
+
 // Degree 3: F_T one Taylor term further, + dt^3/24 (F^(3)(q_t, q_t, q_t) + 3 H(q_t, q_tt) + A q_ttt).
 // A is linear and H bilinear, so the terms are gathered as
 //   F + A (c1 q_t + c2 q_tt + c3 q_ttt) + H(q_t, c2 q_t + 3 c3 q_tt) + c3 F^(3)(q_t, q_t, q_t)
@@ -327,7 +345,7 @@ __device__ __forceinline__ void ft4_core(const St<DIM, R>& s, const R* qt, const
     flux<DIM, R>(s, d, F);
     dflux<DIM, R>(s, d, qc, vc, A);
     d2flux<DIM, R>(s, d, qt, vt, qh, vh, d2p, H);
-    d3flux<DIM, R>(s, d, qt, vt, qt, vt, qt, vt, gm1, T3);
+    d3flux_sym<DIM, R>(s, d, qt, vt, gm1, T3);
 #pragma unroll
     for (int c = 0; c < V; ++c) FT[d][c] = F[c] + A[c] + H[c] + c3 * T3[c];
   }
