@@ -69,9 +69,9 @@ def kelem_bytes_per_elem(rsize):
 # HBM traffic of one launch of each step kernel on the 2D triangle workload (FP32-mixed) from
 # rocprofv3 counters (FETCH_SIZE x 2 + WRITE_SIZE, scale factors from a copy of known size), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"src_sha256": "3889ff41b8a2a8dae70fd762b1459bf6b0885f19329a920506111d33db7f39ba",
-           "bytes_per_launch": {"k_pre": 138932367, "k_elem": 409809510, "k_edge": 381155328,
-                                "k_flim": 174039962, "k_update": 399447040}}  # profiles/lxw_kernels_tri_c3_counters.md
+TRAFFIC = {"src_sha256": "e2c6f33d22e97d9db911cd1b7a12a36f6a8142f6f385f2e124f4789be58e47d0",
+           "bytes_per_launch": {"k_pre": 138976369, "k_elem": 409446605, "k_edge": 381145088,
+                                "k_flim": 174059520, "k_update": 399809536}}  # profiles/lxw_kernels_tri_c3_counters.md
 
 
 def traffic_valid():
